@@ -1,0 +1,569 @@
+"""FP64 CPU oracle for the MUSTER per-iteration optimisation path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module: it exists so that tests, the smoke check and the CPU
+baseline of the benchmark can compare the HIP implementation against a plain,
+slow, obviously correct statement of what the method computes.  It shares no
+code with the HIP path and imports nothing from it.
+
+Every function follows a passage of the MUSTER paper (Multi-Session Temporal
+Registration, arXiv 2412.14671).  Section numbers below are the paper's:
+Sec. 2.1 (deformation conventions), Sec. 2.2 (loss, Eq. cum_deformation),
+Sec. 2.3 (scaling and squaring, Alg. 1), Sec. 2.4 (regularisers, Eq. reg_ss,
+reg_sum), Sec. 2.6 (LNCC Eq. LNCC / sum_lncc; SiLNCC Eq. sim_loss),
+Sec. 2.7 (Adam, warm-up + cosine schedule, three-stage pyramid),
+Sec. 2.8 (Euclidean-distance metric).
+
+Conventions (readings where the paper is silent; each is listed in the design
+notes of the repository):
+  * A volume is a C-order array (D, H, W); a vector field is (3, D, H, W) with
+    components (z, y, x).  Grid point p has coordinate p (voxel indices), and
+    fields hold displacements u = Phi - Omega in voxels of their own grid.
+  * Trilinear sampling clamps the sample position to the grid (border
+    padding), uses the cell whose lower corner is floor(q) (the last cell at the
+    upper border) and has zero derivative along an axis whose coordinate was
+    outside the grid.
+  * Exp takes exactly K squarings of u_0 = phi / 2^K, in the displacement form
+    of Alg. 1.
+  * Pair fields are built by composing outward from the target session.
+  * Window statistics use the maximum-likelihood (1/n) moments over w^3
+    windows whose centres lie at least r = (w-1)/2 from every border.
+  * All arithmetic is float64; inputs are float32 arrays promoted on entry.
+
+Parity status: every function here is pinned by tests against closed forms,
+exact identities, brute force or finite differences, except the end-to-end
+optimisation trajectory (register), whose result is only compared by its
+registration error: "parity unpinned" for the trajectory itself.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+EPS_LNCC = 1e-10   # guard on vF*vM in LNCC (silent in the paper; never active on test data)
+EPS_SILNCC = 1e-6  # guard on vF in SiLNCC (silent in the paper; never active on test data)
+
+LNCC = 0
+SILNCC = 1
+
+
+# ---------------------------------------------------------------------------
+# Grid and trilinear sampling (Sec. 2.2: "trilinear interpolation")
+# ---------------------------------------------------------------------------
+
+def identity_grid(shape) -> np.ndarray:
+    """Omega_I: the coordinates of every grid point, shape (3, D, H, W)."""
+    return np.stack(np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape],
+                                indexing="ij"))
+
+
+def _axis(q: np.ndarray, n: int):
+    """Cell index, fraction and derivative mask along one axis for positions q."""
+    live = (q >= 0.0) & (q <= n - 1.0)
+    qc = np.clip(q, 0.0, n - 1.0)
+    i0 = np.minimum(np.floor(qc), n - 2).astype(np.int64)
+    t = qc - i0
+    return i0, t, live
+
+
+def sample(f: np.ndarray, q: np.ndarray, jac: bool = False):
+    """Trilinear sample of the field f (C, D, H, W) at positions q (3, ...).
+
+    Returns the sampled values (C, ...) and, when jac is set, the derivative of
+    each sampled component with respect to each coordinate of q, (C, 3, ...),
+    ordered (z, y, x).
+    """
+    D, H, W = f.shape[1:]
+    z0, tz, lz = _axis(q[0], D)
+    y0, ty, ly = _axis(q[1], H)
+    x0, tx, lx = _axis(q[2], W)
+    flat = f.reshape(f.shape[0], -1)
+    base = (z0 * H + y0) * W + x0
+    v = {}
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                v[a, b, c] = np.take(flat, base + (a * H + b) * W + c, axis=1)
+    c00 = v[0, 0, 0] + tx * (v[0, 0, 1] - v[0, 0, 0])
+    c01 = v[0, 1, 0] + tx * (v[0, 1, 1] - v[0, 1, 0])
+    c10 = v[1, 0, 0] + tx * (v[1, 0, 1] - v[1, 0, 0])
+    c11 = v[1, 1, 0] + tx * (v[1, 1, 1] - v[1, 1, 0])
+    c0 = c00 + ty * (c01 - c00)
+    c1 = c10 + ty * (c11 - c10)
+    val = c0 + tz * (c1 - c0)
+    if not jac:
+        return val
+    dz = (c1 - c0) * lz
+    dy0 = c01 - c00
+    dy1 = c11 - c10
+    dy = (dy0 + tz * (dy1 - dy0)) * ly
+    e00 = v[0, 0, 1] - v[0, 0, 0]
+    e01 = v[0, 1, 1] - v[0, 1, 0]
+    e10 = v[1, 0, 1] - v[1, 0, 0]
+    e11 = v[1, 1, 1] - v[1, 1, 0]
+    e0 = e00 + ty * (e01 - e00)
+    e1 = e10 + ty * (e11 - e10)
+    dx = (e0 + tz * (e1 - e0)) * lx
+    return val, np.stack([dz, dy, dx], axis=1)
+
+
+def sample_adjoint(g: np.ndarray, q: np.ndarray, shape) -> np.ndarray:
+    """Adjoint of sample() with respect to the sampled field's values.
+
+    Each position q(p) hands g(p) to the 8 corners of its cell with the
+    trilinear weights; the result is a field of the given grid shape.
+    """
+    D, H, W = shape
+    C = g.shape[0]
+    z0, tz, _ = _axis(q[0], D)
+    y0, ty, _ = _axis(q[1], H)
+    x0, tx, _ = _axis(q[2], W)
+    out = np.zeros((C, D * H * W), dtype=np.float64)
+    for a in (0, 1):
+        wz = tz if a else 1.0 - tz
+        for b in (0, 1):
+            wy = ty if b else 1.0 - ty
+            for c in (0, 1):
+                wx = tx if c else 1.0 - tx
+                w = (wz * wy * wx).ravel()
+                flat = (((z0 + a) * H + (y0 + b)) * W + (x0 + c)).ravel()
+                for k in range(C):
+                    out[k] += np.bincount(flat, weights=w * g[k].ravel(), minlength=D * H * W)
+    return out.reshape(C, D, H, W)
+
+
+def jac_transpose_apply(J: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """(J^T g)_b = sum_a J[a, b] g[a] for J of shape (3, 3, ...)."""
+    return np.einsum("ab...,a...->b...", J, g)
+
+
+# ---------------------------------------------------------------------------
+# Exp by scaling and squaring (Sec. 2.3, Alg. 1) and its adjoint
+# ---------------------------------------------------------------------------
+
+def exp_fwd(phi: np.ndarray, K: int) -> List[np.ndarray]:
+    """Displacements u_0..u_K of Exp(phi): u_0 = phi/2^K, then K squarings
+    u_{s+1} = u_s + u_s o (Omega + u_s) (the displacement form of Alg. 1)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    g = identity_grid(phi.shape[1:])
+    us = [phi * (2.0 ** -K)]
+    for _ in range(K):
+        u = us[-1]
+        us.append(u + sample(u, g + u))
+    return us
+
+
+def exp_step_bwd(u: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """Adjoint of one squaring u' = u + S(u, Omega + u): returns dL/du given
+    G = dL/du'.  Three terms: identity, the Jacobian of the sampled field at the
+    sample position, and the scatter of G to the corners that were sampled."""
+    g = identity_grid(u.shape[1:])
+    q = g + u
+    _, J = sample(u, q, jac=True)
+    return G + jac_transpose_apply(J, G) + sample_adjoint(G, q, u.shape[1:])
+
+
+def exp_bwd(us: List[np.ndarray], G_K: np.ndarray) -> np.ndarray:
+    """Given dL/du_K, return dL/du_0 by running the squarings backwards."""
+    G = np.asarray(G_K, dtype=np.float64)
+    for s in range(len(us) - 2, -1, -1):
+        G = exp_step_bwd(us[s], G)
+    return G
+
+
+# ---------------------------------------------------------------------------
+# Consecutive and pairwise deformations (Sec. 2.2 Eq. cum_deformation, Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def pair_index(i: int, j: int, N: int) -> int:
+    """Slot of pair (target i, source j), i != j, in an N(N-1) array."""
+    return i * (N - 1) + (j if j < i else j - 1)
+
+
+def compose(U_prev: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """Eq. cum_deformation in displacement form: U_prev + C o (Omega + U_prev)."""
+    g = identity_grid(U_prev.shape[1:])
+    return U_prev + sample(C, g + U_prev)
+
+
+def compose_bwd(U_prev: np.ndarray, C: np.ndarray, G: np.ndarray):
+    """Adjoint of compose(): (dL/dU_prev, dL/dC) given G = dL/dU_new."""
+    g = identity_grid(U_prev.shape[1:])
+    q = g + U_prev
+    _, J = sample(C, q, jac=True)
+    return G + jac_transpose_apply(J, G), sample_adjoint(G, q, C.shape[1:])
+
+
+def chain_parent(i: int, j: int):
+    """For a pair (i, j) with |i-j| >= 2: the previous pair of its chain and
+    which consecutive field is sampled, as ((i, j_prev), kind, index) with kind
+    'f' (forward Exp(phi_index)) or 'b' (backward Exp(-phi_index))."""
+    if j > i + 1:
+        return (i, j - 1), "f", j - 1
+    if j < i - 1:
+        return (i, j + 1), "b", j
+    raise ValueError("consecutive pair has no parent")
+
+
+def all_pairs(f: List[np.ndarray], b: List[np.ndarray]) -> Dict[Tuple[int, int], np.ndarray]:
+    """Every U[j->i] = Phi_ji^i - Omega for i != j.
+
+    f[i] = Exp(phi_i) lives on grid i and pulls session i+1 to session i;
+    b[i] = Exp(-phi_i) lives on grid i+1 and pulls session i to session i+1.
+    Longer pairs are composed outward from the target: U[j->i] samples f[j-1]
+    (j > i+1) or b[j] (j < i-1) at Omega + U[j-1->i] (resp. U[j+1->i]).
+    """
+    N = len(f) + 1
+    U: Dict[Tuple[int, int], np.ndarray] = {}
+    for i in range(N):
+        if i + 1 < N:
+            U[(i, i + 1)] = f[i]
+        if i - 1 >= 0:
+            U[(i, i - 1)] = b[i - 1]
+    for d in range(2, N):
+        for i in range(N):
+            for j in (i + d, i - d):
+                if 0 <= j < N:
+                    prev, kind, k = chain_parent(i, j)
+                    U[(i, j)] = compose(U[prev], f[k] if kind == "f" else b[k])
+    return U
+
+
+# ---------------------------------------------------------------------------
+# Warp and windowed similarity (Sec. 2.1, Sec. 2.6)
+# ---------------------------------------------------------------------------
+
+def warp(I: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """I o (Omega + U): the image I resampled on the deformed grid."""
+    g = identity_grid(I.shape)
+    return sample(np.asarray(I, np.float64)[None], g + U)[0]
+
+
+def warp_grad(I: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Derivative of warp(I, U)(p) with respect to U(p), shape (3, D, H, W)."""
+    g = identity_grid(I.shape)
+    _, J = sample(np.asarray(I, np.float64)[None], g + U, jac=True)
+    return J[0]
+
+
+def box_sum(X: np.ndarray, r: int) -> np.ndarray:
+    """Sum of X over the w^3 window (w = 2r+1) around every valid centre.
+
+    Valid centres are r <= c_d <= n_d-1-r, so the result has shape n_d - 2r.
+    The sum runs over every offset of the window, as in the definition."""
+    D, H, W = X.shape
+    out = np.zeros((D - 2 * r, H - 2 * r, W - 2 * r), dtype=np.float64)
+    w = 2 * r + 1
+    for a in range(w):
+        for b in range(w):
+            for c in range(w):
+                out += X[a:a + D - 2 * r, b:b + H - 2 * r, c:c + W - 2 * r]
+    return out
+
+
+def box_adjoint(A: np.ndarray, r: int, shape) -> np.ndarray:
+    """Adjoint of box_sum: every voxel y receives the sum of A over the valid
+    centres whose window contains y."""
+    D, H, W = shape
+    out = np.zeros(shape, dtype=np.float64)
+    w = 2 * r + 1
+    for a in range(w):
+        for b in range(w):
+            for c in range(w):
+                out[a:a + D - 2 * r, b:b + H - 2 * r, c:c + W - 2 * r] += A
+    return out
+
+
+def window_moments(F: np.ndarray, M: np.ndarray, w: int):
+    """Means, ML variances and covariance of (F, M) over every valid window."""
+    r = (w - 1) // 2
+    n = float(w ** 3)
+    F = np.asarray(F, np.float64)
+    M = np.asarray(M, np.float64)
+    SF, SM = box_sum(F, r), box_sum(M, r)
+    SFF, SMM, SFM = box_sum(F * F, r), box_sum(M * M, r), box_sum(F * M, r)
+    mF, mM = SF / n, SM / n
+    vF_raw = SFF / n - mF * mF
+    vM_raw = SMM / n - mM * mM
+    c = SFM / n - mF * mM
+    return dict(n=n, r=r, mF=mF, mM=mM, vF_raw=vF_raw, vM_raw=vM_raw,
+                vF=np.maximum(vF_raw, 0.0), vM=np.maximum(vM_raw, 0.0), c=c)
+
+
+def window_loss(mo, metric: int):
+    """Per-window loss l_R and its derivatives a_v = dl/dvM, a_c = dl/dc.
+
+    LNCC (Eq. LNCC): l = 1 - c / sqrt(vF vM), guarded by EPS_LNCC.
+    SiLNCC (Eq. sim_loss): l = vM - c^2 / vF, i.e. the residual variance of the
+    least-squares fit of the warped image on the fixed image, guarded by
+    EPS_SILNCC.  The fixed image (first argument of Sim) is the regressor.
+    """
+    vF, vM, c = mo["vF"], mo["vM"], mo["c"]
+    vm_live = mo["vM_raw"] > 0.0
+    if metric == LNCC:
+        den = vF * vM
+        active = den > EPS_LNCC
+        sd = np.sqrt(np.where(active, den, EPS_LNCC))
+        l = 1.0 - c / sd
+        a_c = -1.0 / sd
+        a_v = np.where(active, c / (2.0 * np.where(vM > 0, vM, 1.0) * sd), 0.0)
+    elif metric == SILNCC:
+        d = np.maximum(vF, EPS_SILNCC)
+        l = vM - c * c / d
+        a_c = -2.0 * c / d
+        a_v = np.ones_like(l)
+    else:
+        raise ValueError("unknown metric")
+    a_v = np.where(vm_live, a_v, 0.0)
+    return l, a_v, a_c
+
+
+def similarity(F: np.ndarray, M: np.ndarray, w: int, metric: int) -> float:
+    """Eq. sum_lncc / sim_loss: the mean of the per-window loss over windows."""
+    mo = window_moments(F, M, w)
+    l, _, _ = window_loss(mo, metric)
+    return float(l.mean())
+
+
+def similarity_grad_M(F: np.ndarray, M: np.ndarray, w: int, metric: int):
+    """Return (Sim, dSim/dM) for the fixed image F and the warped image M."""
+    mo = window_moments(F, M, w)
+    l, a_v, a_c = window_loss(mo, metric)
+    n = mo["n"]
+    NR = l.size
+    alpha = -(2.0 * mo["mM"] * a_v + mo["mF"] * a_c) / n   # dl/dS_M
+    beta = a_v / n                                         # dl/dS_MM
+    gamma = a_c / n                                        # dl/dS_FM
+    r = mo["r"]
+    shp = F.shape
+    Ba = box_adjoint(alpha, r, shp)
+    Bb = box_adjoint(beta, r, shp)
+    Bg = box_adjoint(gamma, r, shp)
+    M = np.asarray(M, np.float64)
+    F = np.asarray(F, np.float64)
+    dM = (Ba + 2.0 * M * Bb + F * Bg) / NR
+    return float(l.mean()), dM
+
+
+# ---------------------------------------------------------------------------
+# Regulariser (Sec. 2.4, Eq. reg_ss; only the spatial-smoothness term is on
+# the path, with alpha_L2 = alpha_ts = 0 in Eq. reg_sum)
+# ---------------------------------------------------------------------------
+
+def reg_ss(phi: np.ndarray) -> float:
+    """||grad phi||_F^2 by forward differences on the flow grid: for every
+    component c and axis d, the mean over valid grid points of the squared
+    difference, summed over the nine (c, d) entries."""
+    phi = np.asarray(phi, np.float64)
+    tot = 0.0
+    for d in range(3):
+        diff = np.diff(phi, axis=d + 1)
+        for c in range(3):
+            tot += float(np.mean(diff[c] ** 2))
+    return tot
+
+
+def reg_ss_grad(phi: np.ndarray) -> np.ndarray:
+    """Gradient of reg_ss with respect to phi."""
+    phi = np.asarray(phi, np.float64)
+    g = np.zeros_like(phi)
+    for d in range(3):
+        diff = np.diff(phi, axis=d + 1)
+        m = diff[0].size
+        hi = [slice(None)] * 4
+        lo = [slice(None)] * 4
+        hi[d + 1] = slice(1, None)
+        lo[d + 1] = slice(None, -1)
+        g[tuple(hi)] += 2.0 * diff / m
+        g[tuple(lo)] -= 2.0 * diff / m
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Loss and gradient (Sec. 2.2 loss, Sec. 2.4 Eq. reg_sum)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Params:
+    K: int = 7                 # squarings in Exp
+    window: int = 5            # w, the window edge
+    metric: int = LNCC         # LNCC or SILNCC
+    alpha_ss: float = 1.0      # weight of L_ss
+    lr: float = 0.1            # peak learning rate (voxels per step)
+    warmup: float = 0.2        # warm-up fraction of each stage
+    betas: Tuple[float, float] = (0.9, 0.999)
+    eps: float = 1e-8
+    iters: Tuple[int, ...] = (50,)   # iterations per pyramid level, coarse to fine
+
+
+def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: bool = False):
+    """Evaluate L(phi) = sum_i sum_{j != i} Sim(I_i, I_j o Phi_ji^i) + alpha_ss L_ss.
+
+    Returns the loss and, with keep=True, every intermediate the backward pass
+    needs (Exp steps, pair fields, warped images)."""
+    N = len(images)
+    imgs = [np.asarray(I, np.float64) for I in images]
+    phis = [np.asarray(ph, np.float64) for ph in phis]
+    fwd = [exp_fwd(ph, p.K) for ph in phis]
+    bwd = [exp_fwd(-ph, p.K) for ph in phis]
+    f = [us[-1] for us in fwd]
+    b = [us[-1] for us in bwd]
+    U = all_pairs(f, b)
+    sims = {}
+    for (i, j), Uij in U.items():
+        M = warp(imgs[j], Uij)
+        sims[(i, j)] = similarity(imgs[i], M, p.window, p.metric)
+    Lsim = float(sum(sims.values()))
+    Lreg = p.alpha_ss * sum(reg_ss(ph) for ph in phis) / (N - 1)
+    L = Lsim + Lreg
+    if not keep:
+        return L
+    return L, dict(fwd=fwd, bwd=bwd, f=f, b=b, U=U, sims=sims, Lsim=Lsim, Lreg=Lreg)
+
+
+def pair_sim_grad(images, U, i, j, p: Params):
+    """(Sim, dSim/dU[j->i]) for one pair: the similarity adjoint followed by the
+    warp derivative."""
+    M = warp(images[j], U)
+    s, dM = similarity_grad_M(images[i], M, p.window, p.metric)
+    return s, dM[None] * warp_grad(images[j], U)
+
+
+def loss_and_grad(phis: List[np.ndarray], images: List[np.ndarray], p: Params):
+    """Return (L, [dL/dphi_i], aux) by hand-written adjoints of every step."""
+    N = len(images)
+    imgs = [np.asarray(I, np.float64) for I in images]
+    L, aux = forward(phis, imgs, p, keep=True)
+    U = aux["U"]
+    f, b = aux["f"], aux["b"]
+    G = {}
+    for (i, j), Uij in U.items():
+        _, G[(i, j)] = pair_sim_grad(imgs, Uij, i, j, p)
+    aux["G_pair_sim"] = {k: v.copy() for k, v in G.items()}
+    Gf = [np.zeros_like(x) for x in f]
+    Gb = [np.zeros_like(x) for x in b]
+    # composition chains, deepest first
+    for d in range(N - 1, 1, -1):
+        for i in range(N):
+            for j in (i + d, i - d):
+                if 0 <= j < N:
+                    prev, kind, k = chain_parent(i, j)
+                    C = f[k] if kind == "f" else b[k]
+                    gp, gc = compose_bwd(U[prev], C, G[(i, j)])
+                    G[prev] = G[prev] + gp
+                    if kind == "f":
+                        Gf[k] += gc
+                    else:
+                        Gb[k] += gc
+    for i in range(N - 1):
+        Gf[i] += G[(i, i + 1)]
+        Gb[i] += G[(i + 1, i)]
+    aux["Gf"], aux["Gb"] = Gf, Gb
+    grads = []
+    scale = 2.0 ** -p.K
+    for i, ph in enumerate(phis):
+        g0f = exp_bwd(aux["fwd"][i], Gf[i])
+        g0b = exp_bwd(aux["bwd"][i], Gb[i])
+        g = scale * (g0f - g0b)
+        g = g + p.alpha_ss / (N - 1) * reg_ss_grad(ph)
+        grads.append(g)
+    return L, grads, aux
+
+
+# ---------------------------------------------------------------------------
+# Optimiser (Sec. 2.7: Adam, linear warm-up over the first 20 %, cosine decay)
+# ---------------------------------------------------------------------------
+
+def lr_schedule(t: int, T: int, lr0: float, warmup: float = 0.2) -> float:
+    """Learning rate at Adam step t = 1..T of a stage of T steps: linear from
+    0 to lr0 over the first W = ceil(warmup*T) steps, then a half cosine from
+    lr0 down to 0 at t = T."""
+    W = max(1, int(math.ceil(warmup * T)))
+    if t <= W:
+        return lr0 * t / W
+    if T == W:
+        return lr0
+    return lr0 * 0.5 * (1.0 + math.cos(math.pi * (t - W) / (T - W)))
+
+
+def adam_step(x, g, m, v, t, lr, betas=(0.9, 0.999), eps=1e-8):
+    """One Adam update with bias correction and no weight decay; returns the
+    new (x, m, v)."""
+    b1, b2 = betas
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    x = x - lr * mhat / (np.sqrt(vhat) + eps)
+    return x, m, v
+
+
+# ---------------------------------------------------------------------------
+# Pyramid (Sec. 2.7: three stages, each initialised from the previous one)
+# ---------------------------------------------------------------------------
+
+def pool2(I: np.ndarray) -> np.ndarray:
+    """2x2x2 mean: one level down the image pyramid."""
+    I = np.asarray(I, np.float64)
+    D, H, W = I.shape
+    return I.reshape(D // 2, 2, H // 2, 2, W // 2, 2).mean(axis=(1, 3, 5))
+
+
+def upsample2(phi: np.ndarray) -> np.ndarray:
+    """A displacement field on a grid twice as fine: fine voxel x sits at
+    coarse coordinate (x - 0.5)/2, and voxel units halve, so values double."""
+    phi = np.asarray(phi, np.float64)
+    D, H, W = phi.shape[1:]
+    g = identity_grid((2 * D, 2 * H, 2 * W))
+    return 2.0 * sample(phi, (g - 0.5) / 2.0)
+
+
+def register(images: List[np.ndarray], p: Params, phis0: Optional[List[np.ndarray]] = None,
+             record: bool = False):
+    """The whole optimisation: pyramid levels coarse to fine, each running
+    Adam on L(phi) for p.iters[level] steps from a schedule that restarts per
+    level.  Returns (phis at full resolution, pair fields, loss history)."""
+    L_lv = len(p.iters)
+    imgs_lv = [[np.asarray(I, np.float64) for I in images]]
+    for _ in range(L_lv - 1):
+        imgs_lv.insert(0, [pool2(I) for I in imgs_lv[0]])
+    N = len(images)
+    phis = None
+    hist = []
+    for lv in range(L_lv):
+        imgs = imgs_lv[lv]
+        shape = imgs[0].shape
+        if phis is None:
+            phis = phis0 if phis0 is not None else [np.zeros((3,) + shape) for _ in range(N - 1)]
+            phis = [np.asarray(x, np.float64) for x in phis]
+        else:
+            phis = [upsample2(x) for x in phis]
+        m = [np.zeros_like(x) for x in phis]
+        v = [np.zeros_like(x) for x in phis]
+        T = p.iters[lv]
+        for t in range(1, T + 1):
+            L, grads, _ = loss_and_grad(phis, imgs, p)
+            hist.append(L)
+            lr = lr_schedule(t, T, p.lr, p.warmup)
+            for k in range(N - 1):
+                phis[k], m[k], v[k] = adam_step(phis[k], grads[k], m[k], v[k], t, lr,
+                                                p.betas, p.eps)
+    fwd = [exp_fwd(ph, p.K)[-1] for ph in phis]
+    bwd = [exp_fwd(-ph, p.K)[-1] for ph in phis]
+    U = all_pairs(fwd, bwd)
+    return phis, U, hist
+
+
+# ---------------------------------------------------------------------------
+# Evaluation (Sec. 2.8)
+# ---------------------------------------------------------------------------
+
+def euclidean_error(phi_true: np.ndarray, phi: np.ndarray, roi: Optional[np.ndarray] = None) -> float:
+    """Eu: mean over the region of interest of the point-wise vector distance."""
+    d = np.sqrt(((np.asarray(phi_true, np.float64) - np.asarray(phi, np.float64)) ** 2).sum(0))
+    if roi is None:
+        return float(d.mean())
+    return float(d[roi].mean())

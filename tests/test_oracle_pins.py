@@ -1,0 +1,528 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names the passage it rests on.  None of them re-types the oracle's
+formula: they check exact identities of the method (scaling and squaring of
+constant and affine fields, composition of affine maps, invariances of the
+similarity metrics), closed forms (matrix powers and exponentials, the OLS
+residual variance, the paper's E[LNCC] approximation), brute force on tiny
+inputs, finite differences of the loss, and library routines (torch's Adam,
+scipy's expm).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+from oracle import muster_oracle as O
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def smooth_field(shape, amp, seed, sigma=2.0):
+    """A smooth random displacement field via scipy's Gaussian filter."""
+    import scipy.ndimage as ndi
+    r = rng(seed)
+    f = np.stack([ndi.gaussian_filter(r.standard_normal(shape), sigma, mode="nearest")
+                  for _ in range(3)])
+    return f * (amp / np.abs(f).max())
+
+
+def affine_field(shape, A, b):
+    """u(x) = A x + b on the grid."""
+    g = O.identity_grid(shape)
+    return np.einsum("ab,b...->a...", A, g) + b[:, None, None, None]
+
+
+# --------------------------------------------------------------------------
+# Trilinear sampling (Sec. 2.2) -- the primitive every step uses
+# --------------------------------------------------------------------------
+
+def test_sample_reproduces_grid_values_and_affine_functions():
+    r = rng(0)
+    f = r.standard_normal((2, 5, 6, 7))
+    g = O.identity_grid((5, 6, 7))
+    got = O.sample(f, g)
+    # exact away from the upper border; the last plane is reached with t = 1
+    assert np.array_equal(got[:, :-1, :-1, :-1], f[:, :-1, :-1, :-1])
+    assert np.allclose(got, f, rtol=0, atol=1e-14)
+    # trilinear interpolation is exact on affine functions inside the grid
+    A = r.standard_normal((3, 3))
+    b = r.standard_normal(3)
+    af = affine_field((5, 6, 7), A, b)
+    q = r.uniform(0, 1, (3, 40)) * np.array([4, 5, 6])[:, None]
+    want = A @ q + b[:, None]
+    assert np.allclose(O.sample(af, q), want, atol=1e-12)
+    _, J = O.sample(af, q, jac=True)
+    assert np.allclose(J, np.broadcast_to(A[:, :, None], J.shape), atol=1e-12)
+
+
+def test_sample_clamps_to_border_and_zeroes_outside_derivative():
+    r = rng(1)
+    f = r.standard_normal((1, 4, 4, 4))
+    q = np.array([[-3.0, 10.0], [1.5, 1.5], [2.0, 2.0]])
+    val, J = O.sample(f, q, jac=True)
+    assert np.allclose(val[0, 0], 0.5 * (f[0, 0, 1, 2] + f[0, 0, 2, 2]))
+    assert np.allclose(val[0, 1], 0.5 * (f[0, 3, 1, 2] + f[0, 3, 2, 2]))
+    assert np.all(J[0, 0] == 0.0)
+
+
+def test_sample_jacobian_matches_finite_differences():
+    r = rng(2)
+    f = r.standard_normal((3, 6, 6, 6))
+    q = r.uniform(0.2, 4.8, (3, 50))
+    _, J = O.sample(f, q, jac=True)
+    h = 1e-6
+    for d in range(3):
+        e = np.zeros((3, 1))
+        e[d] = h
+        fd = (O.sample(f, q + e) - O.sample(f, q - e)) / (2 * h)
+        assert np.allclose(J[:, d], fd, atol=1e-7)
+
+
+def test_sample_adjoint_is_the_transpose():
+    """<S(f, q), g> == <f, S^T(g, q)> for random f, g, q (dot-product test)."""
+    r = rng(3)
+    shape = (5, 7, 6)
+    f = r.standard_normal((3,) + shape)
+    q = r.uniform(-1.5, 8.5, (3, 4, 5, 6))
+    g = r.standard_normal((3, 4, 5, 6))
+    lhs = np.sum(O.sample(f, q) * g)
+    rhs = np.sum(f * O.sample_adjoint(g, q, shape))
+    assert abs(lhs - rhs) < 1e-10 * max(1.0, abs(lhs))
+
+
+# --------------------------------------------------------------------------
+# Exp (Sec. 2.3, Alg. 1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("K", [0, 3, 7])
+def test_T1_zero_svf_gives_identity(K):
+    us = O.exp_fwd(np.zeros((3, 6, 7, 8)), K)
+    assert len(us) == K + 1
+    assert np.all(us[-1] == 0.0)
+
+
+@pytest.mark.parametrize("K", [1, 4, 7])
+def test_T2_constant_svf_gives_exact_translation(K):
+    c = np.array([0.7, -1.3, 2.25])
+    phi = np.broadcast_to(c[:, None, None, None], (3, 9, 8, 7)).copy()
+    uK = O.exp_fwd(phi, K)[-1]
+    assert np.array_equal(uK, phi)
+
+
+@pytest.mark.parametrize("K", [3, 6, 8])
+def test_T3_affine_svf_is_a_matrix_power(K):
+    shape = (26, 26, 26)
+    r = rng(10 + K)
+    A = 0.01 * r.standard_normal((3, 3))
+    c = np.full(3, 12.5)
+    b = 0.05 * r.standard_normal(3)
+    phi = affine_field(shape, A, b - A @ c)      # phi(x) = A (x - c) + b
+    uK = O.exp_fwd(phi, K)[-1]
+    # Phi_0 = x + phi/2^K is affine; Phi_K = Phi_0 composed 2^K times
+    M0 = np.eye(4)
+    M0[:3, :3] += A / 2 ** K
+    M0[:3, 3] = (b - A @ c) / 2 ** K
+    MK = np.linalg.matrix_power(M0, 2 ** K)
+    g = O.identity_grid(shape)
+    want = np.einsum("ab,b...->a...", MK[:3, :3] - np.eye(3), g) + MK[:3, 3][:, None, None, None]
+    s = slice(K + 2, -(K + 2))
+    assert np.max(np.abs(uK[:, s, s, s] - want[:, s, s, s])) < 1e-11
+    # and it approaches the matrix exponential of the generator at O(2^-K)
+    Gen = np.zeros((4, 4))
+    Gen[:3, :3] = A
+    Gen[:3, 3] = b - A @ c
+    E = scipy.linalg.expm(Gen)
+    want_e = np.einsum("ab,b...->a...", E[:3, :3] - np.eye(3), g) + E[:3, 3][:, None, None, None]
+    err = np.max(np.abs(uK[:, s, s, s] - want_e[:, s, s, s]))
+    assert err < 0.2 * 2.0 ** -K
+
+
+def test_T4_composition_of_affine_fields_is_the_matrix_product():
+    shape = (20, 20, 20)
+    r = rng(4)
+    A1, A2 = 0.02 * r.standard_normal((3, 3)), 0.02 * r.standard_normal((3, 3))
+    b1, b2 = 0.3 * r.standard_normal(3), 0.3 * r.standard_normal(3)
+    U1, C = affine_field(shape, A1, b1), affine_field(shape, A2, b2)
+    out = O.compose(U1, C)
+    # (x + C(x)) o (x + U1(x)) = (I + A2)((I + A1) x + b1) + b2
+    Mtot = (np.eye(3) + A2) @ (np.eye(3) + A1)
+    btot = (np.eye(3) + A2) @ b1 + b2
+    want = affine_field(shape, Mtot - np.eye(3), btot)
+    s = slice(2, -2)
+    assert np.max(np.abs(out[:, s, s, s] - want[:, s, s, s])) < 1e-12
+
+
+@pytest.mark.parametrize("K", [4, 7])
+def test_T5_self_composition_equals_one_more_squaring(K):
+    v = smooth_field((12, 13, 14), 1.2, seed=K)
+    f = O.exp_fwd(v, K)[-1]
+    b = O.exp_fwd(-v, K)[-1]
+    # a 3-session series whose two intervals share the same field
+    U = O.all_pairs([f, f], [b, b])
+    want = O.exp_fwd(2 * v, K + 1)[-1]
+    assert np.array_equal(U[(0, 2)], want)
+    want_b = O.exp_fwd(-2 * v, K + 1)[-1]
+    assert np.array_equal(U[(2, 0)], want_b)
+
+
+def test_T6_exp_of_minus_v_inverts_exp_of_v_at_second_order():
+    """Exp(v) o Exp(-v) ~ identity (Sec. 2.3: the inverse is Exp(-phi)).  The
+    residual, in physical units, falls at close to second order when the same
+    continuous field is sampled on finer grids: clearly faster than first
+    order (ratio 2 per halving), about 16x over two halvings."""
+    def residual(n):
+        L = 1.0
+        h = L / (n - 1)
+        x = np.linspace(0, L, n)
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        vphys = 0.04 * np.stack([np.sin(2 * np.pi * Y) * np.cos(np.pi * X),
+                                 np.cos(2 * np.pi * Z) * np.sin(np.pi * X),
+                                 np.sin(np.pi * Z) * np.sin(np.pi * Y)])
+        v = vphys / h
+        f = O.exp_fwd(v, 8)[-1]
+        b = O.exp_fwd(-v, 8)[-1]
+        res = O.compose(f, b)           # (Omega + b) o (Omega + f) - Omega
+        m = n // 4
+        return h * np.sqrt(np.mean(res[:, m:-m, m:-m, m:-m] ** 2))
+    r1, r2, r3 = residual(17), residual(33), residual(65)
+    assert r1 / r2 > 2.5 and r2 / r3 > 2.5
+    assert r1 / r3 > 9.0
+    assert r3 < 3e-5
+
+
+# --------------------------------------------------------------------------
+# Warp (Sec. 2.1) and similarity (Sec. 2.6)
+# --------------------------------------------------------------------------
+
+def test_T7_warp_of_affine_image_is_exact():
+    shape = (10, 11, 12)
+    g = O.identity_grid(shape)
+    cvec, d = np.array([0.3, -0.2, 0.5]), 0.7
+    I = np.einsum("a,a...->...", cvec, g) + d
+    U = smooth_field(shape, 0.8, seed=5)
+    s = slice(2, -2)
+    M = O.warp(I, U)
+    want = np.einsum("a,a...->...", cvec, g + U) + d
+    assert np.allclose(M[s, s, s], want[s, s, s], atol=1e-12)
+    G = O.warp_grad(I, U)
+    assert np.allclose(G[:, s, s, s], np.broadcast_to(cvec[:, None, None, None], G[:, s, s, s].shape),
+                       atol=1e-12)
+
+
+@pytest.mark.parametrize("w", [3, 5, 7])
+def test_T8_lncc_identities(w):
+    r = rng(w)
+    F = r.uniform(0, 1, (12, 12, 12))
+    assert abs(O.similarity(F, F, w, O.LNCC)) < 1e-12
+    assert abs(O.similarity(F, 2.5 * F - 0.4, w, O.LNCC)) < 1e-12
+    assert abs(O.similarity(F, -1.5 * F + 3.0, w, O.LNCC) - 2.0) < 1e-12
+    M = r.uniform(0, 1, (12, 12, 12))
+    base = O.similarity(F, M, w, O.LNCC)
+    assert abs(O.similarity(3 * F + 1, M, w, O.LNCC) - base) < 1e-12
+    assert abs(O.similarity(F, 0.2 * M + 7, w, O.LNCC) - base) < 1e-10
+
+
+@pytest.mark.parametrize("w", [3, 5, 7])
+def test_T8_silncc_identities(w):
+    r = rng(10 + w)
+    F = r.uniform(0, 1, (12, 12, 12))
+    assert abs(O.similarity(F, F, w, O.SILNCC)) < 1e-14
+    assert abs(O.similarity(F, 2.5 * F - 0.4, w, O.SILNCC)) < 1e-13
+    M = r.uniform(0, 1, (12, 12, 12))
+    base = O.similarity(F, M, w, O.SILNCC)
+    assert abs(O.similarity(3 * F + 1, M, w, O.SILNCC) - base) < 1e-12
+    # not invariant in M: scales by c^2 under M -> cM + d
+    assert abs(O.similarity(F, 3 * M + 5, w, O.SILNCC) - 9 * base) < 1e-11
+
+
+@pytest.mark.parametrize("w", [3, 5])
+def test_T9_silncc_is_the_ols_residual_variance(w):
+    """M = aF + b + eps with eps ~ N(0, s^2) gives E[SiLNCC_R] = s^2 (n-2)/n,
+    the residual variance of a least-squares line through n points."""
+    r = rng(20 + w)
+    shape = (40, 40, 40)
+    F = r.uniform(0, 1, shape)
+    s = 0.1
+    M = 1.7 * F - 0.3 + s * r.standard_normal(shape)
+    n = w ** 3
+    want = s * s * (n - 2) / n
+    got = O.similarity(F, M, w, O.SILNCC)
+    n_indep = (40 // w) ** 3
+    tol = 4 * want * math.sqrt(2.0 / (n - 2)) / math.sqrt(n_indep)
+    assert abs(got - want) < tol
+
+
+@pytest.mark.parametrize("w,a,sig", [(3, 1.0, 0.5), (5, 0.7, 0.3), (3, 2.0, 1.5)])
+def test_T10_expected_lncc_matches_the_papers_closed_form(w, a, sig):
+    """Eq. E_lncc: E[LNCC_R] ~ 1 - 1/sqrt(1 + s^2/(a^2 S^2)); the paper bounds
+    the bias of this approximation by about 0.02 at 9 voxels and less at 27."""
+    r = rng(30 + w)
+    shape = (36, 36, 36)
+    F = r.standard_normal(shape)
+    M = a * F + 0.5 + sig * r.standard_normal(shape)
+    mo = O.window_moments(F, F, w)
+    S2 = mo["vF"].mean()
+    want = 1.0 - 1.0 / math.sqrt(1.0 + sig * sig / (a * a * S2))
+    got = O.similarity(F, M, w, O.LNCC)
+    assert abs(got - want) < 0.02
+
+
+@pytest.mark.parametrize("r_", [1, 2])
+def test_T11_box_sums_match_brute_force(r_):
+    r = rng(40 + r_)
+    X = r.standard_normal((7, 8, 9))
+    got = O.box_sum(X, r_)
+    D, H, W = X.shape
+    assert got.shape == (D - 2 * r_, H - 2 * r_, W - 2 * r_)
+    for z in range(r_, D - r_):
+        for y in range(r_, H - r_):
+            for x in range(r_, W - r_):
+                s = 0.0
+                for dz in range(-r_, r_ + 1):
+                    for dy in range(-r_, r_ + 1):
+                        for dx in range(-r_, r_ + 1):
+                            s += X[z + dz, y + dy, x + dx]
+                assert abs(got[z - r_, y - r_, x - r_] - s) < 1e-12
+    # box_adjoint is the transpose of box_sum
+    A = r.standard_normal(got.shape)
+    assert abs(np.sum(got * A) - np.sum(X * O.box_adjoint(A, r_, X.shape))) < 1e-10
+
+
+def test_window_moments_match_numpy_statistics():
+    r = rng(50)
+    F = r.standard_normal((9, 9, 9))
+    M = r.standard_normal((9, 9, 9))
+    mo = O.window_moments(F, M, 5)
+    z, y, x = 3, 4, 2
+    wf = F[z:z + 5, y:y + 5, x:x + 5].ravel()
+    wm = M[z:z + 5, y:y + 5, x:x + 5].ravel()
+    assert abs(mo["vF"][z, y, x] - np.var(wf)) < 1e-12
+    assert abs(mo["vM"][z, y, x] - np.var(wm)) < 1e-12
+    assert abs(mo["c"][z, y, x] - np.cov(wf, wm, bias=True)[0, 1]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Regulariser (Sec. 2.4)
+# --------------------------------------------------------------------------
+
+def test_T12_regulariser_of_affine_field_is_frobenius_norm():
+    r = rng(60)
+    A = r.standard_normal((3, 3))
+    phi = affine_field((6, 7, 8), A, r.standard_normal(3))
+    assert abs(O.reg_ss(phi) - np.sum(A * A)) < 1e-10
+    assert O.reg_ss(np.full((3, 5, 5, 5), 3.3)) == 0.0
+
+
+def test_T12_regulariser_gradient_matches_finite_differences():
+    r = rng(61)
+    phi = r.standard_normal((3, 4, 5, 6))
+    g = O.reg_ss_grad(phi)
+    h = 1e-6
+    for _ in range(40):
+        idx = tuple(int(r.integers(0, n)) for n in phi.shape)
+        e = np.zeros_like(phi)
+        e[idx] = h
+        fd = (O.reg_ss(phi + e) - O.reg_ss(phi - e)) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-7
+
+
+# --------------------------------------------------------------------------
+# Whole-loss gradient (Sec. 2.2 loss; adjoints of every step)
+# --------------------------------------------------------------------------
+
+def _tiny_problem(seed, shape=(8, 8, 8), N=3, amp=0.9):
+    r = rng(seed)
+    import scipy.ndimage as ndi
+    imgs = [ndi.gaussian_filter(r.uniform(0, 1, shape), 1.0) + 0.01 * r.standard_normal(shape)
+            for _ in range(N)]
+    phis = [smooth_field(shape, amp, seed=seed * 10 + k, sigma=1.5) for k in range(N - 1)]
+    return imgs, phis
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("w,K,metric,seed", [(3, 3, O.LNCC, 1), (5, 4, O.SILNCC, 2)])
+def test_T13_gradient_matches_finite_differences_every_parameter(w, K, metric, seed):
+    imgs, phis = _tiny_problem(seed)
+    p = O.Params(K=K, window=w, metric=metric, alpha_ss=0.5)
+    L, grads, _ = O.loss_and_grad(phis, imgs, p)
+    gmax = max(np.abs(g).max() for g in grads)
+
+    def fd(k, idx, h):
+        pp = [x.copy() for x in phis]
+        pm = [x.copy() for x in phis]
+        pp[k][idx] += h
+        pm[k][idx] -= h
+        return (O.forward(pp, imgs, p) - O.forward(pm, imgs, p)) / (2 * h)
+
+    bad = []
+    for k in range(len(phis)):
+        for idx in np.ndindex(phis[k].shape):
+            g = grads[k][idx]
+            ok = abs(fd(k, idx, 1e-5) - g) <= 1e-6 * gmax + 1e-5 * abs(g)
+            if not ok:
+                # the loss is piecewise smooth (trilinear cells, border clamp):
+                # a cell face within 1e-5 of the point spoils the wide
+                # difference, so look again at a narrower one
+                ok = abs(fd(k, idx, 1e-6) - g) <= 1e-6 * gmax + 1e-5 * abs(g)
+            if not ok:
+                bad.append((k, idx))
+    assert bad == []
+
+
+@pytest.mark.parametrize("w,K,metric,N,seed", [(3, 5, O.SILNCC, 4, 3), (5, 6, O.LNCC, 3, 4),
+                                               (3, 3, O.LNCC, 5, 5)])
+def test_T13_gradient_matches_finite_differences_sampled(w, K, metric, N, seed):
+    imgs, phis = _tiny_problem(seed, shape=(8, 9, 10), N=N)
+    p = O.Params(K=K, window=w, metric=metric, alpha_ss=1.0)
+    L, grads, _ = O.loss_and_grad(phis, imgs, p)
+    r = rng(seed)
+    h = 1e-5
+    gmax = max(np.abs(g).max() for g in grads)
+    for _ in range(60):
+        k = int(r.integers(0, N - 1))
+        idx = tuple(int(r.integers(0, n)) for n in phis[k].shape)
+        pp = [x.copy() for x in phis]
+        pm = [x.copy() for x in phis]
+        pp[k][idx] += h
+        pm[k][idx] -= h
+        fd = (O.forward(pp, imgs, p) - O.forward(pm, imgs, p)) / (2 * h)
+        assert abs(fd - grads[k][idx]) < 1e-6 * gmax + 1e-5 * abs(fd)
+    # and along a random direction through every parameter at once
+    dirs = [r.standard_normal(x.shape) for x in phis]
+    hh = 1e-6
+    Lp = O.forward([x + hh * d for x, d in zip(phis, dirs)], imgs, p)
+    Lm = O.forward([x - hh * d for x, d in zip(phis, dirs)], imgs, p)
+    dd = sum(np.sum(g * d) for g, d in zip(grads, dirs))
+    assert abs((Lp - Lm) / (2 * hh) - dd) < 1e-5 * abs(dd) + 1e-8
+
+
+# --------------------------------------------------------------------------
+# Optimiser (Sec. 2.7)
+# --------------------------------------------------------------------------
+
+def test_T14_adam_matches_torch():
+    r = rng(70)
+    x0 = r.standard_normal((3, 4, 5, 6))
+    grads = [r.standard_normal(x0.shape) * 10 ** r.uniform(-6, 0) for _ in range(12)]
+    lrs = [O.lr_schedule(t, 12, 0.1) for t in range(1, 13)]
+    xt = torch.tensor(x0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([xt], lr=0.1, betas=(0.9, 0.999), eps=1e-8)
+    x, m, v = x0.copy(), np.zeros_like(x0), np.zeros_like(x0)
+    for t, (g, lr) in enumerate(zip(grads, lrs), start=1):
+        for pg in opt.param_groups:
+            pg["lr"] = lr
+        xt.grad = torch.tensor(g)
+        opt.step()
+        x, m, v = O.adam_step(x, g, m, v, t, lr)
+    assert np.allclose(x, xt.detach().numpy(), rtol=0, atol=1e-12)
+
+
+def test_T14_learning_rate_schedule_shape():
+    T, lr0 = 50, 0.2
+    W = 10
+    assert O.lr_schedule(1, T, lr0) == pytest.approx(lr0 / W)
+    assert O.lr_schedule(W, T, lr0) == pytest.approx(lr0)
+    assert O.lr_schedule(T, T, lr0) == pytest.approx(0.0, abs=1e-15)
+    assert O.lr_schedule(30, T, lr0) == pytest.approx(lr0 / 2)
+    ws = [O.lr_schedule(t, T, lr0) for t in range(1, W + 1)]
+    assert np.allclose(np.diff(ws), lr0 / W)
+    cs = [O.lr_schedule(t, T, lr0) for t in range(W, T + 1)]
+    assert all(a > b for a, b in zip(cs, cs[1:]))
+
+
+# --------------------------------------------------------------------------
+# Pyramid (Sec. 2.7)
+# --------------------------------------------------------------------------
+
+def test_T15_pool2_of_affine_image_is_affine_at_cell_centres():
+    shape = (8, 10, 12)
+    g = O.identity_grid(shape)
+    c, d = np.array([0.3, -0.7, 1.1]), 2.0
+    I = np.einsum("a,a...->...", c, g) + d
+    P = O.pool2(I)
+    gc = O.identity_grid(P.shape)
+    want = np.einsum("a,a...->...", c, 2 * gc + 0.5) + d
+    assert np.allclose(P, want, atol=1e-12)
+    r = rng(80)
+    X = r.standard_normal(shape)
+    assert abs(O.pool2(X)[1, 2, 3] - X[2:4, 4:6, 6:8].mean()) < 1e-14
+
+
+def test_T15_upsample2_of_affine_field_is_exact_in_the_interior():
+    r = rng(81)
+    A = 0.05 * r.standard_normal((3, 3))
+    b = r.standard_normal(3)
+    coarse = affine_field((6, 7, 8), A, b)
+    fine = O.upsample2(coarse)
+    assert fine.shape == (3, 12, 14, 16)
+    g = O.identity_grid((12, 14, 16))
+    # physical displacement 2*phi_c at coarse position (x - 0.5)/2
+    want = np.einsum("ab,b...->a...", A, g - 0.5) + 2 * b[:, None, None, None]
+    s = (slice(None), slice(1, -1), slice(1, -1), slice(1, -1))
+    assert np.allclose(fine[s], want[s], atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Loss assembly (Sec. 2.2 loss and Eq. cum_deformation; Sec. 2.4 Eq. reg_sum)
+# --------------------------------------------------------------------------
+
+def test_pair_fields_of_an_integer_translation_series_are_exact():
+    """Sessions I_k(x) = B(x + k c) with an integer shift c are related by
+    constant pair fields U[j->i] = (i - j) c; with phi_i = -c every pair field
+    is reproduced exactly and every warped session equals its target away
+    from the border."""
+    r = rng(90)
+    N = 4
+    c = np.array([1, -1, 2])
+    big = r.standard_normal((30, 30, 30))
+    shape = (14, 15, 16)
+    o = np.array([8, 8, 8])
+    imgs = []
+    for k in range(N):
+        s = o + k * c
+        imgs.append(big[s[0]:s[0] + shape[0], s[1]:s[1] + shape[1], s[2]:s[2] + shape[2]])
+    phis = [np.broadcast_to(-c[:, None, None, None].astype(float), (3,) + shape).copy()
+            for _ in range(N - 1)]
+    _, aux = O.forward(phis, imgs, O.Params(K=5, window=3), keep=True)
+    U = aux["U"]
+    assert len(U) == N * (N - 1)
+    m = 2 * (N - 1) + 1
+    for (i, j), Uij in U.items():
+        want = (i - j) * c.astype(float)
+        assert np.array_equal(Uij, np.broadcast_to(want[:, None, None, None], Uij.shape))
+        M = O.warp(imgs[j], Uij)
+        assert np.array_equal(M[m:-m, m:-m, m:-m], imgs[i][m:-m, m:-m, m:-m])
+
+
+def test_loss_sums_similarity_over_ordered_pairs():
+    """N copies of one image up to a positive affine intensity change score 0;
+    flipping the sign of one session turns NCC to -1 (LNCC_R = 2) in each of
+    the 2(N-1) ordered pairs that involve it, so L = 4(N-1)."""
+    r = rng(91)
+    N = 4
+    B = r.uniform(0, 1, (10, 10, 10))
+    imgs = [2.0 * B + 1, 0.5 * B - 3, 1.5 * B, 3.0 * B + 0.2]
+    phis = [np.zeros((3, 10, 10, 10)) for _ in range(N - 1)]
+    p = O.Params(K=4, window=3, metric=O.LNCC)
+    assert abs(O.forward(phis, imgs, p)) < 1e-12
+    imgs[2] = -imgs[2]
+    assert abs(O.forward(phis, imgs, p) - 4 * (N - 1)) < 1e-10
+
+
+def test_loss_weights_the_regulariser_by_alpha_over_intervals():
+    """Constant images have zero SiLNCC under any deformation, so the loss is
+    alpha_ss/(N-1) sum_i ||A_i||_F^2 for affine fields phi_i = A_i x + b_i."""
+    r = rng(92)
+    N = 4
+    shape = (9, 9, 9)
+    imgs = [np.full(shape, 0.3 + 0.1 * k) for k in range(N)]
+    As = [0.02 * r.standard_normal((3, 3)) for _ in range(N - 1)]
+    phis = [affine_field(shape, A, 0.1 * r.standard_normal(3)) for A in As]
+    p = O.Params(K=4, window=3, metric=O.SILNCC, alpha_ss=0.7)
+    want = 0.7 / (N - 1) * sum(np.sum(A * A) for A in As)
+    assert abs(O.forward(phis, imgs, p) - want) < 1e-12
