@@ -1,0 +1,1043 @@
+// HIP kernels (gfx950) of the MUSTER iteration.
+//
+// Data layout: a volume is float32 [D][H][W] (x fastest); a vector field is
+// three such planes (components z, y, x).  Fields hold displacements in
+// voxels.  Every kernel walks a table of work items (see muster_internal.h),
+// so one launch covers all intervals, pairs and subjects of a stage.
+//
+// Sampling (paper Sec. 2.2, "trilinear interpolation"): the sample position
+// q = p + u is clamped to the grid; the cell index is p + floor(u) and the
+// fraction u - floor(u), which keeps the fraction exact for large p; an axis
+// whose coordinate was clamped contributes no derivative.  Interpolation is
+// the nested linear form a + t (b - a), so a constant field is reproduced
+// exactly.
+//
+// The gather/scatter kernels use 8x8x16-voxel tiles and an XCD-aware
+// block-to-tile map: blocks are dealt round-robin over the 8 XCDs, and the
+// map hands each XCD a contiguous run of tiles so the neighbouring rows that
+// the gathers touch stay in that XCD's L2.
+#include <hip/hip_runtime.h>
+#include <climits>
+#include <cmath>
+
+#include "muster_internal.h"
+
+namespace muster {
+
+namespace {
+
+constexpr float EPS_LNCC = 1e-10f;
+constexpr float EPS_SILNCC = 1e-6f;
+
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = b & 7, j = b >> 3;
+  return x * q + min(x, r) + j;
+}
+
+template <class Item>
+__device__ __forceinline__ int find_item(const Item* __restrict__ items, int n, int tile) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct Ax {
+  int i0;
+  float t;
+  float live;  // 1 inside the grid, 0 where the coordinate was clamped
+};
+
+// Axis of a displaced position p + u on n grid points.
+__device__ __forceinline__ Ax axis_disp(int p, float u, int n) {
+  u = fminf(fmaxf(u, -1.0e6f), 1.0e6f);
+  const float fl = floorf(u);
+  const int i = p + (int)fl;
+  const float t = u - fl;
+  Ax a;
+  if (i < 0) {
+    a.i0 = 0; a.t = 0.f; a.live = 0.f;
+  } else if (i >= n - 1) {
+    a.i0 = n - 2; a.t = 1.f; a.live = (i == n - 1 && t == 0.f) ? 1.f : 0.f;
+  } else {
+    a.i0 = i; a.t = t; a.live = 1.f;
+  }
+  return a;
+}
+
+// Axis of an absolute position q on n grid points.
+__device__ __forceinline__ Ax axis_pos(float q, int n) {
+  q = fminf(fmaxf(q, -1.0e6f), 1.0e6f);
+  const float fl = floorf(q);
+  const int i = (int)fl;
+  const float t = q - fl;
+  Ax a;
+  if (i < 0) {
+    a.i0 = 0; a.t = 0.f; a.live = 0.f;
+  } else if (i >= n - 1) {
+    a.i0 = n - 2; a.t = 1.f; a.live = (i == n - 1 && t == 0.f) ? 1.f : 0.f;
+  } else {
+    a.i0 = i; a.t = t; a.live = 1.f;
+  }
+  return a;
+}
+
+__device__ __forceinline__ float lerp_(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// Corner order: bit 0 = x+1, bit 1 = y+1, bit 2 = z+1.
+__device__ __forceinline__ void load8(const float* __restrict__ f, int base, int sy, int sz,
+                                      float (&v)[8]) {
+  v[0] = f[base];
+  v[1] = f[base + 1];
+  v[2] = f[base + sy];
+  v[3] = f[base + sy + 1];
+  v[4] = f[base + sz];
+  v[5] = f[base + sz + 1];
+  v[6] = f[base + sz + sy];
+  v[7] = f[base + sz + sy + 1];
+}
+
+__device__ __forceinline__ float tri_val(const float (&v)[8], float tz, float ty, float tx) {
+  const float c00 = lerp_(v[0], v[1], tx);
+  const float c01 = lerp_(v[2], v[3], tx);
+  const float c10 = lerp_(v[4], v[5], tx);
+  const float c11 = lerp_(v[6], v[7], tx);
+  const float c0 = lerp_(c00, c01, ty);
+  const float c1 = lerp_(c10, c11, ty);
+  return lerp_(c0, c1, tz);
+}
+
+// Value and the three partial derivatives of the trilinear interpolant.
+__device__ __forceinline__ float tri_grad(const float (&v)[8], float tz, float ty, float tx,
+                                          float& dz, float& dy, float& dx) {
+  const float c00 = lerp_(v[0], v[1], tx);
+  const float c01 = lerp_(v[2], v[3], tx);
+  const float c10 = lerp_(v[4], v[5], tx);
+  const float c11 = lerp_(v[6], v[7], tx);
+  const float c0 = lerp_(c00, c01, ty);
+  const float c1 = lerp_(c10, c11, ty);
+  dz = c1 - c0;
+  dy = lerp_(c01 - c00, c11 - c10, tz);
+  const float e0 = lerp_(v[1] - v[0], v[3] - v[2], ty);
+  const float e1 = lerp_(v[5] - v[4], v[7] - v[6], ty);
+  dx = lerp_(e0, e1, tz);
+  return lerp_(c0, c1, tz);
+}
+
+struct PTile {
+  int z0, y0, x0;
+};
+
+__device__ __forceinline__ PTile point_tile(int local, int H, int W) {
+  const int ntx = (W + PT_X - 1) / PT_X;
+  const int nty = (H + PT_Y - 1) / PT_Y;
+  PTile t;
+  t.x0 = (local % ntx) * PT_X;
+  const int r = local / ntx;
+  t.y0 = (r % nty) * PT_Y;
+  t.z0 = (r / nty) * PT_Z;
+  return t;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < BLOCK / 64; ++i) s += red[i];
+  return s;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Bounding box of the cells a tile touches, reduced over the block.
+struct BBox {
+  int lz, ly, lx, ez, ey, ex, cells;
+};
+
+__device__ __forceinline__ BBox block_bbox(int lo[3], int hi[3], int* sbb) {
+  if (threadIdx.x == 0) {
+    sbb[0] = sbb[1] = sbb[2] = INT_MAX;
+    sbb[3] = sbb[4] = sbb[5] = INT_MIN;
+  }
+  __syncthreads();
+  for (int d = 0; d < 3; ++d) {
+    const int a = wave_min(lo[d]);
+    const int b = wave_max(hi[d]);
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(&sbb[d], a);
+      atomicMax(&sbb[3 + d], b);
+    }
+  }
+  __syncthreads();
+  BBox bb;
+  bb.lz = sbb[0]; bb.ly = sbb[1]; bb.lx = sbb[2];
+  if (sbb[3] < sbb[0]) {  // no voxel in the tile
+    bb.ez = bb.ey = bb.ex = 0;
+    bb.cells = 0;
+    return bb;
+  }
+  bb.ez = sbb[3] - sbb[0] + 1;
+  bb.ey = sbb[4] - sbb[1] + 1;
+  bb.ex = sbb[5] - sbb[2] + 1;
+  const long long c = (long long)bb.ez * bb.ey * bb.ex;
+  bb.cells = c > (long long)INT_MAX ? INT_MAX : (int)c;
+  return bb;
+}
+
+// Regulariser of Eq. reg_ss at voxel p for one component plane f: forward
+// differences, mean per (component, axis) over its valid set.  Returns the
+// gradient of R with respect to f(p) and adds f's own forward-difference terms
+// to *val.
+__device__ __forceinline__ float reg_point(const float* __restrict__ f, int z, int y, int x, int D,
+                                           int H, int W, float inv_mz, float inv_my, float inv_mx,
+                                           double* val) {
+  const int HW = H * W;
+  const int p = (z * H + y) * W + x;
+  const float c = f[p];
+  float g = 0.f;
+  if (z + 1 < D) { const float d = f[p + HW] - c; g -= 2.f * d * inv_mz; *val += (double)d * d * inv_mz; }
+  if (z > 0)     { const float d = c - f[p - HW]; g += 2.f * d * inv_mz; }
+  if (y + 1 < H) { const float d = f[p + W] - c;  g -= 2.f * d * inv_my; *val += (double)d * d * inv_my; }
+  if (y > 0)     { const float d = c - f[p - W];  g += 2.f * d * inv_my; }
+  if (x + 1 < W) { const float d = f[p + 1] - c;  g -= 2.f * d * inv_mx; *val += (double)d * d * inv_mx; }
+  if (x > 0)     { const float d = c - f[p - 1];  g += 2.f * d * inv_mx; }
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// Exp forward: one squaring u' = u + u o (Omega + u)   (Alg. 1)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_exp_fwd(const ExpFwdItem* __restrict__ items,
+                                                   int n_items, int n_tiles) {
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const ExpFwdItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const PTile tc = point_tile(tile - it.tile0, H, W);
+  const float a = it.a;
+  const float* __restrict__ s = it.src;
+  float* __restrict__ d = it.dst;
+  for (int k = threadIdx.x; k < PT_VOX; k += BLOCK) {
+    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
+    if (x >= W || y >= H || z >= D) continue;
+    const int p = (z * H + y) * W + x;
+    const float uz = a * s[p], uy = a * s[V + p], ux = a * s[2 * V + p];
+    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
+    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+    float v[8];
+    load8(s, base, W, HW, v);
+    const float sz = tri_val(v, az.t, ay.t, ax.t);
+    load8(s + V, base, W, HW, v);
+    const float sy = tri_val(v, az.t, ay.t, ax.t);
+    load8(s + 2 * V, base, W, HW, v);
+    const float sx = tri_val(v, az.t, ay.t, ax.t);
+    d[p] = uz + a * sz;
+    d[V + p] = uy + a * sy;
+    d[2 * V + p] = ux + a * sx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Composition forward: out = prev + C o (Omega + prev)   (Eq. cum_deformation)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __restrict__ items,
+                                                       int n_items, int n_tiles) {
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const ComposeItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const PTile tc = point_tile(tile - it.tile0, H, W);
+  const float* __restrict__ pr = it.prev;
+  const float* __restrict__ C = it.C;
+  float* __restrict__ o = it.out;
+  for (int k = threadIdx.x; k < PT_VOX; k += BLOCK) {
+    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
+    if (x >= W || y >= H || z >= D) continue;
+    const int p = (z * H + y) * W + x;
+    const float uz = pr[p], uy = pr[V + p], ux = pr[2 * V + p];
+    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
+    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+    float v[8];
+    load8(C, base, W, HW, v);
+    const float cz = tri_val(v, az.t, ay.t, ax.t);
+    load8(C + V, base, W, HW, v);
+    const float cy = tri_val(v, az.t, ay.t, ax.t);
+    load8(C + 2 * V, base, W, HW, v);
+    const float cx = tri_val(v, az.t, ay.t, ax.t);
+    o[p] = uz + cz;
+    o[V + p] = uy + cy;
+    o[2 * V + p] = ux + cx;
+  }
+}
+
+// Scatter of per-voxel cell contributions into a field through LDS bins.
+// Each thread holds up to VPT voxels: cell origin (cz, cy, cx), fractions,
+// the 3-vector to spread with the trilinear weights, and optionally an own
+// term to add at its own position (oz, oy, ox).
+constexpr int VPT = PT_VOX / BLOCK;
+
+struct ScatterVox {
+  int cz, cy, cx;      // cell origin; cz < 0 marks an empty slot
+  int oz, oy, ox;      // own voxel (for the own term)
+  float tz, ty, tx;
+  float g[3];          // value spread over the 8 corners
+  float own[3];        // value added at the own voxel
+};
+
+template <bool OWN>
+__device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], float* __restrict__ out,
+                                             int D, int H, int W, float* acc, int* sbb) {
+  const int HW = H * W, V = D * HW;
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
+  int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (sv[j].cz < 0) continue;
+    lo[0] = min(lo[0], sv[j].cz); hi[0] = max(hi[0], sv[j].cz + 1);
+    lo[1] = min(lo[1], sv[j].cy); hi[1] = max(hi[1], sv[j].cy + 1);
+    lo[2] = min(lo[2], sv[j].cx); hi[2] = max(hi[2], sv[j].cx + 1);
+    if (OWN) {
+      lo[0] = min(lo[0], sv[j].oz); hi[0] = max(hi[0], sv[j].oz);
+      lo[1] = min(lo[1], sv[j].oy); hi[1] = max(hi[1], sv[j].oy);
+      lo[2] = min(lo[2], sv[j].ox); hi[2] = max(hi[2], sv[j].ox);
+    }
+  }
+  const BBox bb = block_bbox(lo, hi, sbb);
+  if (bb.cells == 0) return;
+  if (bb.cells <= SCATTER_CELLS) {
+    const int cells = bb.cells;
+    for (int i = threadIdx.x; i < 3 * cells; i += BLOCK) acc[i] = 0.f;
+    __syncthreads();
+    const int sy = bb.ex, sz = bb.ex * bb.ey;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      if (sv[j].cz < 0) continue;
+      const int l = ((sv[j].cz - bb.lz) * bb.ey + (sv[j].cy - bb.ly)) * bb.ex + (sv[j].cx - bb.lx);
+      const float tz = sv[j].tz, ty = sv[j].ty, tx = sv[j].tx;
+      const float w0z = 1.f - tz, w0y = 1.f - ty, w0x = 1.f - tx;
+      const float w[8] = {w0z * w0y * w0x, w0z * w0y * tx, w0z * ty * w0x, w0z * ty * tx,
+                          tz * w0y * w0x,  tz * w0y * tx,  tz * ty * w0x,  tz * ty * tx};
+      const int off[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float g = sv[j].g[c];
+        if (g == 0.f) continue;
+        float* a = acc + c * cells + l;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) atomicAdd(a + off[q], w[q] * g);
+      }
+      if (OWN) {
+        const int lo2 = ((sv[j].oz - bb.lz) * bb.ey + (sv[j].oy - bb.ly)) * bb.ex + (sv[j].ox - bb.lx);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(acc + c * cells + lo2, sv[j].own[c]);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cells; i += BLOCK) {
+      const int lx = i % bb.ex;
+      const int r = i / bb.ex;
+      const int ly = r % bb.ey;
+      const int lz = r / bb.ey;
+      const int gp = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float v = acc[c * cells + i];
+        if (v != 0.f) unsafeAtomicAdd(out + c * V + gp, v);
+      }
+    }
+  } else {
+    // The footprint does not fit the bins: global atomics.
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      if (sv[j].cz < 0) continue;
+      const int base = (sv[j].cz * H + sv[j].cy) * W + sv[j].cx;
+      const float tz = sv[j].tz, ty = sv[j].ty, tx = sv[j].tx;
+      const float w0z = 1.f - tz, w0y = 1.f - ty, w0x = 1.f - tx;
+      const float w[8] = {w0z * w0y * w0x, w0z * w0y * tx, w0z * ty * w0x, w0z * ty * tx,
+                          tz * w0y * w0x,  tz * w0y * tx,  tz * ty * w0x,  tz * ty * tx};
+      const int off[8] = {0, 1, W, W + 1, HW, HW + 1, HW + W, HW + W + 1};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float g = sv[j].g[c];
+        if (g == 0.f) continue;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) unsafeAtomicAdd(out + c * V + base + off[q], w[q] * g);
+      }
+      if (OWN) {
+        const int po = (sv[j].oz * H + sv[j].oy) * W + sv[j].ox;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) unsafeAtomicAdd(out + c * V + po, sv[j].own[c]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exp backward: one squaring, dL/du_s from dL/du_{s+1}
+//   G_s(p) = G(p) + J_u(q)^T G(p) + sum_{p': corners of q(p') contain p} w G(p')
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict__ items,
+                                                   int n_items, int n_tiles) {
+  __shared__ float acc[3 * SCATTER_CELLS];
+  __shared__ int sbb[6];
+  __shared__ double red[BLOCK / 64];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const ExpBwdItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const PTile tc = point_tile(tile - it.tile0, H, W);
+  const float a = it.a;
+  const float* __restrict__ s = it.src;
+  float* __restrict__ gin = it.gin;
+  const bool reg = it.reg_w != 0.f;
+  const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
+              inv_mx = 1.f / (float)(D * H * (W - 1));
+  double rval = 0.0;
+  ScatterVox sv[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    sv[j].cz = -1;
+    const int k = threadIdx.x + j * BLOCK;
+    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
+    if (x >= W || y >= H || z >= D) continue;
+    const int p = (z * H + y) * W + x;
+    const float uz = a * s[p], uy = a * s[V + p], ux = a * s[2 * V + p];
+    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
+    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+    const float g0 = gin[p], g1 = gin[V + p], g2 = gin[2 * V + p];
+    float own0 = g0, own1 = g1, own2 = g2;
+    float v[8], dz, dy, dx;
+    // row c of the Jacobian of a*src at q, times g_c, added to column terms
+    load8(s, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    own0 = fmaf(a * dz * az.live, g0, own0);
+    own1 = fmaf(a * dy * ay.live, g0, own1);
+    own2 = fmaf(a * dx * ax.live, g0, own2);
+    load8(s + V, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    own0 = fmaf(a * dz * az.live, g1, own0);
+    own1 = fmaf(a * dy * ay.live, g1, own1);
+    own2 = fmaf(a * dx * ax.live, g1, own2);
+    load8(s + 2 * V, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    own0 = fmaf(a * dz * az.live, g2, own0);
+    own1 = fmaf(a * dy * ay.live, g2, own1);
+    own2 = fmaf(a * dx * ax.live, g2, own2);
+    if (reg) {
+      own0 = fmaf(it.reg_w, reg_point(s, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own0);
+      own1 = fmaf(it.reg_w, reg_point(s + V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own1);
+      own2 = fmaf(it.reg_w, reg_point(s + 2 * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval),
+                  own2);
+    }
+    if (it.zero_in) {
+      gin[p] = 0.f;
+      gin[V + p] = 0.f;
+      gin[2 * V + p] = 0.f;
+    }
+    sv[j].cz = az.i0; sv[j].cy = ay.i0; sv[j].cx = ax.i0;
+    sv[j].oz = z; sv[j].oy = y; sv[j].ox = x;
+    sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
+    sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
+    sv[j].own[0] = own0; sv[j].own[1] = own1; sv[j].own[2] = own2;
+  }
+  scatter_tile<true>(sv, it.gout, D, H, W, acc, sbb);
+  if (reg) {
+    const double tot = block_sum(rval, red);
+    if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot * (double)it.reg_loss_w);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Composition backward
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __restrict__ items,
+                                                       int n_items, int n_tiles) {
+  __shared__ float acc[3 * SCATTER_CELLS];
+  __shared__ int sbb[6];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const ComposeBwdItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const PTile tc = point_tile(tile - it.tile0, H, W);
+  const float* __restrict__ C = it.C;
+  const float* __restrict__ pr = it.prev;
+  const float* __restrict__ G = it.g;
+  float* __restrict__ gp = it.gprev;
+  ScatterVox sv[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    sv[j].cz = -1;
+    const int k = threadIdx.x + j * BLOCK;
+    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
+    if (x >= W || y >= H || z >= D) continue;
+    const int p = (z * H + y) * W + x;
+    const float uz = pr[p], uy = pr[V + p], ux = pr[2 * V + p];
+    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
+    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+    const float g0 = G[p], g1 = G[V + p], g2 = G[2 * V + p];
+    float o0 = g0, o1 = g1, o2 = g2;
+    float v[8], dz, dy, dx;
+    load8(C, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    o0 = fmaf(dz * az.live, g0, o0);
+    o1 = fmaf(dy * ay.live, g0, o1);
+    o2 = fmaf(dx * ax.live, g0, o2);
+    load8(C + V, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    o0 = fmaf(dz * az.live, g1, o0);
+    o1 = fmaf(dy * ay.live, g1, o1);
+    o2 = fmaf(dx * ax.live, g1, o2);
+    load8(C + 2 * V, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    o0 = fmaf(dz * az.live, g2, o0);
+    o1 = fmaf(dy * ay.live, g2, o1);
+    o2 = fmaf(dx * ax.live, g2, o2);
+    if (it.prev_atomic) {
+      unsafeAtomicAdd(gp + p, o0);
+      unsafeAtomicAdd(gp + V + p, o1);
+      unsafeAtomicAdd(gp + 2 * V + p, o2);
+    } else {
+      gp[p] += o0;
+      gp[V + p] += o1;
+      gp[2 * V + p] += o2;
+    }
+    sv[j].cz = az.i0; sv[j].cy = ay.i0; sv[j].cx = ax.i0;
+    sv[j].oz = z; sv[j].oy = y; sv[j].ox = x;
+    sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
+    sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
+  }
+  scatter_tile<false>(sv, it.gc, D, H, W, acc, sbb);
+}
+
+// ---------------------------------------------------------------------------
+// Windowed statistics (Sec. 2.6): warp + LNCC/SiLNCC per window, loss and
+// the per-window adjoint coefficients.
+//
+// A block owns ST_Y x ST_X window centres in (y, x) and marches through a
+// chunk of z.  For every input slice it warps the source image on the
+// (ST_Y + 2r) x (ST_X + 2r) patch into an LDS ring of w slices; for every
+// centre slice it sums the five products over z from the ring, then over x
+// and y through LDS.  Values are shifted by one per-block constant before the
+// products, which keeps the variance differences well conditioned.
+// ---------------------------------------------------------------------------
+struct STile {
+  int z0, z1, y0, x0;
+};
+
+__device__ __forceinline__ STile stat_tile(int local, int D, int H, int W, int zc) {
+  const int ntx = (W + ST_X - 1) / ST_X;
+  const int nty = (H + ST_Y - 1) / ST_Y;
+  STile t;
+  t.x0 = (local % ntx) * ST_X;
+  const int r = local / ntx;
+  t.y0 = (r % nty) * ST_Y;
+  t.z0 = (r / nty) * zc;
+  t.z1 = min(t.z0 + zc, D);
+  return t;
+}
+
+template <int R>
+__global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__ items, int n_items,
+                                                     int n_tiles, int zc, int metric) {
+  constexpr int WN = 2 * R + 1;
+  constexpr int PY = ST_Y + 2 * R, PX = ST_X + 2 * R, P1 = PY * PX;
+  __shared__ float rF[WN][P1];
+  __shared__ float rM[WN][P1];
+  __shared__ float zs[5][P1];
+  __shared__ float xs[5][PY * ST_X];
+  __shared__ double red[BLOCK / 64];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const SimItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const STile tc = stat_tile(tile - it.tile0, D, H, W, zc);
+  const float* __restrict__ F = it.F;
+  const float* __restrict__ I = it.I;
+  const float* __restrict__ U = it.U;
+  float* __restrict__ coef = it.coef;
+  const int pm = (min((tc.z0 + tc.z1) / 2, D - 1) * H + min(tc.y0 + ST_Y / 2, H - 1)) * W +
+                 min(tc.x0 + ST_X / 2, W - 1);
+  const float sF = F[pm], sM = I[pm];
+  const float inv_n = 1.f / (float)(WN * WN * WN);
+  const int ty = threadIdx.x / ST_X, tx = threadIdx.x % ST_X;
+  const int y = tc.y0 + ty, x = tc.x0 + tx;
+  const bool yx_in = (y < H) && (x < W);
+  const bool yx_valid = yx_in && y >= R && y <= H - 1 - R && x >= R && x <= W - 1 - R;
+  double lsum = 0.0;
+  for (int zi = tc.z0 - R; zi < tc.z1 + R; ++zi) {
+    const int slot = (zi + WN * 4096) % WN;
+    if (zi >= 0 && zi < D) {
+      for (int col = threadIdx.x; col < P1; col += BLOCK) {
+        const int yy = tc.y0 - R + col / PX, xx = tc.x0 - R + col % PX;
+        float fv = 0.f, mv = 0.f;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+          const int p = (zi * H + yy) * W + xx;
+          const Ax az = axis_disp(zi, U[p], D), ay = axis_disp(yy, U[V + p], H),
+                   ax = axis_disp(xx, U[2 * V + p], W);
+          float v[8];
+          load8(I, (az.i0 * H + ay.i0) * W + ax.i0, W, HW, v);
+          mv = tri_val(v, az.t, ay.t, ax.t) - sM;
+          fv = F[p] - sF;
+        }
+        rF[slot][col] = fv;
+        rM[slot][col] = mv;
+      }
+    }
+    __syncthreads();
+    const int zcen = zi - R;
+    if (zcen >= tc.z0) {
+      const bool zvalid = zcen >= R && zcen <= D - 1 - R;
+      if (zvalid) {
+        for (int col = threadIdx.x; col < P1; col += BLOCK) {
+          float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+          for (int k = 0; k < WN; ++k) {
+            const float f = rF[k][col], m = rM[k][col];
+            s0 += f;
+            s1 += m;
+            s2 = fmaf(f, f, s2);
+            s3 = fmaf(m, m, s3);
+            s4 = fmaf(f, m, s4);
+          }
+          zs[0][col] = s0; zs[1][col] = s1; zs[2][col] = s2; zs[3][col] = s3; zs[4][col] = s4;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < PY * ST_X; e += BLOCK) {
+          const int row = e / ST_X, c = e % ST_X;
+          const int b = row * PX + c;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < WN; ++k) acc += zs[q][b + k];
+            xs[q][e] = acc;
+          }
+        }
+        __syncthreads();
+      }
+      if (yx_in) {
+        const int p = (zcen * H + y) * W + x;
+        float al = 0.f, be = 0.f, ga = 0.f;
+        if (zvalid && yx_valid) {
+          float S[5];
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < WN; ++k) acc += xs[q][(ty + k) * ST_X + tx];
+            S[q] = acc;
+          }
+          const float mF = S[0] * inv_n, mM = S[1] * inv_n;
+          const float vFr = S[2] * inv_n - mF * mF;
+          const float vMr = S[3] * inv_n - mM * mM;
+          const float c = S[4] * inv_n - mF * mM;
+          const float vF = fmaxf(vFr, 0.f), vM = fmaxf(vMr, 0.f);
+          float l, av, ac;
+          if (metric == 0) {
+            const float den = vF * vM;
+            if (den > EPS_LNCC) {
+              const float sd = sqrtf(den);
+              l = 1.f - c / sd;
+              ac = -1.f / sd;
+              av = c / (2.f * vM * sd);
+            } else {
+              const float sd = sqrtf(EPS_LNCC);
+              l = 1.f - c / sd;
+              ac = -1.f / sd;
+              av = 0.f;
+            }
+          } else {
+            const float dd = fmaxf(vF, EPS_SILNCC);
+            l = vM - c * c / dd;
+            ac = -2.f * c / dd;
+            av = 1.f;
+          }
+          if (!(vMr > 0.f)) av = 0.f;
+          lsum += (double)l;
+          const float mFt = mF + sF, mMt = mM + sM;
+          al = -(2.f * mMt * av + mFt * ac) * inv_n;
+          be = av * inv_n;
+          ga = ac * inv_n;
+        }
+        if (coef) {
+          coef[p] = al;
+          coef[V + p] = be;
+          coef[2 * V + p] = ga;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const double tot = block_sum(lsum, red);
+  if (threadIdx.x == 0) {
+    const double v = tot * it.inv_nr;
+    if (it.js) unsafeAtomicAdd(&it.js->loss_sim, v);
+    if (it.sim_out) unsafeAtomicAdd(it.sim_out, v);
+  }
+}
+
+// Gradient of Sim with respect to the pair field:
+//   dSim/dM(y) = (Box alpha + 2 M Box beta + F Box gamma)(y) / N_R,
+//   dSim/dU(y) = dSim/dM(y) * grad I_j(y + U(y)).
+template <int R>
+__global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ items, int n_items,
+                                                    int n_tiles, int zc) {
+  constexpr int WN = 2 * R + 1;
+  constexpr int PY = ST_Y + 2 * R, PX = ST_X + 2 * R, P1 = PY * PX;
+  __shared__ float ring[3][WN][P1];
+  __shared__ float zs[3][P1];
+  __shared__ float xs[3][PY * ST_X];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const SimItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const STile tc = stat_tile(tile - it.tile0, D, H, W, zc);
+  const float* __restrict__ F = it.F;
+  const float* __restrict__ I = it.I;
+  const float* __restrict__ U = it.U;
+  const float* __restrict__ coef = it.coef;
+  float* __restrict__ gU = it.gU;
+  const float inv_nr = (float)it.inv_nr;
+  const int ty = threadIdx.x / ST_X, tx = threadIdx.x % ST_X;
+  const int y = tc.y0 + ty, x = tc.x0 + tx;
+  for (int zi = tc.z0 - R; zi < tc.z1 + R; ++zi) {
+    const int slot = (zi + WN * 4096) % WN;
+    const bool zin = zi >= 0 && zi < D;
+    for (int col = threadIdx.x; col < P1; col += BLOCK) {
+      const int yy = tc.y0 - R + col / PX, xx = tc.x0 - R + col % PX;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+      if (zin && yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const int p = (zi * H + yy) * W + xx;
+        a0 = coef[p];
+        a1 = coef[V + p];
+        a2 = coef[2 * V + p];
+      }
+      ring[0][slot][col] = a0;
+      ring[1][slot][col] = a1;
+      ring[2][slot][col] = a2;
+    }
+    __syncthreads();
+    const int zo = zi - R;
+    if (zo >= tc.z0) {
+      for (int col = threadIdx.x; col < P1; col += BLOCK) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < WN; ++k) acc += ring[q][k][col];
+          zs[q][col] = acc;
+        }
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < PY * ST_X; e += BLOCK) {
+        const int row = e / ST_X, c = e % ST_X;
+        const int b = row * PX + c;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < WN; ++k) acc += zs[q][b + k];
+          xs[q][e] = acc;
+        }
+      }
+      __syncthreads();
+      if (y < H && x < W) {
+        float B[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < WN; ++k) acc += xs[q][(ty + k) * ST_X + tx];
+          B[q] = acc;
+        }
+        const int p = (zo * H + y) * W + x;
+        const Ax az = axis_disp(zo, U[p], D), ay = axis_disp(y, U[V + p], H),
+                 ax = axis_disp(x, U[2 * V + p], W);
+        float v[8], dz, dy, dx;
+        load8(I, (az.i0 * H + ay.i0) * W + ax.i0, W, HW, v);
+        const float M = tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+        const float dM = (B[0] + 2.f * M * B[1] + F[p] * B[2]) * inv_nr;
+        gU[p] = dM * dz * az.live;
+        gU[V + p] = dM * dy * ay.live;
+        gU[2 * V + p] = dM * dx * ax.live;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adam (PyTorch semantics) with the warm-up + cosine schedule (Sec. 2.7),
+// or the plain gradient (mode 1).  Clears g0f / g0b after reading them.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double schedule_lr(const JobState* js, int step) {
+  const int T = js->T, Wu = js->W;
+  if (step <= Wu) return (double)js->lr0 * step / (double)Wu;
+  if (T == Wu) return (double)js->lr0;
+  return (double)js->lr0 * 0.5 * (1.0 + cos(M_PI * (double)(step - Wu) / (double)(T - Wu)));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adam(const AdamItem* __restrict__ items, int n_items,
+                                                int n_tiles) {
+  const int tile = blockIdx.x;
+  const AdamItem it = items[find_item(items, n_items, tile)];
+  const int n = it.n;
+  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
+  if (it.mode == 1) {
+    for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
+      const int q = q0 + k;
+      if (q >= n) break;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int i = c * n + q;
+        const float g = it.scale * (it.g0f[i] - it.g0b[i]);
+        it.g0f[i] = 0.f;
+        it.g0b[i] = 0.f;
+        it.gout[i] = g * it.gscale;
+      }
+    }
+    return;
+  }
+  const JobState* js = it.js;
+  const int step = js->t + 1;
+  const double lr = schedule_lr(js, step);
+  const double bc1 = 1.0 - pow((double)js->b1, (double)step);
+  const double bc2 = 1.0 - pow((double)js->b2, (double)step);
+  const float step_size = (float)(lr / bc1);
+  const float bc2s = (float)sqrt(bc2);
+  const float b1 = js->b1, b2 = js->b2, eps = js->eps;
+  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
+    const int q = q0 + k;
+    if (q >= n) break;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int i = c * n + q;
+      const float g = it.scale * (it.g0f[i] - it.g0b[i]);
+      it.g0f[i] = 0.f;
+      it.g0b[i] = 0.f;
+      float m = it.m[i], v = it.v[i];
+      m = fmaf(1.f - b1, g - m, m);
+      v = fmaf(1.f - b2, g * g, v * b2);
+      const float den = sqrtf(v) / bc2s + eps;
+      it.phi[i] -= step_size * (m / den);
+      it.m[i] = m;
+      it.v[i] = v;
+    }
+  }
+}
+
+__global__ void k_finish(JobState* const* __restrict__ states, int n_jobs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_jobs) return;
+  JobState* js = states[i];
+  const double L = js->loss_sim + js->loss_reg;
+  const int h = js->hist_base + js->t;
+  if (js->history && h >= 0 && h < js->hist_len) js->history[h] = L;
+  if (!isfinite(L)) js->nonfinite = 1;
+  js->loss_sim = 0.0;
+  js->loss_reg = 0.0;
+  js->t += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Pyramid (Sec. 2.7)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_pool2(const PoolItem* __restrict__ items, int n_items,
+                                                 int n_tiles) {
+  const int tile = blockIdx.x;
+  const PoolItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W;
+  const int D2 = D / 2, H2 = H / 2, W2 = W / 2;
+  const int n = D2 * H2 * W2;
+  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
+  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
+    const int q = q0 + k;
+    if (q >= n) break;
+    const int X = q % W2, Y = (q / W2) % H2, Z = q / (W2 * H2);
+    const float* s = it.src + ((2 * Z) * H + 2 * Y) * W + 2 * X;
+    const int HW = H * W;
+    const float a = (s[0] + s[1]) + (s[W] + s[W + 1]);
+    const float b = (s[HW] + s[HW + 1]) + (s[HW + W] + s[HW + W + 1]);
+    it.dst[q] = (a + b) * 0.125f;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_upsample2(const UpItem* __restrict__ items, int n_items,
+                                                     int n_tiles) {
+  const int tile = blockIdx.x;
+  const UpItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W;
+  const int n = D2 * H2 * W2;
+  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
+  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
+    const int q = q0 + k;
+    if (q >= n) break;
+    const int x = q % W2, y = (q / W2) % H2, z = q / (W2 * H2);
+    const Ax az = axis_pos(((float)z - 0.5f) * 0.5f, D), ay = axis_pos(((float)y - 0.5f) * 0.5f, H),
+             ax = axis_pos(((float)x - 0.5f) * 0.5f, W);
+    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+    float v[8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      load8(it.src + c * V, base, W, HW, v);
+      it.dst[c * n + q] = 2.f * tri_val(v, az.t, ay.t, ax.t);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Single-step helpers for the unit entry points
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_adam_flat(int64_t n, float* x, const float* g, float* m,
+                                                     float* v, float step_size, float bc2s,
+                                                     float b1, float b2, float eps) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const float gg = g[i];
+  float mm = m[i], vv = v[i];
+  mm = fmaf(1.f - b1, gg - mm, mm);
+  vv = fmaf(1.f - b2, gg * gg, vv * b2);
+  const float den = sqrtf(vv) / bc2s + eps;
+  x[i] -= step_size * (mm / den);
+  m[i] = mm;
+  v[i] = vv;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reg(int D, int H, int W, const float* phi, double* out,
+                                               float* grad) {
+  __shared__ double red[BLOCK / 64];
+  const int V = D * H * W;
+  const int q = blockIdx.x * BLOCK + threadIdx.x;
+  const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
+              inv_mx = 1.f / (float)(D * H * (W - 1));
+  double val = 0.0;
+  if (q < V) {
+    const int x = q % W, y = (q / W) % H, z = q / (W * H);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float g = reg_point(phi + c * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &val);
+      if (grad) grad[c * V + q] = g;
+    }
+  }
+  const double tot = block_sum(val, red);
+  if (threadIdx.x == 0) unsafeAtomicAdd(out, tot);
+}
+
+__global__ void k_fill(float* p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_exp_fwd(const ExpFwdItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exp_fwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compose_fwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exp_bwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
+                              hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compose_bwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int zc, int window,
+                            int metric, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (window) {
+    case 3: hipLaunchKernelGGL(k_sim_stats<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc, metric); break;
+    case 5: hipLaunchKernelGGL(k_sim_stats<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc, metric); break;
+    case 7: hipLaunchKernelGGL(k_sim_stats<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc, metric); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int zc, int window,
+                           hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (window) {
+    case 3: hipLaunchKernelGGL(k_sim_grad<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc); break;
+    case 5: hipLaunchKernelGGL(k_sim_grad<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc); break;
+    case 7: hipLaunchKernelGGL(k_sim_grad<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adam, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finish, dim3(ceil_div(n_jobs, 64)), dim3(64), 0, s, states, n_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool2, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_upsample2(const UpItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_upsample2, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_flat(int64_t n, float* x, const float* g, float* m, float* v, int t,
+                            float lr, float b1, float b2, float eps, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const double bc1 = 1.0 - std::pow((double)b1, (double)t);
+  const double bc2 = 1.0 - std::pow((double)b2, (double)t);
+  const float step_size = (float)(lr / bc1);
+  const float bc2s = (float)std::sqrt(bc2);
+  const int64_t blocks = (n + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(k_adam_flat, dim3((unsigned)blocks), dim3(BLOCK), 0, s, n, x, g, m, v,
+                     step_size, bc2s, b1, b2, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hipStream_t s) {
+  const int V = d.D * d.H * d.W;
+  hipLaunchKernelGGL(k_reg, dim3(ceil_div(V, BLOCK)), dim3(BLOCK), 0, s, d.D, d.H, d.W, phi, out,
+                     grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(BLOCK), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace muster

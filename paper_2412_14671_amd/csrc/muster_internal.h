@@ -1,0 +1,169 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+//
+// Every kernel takes a table of work items in device memory.  An item is one
+// field-sized piece of work (one squaring of one direction, one composition,
+// one session pair, ...) on its own grid, so a single launch can cover every
+// interval, pair and subject of a batch with uneven grids.  Items in a table
+// are sorted by tile0, the first global tile index of the item; a block finds
+// its item by binary search.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace muster {
+
+// Per-job device state: optimiser step counter and schedule, loss
+// accumulators and the loss history.  Lives in device memory so that a
+// captured iteration can be replayed without host involvement.
+struct JobState {
+  int t;            // completed Adam steps at the current level
+  int T;            // steps at this level
+  int W;            // warm-up steps
+  int nonfinite;    // set once the loss is not finite
+  float lr0, b1, b2, eps;
+  double loss_sim;  // accumulated over the current iteration
+  double loss_reg;
+  double* history;  // loss per step (device), length hist_len
+  int hist_len;
+  int hist_base;    // index of this level's first step in history
+};
+
+struct GridDims {
+  int D, H, W;
+};
+
+// u_{s+1} = u + u o (Omega + u) with u = a * src.
+struct ExpFwdItem {
+  int tile0;
+  int D, H, W;
+  const float* src;
+  float* dst;
+  float a;
+  int pad;
+};
+
+// out = prev + C o (Omega + prev).
+struct ComposeItem {
+  int tile0;
+  int D, H, W;
+  const float* prev;
+  const float* C;
+  float* out;
+};
+
+// One backward squaring: given gin = dL/du_{s+1}, accumulate dL/du_s into
+// gout (zeroed beforehand).  u_s = a * src.  If zero_in, gin is cleared
+// after it is read.  If reg_w != 0, the regulariser gradient of src (= phi)
+// times reg_w is added to the voxel's own term, and the regulariser value
+// times reg_loss_w is added to the job's loss.
+struct ExpBwdItem {
+  int tile0;
+  int D, H, W;
+  const float* src;
+  float* gin;
+  float* gout;
+  float a;
+  int zero_in;
+  float reg_w;
+  float reg_loss_w;
+  JobState* js;
+};
+
+// Backward of one composition out = prev + C o (Omega + prev): given
+// g = dL/dout, add (I + J_C^T) g to gprev (atomically if prev_atomic) and
+// scatter g into gc.
+struct ComposeBwdItem {
+  int tile0;
+  int D, H, W;
+  const float* g;
+  const float* prev;
+  const float* C;
+  float* gprev;
+  float* gc;
+  int prev_atomic;
+  int pad;
+};
+
+// One session pair (target F = I_i, source I_j, field U = U[j->i]).
+struct SimItem {
+  int tile0;
+  int D, H, W;
+  const float* F;
+  const float* I;
+  const float* U;
+  float* coef;   // [3][V]: alpha, beta, gamma per window centre (may be null in sim_stats)
+  float* gU;     // [3][V]: dSim/dU, written by sim_grad
+  double inv_nr; // 1 / number of windows
+  JobState* js;  // loss accumulator (may be null)
+  double* sim_out;  // optional per-pair accumulator
+};
+
+// Adam step (mode 0) or gradient output (mode 1) for one interval.
+struct AdamItem {
+  int tile0;
+  int n;          // voxels
+  float* phi;
+  float* g0f;     // dL/du_0 of the forward direction (cleared after read)
+  float* g0b;     // dL/du_0 of the backward direction (cleared after read)
+  float* m;
+  float* v;
+  float* gout;    // mode 1 output
+  float scale;    // 2^-K
+  float gscale;   // mode 1: grad_out
+  int mode;
+  int pad;
+  JobState* js;
+};
+
+struct PoolItem {
+  int tile0;
+  int D, H, W;  // source dims
+  const float* src;
+  float* dst;
+};
+
+struct UpItem {
+  int tile0;
+  int D, H, W;  // coarse dims
+  const float* src;
+  float* dst;   // [3][2D][2H][2W]
+};
+
+// Tiles of the gather/scatter kernels.
+constexpr int PT_Z = 8, PT_Y = 8, PT_X = 16;   // 1024 voxels, 256 threads
+constexpr int PT_VOX = PT_Z * PT_Y * PT_X;
+constexpr int BLOCK = 256;
+constexpr int SCATTER_CELLS = 3072;            // LDS bins per component
+// Tiles of the windowed-statistics kernels: TY x TX columns, z chunks.
+constexpr int ST_Y = 8, ST_X = 32;
+constexpr int ELEM_PER_BLOCK = 1024;           // elementwise kernels
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline int point_tiles(int D, int H, int W) {
+  return ceil_div(D, PT_Z) * ceil_div(H, PT_Y) * ceil_div(W, PT_X);
+}
+inline int stat_tiles(int D, int H, int W, int zc) {
+  return ceil_div(D, zc) * ceil_div(H, ST_Y) * ceil_div(W, ST_X);
+}
+
+// Launchers (kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_exp_fwd(const ExpFwdItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
+                              hipStream_t s);
+hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int zc, int window,
+                            int metric, hipStream_t s);
+hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int zc, int window,
+                           hipStream_t s);
+hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s);
+hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_upsample2(const UpItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_adam_flat(int64_t n, float* x, const float* g, float* m, float* v, int t,
+                            float lr, float b1, float b2, float eps, hipStream_t s);
+hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+
+}  // namespace muster

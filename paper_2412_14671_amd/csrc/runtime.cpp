@@ -1,0 +1,1660 @@
+// Host runtime of libmuster: context and arena, registration jobs, launch
+// plans (one optimisation iteration of many jobs as a fixed sequence of
+// batched launches, replayed eagerly or from a captured hipGraph), the
+// continuous-batching server, and the C ABI of include/muster.h.
+#include "runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+namespace muster {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+void fail(muster_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw Error{st, std::string(buf)};
+}
+
+double now_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <class F>
+static muster_status guard(Ctx* ctx, F&& f) {
+  try {
+    if (ctx && ctx->poisoned) fail(MUSTER_E_DEVICE, "context poisoned by an earlier device error");
+    if (ctx) MUSTER_HIP(hipSetDevice(ctx->device));
+    f();
+    g_err.clear();
+    return MUSTER_OK;
+  } catch (const Error& e) {
+    g_err = e.msg;
+    if (e.st == MUSTER_E_DEVICE && ctx) ctx->poisoned = true;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return MUSTER_E_NOMEM;
+  } catch (...) {
+    g_err = "unexpected internal exception";
+    return MUSTER_E_INTERNAL;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// arena
+// ---------------------------------------------------------------------------
+void* Arena::try_alloc(size_t bytes) {
+  std::lock_guard<std::mutex> lk(mu_);
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (budget_ && used_ + bytes > budget_) return nullptr;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  live_[p] = bytes;
+  used_ += bytes;
+  return p;
+}
+
+void Arena::release(void* p) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  (void)hipFree(p);
+  used_ -= it->second;
+  live_.erase(it);
+}
+
+void DevMem::alloc(Ctx* c, size_t n) {
+  reset();
+  ctx = c;
+  p = c->arena.try_alloc(n);
+  if (!p)
+    fail(MUSTER_E_NOMEM, "device allocation of %zu bytes failed (arena %llu of %llu bytes in use)",
+         n, (unsigned long long)c->arena.used(), (unsigned long long)c->arena.budget());
+  bytes = n;
+}
+
+// ---------------------------------------------------------------------------
+// validation and footprint
+// ---------------------------------------------------------------------------
+static int pair_index(int i, int j, int N) { return i * (N - 1) + (j < i ? j : j - 1); }
+
+void validate_params(const muster_params& p) {
+  if (p.levels < 1 || p.levels > MUSTER_MAX_LEVELS)
+    fail(MUSTER_E_INVALID, "levels must be in 1..%d (got %d)", MUSTER_MAX_LEVELS, p.levels);
+  for (int l = 0; l < p.levels; ++l)
+    if (p.iters[l] < 0 || p.iters[l] > 1000000)
+      fail(MUSTER_E_INVALID, "iters[%d] = %d out of range", l, p.iters[l]);
+  if (p.K < 1 || p.K > 20) fail(MUSTER_E_INVALID, "K must be in 1..20 (got %d)", p.K);
+  if (p.window != 3 && p.window != 5 && p.window != 7)
+    fail(MUSTER_E_INVALID, "window must be 3, 5 or 7 (got %d)", p.window);
+  if (p.metric != MUSTER_METRIC_LNCC && p.metric != MUSTER_METRIC_SILNCC)
+    fail(MUSTER_E_INVALID, "unknown metric %d", p.metric);
+  if (!(p.alpha_ss >= 0.f) || !std::isfinite(p.alpha_ss)) fail(MUSTER_E_INVALID, "alpha_ss must be >= 0");
+  if (!(p.lr >= 0.f) || !std::isfinite(p.lr)) fail(MUSTER_E_INVALID, "lr must be >= 0");
+  if (!(p.warmup >= 0.f && p.warmup <= 1.f)) fail(MUSTER_E_INVALID, "warmup must be in [0, 1]");
+  if (!(p.beta1 >= 0.f && p.beta1 < 1.f) || !(p.beta2 >= 0.f && p.beta2 < 1.f) || !(p.eps > 0.f))
+    fail(MUSTER_E_INVALID, "bad Adam constants");
+  if (p.exp_mode != MUSTER_EXP_STORE && p.exp_mode != MUSTER_EXP_RECOMPUTE)
+    fail(MUSTER_E_INVALID, "unknown exp_mode %d", p.exp_mode);
+}
+
+void validate_problem(int N, const int dims[3], const muster_params& p, const double* times) {
+  if (N < 2) fail(MUSTER_E_INVALID, "need at least 2 sessions (got %d)", N);
+  if (N > 64) fail(MUSTER_E_INVALID, "at most 64 sessions are supported (got %d)", N);
+  if (!dims) fail(MUSTER_E_INVALID, "dims is NULL");
+  validate_params(p);
+  const int f = 1 << (p.levels - 1);
+  uint64_t V = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (dims[d] % f != 0)
+      fail(MUSTER_E_INVALID, "dims[%d] = %d is not divisible by 2^(levels-1) = %d", d, dims[d], f);
+    if (dims[d] / f < p.window)
+      fail(MUSTER_E_INVALID, "dims[%d] = %d is smaller than the window at the coarsest level", d,
+           dims[d]);
+    V *= (uint64_t)dims[d];
+  }
+  if (V * 3 >= (uint64_t)INT32_MAX) fail(MUSTER_E_INVALID, "volume too large (%llu voxels)",
+                                         (unsigned long long)V);
+  if (times) {
+    for (int i = 0; i < N; ++i) {
+      if (!std::isfinite(times[i])) fail(MUSTER_E_INVALID, "times[%d] is not finite", i);
+      if (i > 0 && !(times[i] > times[i - 1]))
+        fail(MUSTER_E_INVALID, "times must be strictly increasing (times[%d] <= times[%d])", i,
+             i - 1);
+    }
+  }
+}
+
+static int per_dir_fields(const muster_params& p) {
+  return p.exp_mode == MUSTER_EXP_STORE ? p.K : 3;
+}
+
+uint64_t job_footprint(int N, const int dims[3], const muster_params& p) {
+  const uint64_t V = (uint64_t)dims[0] * dims[1] * dims[2];
+  const uint64_t F = 3 * V * sizeof(float);
+  const uint64_t n1 = N - 1, P = (uint64_t)N * (N - 1), Pd = (uint64_t)(N - 1) * (N - 2);
+  uint64_t fields = 3 * n1 + 2 * n1 * per_dir_fields(p) + std::max<uint64_t>(Pd, 1) + P + 4 * n1 + P;
+  uint64_t bytes = fields * F;
+  uint64_t imgs = 0;
+  for (int l = 0; l < p.levels - 1; ++l) {
+    const int f = 1 << (p.levels - 1 - l);
+    imgs += (uint64_t)N * (dims[0] / f) * (dims[1] / f) * (dims[2] / f) * sizeof(float);
+  }
+  uint64_t hist = 0;
+  for (int l = 0; l < p.levels; ++l) hist += p.iters[l];
+  bytes += imgs + hist * sizeof(double) + 4096 + 65536;
+  // allocations are rounded to 256 bytes
+  return bytes + 16 * 256;
+}
+
+// ---------------------------------------------------------------------------
+// jobs
+// ---------------------------------------------------------------------------
+Job::~Job() {
+  if (host_state) (void)hipHostFree(host_state);
+}
+
+float* Job::us_field(int dir, int slot) const {
+  return field(m_us.as<float>(), (size_t)dir * per_dir_fields(p) + slot);
+}
+
+float* Job::u_step(int dir, int s) const {
+  if (p.exp_mode == MUSTER_EXP_STORE) return us_field(dir, s - 1);
+  if (s == p.K) return us_field(dir, 0);
+  return us_field(dir, 1 + ((s - 1) % 2));
+}
+
+float* Job::pair_field(int i, int j) const {
+  if (j == i + 1) return u_final(2 * i);
+  if (j == i - 1) return u_final(2 * (i - 1) + 1);
+  return field(m_deep.as<float>(), (size_t)deep_slot[i * N + j]);
+}
+
+float* Job::pair_grad(int i, int j) const {
+  return field(m_gpair.as<float>(), (size_t)pair_index(i, j, N));
+}
+
+float* Job::coef(int i, int j) const {
+  return field(m_coef.as<float>(), (size_t)pair_index(i, j, N));
+}
+
+std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
+  validate_problem(jd.N, jd.dims, jd.params, jd.times_host);
+  if (!jd.images_dev) fail(MUSTER_E_INVALID, "images is NULL");
+  auto job = std::make_unique<Job>();
+  Job& J = *job;
+  J.ctx = ctx;
+  J.N = jd.N;
+  std::memcpy(J.dims, jd.dims, sizeof J.dims);
+  J.p = jd.params;
+  J.images_fine = jd.images_dev;
+  J.svf_init = jd.svf_init_dev;
+  J.svf_out = jd.svf_out_dev;
+  J.pairs_out = jd.pairs_out_dev;
+  const int L = J.p.levels;
+  for (int l = 0; l < L; ++l) {
+    const int f = 1 << (L - 1 - l);
+    for (int d = 0; d < 3; ++d) J.ldims[l][d] = jd.dims[d] / f;
+  }
+  const int N = J.N;
+  J.deep_slot.assign((size_t)N * N, -1);
+  int slot = 0;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      if (std::abs(i - j) >= 2) J.deep_slot[i * N + j] = slot++;
+  const size_t V0 = J.V(L - 1);
+  const size_t F = 3 * V0 * sizeof(float);
+  const size_t n1 = N - 1;
+  const size_t P = (size_t)N * (N - 1);
+  J.m_phi.alloc(ctx, n1 * F);
+  J.m_m.alloc(ctx, n1 * F);
+  J.m_v.alloc(ctx, n1 * F);
+  J.m_us.alloc(ctx, 2 * n1 * per_dir_fields(J.p) * F);
+  J.m_deep.alloc(ctx, std::max<size_t>(slot, 1) * F);
+  J.m_gpair.alloc(ctx, P * F);
+  J.m_pp.alloc(ctx, 4 * n1 * F);
+  J.m_coef.alloc(ctx, P * F);
+  size_t img = 0;
+  for (int l = 0; l < L - 1; ++l) img += (size_t)N * J.V(l);
+  J.m_img.alloc(ctx, std::max<size_t>(img, 1) * sizeof(float));
+  J.m_state.alloc(ctx, sizeof(JobState));
+  J.hist_len = 0;
+  for (int l = 0; l < L; ++l) J.hist_len += J.p.iters[l];
+  J.m_hist.alloc(ctx, std::max(J.hist_len, 1) * sizeof(double));
+  J.phi = J.m_phi.as<float>();
+  J.mbuf = J.m_m.as<float>();
+  J.vbuf = J.m_v.as<float>();
+  J.js = J.m_state.as<JobState>();
+  J.hist = J.m_hist.as<double>();
+  J.level_images.resize(L);
+  size_t off = 0;
+  for (int l = 0; l < L - 1; ++l) {
+    J.level_images[l] = J.m_img.as<float>() + off;
+    off += (size_t)N * J.V(l);
+  }
+  J.level_images[L - 1] = const_cast<float*>(J.images_fine);
+  MUSTER_HIP(hipHostMalloc((void**)&J.host_state, sizeof(JobState), hipHostMallocDefault));
+  std::memset(J.host_state, 0, sizeof(JobState));
+  J.footprint = J.m_phi.bytes + J.m_m.bytes + J.m_v.bytes + J.m_us.bytes + J.m_deep.bytes +
+                J.m_gpair.bytes + J.m_pp.bytes + J.m_coef.bytes + J.m_img.bytes +
+                J.m_state.bytes + J.m_hist.bytes;
+  return job;
+}
+
+// Small item tables used outside plans (pyramid, upsampling) go through this
+// helper: upload, launch, synchronise.
+template <class Item, class Launch>
+static void run_items(Ctx* ctx, std::vector<Item>& items, int n_tiles, hipStream_t s,
+                      Launch&& launch) {
+  if (items.empty() || n_tiles <= 0) return;
+  DevMem d;
+  d.alloc(ctx, items.size() * sizeof(Item));
+  MUSTER_HIP(hipMemcpyAsync(d.p, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+  MUSTER_HIP(launch(d.as<Item>(), (int)items.size(), n_tiles, s));
+  MUSTER_HIP(hipStreamSynchronize(s));
+}
+
+static int elem_tiles(size_t n) { return (int)((n + ELEM_PER_BLOCK - 1) / ELEM_PER_BLOCK); }
+
+void job_begin_level(Job& J, int level, hipStream_t s) {
+  Ctx* ctx = J.ctx;
+  const int L = J.p.levels;
+  const int N = J.N;
+  if (level == 0 && L > 1) {
+    // image pyramid: repeated 2x2x2 means from the finest level down
+    for (int l = L - 2; l >= 0; --l) {
+      std::vector<PoolItem> items;
+      int tiles = 0;
+      const int* dd = J.ldims[l + 1];
+      const size_t Vs = J.V(l + 1), Vd = J.V(l);
+      for (int i = 0; i < N; ++i) {
+        PoolItem it{};
+        it.tile0 = tiles;
+        it.D = dd[0]; it.H = dd[1]; it.W = dd[2];
+        it.src = J.level_images[l + 1] + (size_t)i * Vs;
+        it.dst = J.level_images[l] + (size_t)i * Vd;
+        items.push_back(it);
+        tiles += elem_tiles(Vd);
+      }
+      run_items(ctx, items, tiles, s, launch_pool2);
+    }
+  }
+  J.level = level;
+  const size_t V = J.Vc();
+  const size_t n1 = N - 1;
+  if (!J.grad_mode) {
+    if (level == 0) {
+      if (J.svf_init)
+        MUSTER_HIP(hipMemcpyAsync(J.phi, J.svf_init, n1 * 3 * V * sizeof(float),
+                                  hipMemcpyDeviceToDevice, s));
+      else
+        MUSTER_HIP(launch_fill(J.phi, (int64_t)(n1 * 3 * V), 0.f, s));
+    } else {
+      // phi_fine(x) = 2 phi_coarse((x - 0.5)/2), into the m buffer, then swap
+      std::vector<UpItem> items;
+      int tiles = 0;
+      const int* dc = J.ldims[level - 1];
+      const size_t Vcoarse = J.V(level - 1);
+      for (size_t i = 0; i < n1; ++i) {
+        UpItem it{};
+        it.tile0 = tiles;
+        it.D = dc[0]; it.H = dc[1]; it.W = dc[2];
+        it.src = J.phi + i * 3 * Vcoarse;
+        it.dst = J.mbuf + i * 3 * V;
+        items.push_back(it);
+        tiles += elem_tiles(V);
+      }
+      run_items(ctx, items, tiles, s, launch_upsample2);
+      std::swap(J.phi, J.mbuf);
+    }
+    MUSTER_HIP(launch_fill(J.mbuf, (int64_t)(n1 * 3 * V), 0.f, s));
+    MUSTER_HIP(launch_fill(J.vbuf, (int64_t)(n1 * 3 * V), 0.f, s));
+  }
+  MUSTER_HIP(launch_fill(J.m_pp.as<float>(), (int64_t)(4 * n1 * 3 * V), 0.f, s));
+  JobState st{};
+  const int prev_nonfinite = level > 0 ? J.host_state->nonfinite : 0;
+  st.t = 0;
+  st.T = J.p.iters[level];
+  st.W = std::max(1, (int)std::ceil((double)J.p.warmup * st.T));
+  st.nonfinite = prev_nonfinite;
+  st.lr0 = J.p.lr;
+  st.b1 = J.p.beta1;
+  st.b2 = J.p.beta2;
+  st.eps = J.p.eps;
+  st.history = J.hist;
+  st.hist_len = J.hist_len;
+  int base = 0;
+  for (int l = 0; l < level; ++l) base += J.p.iters[l];
+  st.hist_base = base;
+  *J.host_state = st;
+  MUSTER_HIP(hipMemcpyAsync(J.js, J.host_state, sizeof(JobState), hipMemcpyHostToDevice, s));
+  MUSTER_HIP(hipStreamSynchronize(s));
+}
+
+static void read_state(Job& J, hipStream_t s) {
+  MUSTER_HIP(hipMemcpyAsync(J.host_state, J.js, sizeof(JobState), hipMemcpyDeviceToHost, s));
+  MUSTER_HIP(hipStreamSynchronize(s));
+}
+
+void job_final_outputs(Job& J, hipStream_t s) {
+  Ctx* ctx = J.ctx;
+  std::vector<Job*> one{&J};
+  auto plan = build_plan(one, PLAN_FORWARD);
+  plan->upload(ctx, s);
+  plan->run(ctx, s);
+  const size_t V = J.Vc();
+  if (J.svf_out)
+    MUSTER_HIP(hipMemcpyAsync(J.svf_out, J.phi, (size_t)(J.N - 1) * 3 * V * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+  if (J.pairs_out) {
+    for (int i = 0; i < J.N; ++i)
+      for (int j = 0; j < J.N; ++j)
+        if (i != j)
+          MUSTER_HIP(hipMemcpyAsync(J.pairs_out + (size_t)pair_index(i, j, J.N) * 3 * V,
+                                    J.pair_field(i, j), 3 * V * sizeof(float),
+                                    hipMemcpyDeviceToDevice, s));
+  }
+  MUSTER_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+namespace {
+
+// Algorithmic bytes per voxel (the unique bytes each step must move).
+constexpr double B_EXP_FWD = 24, B_COMPOSE_FWD = 36, B_SIM_STATS = 20, B_SIM_GRAD = 32,
+                 B_COMPOSE_BWD = 84, B_EXP_BWD = 60, B_ADAM = 96;
+
+struct Builder {
+  Plan* plan;
+  template <class Item>
+  void add(StageKind kind, std::vector<Item>& items, int tiles, double bytes, int window = 0,
+           int metric = 0, int zc = 32) {
+    if (items.empty()) return;
+    size_t off = (plan->blob.size() + 63) & ~(size_t)63;
+    plan->blob.resize(off + items.size() * sizeof(Item));
+    std::memcpy(plan->blob.data() + off, items.data(), items.size() * sizeof(Item));
+    Stage st;
+    st.kind = kind;
+    st.off = off;
+    st.n_items = (int)items.size();
+    st.n_tiles = tiles;
+    st.window = window;
+    st.metric = metric;
+    st.zc = zc;
+    st.bytes = bytes;
+    plan->stages.push_back(st);
+  }
+};
+
+int sim_zc(const Job& J) { return std::min(32, J.ldims[J.level][0]); }
+
+void add_exp_fwd_step(Builder& b, const std::vector<Job*>& jobs, int s, bool recompute_only,
+                      int upto) {
+  // One squaring s -> s+1 for every direction of every job.  With
+  // recompute_only, this is step s of recomputing u_upto in the scratch slots.
+  std::vector<ExpFwdItem> items;
+  int tiles = 0;
+  double bytes = 0;
+  for (Job* J : jobs) {
+    if (s >= J->K()) continue;
+    if (recompute_only && (J->p.exp_mode != MUSTER_EXP_RECOMPUTE || upto > J->K() - 1)) continue;
+    const int* d = J->ldims[J->level];
+    const float scale = std::ldexp(1.f, -J->K());
+    for (int dir = 0; dir < 2 * (J->N - 1); ++dir) {
+      const int i = dir / 2;
+      const float sign = (dir % 2 == 0) ? 1.f : -1.f;
+      ExpFwdItem it{};
+      it.tile0 = tiles;
+      it.D = d[0]; it.H = d[1]; it.W = d[2];
+      if (s == 0) {
+        it.src = J->field(J->phi, i);
+        it.a = sign * scale;
+      } else {
+        it.src = J->u_step(dir, s);
+        it.a = 1.f;
+      }
+      it.dst = J->u_step(dir, s + 1);
+      items.push_back(it);
+      tiles += point_tiles(d[0], d[1], d[2]);
+      bytes += B_EXP_FWD * J->Vc();
+    }
+  }
+  b.add(ST_EXP_FWD, items, tiles, bytes);
+}
+
+void add_forward(Builder& b, const std::vector<Job*>& jobs) {
+  int maxK = 0, maxN = 0;
+  for (Job* J : jobs) {
+    maxK = std::max(maxK, J->K());
+    maxN = std::max(maxN, J->N);
+  }
+  for (int s = 0; s < maxK; ++s) add_exp_fwd_step(b, jobs, s, false, 0);
+  for (int d = 2; d < maxN; ++d) {
+    std::vector<ComposeItem> items;
+    int tiles = 0;
+    double bytes = 0;
+    for (Job* J : jobs) {
+      const int N = J->N;
+      if (d >= N) continue;
+      const int* dd = J->ldims[J->level];
+      for (int i = 0; i < N; ++i) {
+        for (int j : {i + d, i - d}) {
+          if (j < 0 || j >= N) continue;
+          ComposeItem it{};
+          it.tile0 = tiles;
+          it.D = dd[0]; it.H = dd[1]; it.W = dd[2];
+          if (j > i) {
+            it.prev = J->pair_field(i, j - 1);
+            it.C = J->u_final(2 * (j - 1));
+          } else {
+            it.prev = J->pair_field(i, j + 1);
+            it.C = J->u_final(2 * j + 1);
+          }
+          it.out = J->pair_field(i, j);
+          items.push_back(it);
+          tiles += point_tiles(dd[0], dd[1], dd[2]);
+          bytes += B_COMPOSE_FWD * J->Vc();
+        }
+      }
+    }
+    b.add(ST_COMPOSE_FWD, items, tiles, bytes);
+  }
+}
+
+std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int& tiles, double& vox, int& zc) {
+  std::vector<SimItem> items;
+  tiles = 0;
+  vox = 0;
+  zc = 32;
+  for (Job* J : jobs) zc = std::min(zc, sim_zc(*J));
+  for (Job* J : jobs) {
+    const int N = J->N;
+    const int* d = J->ldims[J->level];
+    const int r = (J->p.window - 1) / 2;
+    const double nr = (double)(d[0] - 2 * r) * (d[1] - 2 * r) * (d[2] - 2 * r);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        if (i == j) continue;
+        SimItem it{};
+        it.tile0 = tiles;
+        it.D = d[0]; it.H = d[1]; it.W = d[2];
+        it.F = J->image(i);
+        it.I = J->image(j);
+        it.U = J->pair_field(i, j);
+        it.coef = J->coef(i, j);
+        it.gU = J->pair_grad(i, j);
+        it.inv_nr = 1.0 / nr;
+        it.js = J->js;
+        it.sim_out = nullptr;
+        items.push_back(it);
+        tiles += stat_tiles(d[0], d[1], d[2], zc);
+        vox += (double)J->Vc();
+      }
+  }
+  return items;
+}
+
+void add_backward(Builder& b, const std::vector<Job*>& jobs) {
+  int maxK = 0, maxN = 0;
+  for (Job* J : jobs) {
+    maxK = std::max(maxK, J->K());
+    maxN = std::max(maxN, J->N);
+  }
+  const int window = jobs[0]->p.window;
+  {
+    int tiles, zc;
+    double vox;
+    auto items = sim_items(jobs, tiles, vox, zc);
+    b.add(ST_SIM_GRAD, items, tiles, B_SIM_GRAD * vox, window, 0, zc);
+  }
+  for (int d = maxN - 1; d >= 2; --d) {
+    std::vector<ComposeBwdItem> items;
+    int tiles = 0;
+    double bytes = 0;
+    for (Job* J : jobs) {
+      const int N = J->N;
+      if (d >= N) continue;
+      const int* dd = J->ldims[J->level];
+      for (int i = 0; i < N; ++i) {
+        for (int j : {i + d, i - d}) {
+          if (j < 0 || j >= N) continue;
+          ComposeBwdItem it{};
+          it.tile0 = tiles;
+          it.D = dd[0]; it.H = dd[1]; it.W = dd[2];
+          it.g = J->pair_grad(i, j);
+          if (j > i) {
+            it.prev = J->pair_field(i, j - 1);
+            it.C = J->u_final(2 * (j - 1));
+            it.gprev = J->pair_grad(i, j - 1);
+            it.gc = J->pair_grad(j - 1, j);
+          } else {
+            it.prev = J->pair_field(i, j + 1);
+            it.C = J->u_final(2 * j + 1);
+            it.gprev = J->pair_grad(i, j + 1);
+            it.gc = J->pair_grad(j + 1, j);
+          }
+          it.prev_atomic = (d == 2) ? 1 : 0;
+          items.push_back(it);
+          tiles += point_tiles(dd[0], dd[1], dd[2]);
+          bytes += B_COMPOSE_BWD * J->Vc();
+        }
+      }
+    }
+    b.add(ST_COMPOSE_BWD, items, tiles, bytes);
+  }
+  for (int s = maxK - 1; s >= 0; --s) {
+    // recompute u_s where needed
+    if (s >= 1)
+      for (int k = 0; k < s; ++k) add_exp_fwd_step(b, jobs, k, true, s);
+    std::vector<ExpBwdItem> items;
+    int tiles = 0;
+    double bytes = 0;
+    for (Job* J : jobs) {
+      const int K = J->K();
+      if (s >= K) continue;
+      const int* d = J->ldims[J->level];
+      const float scale = std::ldexp(1.f, -K);
+      for (int dir = 0; dir < 2 * (J->N - 1); ++dir) {
+        const int i = dir / 2;
+        const bool fwd = dir % 2 == 0;
+        ExpBwdItem it{};
+        it.tile0 = tiles;
+        it.D = d[0]; it.H = d[1]; it.W = d[2];
+        if (s == 0) {
+          it.src = J->field(J->phi, i);
+          it.a = (fwd ? 1.f : -1.f) * scale;
+        } else {
+          it.src = J->u_step(dir, s);
+          it.a = 1.f;
+        }
+        if (s == K - 1)
+          it.gin = fwd ? J->pair_grad(i, i + 1) : J->pair_grad(i + 1, i);
+        else
+          it.gin = J->pp(dir, (s + 1) % 2);
+        it.gout = J->pp(dir, s % 2);
+        it.zero_in = (s < K - 1) ? 1 : 0;
+        if (s == 0 && fwd && J->p.alpha_ss > 0.f) {
+          it.reg_w = std::ldexp(1.f, K) * J->p.alpha_ss / (float)(J->N - 1);
+          it.reg_loss_w = J->p.alpha_ss / (float)(J->N - 1);
+        }
+        it.js = J->js;
+        items.push_back(it);
+        tiles += point_tiles(d[0], d[1], d[2]);
+        bytes += B_EXP_BWD * J->Vc();
+      }
+    }
+    b.add(ST_EXP_BWD, items, tiles, bytes);
+  }
+  {
+    std::vector<AdamItem> items;
+    int tiles = 0;
+    double bytes = 0;
+    for (Job* J : jobs) {
+      const size_t V = J->Vc();
+      for (int i = 0; i < J->N - 1; ++i) {
+        AdamItem it{};
+        it.tile0 = tiles;
+        it.n = (int)V;
+        it.phi = J->field(J->phi, i);
+        it.g0f = J->pp(2 * i, 0);
+        it.g0b = J->pp(2 * i + 1, 0);
+        it.m = J->field(J->mbuf, i);
+        it.v = J->field(J->vbuf, i);
+        it.scale = std::ldexp(1.f, -J->K());
+        it.mode = J->grad_mode ? 1 : 0;
+        it.gout = J->grad_mode ? J->grad_out + (size_t)i * 3 * V : nullptr;
+        it.gscale = J->grad_scale;
+        it.js = J->js;
+        items.push_back(it);
+        tiles += elem_tiles(V);
+        bytes += B_ADAM * V;
+      }
+    }
+    b.add(ST_ADAM, items, tiles, bytes);
+  }
+}
+
+}  // namespace
+
+std::unique_ptr<Plan> build_plan(const std::vector<Job*>& jobs, PlanScope scope) {
+  auto plan = std::make_unique<Plan>();
+  Builder b{plan.get()};
+  if (jobs.empty()) return plan;
+  const int window = jobs[0]->p.window, metric = jobs[0]->p.metric;
+  for (Job* J : jobs)
+    if (J->p.window != window || J->p.metric != metric)
+      fail(MUSTER_E_INVALID, "jobs batched together must share window and metric");
+  if (scope == PLAN_ITERATION || scope == PLAN_FORWARD || scope == PLAN_LOSS_FWD) add_forward(b, jobs);
+  if (scope == PLAN_ITERATION || scope == PLAN_LOSS_FWD) {
+    int tiles, zc;
+    double vox;
+    auto items = sim_items(jobs, tiles, vox, zc);
+    b.add(ST_SIM_STATS, items, tiles, B_SIM_STATS * vox, window, metric, zc);
+  }
+  if (scope == PLAN_ITERATION || scope == PLAN_LOSS_BWD) add_backward(b, jobs);
+  if (scope == PLAN_ITERATION) {
+    std::vector<JobState*> st;
+    for (Job* J : jobs) st.push_back(J->js);
+    b.add(ST_FINISH, st, (int)st.size(), 0.0);
+  }
+  return plan;
+}
+
+Plan::~Plan() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+}
+
+void Plan::upload(Ctx* ctx, hipStream_t s) {
+  if (blob.empty()) return;
+  dev.alloc(ctx, blob.size());
+  MUSTER_HIP(hipMemcpyAsync(dev.p, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
+  MUSTER_HIP(hipStreamSynchronize(s));
+}
+
+static int kclass(StageKind k) {
+  switch (k) {
+    case ST_EXP_FWD: return MUSTER_K_EXP_FWD;
+    case ST_COMPOSE_FWD: return MUSTER_K_COMPOSE_FWD;
+    case ST_SIM_STATS: return MUSTER_K_SIM_STATS;
+    case ST_SIM_GRAD: return MUSTER_K_SIM_GRAD;
+    case ST_COMPOSE_BWD: return MUSTER_K_COMPOSE_BWD;
+    case ST_EXP_BWD: return MUSTER_K_EXP_BWD;
+    case ST_ADAM: return MUSTER_K_ADAM;
+    case ST_FINISH: return MUSTER_K_FINISH;
+  }
+  return MUSTER_K_FINISH;
+}
+
+static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipStream_t s) {
+  const void* p = base + st.off;
+  switch (st.kind) {
+    case ST_EXP_FWD: return launch_exp_fwd((const ExpFwdItem*)p, st.n_items, st.n_tiles, s);
+    case ST_COMPOSE_FWD: return launch_compose_fwd((const ComposeItem*)p, st.n_items, st.n_tiles, s);
+    case ST_SIM_STATS:
+      return launch_sim_stats((const SimItem*)p, st.n_items, st.n_tiles, st.zc, st.window, st.metric, s);
+    case ST_SIM_GRAD:
+      return launch_sim_grad((const SimItem*)p, st.n_items, st.n_tiles, st.zc, st.window, s);
+    case ST_COMPOSE_BWD:
+      return launch_compose_bwd((const ComposeBwdItem*)p, st.n_items, st.n_tiles, s);
+    case ST_EXP_BWD: return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, s);
+    case ST_ADAM: return launch_adam((const AdamItem*)p, st.n_items, st.n_tiles, s);
+    case ST_FINISH: return launch_finish((JobState* const*)p, st.n_items, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Event pairs of timed launches, resolved at the next synchronisation.
+struct TimedLaunch {
+  hipEvent_t a, b;
+  int k;
+  double bytes;
+};
+static std::mutex g_timing_mu;
+static std::vector<TimedLaunch> g_pending;
+
+static void resolve_timing(Ctx* ctx) {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  for (auto& t : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      ctx->stats.launches[t.k] += 1;
+      ctx->stats.ms[t.k] += ms;
+      ctx->stats.bytes[t.k] += t.bytes;
+    }
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  g_pending.clear();
+}
+
+void Plan::run(Ctx* ctx, hipStream_t s) {
+  const unsigned char* base = dev.as<unsigned char>();
+  for (const Stage& st : stages) {
+    if (ctx->timing) {
+      TimedLaunch t{};
+      t.k = kclass(st.kind);
+      t.bytes = st.bytes;
+      MUSTER_HIP(hipEventCreate(&t.a));
+      MUSTER_HIP(hipEventCreate(&t.b));
+      MUSTER_HIP(hipEventRecord(t.a, s));
+      MUSTER_HIP(launch_stage(st, base, s));
+      MUSTER_HIP(hipEventRecord(t.b, s));
+      std::lock_guard<std::mutex> lk(g_timing_mu);
+      g_pending.push_back(t);
+    } else {
+      MUSTER_HIP(launch_stage(st, base, s));
+    }
+  }
+}
+
+void Plan::capture(Ctx* ctx, hipStream_t s) {
+  const unsigned char* base = dev.as<unsigned char>();
+  MUSTER_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (const Stage& st : stages) {
+    err = launch_stage(st, base, s);
+    if (err != hipSuccess) break;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(s, &g);
+  MUSTER_HIP(err);
+  MUSTER_HIP(e2);
+  graph = g;
+  MUSTER_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  (void)ctx;
+}
+
+void Plan::replay(hipStream_t s) { MUSTER_HIP(hipGraphLaunch(exec, s)); }
+
+// ---------------------------------------------------------------------------
+// batched registration engine (one or many jobs in lockstep)
+// ---------------------------------------------------------------------------
+static void run_level(Ctx* ctx, std::vector<Job*>& jobs, int level, hipStream_t s, bool use_graph) {
+  for (Job* J : jobs) job_begin_level(*J, level, s);
+  const int T = jobs[0]->p.iters[level];
+  if (T <= 0) return;
+  auto plan = build_plan(jobs, PLAN_ITERATION);
+  plan->upload(ctx, s);
+  if (use_graph && !ctx->timing) {
+    plan->capture(ctx, s);
+    for (int t = 0; t < T; ++t) plan->replay(s);
+  } else {
+    for (int t = 0; t < T; ++t) plan->run(ctx, s);
+  }
+  MUSTER_HIP(hipStreamSynchronize(s));
+  if (ctx->timing) resolve_timing(ctx);
+  for (Job* J : jobs) read_state(*J, s);
+}
+
+static void fill_report(Job& J, double t0, muster_report* rep, hipStream_t s) {
+  if (!rep) return;
+  std::vector<double> h(std::max(J.hist_len, 1), 0.0);
+  if (J.hist_len > 0) {
+    MUSTER_HIP(hipMemcpyAsync(h.data(), J.hist, J.hist_len * sizeof(double), hipMemcpyDeviceToHost, s));
+    MUSTER_HIP(hipStreamSynchronize(s));
+  }
+  rep->status = J.host_state->nonfinite ? MUSTER_E_NONFINITE : MUSTER_OK;
+  rep->iterations = J.hist_len;
+  rep->loss_first = J.hist_len > 0 ? h[0] : 0.0;
+  rep->loss_last = J.hist_len > 0 ? h[J.hist_len - 1] : 0.0;
+  rep->seconds = now_seconds() - t0;
+  rep->queue_seconds = 0.0;
+  rep->footprint_bytes = J.footprint;
+}
+
+static void register_jobs(Ctx* ctx, hipStream_t caller, std::vector<std::unique_ptr<Job>>& owned,
+                          muster_report* reports) {
+  const double t0 = now_seconds();
+  hipStream_t s = ctx->ws;
+  hipEvent_t ev;
+  MUSTER_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  MUSTER_HIP(hipEventRecord(ev, caller));
+  MUSTER_HIP(hipStreamWaitEvent(s, ev, 0));
+  (void)hipEventDestroy(ev);
+  std::vector<Job*> jobs;
+  for (auto& j : owned) jobs.push_back(j.get());
+  const muster_params& p = jobs[0]->p;
+  for (int l = 0; l < p.levels; ++l) run_level(ctx, jobs, l, s, p.use_graph != 0);
+  for (Job* J : jobs) job_final_outputs(*J, s);
+  bool bad = false;
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    fill_report(*jobs[k], t0, reports ? &reports[k] : nullptr, s);
+    if (jobs[k]->host_state->nonfinite) bad = true;
+  }
+  if (bad) fail(MUSTER_E_NONFINITE, "the loss of a job became non-finite");
+}
+
+// ---------------------------------------------------------------------------
+// serving
+// ---------------------------------------------------------------------------
+void Server::loop() {
+  hipStream_t s = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(mu);
+    stop = true;
+    return;
+  }
+  std::unique_ptr<Plan> plan;
+  std::vector<std::pair<uint64_t, int>> sig;
+  auto finish = [&](std::shared_ptr<Ticket>& t, int state, muster_status st, const std::string& err) {
+    if (t->rt) {
+      t->report.footprint_bytes = t->rt->footprint;
+      t->rt.reset();
+    }
+    t->state = state;
+    t->status = st;
+    t->err = err;
+    t->t_done = now_seconds();
+    t->report.status = st;
+    t->report.seconds = t->t_done - t->t_submit;
+    t->report.queue_seconds = (t->t_admit > 0 ? t->t_admit : t->t_done) - t->t_submit;
+    t->report.iterations = t->total_iter;
+  };
+  for (;;) {
+    std::vector<std::shared_ptr<Ticket>> admit;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stop || !queue.empty() || !resident.empty(); });
+      if (stop) break;
+      // cancellations
+      for (auto it = queue.begin(); it != queue.end();) {
+        if ((*it)->cancel) {
+          finish(*it, 4, MUSTER_E_CANCELLED, "cancelled");
+          it = queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      for (auto it = resident.begin(); it != resident.end();) {
+        if ((*it)->cancel) {
+          finish(*it, 4, MUSTER_E_CANCELLED, "cancelled");
+          it = resident.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      // admission by footprint, first come first served
+      uint64_t pending = 0;
+      while (!queue.empty()) {
+        auto& t = queue.front();
+        const uint64_t fp = job_footprint(t->job.N, t->job.dims, t->job.params);
+        if (!ctx->arena.fits(pending + fp)) break;
+        if (!resident.empty() || !admit.empty()) {
+          // jobs batched together must share window and metric
+          const muster_params& a = resident.empty() ? admit[0]->job.params : resident[0]->job.params;
+          if (a.window != t->job.params.window || a.metric != t->job.params.metric ||
+              a.K != t->job.params.K)
+            break;
+        }
+        pending += fp;
+        admit.push_back(t);
+        queue.pop_front();
+      }
+      done_cv.notify_all();
+    }
+    for (auto& t : admit) {
+      try {
+        t->rt = make_job(ctx, t->job);
+        job_begin_level(*t->rt, 0, s);
+        t->t_admit = now_seconds();
+        std::lock_guard<std::mutex> lk(mu);
+        t->state = 1;
+        resident.push_back(t);
+      } catch (const Error& e) {
+        std::lock_guard<std::mutex> lk(mu);
+        finish(t, 3, e.st, e.msg);
+        if (e.st == MUSTER_E_DEVICE) ctx->poisoned = true;
+        done_cv.notify_all();
+      }
+    }
+    std::vector<std::shared_ptr<Ticket>> res;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      res = resident;
+    }
+    if (res.empty()) continue;
+    try {
+      // skip jobs whose current level has no steps
+      std::vector<Job*> jobs;
+      std::vector<std::pair<uint64_t, int>> nsig;
+      for (auto& t : res) {
+        jobs.push_back(t->rt.get());
+        nsig.push_back({t->id, t->rt->level});
+      }
+      if (nsig != sig || !plan) {
+        plan = build_plan(jobs, PLAN_ITERATION);
+        plan->upload(ctx, s);
+        sig = nsig;
+      }
+      bool any_steps = false;
+      for (auto& t : res)
+        if (t->job.params.iters[t->rt->level] > 0) any_steps = true;
+      if (any_steps) plan->run(ctx, s);
+      for (auto& t : res)
+        MUSTER_HIP(hipMemcpyAsync(t->rt->host_state, t->rt->js, sizeof(JobState),
+                                  hipMemcpyDeviceToHost, s));
+      MUSTER_HIP(hipStreamSynchronize(s));
+      std::vector<std::shared_ptr<Ticket>> done;
+      for (auto& t : res) {
+        Job& J = *t->rt;
+        const int T = t->job.params.iters[J.level];
+        if (T > 0) {
+          t->level_iter++;
+          t->total_iter++;
+        }
+        if (J.host_state->nonfinite) {
+          done.push_back(t);
+          continue;
+        }
+        if (t->level_iter >= T) {
+          if (J.level + 1 < J.p.levels) {
+            job_begin_level(J, J.level + 1, s);
+            t->level_iter = 0;
+          } else {
+            job_final_outputs(J, s);
+            fill_report(J, t->t_submit, &t->report, s);
+            done.push_back(t);
+          }
+        }
+      }
+      if (!done.empty()) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& t : done) {
+          const bool nf = t->rt && t->rt->host_state->nonfinite;
+          finish(t, nf ? 3 : 2, nf ? MUSTER_E_NONFINITE : MUSTER_OK,
+                 nf ? "the loss became non-finite" : "");
+          resident.erase(std::remove(resident.begin(), resident.end(), t), resident.end());
+        }
+        done_cv.notify_all();
+      }
+    } catch (const Error& e) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (e.st == MUSTER_E_DEVICE) ctx->poisoned = true;
+      for (auto& t : resident) finish(t, 3, e.st, e.msg);
+      resident.clear();
+      plan.reset();
+      done_cv.notify_all();
+    }
+  }
+  // shut down: fail what is left
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& t : queue) finish(t, 4, MUSTER_E_CANCELLED, "server stopped");
+    for (auto& t : resident) finish(t, 4, MUSTER_E_CANCELLED, "server stopped");
+    queue.clear();
+    resident.clear();
+    done_cv.notify_all();
+  }
+  plan.reset();
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+}
+
+}  // namespace muster
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace muster;
+
+struct muster_ctx {
+  Ctx* c;
+};
+
+struct muster_saved {
+  muster_ctx* ctx;
+  std::unique_ptr<Job> job;
+  bool used = false;
+};
+
+static Ctx* C(muster_ctx* h) { return h ? h->c : nullptr; }
+
+#define NEED(cond, ...) \
+  do {                  \
+    if (!(cond)) fail(MUSTER_E_INVALID, __VA_ARGS__); \
+  } while (0)
+
+namespace {
+
+struct StepCall {
+  Ctx* ctx;
+  hipStream_t s;
+  std::vector<unsigned char> blob;
+  template <class Item>
+  size_t add(const Item& it) {
+    size_t off = (blob.size() + 63) & ~(size_t)63;
+    blob.resize(off + sizeof(Item));
+    std::memcpy(blob.data() + off, &it, sizeof(Item));
+    return off;
+  }
+  const unsigned char* dev() const { return (const unsigned char*)ctx->step_items; }
+  void upload() {
+    NEED(blob.size() <= ctx->step_items_bytes, "too many steps for one call");
+    if (!blob.empty())
+      MUSTER_HIP(hipMemcpyAsync(ctx->step_items, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
+  }
+};
+
+void check_dims(const int dims[3], int min_edge) {
+  NEED(dims, "dims is NULL");
+  uint64_t V = 1;
+  for (int d = 0; d < 3; ++d) {
+    NEED(dims[d] >= min_edge, "dims[%d] = %d must be at least %d", d, dims[d], min_edge);
+    V *= (uint64_t)dims[d];
+  }
+  NEED(V * 3 < (uint64_t)INT32_MAX, "volume too large");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* muster_last_error(void) { return g_err.c_str(); }
+const char* muster_version(void) { return "muster-mi355x 0.1.0 (gfx950)"; }
+
+muster_status muster_ctx_create(int device, uint64_t hbm_budget, muster_ctx** out) {
+  return guard(nullptr, [&] {
+    NEED(out, "out is NULL");
+    int n = 0;
+    MUSTER_HIP(hipGetDeviceCount(&n));
+    NEED(device >= 0 && device < n, "device %d out of range (%d devices)", device, n);
+    MUSTER_HIP(hipSetDevice(device));
+    auto c = std::make_unique<Ctx>(hbm_budget);
+    c->device = device;
+    MUSTER_HIP(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking));
+    c->step_items_bytes = 1 << 20;
+    c->step_items = c->arena.try_alloc(c->step_items_bytes);
+    c->step_acc = (double*)c->arena.try_alloc(64 * sizeof(double));
+    NEED(c->step_items && c->step_acc, "could not allocate context buffers");
+    *out = new muster_ctx{c.release()};
+  });
+}
+
+muster_status muster_ctx_destroy(muster_ctx* h) {
+  if (!h) return MUSTER_OK;
+  Ctx* c = h->c;
+  if (c->server) {
+    {
+      std::lock_guard<std::mutex> lk(c->server->mu);
+      c->server->stop = true;
+    }
+    c->server->cv.notify_all();
+    if (c->server->th.joinable()) c->server->th.join();
+    c->server.reset();
+  }
+  (void)hipSetDevice(c->device);
+  if (c->ws) {
+    (void)hipStreamSynchronize(c->ws);
+    (void)hipStreamDestroy(c->ws);
+  }
+  if (c->step_items) c->arena.release(c->step_items);
+  if (c->step_acc) c->arena.release(c->step_acc);
+  delete c;
+  delete h;
+  return MUSTER_OK;
+}
+
+muster_status muster_params_default(muster_params* p) {
+  return guard(nullptr, [&] {
+    NEED(p, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->levels = 1;
+    p->iters[0] = 100;
+    p->K = 7;
+    p->window = 5;
+    p->metric = MUSTER_METRIC_LNCC;
+    p->alpha_ss = 1.0f;
+    p->lr = 0.1f;
+    p->warmup = 0.2f;
+    p->beta1 = 0.9f;
+    p->beta2 = 0.999f;
+    p->eps = 1e-8f;
+    p->exp_mode = MUSTER_EXP_STORE;
+    p->use_graph = 1;
+  });
+}
+
+muster_status muster_footprint(int N, const int dims[3], const muster_params* p, uint64_t* bytes) {
+  return guard(nullptr, [&] {
+    NEED(p && bytes, "NULL argument");
+    validate_problem(N, dims, *p, nullptr);
+    *bytes = job_footprint(N, dims, *p);
+  });
+}
+
+muster_status muster_register(muster_ctx* h, void* stream, int N, const int dims[3],
+                              const float* images_dev, const double* times_host,
+                              const muster_params* params, float* svf_out_dev,
+                              float* pairs_out_dev, muster_report* report) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx, "ctx is NULL");
+    NEED(params, "params is NULL");
+    NEED(images_dev && svf_out_dev, "images and svf_out must not be NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    muster_job jd{};
+    jd.N = N;
+    if (dims) std::memcpy(jd.dims, dims, sizeof jd.dims);
+    jd.images_dev = images_dev;
+    jd.times_host = times_host;
+    jd.svf_out_dev = svf_out_dev;
+    jd.pairs_out_dev = pairs_out_dev;
+    jd.params = *params;
+    NEED(dims, "dims is NULL");
+    std::vector<std::unique_ptr<Job>> jobs;
+    jobs.push_back(make_job(ctx, jd));
+    register_jobs(ctx, (hipStream_t)stream, jobs, report);
+  });
+}
+
+muster_status muster_register_batch(muster_ctx* h, void* stream, int n_jobs, const muster_job* jobs,
+                                    muster_report* reports) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && jobs && n_jobs > 0, "bad arguments");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const muster_params& p0 = jobs[0].params;
+    for (int k = 0; k < n_jobs; ++k) {
+      const muster_params& p = jobs[k].params;
+      NEED(jobs[k].svf_out_dev, "job %d: svf_out is NULL", k);
+      bool same = p.levels == p0.levels && p.K == p0.K && p.window == p0.window &&
+                  p.metric == p0.metric;
+      for (int l = 0; same && l < p.levels; ++l) same = p.iters[l] == p0.iters[l];
+      NEED(same, "job %d: batched jobs must share levels, iters, K, window and metric", k);
+    }
+    std::vector<std::unique_ptr<Job>> owned;
+    for (int k = 0; k < n_jobs; ++k) owned.push_back(make_job(ctx, jobs[k]));
+    register_jobs(ctx, (hipStream_t)stream, owned, reports);
+  });
+}
+
+muster_status muster_server_start(muster_ctx* h, int max_queue) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx, "ctx is NULL");
+    NEED(max_queue > 0, "max_queue must be positive");
+    NEED(!ctx->server, "server already running");
+    ctx->server = std::make_unique<Server>(ctx, max_queue);
+    Server* sv = ctx->server.get();
+    sv->th = std::thread([sv] { sv->loop(); });
+  });
+}
+
+muster_status muster_submit(muster_ctx* h, const muster_job* job, uint64_t* ticket) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && job && ticket, "NULL argument");
+    NEED(ctx->server, "server not started");
+    validate_problem(job->N, job->dims, job->params, job->times_host);
+    NEED(job->images_dev && job->svf_out_dev, "images and svf_out must not be NULL");
+    const uint64_t fp = job_footprint(job->N, job->dims, job->params);
+    NEED(ctx->arena.budget() == 0 || fp <= ctx->arena.budget(),
+         "job footprint %llu exceeds the context budget", (unsigned long long)fp);
+    Server& sv = *ctx->server;
+    std::lock_guard<std::mutex> lk(sv.mu);
+    if ((int)sv.queue.size() >= sv.max_queue) fail(MUSTER_E_BUSY, "serving queue is full");
+    auto t = std::make_shared<Ticket>();
+    t->id = sv.next_id++;
+    t->job = *job;
+    t->t_submit = now_seconds();
+    sv.queue.push_back(t);
+    sv.all[t->id] = t;
+    *ticket = t->id;
+    sv.cv.notify_all();
+  });
+}
+
+muster_status muster_poll(muster_ctx* h, uint64_t ticket, int* state) {
+  Ctx* ctx = C(h);
+  return guard(nullptr, [&] {
+    NEED(ctx && ctx->server && state, "bad arguments");
+    Server& sv = *ctx->server;
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.all.find(ticket);
+    NEED(it != sv.all.end(), "unknown ticket %llu", (unsigned long long)ticket);
+    *state = it->second->state;
+  });
+}
+
+muster_status muster_wait(muster_ctx* h, uint64_t ticket, muster_report* report) {
+  Ctx* ctx = C(h);
+  muster_status st = MUSTER_OK;
+  const muster_status g = guard(nullptr, [&] {
+    NEED(ctx && ctx->server, "server not started");
+    Server& sv = *ctx->server;
+    std::unique_lock<std::mutex> lk(sv.mu);
+    auto it = sv.all.find(ticket);
+    NEED(it != sv.all.end(), "unknown ticket %llu", (unsigned long long)ticket);
+    auto t = it->second;
+    sv.done_cv.wait(lk, [&] { return t->state >= 2 || sv.stop; });
+    if (t->state < 2) fail(MUSTER_E_CANCELLED, "server stopped");
+    if (report) *report = t->report;
+    st = t->status;
+    if (st != MUSTER_OK) set_error("%s", t->err.c_str());
+    sv.all.erase(it);
+  });
+  if (g != MUSTER_OK) return g;
+  if (st != MUSTER_OK) {
+    // keep the job's error text for the caller
+    return st;
+  }
+  return MUSTER_OK;
+}
+
+muster_status muster_cancel(muster_ctx* h, uint64_t ticket) {
+  Ctx* ctx = C(h);
+  return guard(nullptr, [&] {
+    NEED(ctx && ctx->server, "server not started");
+    Server& sv = *ctx->server;
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.all.find(ticket);
+    NEED(it != sv.all.end(), "unknown ticket %llu", (unsigned long long)ticket);
+    it->second->cancel = true;
+    sv.cv.notify_all();
+  });
+}
+
+muster_status muster_server_stats(muster_ctx* h, int* resident, int* queued, uint64_t* bytes) {
+  Ctx* ctx = C(h);
+  return guard(nullptr, [&] {
+    NEED(ctx && ctx->server, "server not started");
+    Server& sv = *ctx->server;
+    std::lock_guard<std::mutex> lk(sv.mu);
+    if (resident) *resident = (int)sv.resident.size();
+    if (queued) *queued = (int)sv.queue.size();
+    if (bytes) *bytes = ctx->arena.used();
+  });
+}
+
+// ---- autograd ---------------------------------------------------------------
+
+muster_status muster_loss_forward(muster_ctx* h, void* stream, int N, const int dims[3],
+                                  const float* images_dev, const float* svf_dev,
+                                  const muster_params* params, double* loss_host,
+                                  muster_saved** saved) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && params && images_dev && svf_dev && loss_host && saved, "NULL argument");
+    NEED(dims, "dims is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = (hipStream_t)stream;
+    muster_job jd{};
+    jd.N = N;
+    std::memcpy(jd.dims, dims, sizeof jd.dims);
+    jd.images_dev = images_dev;
+    jd.params = *params;
+    jd.params.levels = 1;
+    jd.params.iters[0] = 0;
+    auto job = make_job(ctx, jd);
+    Job& J = *job;
+    J.grad_mode = true;
+    J.phi = const_cast<float*>(svf_dev);
+    job_begin_level(J, 0, s);
+    std::vector<Job*> one{&J};
+    auto plan = build_plan(one, PLAN_LOSS_FWD);
+    plan->upload(ctx, s);
+    plan->run(ctx, s);
+    const size_t V = J.Vc();
+    for (int i = 0; i < N - 1; ++i)
+      MUSTER_HIP(launch_reg(GridDims{dims[0], dims[1], dims[2]}, svf_dev + (size_t)i * 3 * V,
+                            &J.js->loss_reg, nullptr, s));
+    read_state(J, s);
+    if (ctx->timing) resolve_timing(ctx);
+    *loss_host = J.host_state->loss_sim + (double)params->alpha_ss / (N - 1) * J.host_state->loss_reg;
+    auto* sv = new muster_saved;
+    sv->ctx = h;
+    sv->job = std::move(job);
+    *saved = sv;
+  });
+}
+
+muster_status muster_loss_backward(muster_ctx* h, void* stream, muster_saved* saved,
+                                   double grad_out, float* grad_svf_dev) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && saved && grad_svf_dev, "NULL argument");
+    NEED(!saved->used, "saved state was already used by a backward pass");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = (hipStream_t)stream;
+    Job& J = *saved->job;
+    J.grad_out = grad_svf_dev;
+    J.grad_scale = (float)grad_out;
+    std::vector<Job*> one{&J};
+    auto plan = build_plan(one, PLAN_LOSS_BWD);
+    plan->upload(ctx, s);
+    plan->run(ctx, s);
+    MUSTER_HIP(hipStreamSynchronize(s));
+    if (ctx->timing) resolve_timing(ctx);
+    saved->used = true;
+  });
+}
+
+muster_status muster_saved_free(muster_saved* saved) {
+  if (!saved) return MUSTER_OK;
+  if (saved->ctx) (void)hipSetDevice(saved->ctx->c->device);
+  delete saved;
+  return MUSTER_OK;
+}
+
+// ---- single steps -------------------------------------------------------------
+
+
+muster_status muster_exp(muster_ctx* h, void* stream, const int dims[3], int K, int sign,
+                         const float* svf, float* disp, float* steps) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && svf && disp, "NULL argument");
+    check_dims(dims, 2);
+    NEED(K >= 1 && K <= 20, "K must be in 1..20");
+    NEED(sign == 1 || sign == -1, "sign must be +1 or -1");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2];
+    DevMem tmp;
+    if (!steps) tmp.alloc(ctx, 2 * 3 * V * sizeof(float));
+    auto buf = [&](int k) -> float* {  // u_k, k in 1..K-1
+      if (steps) return steps + (size_t)(k - 1) * 3 * V;
+      return tmp.as<float>() + (size_t)((k - 1) % 2) * 3 * V;
+    };
+    const int tiles = point_tiles(dims[0], dims[1], dims[2]);
+    std::vector<size_t> offs;
+    for (int s = 0; s < K; ++s) {
+      ExpFwdItem it{};
+      it.tile0 = 0;
+      it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+      it.src = s == 0 ? svf : buf(s);
+      it.a = s == 0 ? (float)sign * std::ldexp(1.f, -K) : 1.f;
+      it.dst = s == K - 1 ? disp : buf(s + 1);
+      offs.push_back(sc.add(it));
+    }
+    sc.upload();
+    for (int s = 0; s < K; ++s)
+      MUSTER_HIP(launch_exp_fwd((const ExpFwdItem*)(sc.dev() + offs[s]), 1, tiles, sc.s));
+    if (steps)
+      MUSTER_HIP(hipMemcpyAsync(steps + (size_t)(K - 1) * 3 * V, disp, 3 * V * sizeof(float),
+                                hipMemcpyDeviceToDevice, sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
+muster_status muster_exp_bwd(muster_ctx* h, void* stream, const int dims[3], int K, int sign,
+                             const float* svf, const float* grad_disp, float* grad_svf, int mode) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && svf && grad_disp && grad_svf, "NULL argument");
+    check_dims(dims, 2);
+    NEED(K >= 1 && K <= 20, "K must be in 1..20");
+    NEED(sign == 1 || sign == -1, "sign must be +1 or -1");
+    NEED(mode == MUSTER_EXP_STORE || mode == MUSTER_EXP_RECOMPUTE, "bad mode");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2];
+    const size_t F = 3 * V;
+    const int nstore = mode == MUSTER_EXP_STORE ? std::max(K - 1, 0) : 2;
+    DevMem us, pp, zero;
+    us.alloc(ctx, std::max<size_t>(nstore, 1) * F * sizeof(float));
+    pp.alloc(ctx, 2 * F * sizeof(float));
+    zero.alloc(ctx, F * sizeof(float));
+    MUSTER_HIP(launch_fill(pp.as<float>(), (int64_t)(2 * F), 0.f, sc.s));
+    MUSTER_HIP(launch_fill(zero.as<float>(), (int64_t)F, 0.f, sc.s));
+    const float a0 = (float)sign * std::ldexp(1.f, -K);
+    auto ustore = [&](int k) { return us.as<float>() + (size_t)(k - 1) * F; };        // store: u_k
+    auto uscr = [&](int k) { return us.as<float>() + (size_t)((k - 1) % 2) * F; };    // recompute
+    const int tiles = point_tiles(dims[0], dims[1], dims[2]);
+    struct L { int kind; size_t off; };
+    std::vector<L> seq;
+    auto fwd_step = [&](int k, float* src, float* dst) {
+      ExpFwdItem it{};
+      it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+      it.src = k == 0 ? svf : src;
+      it.a = k == 0 ? a0 : 1.f;
+      it.dst = dst;
+      seq.push_back({0, sc.add(it)});
+    };
+    if (mode == MUSTER_EXP_STORE)
+      for (int k = 0; k < K - 1; ++k) fwd_step(k, k == 0 ? nullptr : ustore(k), ustore(k + 1));
+    for (int s = K - 1; s >= 0; --s) {
+      const float* us_src;
+      if (s == 0) {
+        us_src = svf;
+      } else if (mode == MUSTER_EXP_STORE) {
+        us_src = ustore(s);
+      } else {
+        for (int k = 0; k < s; ++k) fwd_step(k, k == 0 ? nullptr : uscr(k), uscr(k + 1));
+        us_src = uscr(s);
+      }
+      ExpBwdItem it{};
+      it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+      it.src = us_src;
+      it.a = s == 0 ? a0 : 1.f;
+      it.gin = s == K - 1 ? const_cast<float*>(grad_disp) : pp.as<float>() + (size_t)((s + 1) % 2) * F;
+      it.gout = pp.as<float>() + (size_t)(s % 2) * F;
+      it.zero_in = s < K - 1 ? 1 : 0;
+      seq.push_back({1, sc.add(it)});
+    }
+    AdamItem ai{};
+    ai.n = (int)V;
+    ai.g0f = pp.as<float>();
+    ai.g0b = zero.as<float>();
+    ai.gout = grad_svf;
+    ai.scale = a0;
+    ai.gscale = 1.f;
+    ai.mode = 1;
+    seq.push_back({2, sc.add(ai)});
+    sc.upload();
+    for (auto& l : seq) {
+      const unsigned char* p = sc.dev() + l.off;
+      if (l.kind == 0) MUSTER_HIP(launch_exp_fwd((const ExpFwdItem*)p, 1, tiles, sc.s));
+      if (l.kind == 1) MUSTER_HIP(launch_exp_bwd((const ExpBwdItem*)p, 1, tiles, sc.s));
+      if (l.kind == 2) MUSTER_HIP(launch_adam((const AdamItem*)p, 1, elem_tiles(V), sc.s));
+    }
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
+muster_status muster_compose(muster_ctx* h, void* stream, const int dims[3], const float* U_prev,
+                             const float* Cf, float* out) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && U_prev && Cf && out, "NULL argument");
+    check_dims(dims, 2);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    ComposeItem it{};
+    it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.prev = U_prev;
+    it.C = Cf;
+    it.out = out;
+    const size_t off = sc.add(it);
+    sc.upload();
+    MUSTER_HIP(launch_compose_fwd((const ComposeItem*)(sc.dev() + off), 1,
+                                  point_tiles(dims[0], dims[1], dims[2]), sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
+muster_status muster_compose_bwd(muster_ctx* h, void* stream, const int dims[3], const float* U_prev,
+                                 const float* Cf, const float* G, float* G_prev, float* G_C) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && U_prev && Cf && G && G_prev && G_C, "NULL argument");
+    check_dims(dims, 2);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    ComposeBwdItem it{};
+    it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.g = G;
+    it.prev = U_prev;
+    it.C = Cf;
+    it.gprev = G_prev;
+    it.gc = G_C;
+    it.prev_atomic = 1;
+    const size_t off = sc.add(it);
+    sc.upload();
+    MUSTER_HIP(launch_compose_bwd((const ComposeBwdItem*)(sc.dev() + off), 1,
+                                  point_tiles(dims[0], dims[1], dims[2]), sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
+muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int window, int metric,
+                         const float* F, const float* I, const float* U, double* sim_host,
+                         float* grad_U) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && F && I && U && sim_host, "NULL argument");
+    NEED(window == 3 || window == 5 || window == 7, "window must be 3, 5 or 7");
+    NEED(metric == MUSTER_METRIC_LNCC || metric == MUSTER_METRIC_SILNCC, "unknown metric");
+    check_dims(dims, window);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2];
+    DevMem coef;
+    if (grad_U) coef.alloc(ctx, 3 * V * sizeof(float));
+    const int r = (window - 1) / 2;
+    const int zc = std::min(32, dims[0]);
+    SimItem it{};
+    it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.F = F;
+    it.I = I;
+    it.U = U;
+    it.coef = grad_U ? coef.as<float>() : nullptr;
+    it.gU = grad_U;
+    it.inv_nr = 1.0 / ((double)(dims[0] - 2 * r) * (dims[1] - 2 * r) * (dims[2] - 2 * r));
+    it.js = nullptr;
+    it.sim_out = ctx->step_acc;
+    const size_t off = sc.add(it);
+    sc.upload();
+    MUSTER_HIP(hipMemsetAsync(ctx->step_acc, 0, sizeof(double), sc.s));
+    const int tiles = stat_tiles(dims[0], dims[1], dims[2], zc);
+    MUSTER_HIP(launch_sim_stats((const SimItem*)(sc.dev() + off), 1, tiles, zc, window, metric, sc.s));
+    if (grad_U)
+      MUSTER_HIP(launch_sim_grad((const SimItem*)(sc.dev() + off), 1, tiles, zc, window, sc.s));
+    MUSTER_HIP(hipMemcpyAsync(sim_host, ctx->step_acc, sizeof(double), hipMemcpyDeviceToHost, sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
+muster_status muster_adam(muster_ctx* h, void* stream, int64_t n, float* x, const float* g, float* m,
+                          float* v, int t, float lr, float beta1, float beta2, float eps) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && x && g && m && v, "NULL argument");
+    NEED(n >= 0 && t >= 1, "need n >= 0 and t >= 1");
+    NEED(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f, "bad Adam constants");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = (hipStream_t)stream;
+    MUSTER_HIP(launch_adam_flat(n, x, g, m, v, t, lr, beta1, beta2, eps, s));
+    MUSTER_HIP(hipStreamSynchronize(s));
+  });
+}
+
+muster_status muster_reg(muster_ctx* h, void* stream, const int dims[3], const float* phi,
+                         double* reg_host, float* grad) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && phi && reg_host, "NULL argument");
+    check_dims(dims, 2);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = (hipStream_t)stream;
+    MUSTER_HIP(hipMemsetAsync(ctx->step_acc, 0, sizeof(double), s));
+    MUSTER_HIP(launch_reg(GridDims{dims[0], dims[1], dims[2]}, phi, ctx->step_acc, grad, s));
+    MUSTER_HIP(hipMemcpyAsync(reg_host, ctx->step_acc, sizeof(double), hipMemcpyDeviceToHost, s));
+    MUSTER_HIP(hipStreamSynchronize(s));
+  });
+}
+
+muster_status muster_pool2(muster_ctx* h, void* stream, const int dims[3], const float* src,
+                           float* dst) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && src && dst, "NULL argument");
+    check_dims(dims, 2);
+    NEED(dims[0] % 2 == 0 && dims[1] % 2 == 0 && dims[2] % 2 == 0, "dims must be even");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    PoolItem it{};
+    it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.src = src;
+    it.dst = dst;
+    const size_t off = sc.add(it);
+    sc.upload();
+    const size_t n = (size_t)(dims[0] / 2) * (dims[1] / 2) * (dims[2] / 2);
+    MUSTER_HIP(launch_pool2((const PoolItem*)(sc.dev() + off), 1, elem_tiles(n), sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
+muster_status muster_upsample2(muster_ctx* h, void* stream, const int dims[3], const float* src,
+                               float* dst) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && src && dst, "NULL argument");
+    check_dims(dims, 2);
+    NEED((uint64_t)dims[0] * dims[1] * dims[2] * 8 * 3 < (uint64_t)INT32_MAX, "volume too large");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    UpItem it{};
+    it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.src = src;
+    it.dst = dst;
+    const size_t off = sc.add(it);
+    sc.upload();
+    const size_t n = (size_t)dims[0] * dims[1] * dims[2] * 8;
+    MUSTER_HIP(launch_upsample2((const UpItem*)(sc.dev() + off), 1, elem_tiles(n), sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
+// ---- measurement ----------------------------------------------------------------
+
+muster_status muster_set_kernel_timing(muster_ctx* h, int enable) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx, "ctx is NULL");
+    ctx->timing = enable != 0;
+  });
+}
+
+muster_status muster_kernel_stats(muster_ctx* h, int64_t launches[MUSTER_K_COUNT],
+                                  double ms[MUSTER_K_COUNT], double bytes[MUSTER_K_COUNT]) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx, "ctx is NULL");
+    resolve_timing(ctx);
+    for (int k = 0; k < MUSTER_K_COUNT; ++k) {
+      if (launches) launches[k] = ctx->stats.launches[k];
+      if (ms) ms[k] = ctx->stats.ms[k];
+      if (bytes) bytes[k] = ctx->stats.bytes[k];
+    }
+  });
+}
+
+muster_status muster_kernel_stats_reset(muster_ctx* h) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx, "ctx is NULL");
+    resolve_timing(ctx);
+    ctx->stats = KernelStats{};
+  });
+}
+
+const char* muster_kernel_name(int k) {
+  static const char* names[MUSTER_K_COUNT] = {"exp_fwd", "compose_fwd", "sim_stats", "sim_grad",
+                                              "compose_bwd", "exp_bwd", "adam", "finish",
+                                              "pool2", "upsample2"};
+  if (k < 0 || k >= MUSTER_K_COUNT) return "";
+  return names[k];
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+// Host runtime of libmuster: context, device arena, registration jobs and the
+// launch plans that turn one optimisation iteration of many jobs into a
+// fixed sequence of batched kernel launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/muster.h"
+#include "muster_internal.h"
+
+namespace muster {
+
+void set_error(const char* fmt, ...);
+
+// Thrown inside the library only; converted to a status at the ABI.
+struct Error {
+  muster_status st;
+  std::string msg;
+};
+[[noreturn]] void fail(muster_status st, const char* fmt, ...);
+
+#define MUSTER_HIP(expr)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      ::muster::fail(MUSTER_E_DEVICE, "%s failed: %s (%s:%d)", #expr,                 \
+                     hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+class Arena {
+ public:
+  explicit Arena(uint64_t budget) : budget_(budget) {}
+  // Returns nullptr (no throw) when the budget or the device is full.
+  void* try_alloc(size_t bytes);
+  void release(void* p);
+  uint64_t used() const { return used_; }
+  uint64_t budget() const { return budget_; }
+  bool fits(uint64_t bytes) const { return budget_ == 0 || used_ + bytes <= budget_; }
+
+ private:
+  std::mutex mu_;
+  uint64_t budget_;
+  uint64_t used_ = 0;
+  std::map<void*, size_t> live_;
+};
+
+struct KernelStats {
+  int64_t launches[MUSTER_K_COUNT] = {};
+  double ms[MUSTER_K_COUNT] = {};
+  double bytes[MUSTER_K_COUNT] = {};
+};
+
+struct Server;
+
+struct Ctx {
+  int device = 0;
+  Arena arena;
+  hipStream_t ws = nullptr;          // work stream (capturable)
+  bool poisoned = false;
+  bool timing = false;
+  KernelStats stats;
+  std::mutex mu;                     // serialises API calls that use ws
+  void* step_items = nullptr;        // device buffer for single-step item tables
+  size_t step_items_bytes = 0;
+  double* step_acc = nullptr;        // device doubles for single-step results
+  std::unique_ptr<Server> server;
+  explicit Ctx(uint64_t budget) : arena(budget) {}
+};
+
+// Device allocation owned through the context's arena.
+struct DevMem {
+  Ctx* ctx = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() { reset(); }
+  void reset() {
+    if (p && ctx) ctx->arena.release(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(Ctx* c, size_t n);
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// One registration job: buffers sized for its finest grid and reused, with
+// the level's own stride, at coarser levels.
+struct Job {
+  Ctx* ctx = nullptr;
+  int N = 0;
+  int dims[3] = {0, 0, 0};
+  muster_params p{};
+  const float* images_fine = nullptr;
+  const float* svf_init = nullptr;
+  float* svf_out = nullptr;
+  float* pairs_out = nullptr;
+  bool grad_mode = false;            // autograd: phi is the caller's, Adam writes a gradient
+  float* grad_out = nullptr;
+  float grad_scale = 1.f;
+
+  int level = 0;                     // current pyramid level (0 = coarsest)
+  int ldims[MUSTER_MAX_LEVELS][3];
+  std::vector<int> deep_slot;        // N*N -> slot of |i-j| >= 2 pairs, -1 otherwise
+
+  DevMem m_phi, m_m, m_v, m_us, m_deep, m_gpair, m_pp, m_coef, m_img, m_state, m_hist;
+  float* phi = nullptr;              // may alias the caller's field in grad_mode
+  float* mbuf = nullptr;
+  float* vbuf = nullptr;
+  JobState* js = nullptr;
+  double* hist = nullptr;
+  int hist_len = 0;
+  std::vector<float*> level_images;  // per level: [N][V_l]
+  JobState* host_state = nullptr;    // pinned
+  uint64_t footprint = 0;
+
+  ~Job();
+  size_t V(int l) const { return (size_t)ldims[l][0] * ldims[l][1] * ldims[l][2]; }
+  size_t Vc() const { return V(level); }
+  int K() const { return p.K; }
+  float* field(float* base, size_t idx) const { return base + idx * 3 * Vc(); }
+  float* us_field(int dir, int slot) const;     // see runtime.cpp
+  float* u_step(int dir, int s) const;          // u_s for s in 1..K (store or recompute layout)
+  float* u_final(int dir) const { return u_step(dir, p.K); }
+  float* pair_field(int i, int j) const;        // U[j->i]
+  float* pair_grad(int i, int j) const;
+  float* pp(int dir, int k) const { return field(m_pp.as<float>(), (size_t)dir * 2 + k); }
+  float* coef(int i, int j) const;
+  const float* image(int i) const { return level_images[level] + (size_t)i * Vc(); }
+};
+
+uint64_t job_footprint(int N, const int dims[3], const muster_params& p);
+void validate_params(const muster_params& p);
+void validate_problem(int N, const int dims[3], const muster_params& p, const double* times);
+std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& j);
+void job_begin_level(Job& job, int level, hipStream_t s);   // pyramid, init/upsample, zero state
+void job_final_outputs(Job& job, hipStream_t s);           // final forward + copies to the caller
+
+// A launch plan: one iteration (or a forward pass) of a set of jobs.
+enum StageKind {
+  ST_EXP_FWD, ST_COMPOSE_FWD, ST_SIM_STATS, ST_SIM_GRAD, ST_COMPOSE_BWD, ST_EXP_BWD, ST_ADAM,
+  ST_FINISH
+};
+
+struct Stage {
+  StageKind kind;
+  size_t off;        // byte offset of the item table in the blob
+  int n_items;
+  int n_tiles;
+  int window = 0, metric = 0, zc = 32;
+  double bytes = 0;  // algorithmic bytes of the launch
+};
+
+struct Plan {
+  std::vector<unsigned char> blob;
+  std::vector<Stage> stages;
+  DevMem dev;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Plan();
+  void upload(Ctx* ctx, hipStream_t s);
+  void run(Ctx* ctx, hipStream_t s);            // eager
+  void capture(Ctx* ctx, hipStream_t s);
+  void replay(hipStream_t s);
+};
+
+enum PlanScope { PLAN_ITERATION, PLAN_FORWARD, PLAN_LOSS_FWD, PLAN_LOSS_BWD };
+std::unique_ptr<Plan> build_plan(const std::vector<Job*>& jobs, PlanScope scope);
+
+// Serving: continuous batching over the context's work stream.
+struct Ticket {
+  uint64_t id;
+  muster_job job;
+  std::unique_ptr<Job> rt;
+  int state = 0;                      // 0 queued, 1 running, 2 done, 3 failed, 4 cancelled
+  muster_status status = MUSTER_OK;
+  std::string err;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int level_iter = 0;                 // steps done at the current level
+  int total_iter = 0;
+  bool cancel = false;
+  muster_report report{};
+};
+
+struct Server {
+  Ctx* ctx;
+  int max_queue;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  bool stop = false;
+  uint64_t next_id = 1;
+  std::deque<std::shared_ptr<Ticket>> queue;
+  std::vector<std::shared_ptr<Ticket>> resident;
+  std::map<uint64_t, std::shared_ptr<Ticket>> all;
+  Server(Ctx* c, int mq) : ctx(c), max_queue(mq) {}
+  void loop();
+};
+
+double now_seconds();
+
+}  // namespace muster

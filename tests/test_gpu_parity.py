@@ -1,0 +1,248 @@
+"""Parity of every HIP kernel with the FP64 oracle, element by element, through
+the C ABI.  Tolerances (FP32 kernels against an FP64 reference): 1e-4 voxel
+maximum displacement error per integration and composition, 1e-3 relative on
+losses and gradients (relative L2, and maximum error within 1e-3 of the largest
+magnitude).  Shapes span several tiles and ragged tails (tiles are 8x8x16
+voxels for the gather kernels and 8x32 columns for the window statistics)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+import torch
+
+from oracle import muster_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2412_14671_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def smooth_field(shape, amp, seed, sigma=3.0):
+    r = rng(seed)
+    f = np.stack([ndi.gaussian_filter(r.standard_normal(shape), sigma, mode="wrap") for _ in range(3)])
+    return (f * (amp / np.abs(f).max())).astype(np.float32)
+
+
+def smooth_image(shape, seed, sigma=2.0, noise=0.02):
+    r = rng(seed)
+    x = ndi.gaussian_filter(r.uniform(0, 1, shape), sigma, mode="wrap")
+    x = (x - x.min()) / (x.max() - x.min())
+    return (x + noise * r.standard_normal(shape)).astype(np.float32)
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def assert_grad_close(got, want, tol=1e-3):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    scale = np.abs(want).max()
+    rel = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+    mx = np.abs(got - want).max() / max(scale, 1e-300)
+    assert rel < tol and mx < tol, f"rel L2 {rel:.2e}, max {mx:.2e}"
+
+
+SHAPES = [(32, 32, 32), (20, 27, 35), (45, 37, 70)]
+
+
+# ---------------------------------------------------------------------------
+# Exp (Alg. 1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("K,sign", [(7, 1), (6, -1)])
+def test_exp_matches_oracle(ctx, shape, K, sign):
+    log(f"exp {shape} K={K} sign={sign}")
+    phi = smooth_field(shape, 2.5, seed=sum(shape) + K)
+    disp, steps = ctx.exp(gpu(phi), K, sign, steps=True)
+    us = O.exp_fwd(sign * phi.astype(np.float64), K)
+    st = host(steps)
+    for s in range(1, K + 1):
+        err = np.abs(st[s - 1] - us[s]).max()
+        assert err < 1e-4, f"step {s}: {err}"
+    assert np.array_equal(host(disp), st[K - 1])
+
+
+def test_exp_of_constant_field_is_exact(ctx):
+    shape = (19, 24, 33)
+    c = np.array([0.75, -1.5, 2.25], np.float32)
+    phi = np.broadcast_to(c[:, None, None, None], (3,) + shape).copy()
+    out = host(ctx.exp(gpu(phi), 7, 1))
+    assert np.array_equal(out, phi.astype(np.float64))
+    out = host(ctx.exp(gpu(phi), 5, -1))
+    assert np.array_equal(out, -phi.astype(np.float64))
+
+
+def test_exp_of_zero_field_is_identity(ctx):
+    out = host(ctx.exp(torch.zeros((3, 17, 18, 19), device=DEV), 7, 1))
+    assert np.all(out == 0.0)
+
+
+@pytest.mark.parametrize("shape,K", [((32, 32, 32), 7), ((20, 27, 35), 4), ((24, 40, 52), 6)])
+@pytest.mark.parametrize("mode", ["store", "recompute"])
+def test_exp_bwd_matches_oracle(ctx, shape, K, mode):
+    log(f"exp_bwd {shape} K={K} {mode}")
+    phi = smooth_field(shape, 2.0, seed=K + 100)
+    G = smooth_field(shape, 1.0, seed=K + 200, sigma=1.0)
+    for sign in (1, -1):
+        got = host(ctx.exp_bwd(gpu(phi), gpu(G), K, sign, mode))
+        us = O.exp_fwd(sign * phi.astype(np.float64), K)
+        want = sign * 2.0 ** -K * O.exp_bwd(us, G.astype(np.float64))
+        assert_grad_close(got, want)
+
+
+def test_exp_bwd_store_and_recompute_agree(ctx):
+    shape = (28, 30, 33)
+    phi = smooth_field(shape, 2.0, seed=7)
+    G = smooth_field(shape, 1.0, seed=8, sigma=1.0)
+    a = host(ctx.exp_bwd(gpu(phi), gpu(G), 7, 1, "store"))
+    b = host(ctx.exp_bwd(gpu(phi), gpu(G), 7, 1, "recompute"))
+    # identical arithmetic; only the order of float atomics differs
+    assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
+
+
+# ---------------------------------------------------------------------------
+# Composition (Eq. cum_deformation)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_compose_matches_oracle(ctx, shape):
+    log(f"compose {shape}")
+    U = smooth_field(shape, 4.0, seed=1)
+    C = smooth_field(shape, 2.0, seed=2)
+    got = host(ctx.compose(gpu(U), gpu(C)))
+    want = O.compose(U.astype(np.float64), C.astype(np.float64))
+    assert np.abs(got - want).max() < 1e-4
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_compose_bwd_matches_oracle(ctx, shape):
+    log(f"compose_bwd {shape}")
+    U = smooth_field(shape, 4.0, seed=3)
+    C = smooth_field(shape, 2.0, seed=4)
+    G = smooth_field(shape, 1.0, seed=5, sigma=1.0)
+    gp = torch.zeros((3,) + shape, device=DEV)
+    gc = torch.zeros((3,) + shape, device=DEV)
+    ctx.compose_bwd(gpu(U), gpu(C), gpu(G), gp, gc)
+    wp, wc = O.compose_bwd(U.astype(np.float64), C.astype(np.float64), G.astype(np.float64))
+    assert_grad_close(host(gp), wp)
+    assert_grad_close(host(gc), wc)
+
+
+# ---------------------------------------------------------------------------
+# Warp + windowed similarity (Sec. 2.6)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (21, 26, 45), (40, 17, 66)])
+@pytest.mark.parametrize("w", [3, 5, 7])
+@pytest.mark.parametrize("metric", ["lncc", "silncc"])
+def test_sim_matches_oracle(ctx, shape, w, metric):
+    log(f"sim {shape} w={w} {metric}")
+    F = smooth_image(shape, seed=w)
+    I = smooth_image(shape, seed=w + 1)
+    U = smooth_field(shape, 2.0, seed=w + 2)
+    val, g = ctx.sim(gpu(F), gpu(I), gpu(U), w, metric, grad=True)
+    m = O.LNCC if metric == "lncc" else O.SILNCC
+    p = O.Params(window=w, metric=m)
+    s_ref, g_ref = O.pair_sim_grad([F.astype(np.float64), I.astype(np.float64)],
+                                   U.astype(np.float64), 0, 1, p)
+    assert abs(val - s_ref) < 1e-3 * abs(s_ref)
+    assert_grad_close(host(g), g_ref)
+
+
+def test_sim_of_identical_images_is_zero(ctx):
+    shape = (30, 34, 38)
+    F = smooth_image(shape, seed=3)
+    zero = torch.zeros((3,) + shape, device=DEV)
+    v = ctx.sim(gpu(F), gpu(F), zero, 5, "lncc")
+    assert abs(v) < 1e-5
+    v = ctx.sim(gpu(F), gpu(2 * F + 1), zero, 5, "silncc")
+    assert abs(v) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Regulariser, Adam, pyramid
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (21, 30, 47)])
+def test_reg_matches_oracle(ctx, shape):
+    phi = smooth_field(shape, 1.5, seed=9, sigma=1.5)
+    val, g = ctx.reg(gpu(phi), grad=True)
+    assert abs(val - O.reg_ss(phi.astype(np.float64))) < 1e-5 * O.reg_ss(phi.astype(np.float64))
+    assert_grad_close(host(g), O.reg_ss_grad(phi.astype(np.float64)))
+
+
+def test_adam_matches_oracle(ctx):
+    r = rng(3)
+    n = 10_001
+    x0 = r.standard_normal(n).astype(np.float32)
+    x, m, v = gpu(x0), torch.zeros(n, device=DEV), torch.zeros(n, device=DEV)
+    xr, mr, vr = x0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in range(1, 8):
+        g = (r.standard_normal(n) * 1e-3).astype(np.float32)
+        lr = O.lr_schedule(t, 7, 0.1)
+        ctx.adam(x, gpu(g), m, v, t, lr)
+        xr, mr, vr = O.adam_step(xr, g.astype(np.float64), mr, vr, t, lr)
+    assert np.abs(host(x) - xr).max() < 1e-5
+
+
+def test_pool2_and_upsample2_match_oracle(ctx):
+    img = smooth_image((34, 40, 22), seed=4)
+    got = host(ctx.pool2(gpu(img)))
+    assert np.abs(got - O.pool2(img.astype(np.float64))).max() < 1e-6
+    phi = smooth_field((9, 14, 11), 1.0, seed=5, sigma=1.5)
+    got = host(ctx.upsample2(gpu(phi)))
+    assert np.abs(got - O.upsample2(phi.astype(np.float64))).max() < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# The whole loss and its gradient (Sec. 2.2 loss with Eq. reg_sum)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", [
+    dict(shape=(32, 32, 32), N=3, K=7, w=5, metric="lncc"),
+    dict(shape=(24, 30, 36), N=4, K=5, w=3, metric="silncc"),
+    dict(shape=(20, 22, 40), N=5, K=4, w=7, metric="lncc"),
+    dict(shape=(18, 18, 18), N=2, K=6, w=5, metric="silncc"),
+])
+@pytest.mark.parametrize("mode", ["store", "recompute"])
+def test_loss_and_gradient_match_oracle(ctx, case, mode):
+    from paper_2412_14671_amd import MusterLoss, MusterParams
+    log(f"loss {case} {mode}")
+    shape, N = case["shape"], case["N"]
+    imgs = np.stack([smooth_image(shape, seed=10 + k) for k in range(N)])
+    phis = np.stack([smooth_field(shape, 1.5, seed=20 + k) for k in range(N - 1)])
+    svf = gpu(phis).requires_grad_(True)
+    params = MusterParams(K=case["K"], window=case["w"], metric=case["metric"], alpha_ss=0.8,
+                          exp_mode=mode)
+    loss = MusterLoss.apply(svf, gpu(imgs), params, ctx)
+    loss.backward()
+    p = O.Params(K=case["K"], window=case["w"],
+                 metric=O.LNCC if case["metric"] == "lncc" else O.SILNCC, alpha_ss=0.8)
+    L_ref, g_ref, _ = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
+    assert abs(float(loss) - L_ref) < 1e-3 * abs(L_ref)
+    assert_grad_close(host(svf.grad), np.stack(g_ref))
