@@ -1,0 +1,175 @@
+"""End-to-end checks of the registration path on the GPU: one solver iteration
+against the oracle, the whole optimisation against the oracle's final error,
+graph replay against eager launches, batched against alone, the pairwise
+outputs, failure isolation, and the continuous-batching server."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import muster_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2412_14671_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def eu(true, est, roi):
+    d = np.sqrt(((np.asarray(true, np.float64) - np.asarray(est, np.float64)) ** 2).sum(1))
+    return float(d[:, roi].mean())
+
+
+def test_first_solver_step_matches_oracle(ctx):
+    """One Adam step of the solver from phi = 0: the recorded loss is the
+    oracle's L(0), and phi_1 = -lr m^/(sqrt(v^) + eps) with the oracle's
+    gradient (compared where the gradient is not negligible)."""
+    from paper_2412_14671_amd import MusterParams, synth
+    s = synth.phantom_series((24, 28, 32), 4, seed=9)
+    imgs = s.images.to(DEV)
+    params = MusterParams(iters=[1], K=6, window=5, metric="silncc", alpha_ss=1.0, lr=0.05,
+                          use_graph=False)
+    svf, _, rep = ctx.register(imgs, s.times, params)
+    p = O.Params(K=6, window=5, metric=O.SILNCC, alpha_ss=1.0)
+    zero = [np.zeros((3, 24, 28, 32)) for _ in range(3)]
+    L0, grads, _ = O.loss_and_grad(zero, [x.numpy() for x in s.images], p)
+    assert abs(rep["loss_first"] - L0) < 1e-3 * abs(L0)
+    g = np.stack(grads)
+    want = np.zeros_like(g)
+    want, _, _ = O.adam_step(want, g, np.zeros_like(g), np.zeros_like(g), 1,
+                             O.lr_schedule(1, 1, 0.05))
+    got = svf.cpu().numpy().astype(np.float64)
+    big = np.abs(g) > 1e-2 * np.abs(g).max()
+    assert big.mean() > 0.05
+    assert np.abs(got[big] - want[big]).max() < 1e-3 * 0.05
+
+
+def test_config1_registration_matches_oracle_error(ctx):
+    """The 50-step single-level run on the 32^3 blob series reaches the
+    oracle's final registration error (trajectories differ by rounding only)."""
+    from paper_2412_14671_amd import MusterParams, synth
+    gold = json.load(open(os.path.join(HERE, "golden", "config1_oracle.json")))
+    s = synth.config1()
+    params = MusterParams(iters=[50], K=7, window=5, metric="lncc", alpha_ss=1.0, lr=0.1)
+    svf, pairs, rep = ctx.register(s.images.to(DEV), s.times, params, pairs=True)
+    e = eu(s.svf_true.numpy(), svf.cpu().numpy(), s.roi.numpy())
+    log(f"config1: Eu {e:.4f} (oracle {gold['eu_final']:.4f}, zero {gold['eu_zero']:.4f})")
+    assert e < 0.8 * gold["eu_zero"]
+    assert abs(e - gold["eu_final"]) < 1e-3
+    assert abs(rep["loss_first"] - gold["loss"][0]) < 1e-3 * abs(gold["loss"][0])
+    assert abs(rep["loss_last"] - gold["loss"][-1]) < 1e-3 * abs(gold["loss"][-1])
+    # the pair fields returned are the compositions of the returned SVFs
+    f0 = ctx.exp(svf[0].contiguous(), 7, 1)
+    f1 = ctx.exp(svf[1].contiguous(), 7, 1)
+    U02 = ctx.compose(f0, f1)
+    N = 3
+    idx = lambda i, j: i * (N - 1) + (j if j < i else j - 1)  # noqa: E731
+    assert torch.allclose(pairs[idx(0, 1)], f0, atol=1e-6)
+    assert torch.allclose(pairs[idx(0, 2)], U02, atol=1e-5)
+
+
+def test_graph_replay_matches_eager(ctx):
+    from paper_2412_14671_amd import MusterParams, synth
+    s = synth.phantom_series((32, 24, 40), 3, seed=4)
+    imgs = s.images.to(DEV)
+    a, _, ra = ctx.register(imgs, s.times, MusterParams(iters=[4, 6], K=5, window=3,
+                                                         metric="silncc", use_graph=True))
+    b, _, rb = ctx.register(imgs, s.times, MusterParams(iters=[4, 6], K=5, window=3,
+                                                         metric="silncc", use_graph=False))
+    assert torch.allclose(a, b, atol=1e-4)
+    assert abs(ra["loss_last"] - rb["loss_last"]) < 1e-5 * abs(rb["loss_last"])
+
+
+def test_batch_matches_alone(ctx):
+    from paper_2412_14671_amd import MusterParams, synth
+    subjects = [synth.phantom_series((24, 24, 24), 3, seed=31),
+                synth.phantom_series((32, 40, 24), 5, seed=32),
+                synth.phantom_series((16, 24, 32), 2, seed=33)]
+    params = MusterParams(iters=[3, 5], K=5, window=5, metric="silncc", lr=0.1)
+    outs, reps = ctx.register_batch([s.images.to(DEV) for s in subjects],
+                                    [s.times for s in subjects], params)
+    for s, o, r in zip(subjects, outs, reps):
+        alone, _, ra = ctx.register(s.images.to(DEV), s.times, params)
+        assert r["status"] == 0
+        assert torch.allclose(o, alone, atol=1e-4)
+        assert abs(r["loss_last"] - ra["loss_last"]) < 1e-5 * abs(ra["loss_last"])
+
+
+def test_three_level_pyramid_runs_and_improves(ctx):
+    from paper_2412_14671_amd import MusterParams, synth
+    s = synth.phantom_series((48, 48, 48), 3, seed=12)
+    params = MusterParams(iters=[30, 20, 10], K=7, window=5, metric="silncc", lr=0.1)
+    svf, _, rep = ctx.register(s.images.to(DEV), s.times, params)
+    roi = s.roi.numpy()
+    e = eu(s.svf_true.numpy(), svf.cpu().numpy(), roi)
+    e0 = eu(s.svf_true.numpy(), np.zeros(svf.shape), roi)
+    log(f"pyramid: Eu {e:.4f} vs {e0:.4f} at zero; iterations {rep['iterations']}")
+    assert rep["iterations"] == 60
+    assert e < e0
+
+
+def test_nonfinite_input_fails_only_that_job(ctx):
+    from paper_2412_14671_amd import MusterError, MusterParams, synth
+    s = synth.phantom_series((16, 16, 16), 3, seed=2)
+    bad = s.images.clone()
+    bad[1, 3, 4, 5] = float("nan")
+    params = MusterParams(iters=[3], K=4, window=3, metric="silncc")
+    with pytest.raises(MusterError) as ei:
+        ctx.register(bad.to(DEV), s.times, params)
+    assert "E_NONFINITE" in str(ei.value)
+    svf, _, rep = ctx.register(s.images.to(DEV), s.times, params)
+    assert torch.isfinite(svf).all() and rep["status"] == 0
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    from paper_2412_14671_amd import MusterError, MusterParams
+    imgs = torch.zeros((3, 16, 16, 16), device=DEV)
+    with pytest.raises(MusterError, match="E_INVALID"):
+        ctx.register(imgs, [0.0, 2.0, 1.0], MusterParams(iters=[1], window=3))
+    with pytest.raises(MusterError, match="E_INVALID"):
+        ctx.register(imgs, None, MusterParams(iters=[1, 1, 1, 1, 1], window=3))
+    with pytest.raises(MusterError, match="E_INVALID"):
+        ctx.register(imgs[:1], None, MusterParams(iters=[1], window=3))
+
+
+def test_server_results_match_alone(ctx):
+    """Jobs submitted together are admitted, batched with each other and
+    retired between ticks; each result equals the job run alone."""
+    from paper_2412_14671_amd import Context, MusterParams, Server, synth
+    c2 = Context(0)
+    srv = Server(c2)
+    subjects = [synth.phantom_series((24, 24, 24), 3, seed=41),
+                synth.phantom_series((32, 24, 16), 4, seed=42),
+                synth.phantom_series((16, 16, 32), 3, seed=43),
+                synth.phantom_series((24, 32, 24), 2, seed=44)]
+    params = [MusterParams(iters=[4, 6], K=5, window=3, metric="silncc"),
+              MusterParams(iters=[2, 3], K=5, window=3, metric="silncc"),
+              MusterParams(iters=[5], K=5, window=3, metric="silncc"),
+              MusterParams(iters=[1, 2, 3], K=5, window=3, metric="silncc")]
+    imgs = [s.images.to(DEV) for s in subjects]
+    tickets = [srv.submit(im, s.times, p) for im, s, p in zip(imgs, subjects, params)]
+    reps = [srv.wait(tk) for tk, _ in tickets]
+    for (tk, out), im, s, p, r in zip(tickets, imgs, subjects, params, reps):
+        assert r["status"] == 0, r
+        alone, _, ra = ctx.register(im, s.times, p)
+        assert torch.allclose(out, alone, atol=1e-4)
+        assert r["iterations"] == sum(p.iters)
+    st = srv.stats()
+    assert st["resident"] == 0 and st["queued"] == 0
+    c2.close()
