@@ -546,7 +546,7 @@ __device__ __forceinline__ STile stat_tile(int local, int D, int H, int W, int z
 
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__ items, int n_items,
-                                                     int n_tiles, int zc, int metric) {
+                                                     int n_tiles, int metric) {
   constexpr int WN = 2 * R + 1;
   constexpr int PY = ST_Y + 2 * R, PX = ST_X + 2 * R, P1 = PY * PX;
   __shared__ float rF[WN][P1];
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const SimItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
-  const STile tc = stat_tile(tile - it.tile0, D, H, W, zc);
+  const STile tc = stat_tile(tile - it.tile0, D, H, W, it.zc);
   const float* __restrict__ F = it.F;
   const float* __restrict__ I = it.I;
   const float* __restrict__ U = it.U;
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
 //   dSim/dU(y) = dSim/dM(y) * grad I_j(y + U(y)).
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ items, int n_items,
-                                                    int n_tiles, int zc) {
+                                                    int n_tiles) {
   constexpr int WN = 2 * R + 1;
   constexpr int PY = ST_Y + 2 * R, PX = ST_X + 2 * R, P1 = PY * PX;
   __shared__ float ring[3][WN][P1];
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const SimItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
-  const STile tc = stat_tile(tile - it.tile0, D, H, W, zc);
+  const STile tc = stat_tile(tile - it.tile0, D, H, W, it.zc);
   const float* __restrict__ F = it.F;
   const float* __restrict__ I = it.I;
   const float* __restrict__ U = it.U;
@@ -965,25 +965,25 @@ hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_ti
   return hipGetLastError();
 }
 
-hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int zc, int window,
-                            int metric, hipStream_t s) {
+hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,
+                            hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   switch (window) {
-    case 3: hipLaunchKernelGGL(k_sim_stats<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc, metric); break;
-    case 5: hipLaunchKernelGGL(k_sim_stats<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc, metric); break;
-    case 7: hipLaunchKernelGGL(k_sim_stats<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc, metric); break;
+    case 3: hipLaunchKernelGGL(k_sim_stats<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, metric); break;
+    case 5: hipLaunchKernelGGL(k_sim_stats<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, metric); break;
+    case 7: hipLaunchKernelGGL(k_sim_stats<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, metric); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int zc, int window,
+hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window,
                            hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   switch (window) {
-    case 3: hipLaunchKernelGGL(k_sim_grad<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc); break;
-    case 5: hipLaunchKernelGGL(k_sim_grad<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc); break;
-    case 7: hipLaunchKernelGGL(k_sim_grad<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, zc); break;
+    case 3: hipLaunchKernelGGL(k_sim_grad<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 5: hipLaunchKernelGGL(k_sim_grad<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 7: hipLaunchKernelGGL(k_sim_grad<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -89,6 +89,8 @@ struct ComposeBwdItem {
 struct SimItem {
   int tile0;
   int D, H, W;
+  int zc;        // z-chunk length of this item's tiles
+  int pad;
   const float* F;
   const float* I;
   const float* U;
@@ -153,9 +155,9 @@ hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles
 hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
                               hipStream_t s);
-hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int zc, int window,
-                            int metric, hipStream_t s);
-hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int zc, int window,
+hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,
+                            hipStream_t s);
+hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window,
                            hipStream_t s);
 hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s);

@@ -489,16 +489,15 @@ void add_forward(Builder& b, const std::vector<Job*>& jobs) {
   }
 }
 
-std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int& tiles, double& vox, int& zc) {
+std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int& tiles, double& vox) {
   std::vector<SimItem> items;
   tiles = 0;
   vox = 0;
-  zc = 32;
-  for (Job* J : jobs) zc = std::min(zc, sim_zc(*J));
   for (Job* J : jobs) {
     const int N = J->N;
     const int* d = J->ldims[J->level];
     const int r = (J->p.window - 1) / 2;
+    const int zc = sim_zc(*J);
     const double nr = (double)(d[0] - 2 * r) * (d[1] - 2 * r) * (d[2] - 2 * r);
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) {
@@ -506,6 +505,7 @@ std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int& tiles, double
         SimItem it{};
         it.tile0 = tiles;
         it.D = d[0]; it.H = d[1]; it.W = d[2];
+        it.zc = zc;
         it.F = J->image(i);
         it.I = J->image(j);
         it.U = J->pair_field(i, j);
@@ -530,10 +530,10 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
   }
   const int window = jobs[0]->p.window;
   {
-    int tiles, zc;
+    int tiles;
     double vox;
-    auto items = sim_items(jobs, tiles, vox, zc);
-    b.add(ST_SIM_GRAD, items, tiles, B_SIM_GRAD * vox, window, 0, zc);
+    auto items = sim_items(jobs, tiles, vox);
+    b.add(ST_SIM_GRAD, items, tiles, B_SIM_GRAD * vox, window, 0);
   }
   for (int d = maxN - 1; d >= 2; --d) {
     std::vector<ComposeBwdItem> items;
@@ -654,10 +654,10 @@ std::unique_ptr<Plan> build_plan(const std::vector<Job*>& jobs, PlanScope scope)
       fail(MUSTER_E_INVALID, "jobs batched together must share window and metric");
   if (scope == PLAN_ITERATION || scope == PLAN_FORWARD || scope == PLAN_LOSS_FWD) add_forward(b, jobs);
   if (scope == PLAN_ITERATION || scope == PLAN_LOSS_FWD) {
-    int tiles, zc;
+    int tiles;
     double vox;
-    auto items = sim_items(jobs, tiles, vox, zc);
-    b.add(ST_SIM_STATS, items, tiles, B_SIM_STATS * vox, window, metric, zc);
+    auto items = sim_items(jobs, tiles, vox);
+    b.add(ST_SIM_STATS, items, tiles, B_SIM_STATS * vox, window, metric);
   }
   if (scope == PLAN_ITERATION || scope == PLAN_LOSS_BWD) add_backward(b, jobs);
   if (scope == PLAN_ITERATION) {
@@ -700,9 +700,9 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_EXP_FWD: return launch_exp_fwd((const ExpFwdItem*)p, st.n_items, st.n_tiles, s);
     case ST_COMPOSE_FWD: return launch_compose_fwd((const ComposeItem*)p, st.n_items, st.n_tiles, s);
     case ST_SIM_STATS:
-      return launch_sim_stats((const SimItem*)p, st.n_items, st.n_tiles, st.zc, st.window, st.metric, s);
+      return launch_sim_stats((const SimItem*)p, st.n_items, st.n_tiles, st.window, st.metric, s);
     case ST_SIM_GRAD:
-      return launch_sim_grad((const SimItem*)p, st.n_items, st.n_tiles, st.zc, st.window, s);
+      return launch_sim_grad((const SimItem*)p, st.n_items, st.n_tiles, st.window, s);
     case ST_COMPOSE_BWD:
       return launch_compose_bwd((const ComposeBwdItem*)p, st.n_items, st.n_tiles, s);
     case ST_EXP_BWD: return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, s);
@@ -1525,6 +1525,7 @@ muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int win
     const int zc = std::min(32, dims[0]);
     SimItem it{};
     it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.zc = zc;
     it.F = F;
     it.I = I;
     it.U = U;
@@ -1537,9 +1538,9 @@ muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int win
     sc.upload();
     MUSTER_HIP(hipMemsetAsync(ctx->step_acc, 0, sizeof(double), sc.s));
     const int tiles = stat_tiles(dims[0], dims[1], dims[2], zc);
-    MUSTER_HIP(launch_sim_stats((const SimItem*)(sc.dev() + off), 1, tiles, zc, window, metric, sc.s));
+    MUSTER_HIP(launch_sim_stats((const SimItem*)(sc.dev() + off), 1, tiles, window, metric, sc.s));
     if (grad_U)
-      MUSTER_HIP(launch_sim_grad((const SimItem*)(sc.dev() + off), 1, tiles, zc, window, sc.s));
+      MUSTER_HIP(launch_sim_grad((const SimItem*)(sc.dev() + off), 1, tiles, window, sc.s));
     MUSTER_HIP(hipMemcpyAsync(sim_host, ctx->step_acc, sizeof(double), hipMemcpyDeviceToHost, sc.s));
     MUSTER_HIP(hipStreamSynchronize(sc.s));
   });
