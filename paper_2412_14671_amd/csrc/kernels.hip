@@ -26,6 +26,19 @@ namespace muster {
 
 namespace {
 
+// Field pointers are used through the global address space so that loads,
+// stores and atomics compile to global (not flat) memory instructions.
+#define GLOBAL __attribute__((address_space(1)))
+typedef GLOBAL float gfloat;
+typedef GLOBAL const float cgfloat;
+typedef float float2a __attribute__((ext_vector_type(2), aligned(4)));
+
+__device__ __forceinline__ const cgfloat* gp(const float* p) { return (const cgfloat*)p; }
+__device__ __forceinline__ gfloat* gp(float* p) { return (gfloat*)p; }
+__device__ __forceinline__ void gadd(gfloat* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr float EPS_LNCC = 1e-10f;
 constexpr float EPS_SILNCC = 1e-6f;
 
@@ -87,17 +100,22 @@ __device__ __forceinline__ Ax axis_pos(float q, int n) {
 
 __device__ __forceinline__ float lerp_(float a, float b, float t) { return fmaf(t, b - a, a); }
 
-// Corner order: bit 0 = x+1, bit 1 = y+1, bit 2 = z+1.
-__device__ __forceinline__ void load8(const float* __restrict__ f, int base, int sy, int sz,
+// Two consecutive floats in one 8-byte load (dword alignment suffices for
+// multi-dword global loads); halves the address work of a gather.
+__device__ __forceinline__ float2a ld2(const cgfloat* p) { return *(const GLOBAL float2a*)p; }
+
+// The 8 corners of a cell.  Corner order: bit 0 = x+1, bit 1 = y+1,
+// bit 2 = z+1; the x pairs are adjacent in memory and come in one load.
+__device__ __forceinline__ void load8(const cgfloat* __restrict__ f, int base, int sy, int sz,
                                       float (&v)[8]) {
-  v[0] = f[base];
-  v[1] = f[base + 1];
-  v[2] = f[base + sy];
-  v[3] = f[base + sy + 1];
-  v[4] = f[base + sz];
-  v[5] = f[base + sz + 1];
-  v[6] = f[base + sz + sy];
-  v[7] = f[base + sz + sy + 1];
+  const float2a a = ld2(f + base);
+  const float2a b = ld2(f + base + sy);
+  const float2a c = ld2(f + base + sz);
+  const float2a d = ld2(f + base + sz + sy);
+  v[0] = a.x; v[1] = a.y;
+  v[2] = b.x; v[3] = b.y;
+  v[4] = c.x; v[5] = c.y;
+  v[6] = d.x; v[7] = d.y;
 }
 
 __device__ __forceinline__ float tri_val(const float (&v)[8], float tz, float ty, float tx) {
@@ -200,7 +218,7 @@ __device__ __forceinline__ BBox block_bbox(int lo[3], int hi[3], int* sbb) {
 // differences, mean per (component, axis) over its valid set.  Returns the
 // gradient of R with respect to f(p) and adds f's own forward-difference terms
 // to *val.
-__device__ __forceinline__ float reg_point(const float* __restrict__ f, int z, int y, int x, int D,
+__device__ __forceinline__ float reg_point(const cgfloat* __restrict__ f, int z, int y, int x, int D,
                                            int H, int W, float inv_mz, float inv_my, float inv_mx,
                                            double* val) {
   const int HW = H * W;
@@ -226,8 +244,8 @@ __global__ __launch_bounds__(BLOCK) void k_exp_fwd(const ExpFwdItem* __restrict_
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const PTile tc = point_tile(tile - it.tile0, H, W);
   const float a = it.a;
-  const float* __restrict__ s = it.src;
-  float* __restrict__ d = it.dst;
+  const cgfloat* __restrict__ s = gp(it.src);
+  gfloat* __restrict__ d = gp(it.dst);
   for (int k = threadIdx.x; k < PT_VOX; k += BLOCK) {
     const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
     if (x >= W || y >= H || z >= D) continue;
@@ -257,9 +275,9 @@ __global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __rest
   const ComposeItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const PTile tc = point_tile(tile - it.tile0, H, W);
-  const float* __restrict__ pr = it.prev;
-  const float* __restrict__ C = it.C;
-  float* __restrict__ o = it.out;
+  const cgfloat* __restrict__ pr = gp(it.prev);
+  const cgfloat* __restrict__ C = gp(it.C);
+  gfloat* __restrict__ o = gp(it.out);
   for (int k = threadIdx.x; k < PT_VOX; k += BLOCK) {
     const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
     if (x >= W || y >= H || z >= D) continue;
@@ -314,7 +332,7 @@ __device__ __forceinline__ float block_max(float v, float* sred) {
 }
 
 template <bool OWN>
-__device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], float* __restrict__ out,
+__device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat* __restrict__ out,
                                              int D, int H, int W, int* acc, int* sbb,
                                              float* sred) {
   const int HW = H * W, V = D * HW;
@@ -374,11 +392,11 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], float*
       const int r = i / bb.ex;
       const int ly = r % bb.ey;
       const int lz = r / bb.ey;
-      const int gp = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
+      const int gpos = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int v = acc[c * cells + i];
-        if (v != 0) unsafeAtomicAdd(out + c * V + gp, (float)v * inv);
+        if (v != 0) gadd(out + c * V + gpos, (float)v * inv);
       }
     }
   } else {
@@ -398,12 +416,12 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], float*
         const float g = sv[j].g[c];
         if (g == 0.f) continue;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) unsafeAtomicAdd(out + c * V + base + off[q], w[q] * g);
+        for (int q = 0; q < 8; ++q) gadd(out + c * V + base + off[q], w[q] * g);
       }
       if (OWN) {
         const int po = (sv[j].oz * H + sv[j].oy) * W + sv[j].ox;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) unsafeAtomicAdd(out + c * V + po, sv[j].own[c]);
+        for (int c = 0; c < 3; ++c) gadd(out + c * V + po, sv[j].own[c]);
       }
     }
   }
@@ -424,8 +442,8 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const PTile tc = point_tile(tile - it.tile0, H, W);
   const float a = it.a;
-  const float* __restrict__ s = it.src;
-  float* __restrict__ gin = it.gin;
+  const cgfloat* __restrict__ s = gp(it.src);
+  gfloat* __restrict__ gin = gp(it.gin);
   const bool reg = it.reg_w != 0.f;
   const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
               inv_mx = 1.f / (float)(D * H * (W - 1));
@@ -477,7 +495,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
     sv[j].own[0] = own0; sv[j].own[1] = own1; sv[j].own[2] = own2;
   }
-  scatter_tile<true>(sv, it.gout, D, H, W, acc, sbb, sred);
+  scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sbb, sred);
   if (reg) {
     const double tot = block_sum(rval, red);
     if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot * (double)it.reg_loss_w);
@@ -496,10 +514,10 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
   const ComposeBwdItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const PTile tc = point_tile(tile - it.tile0, H, W);
-  const float* __restrict__ C = it.C;
-  const float* __restrict__ pr = it.prev;
-  const float* __restrict__ G = it.g;
-  float* __restrict__ gp = it.gprev;
+  const cgfloat* __restrict__ C = gp(it.C);
+  const cgfloat* __restrict__ pr = gp(it.prev);
+  const cgfloat* __restrict__ G = gp(it.g);
+  gfloat* __restrict__ gpv = gp(it.gprev);
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
@@ -530,20 +548,20 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
     o1 = fmaf(dy * ay.live, g2, o1);
     o2 = fmaf(dx * ax.live, g2, o2);
     if (it.prev_atomic) {
-      unsafeAtomicAdd(gp + p, o0);
-      unsafeAtomicAdd(gp + V + p, o1);
-      unsafeAtomicAdd(gp + 2 * V + p, o2);
+      gadd(gpv + p, o0);
+      gadd(gpv + V + p, o1);
+      gadd(gpv + 2 * V + p, o2);
     } else {
-      gp[p] += o0;
-      gp[V + p] += o1;
-      gp[2 * V + p] += o2;
+      gpv[p] += o0;
+      gpv[V + p] += o1;
+      gpv[2 * V + p] += o2;
     }
     sv[j].cz = az.i0; sv[j].cy = ay.i0; sv[j].cx = ax.i0;
     sv[j].oz = z; sv[j].oy = y; sv[j].ox = x;
     sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
     sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
   }
-  scatter_tile<false>(sv, it.gc, D, H, W, acc, sbb, sred);
+  scatter_tile<false>(sv, gp(it.gc), D, H, W, acc, sbb, sred);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,10 +605,10 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
   const SimItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const STile tc = stat_tile(tile - it.tile0, D, H, W, it.zc);
-  const float* __restrict__ F = it.F;
-  const float* __restrict__ I = it.I;
-  const float* __restrict__ U = it.U;
-  float* __restrict__ coef = it.coef;
+  const cgfloat* __restrict__ F = gp(it.F);
+  const cgfloat* __restrict__ I = gp(it.I);
+  const cgfloat* __restrict__ U = gp(it.U);
+  gfloat* __restrict__ coef = gp(it.coef);
   const int pm = (min((tc.z0 + tc.z1) / 2, D - 1) * H + min(tc.y0 + ST_Y / 2, H - 1)) * W +
                  min(tc.x0 + ST_X / 2, W - 1);
   const float sF = F[pm], sM = I[pm];
@@ -727,11 +745,11 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
   const SimItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const STile tc = stat_tile(tile - it.tile0, D, H, W, it.zc);
-  const float* __restrict__ F = it.F;
-  const float* __restrict__ I = it.I;
-  const float* __restrict__ U = it.U;
-  const float* __restrict__ coef = it.coef;
-  float* __restrict__ gU = it.gU;
+  const cgfloat* __restrict__ F = gp(it.F);
+  const cgfloat* __restrict__ I = gp(it.I);
+  const cgfloat* __restrict__ U = gp(it.U);
+  const cgfloat* __restrict__ coef = gp(it.coef);
+  gfloat* __restrict__ gU = gp(it.gU);
   const float inv_nr = (float)it.inv_nr;
   const int ty = threadIdx.x / ST_X, tx = threadIdx.x % ST_X;
   const int y = tc.y0 + ty, x = tc.x0 + tx;
@@ -915,7 +933,7 @@ __global__ __launch_bounds__(BLOCK) void k_upsample2(const UpItem* __restrict__ 
     float v[8];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      load8(it.src + c * V, base, W, HW, v);
+      load8(gp(it.src) + c * V, base, W, HW, v);
       it.dst[c * n + q] = 2.f * tri_val(v, az.t, ay.t, ax.t);
     }
   }
@@ -951,7 +969,7 @@ __global__ __launch_bounds__(BLOCK) void k_reg(int D, int H, int W, const float*
     const int x = q % W, y = (q / W) % H, z = q / (W * H);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float g = reg_point(phi + c * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &val);
+      const float g = reg_point(gp(phi) + c * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &val);
       if (grad) grad[c * V + q] = g;
     }
   }
