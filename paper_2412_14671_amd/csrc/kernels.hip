@@ -235,34 +235,121 @@ __device__ __forceinline__ float reg_point(const cgfloat* __restrict__ f, int z,
 }
 
 // ---------------------------------------------------------------------------
+// Point tiles.  A thread owns VPT voxels of an 8x8x16 tile.  Their loads are
+// issued together, component by component across the voxels, so each round
+// trip to memory carries VPT gathers per thread: the gather kernels are bound
+// by memory latency, not by bandwidth or address throughput, so memory-level
+// parallelism is what sets their speed.  Voxels beyond the grid are clamped
+// onto it (their loads stay in bounds) and their results are discarded.
+// ---------------------------------------------------------------------------
+constexpr int VPT = PT_VOX / BLOCK;
+
+struct VoxSet {
+  int p[VPT];           // linear index of the (clamped) voxel
+  int z[VPT], y[VPT], x[VPT];
+  bool ok[VPT];
+};
+
+__device__ __forceinline__ void vox_set(const PTile& tc, int D, int H, int W, VoxSet& vs) {
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int k = threadIdx.x + j * BLOCK;
+    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
+    vs.ok[j] = x < W && y < H && z < D;
+    vs.x[j] = min(x, W - 1);
+    vs.y[j] = min(y, H - 1);
+    vs.z[j] = min(z, D - 1);
+    vs.p[j] = (vs.z[j] * H + vs.y[j]) * W + vs.x[j];
+  }
+}
+
+struct CellSet {
+  int base[VPT];
+  Ax az[VPT], ay[VPT], ax[VPT];
+};
+
+// Displacements (scaled by a) of the owned voxels and the cells they sample.
+__device__ __forceinline__ void load_cells(const cgfloat* __restrict__ u, float a, int D, int H,
+                                           int W, const VoxSet& vs, float (&uu)[VPT][3],
+                                           CellSet& cs) {
+  const int V = D * H * W;
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    uu[j][0] = a * u[vs.p[j]];
+    uu[j][1] = a * u[V + vs.p[j]];
+    uu[j][2] = a * u[2 * V + vs.p[j]];
+  }
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    cs.az[j] = axis_disp(vs.z[j], uu[j][0], D);
+    cs.ay[j] = axis_disp(vs.y[j], uu[j][1], H);
+    cs.ax[j] = axis_disp(vs.x[j], uu[j][2], W);
+    cs.base[j] = (cs.az[j].i0 * H + cs.ay[j].i0) * W + cs.ax[j].i0;
+  }
+}
+
+// Trilinear values of the three components of f at the cells.
+__device__ __forceinline__ void sample_cells(const cgfloat* __restrict__ f, int V, int H, int W,
+                                             const CellSet& cs, float (&out)[VPT][3]) {
+  const int HW = H * W;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float v[VPT][8];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) load8(f + c * V, cs.base[j], W, HW, v[j]);
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) out[j][c] = tri_val(v[j], cs.az[j].t, cs.ay[j].t, cs.ax[j].t);
+  }
+}
+
+// (J^T g) at the cells, J the Jacobian of a * f (rows: components of f,
+// columns: z, y, x; clamped axes contribute nothing).
+__device__ __forceinline__ void jt_cells(const cgfloat* __restrict__ f, float a, int V, int H,
+                                         int W, const CellSet& cs, const float (&g)[VPT][3],
+                                         float (&acc)[VPT][3]) {
+  const int HW = H * W;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float v[VPT][8];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) load8(f + c * V, cs.base[j], W, HW, v[j]);
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      float dz, dy, dx;
+      tri_grad(v[j], cs.az[j].t, cs.ay[j].t, cs.ax[j].t, dz, dy, dx);
+      const float gc = a * g[j][c];
+      acc[j][0] = fmaf(dz * cs.az[j].live, gc, acc[j][0]);
+      acc[j][1] = fmaf(dy * cs.ay[j].live, gc, acc[j][1]);
+      acc[j][2] = fmaf(dx * cs.ax[j].live, gc, acc[j][2]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Exp forward: one squaring u' = u + u o (Omega + u)   (Alg. 1)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_exp_fwd(const ExpFwdItem* __restrict__ items,
                                                    int n_items, int n_tiles) {
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ExpFwdItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
   const PTile tc = point_tile(tile - it.tile0, H, W);
   const float a = it.a;
   const cgfloat* __restrict__ s = gp(it.src);
   gfloat* __restrict__ d = gp(it.dst);
-  for (int k = threadIdx.x; k < PT_VOX; k += BLOCK) {
-    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
-    if (x >= W || y >= H || z >= D) continue;
-    const int p = (z * H + y) * W + x;
-    const float uz = a * s[p], uy = a * s[V + p], ux = a * s[2 * V + p];
-    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
-    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
-    float v[8];
-    load8(s, base, W, HW, v);
-    const float sz = tri_val(v, az.t, ay.t, ax.t);
-    load8(s + V, base, W, HW, v);
-    const float sy = tri_val(v, az.t, ay.t, ax.t);
-    load8(s + 2 * V, base, W, HW, v);
-    const float sx = tri_val(v, az.t, ay.t, ax.t);
-    d[p] = uz + a * sz;
-    d[V + p] = uy + a * sy;
-    d[2 * V + p] = ux + a * sx;
+  VoxSet vs;
+  vox_set(tc, D, H, W, vs);
+  float uu[VPT][3];
+  CellSet cs;
+  load_cells(s, a, D, H, W, vs, uu, cs);
+  float sm[VPT][3];
+  sample_cells(s, V, H, W, cs, sm);
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vs.ok[j]) continue;
+    d[vs.p[j]] = uu[j][0] + a * sm[j][0];
+    d[V + vs.p[j]] = uu[j][1] + a * sm[j][1];
+    d[2 * V + vs.p[j]] = uu[j][2] + a * sm[j][2];
   }
 }
 
@@ -273,28 +360,24 @@ __global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __rest
                                                        int n_items, int n_tiles) {
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ComposeItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
   const PTile tc = point_tile(tile - it.tile0, H, W);
   const cgfloat* __restrict__ pr = gp(it.prev);
   const cgfloat* __restrict__ C = gp(it.C);
   gfloat* __restrict__ o = gp(it.out);
-  for (int k = threadIdx.x; k < PT_VOX; k += BLOCK) {
-    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
-    if (x >= W || y >= H || z >= D) continue;
-    const int p = (z * H + y) * W + x;
-    const float uz = pr[p], uy = pr[V + p], ux = pr[2 * V + p];
-    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
-    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
-    float v[8];
-    load8(C, base, W, HW, v);
-    const float cz = tri_val(v, az.t, ay.t, ax.t);
-    load8(C + V, base, W, HW, v);
-    const float cy = tri_val(v, az.t, ay.t, ax.t);
-    load8(C + 2 * V, base, W, HW, v);
-    const float cx = tri_val(v, az.t, ay.t, ax.t);
-    o[p] = uz + cz;
-    o[V + p] = uy + cy;
-    o[2 * V + p] = ux + cx;
+  VoxSet vs;
+  vox_set(tc, D, H, W, vs);
+  float uu[VPT][3];
+  CellSet cs;
+  load_cells(pr, 1.f, D, H, W, vs, uu, cs);
+  float sm[VPT][3];
+  sample_cells(C, V, H, W, cs, sm);
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vs.ok[j]) continue;
+    o[vs.p[j]] = uu[j][0] + sm[j][0];
+    o[V + vs.p[j]] = uu[j][1] + sm[j][1];
+    o[2 * V + vs.p[j]] = uu[j][2] + sm[j][2];
   }
 }
 
@@ -311,7 +394,6 @@ __global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __rest
 // total weight up to 256 (a 256-fold local compression of the sampling
 // positions) before it could overflow.  Each non-zero bin is then added to the
 // field with one hardware float atomic.
-constexpr int VPT = PT_VOX / BLOCK;
 constexpr float FIX_SCALE = 8388608.0f;  // 2^23
 
 struct ScatterVox {
@@ -439,7 +521,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   __shared__ double red[BLOCK / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ExpBwdItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
   const PTile tc = point_tile(tile - it.tile0, H, W);
   const float a = it.a;
   const cgfloat* __restrict__ s = gp(it.src);
@@ -447,53 +529,49 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   const bool reg = it.reg_w != 0.f;
   const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
               inv_mx = 1.f / (float)(D * H * (W - 1));
+  VoxSet vs;
+  vox_set(tc, D, H, W, vs);
+  float g[VPT][3];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    g[j][0] = gin[vs.p[j]];
+    g[j][1] = gin[V + vs.p[j]];
+    g[j][2] = gin[2 * V + vs.p[j]];
+  }
+  float uu[VPT][3];
+  CellSet cs;
+  load_cells(s, a, D, H, W, vs, uu, cs);
+  float own[VPT][3];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    own[j][0] = g[j][0];
+    own[j][1] = g[j][1];
+    own[j][2] = g[j][2];
+  }
+  jt_cells(s, a, V, H, W, cs, g, own);
   double rval = 0.0;
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     sv[j].cz = -1;
-    const int k = threadIdx.x + j * BLOCK;
-    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
-    if (x >= W || y >= H || z >= D) continue;
-    const int p = (z * H + y) * W + x;
-    const float uz = a * s[p], uy = a * s[V + p], ux = a * s[2 * V + p];
-    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
-    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
-    const float g0 = gin[p], g1 = gin[V + p], g2 = gin[2 * V + p];
-    float own0 = g0, own1 = g1, own2 = g2;
-    float v[8], dz, dy, dx;
-    // row c of the Jacobian of a*src at q, times g_c, added to column terms
-    load8(s, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    own0 = fmaf(a * dz * az.live, g0, own0);
-    own1 = fmaf(a * dy * ay.live, g0, own1);
-    own2 = fmaf(a * dx * ax.live, g0, own2);
-    load8(s + V, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    own0 = fmaf(a * dz * az.live, g1, own0);
-    own1 = fmaf(a * dy * ay.live, g1, own1);
-    own2 = fmaf(a * dx * ax.live, g1, own2);
-    load8(s + 2 * V, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    own0 = fmaf(a * dz * az.live, g2, own0);
-    own1 = fmaf(a * dy * ay.live, g2, own1);
-    own2 = fmaf(a * dx * ax.live, g2, own2);
+    if (!vs.ok[j]) continue;
     if (reg) {
-      own0 = fmaf(it.reg_w, reg_point(s, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own0);
-      own1 = fmaf(it.reg_w, reg_point(s + V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own1);
-      own2 = fmaf(it.reg_w, reg_point(s + 2 * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval),
-                  own2);
+      const int z = vs.z[j], y = vs.y[j], x = vs.x[j];
+      own[j][0] = fmaf(it.reg_w, reg_point(s, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own[j][0]);
+      own[j][1] = fmaf(it.reg_w, reg_point(s + V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own[j][1]);
+      own[j][2] = fmaf(it.reg_w, reg_point(s + 2 * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval),
+                       own[j][2]);
     }
     if (it.zero_in) {
-      gin[p] = 0.f;
-      gin[V + p] = 0.f;
-      gin[2 * V + p] = 0.f;
+      gin[vs.p[j]] = 0.f;
+      gin[V + vs.p[j]] = 0.f;
+      gin[2 * V + vs.p[j]] = 0.f;
     }
-    sv[j].cz = az.i0; sv[j].cy = ay.i0; sv[j].cx = ax.i0;
-    sv[j].oz = z; sv[j].oy = y; sv[j].ox = x;
-    sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
-    sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
-    sv[j].own[0] = own0; sv[j].own[1] = own1; sv[j].own[2] = own2;
+    sv[j].cz = cs.az[j].i0; sv[j].cy = cs.ay[j].i0; sv[j].cx = cs.ax[j].i0;
+    sv[j].oz = vs.z[j]; sv[j].oy = vs.y[j]; sv[j].ox = vs.x[j];
+    sv[j].tz = cs.az[j].t; sv[j].ty = cs.ay[j].t; sv[j].tx = cs.ax[j].t;
+    sv[j].g[0] = g[j][0]; sv[j].g[1] = g[j][1]; sv[j].g[2] = g[j][2];
+    sv[j].own[0] = own[j][0]; sv[j].own[1] = own[j][1]; sv[j].own[2] = own[j][2];
   }
   scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sbb, sred);
   if (reg) {
@@ -512,54 +590,51 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
   __shared__ float sred[BLOCK / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ComposeBwdItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
   const PTile tc = point_tile(tile - it.tile0, H, W);
   const cgfloat* __restrict__ C = gp(it.C);
   const cgfloat* __restrict__ pr = gp(it.prev);
   const cgfloat* __restrict__ G = gp(it.g);
   gfloat* __restrict__ gpv = gp(it.gprev);
+  VoxSet vs;
+  vox_set(tc, D, H, W, vs);
+  float g[VPT][3];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    g[j][0] = G[vs.p[j]];
+    g[j][1] = G[V + vs.p[j]];
+    g[j][2] = G[2 * V + vs.p[j]];
+  }
+  float uu[VPT][3];
+  CellSet cs;
+  load_cells(pr, 1.f, D, H, W, vs, uu, cs);
+  float o[VPT][3];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    o[j][0] = g[j][0];
+    o[j][1] = g[j][1];
+    o[j][2] = g[j][2];
+  }
+  jt_cells(C, 1.f, V, H, W, cs, g, o);
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     sv[j].cz = -1;
-    const int k = threadIdx.x + j * BLOCK;
-    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
-    if (x >= W || y >= H || z >= D) continue;
-    const int p = (z * H + y) * W + x;
-    const float uz = pr[p], uy = pr[V + p], ux = pr[2 * V + p];
-    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
-    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
-    const float g0 = G[p], g1 = G[V + p], g2 = G[2 * V + p];
-    float o0 = g0, o1 = g1, o2 = g2;
-    float v[8], dz, dy, dx;
-    load8(C, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    o0 = fmaf(dz * az.live, g0, o0);
-    o1 = fmaf(dy * ay.live, g0, o1);
-    o2 = fmaf(dx * ax.live, g0, o2);
-    load8(C + V, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    o0 = fmaf(dz * az.live, g1, o0);
-    o1 = fmaf(dy * ay.live, g1, o1);
-    o2 = fmaf(dx * ax.live, g1, o2);
-    load8(C + 2 * V, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    o0 = fmaf(dz * az.live, g2, o0);
-    o1 = fmaf(dy * ay.live, g2, o1);
-    o2 = fmaf(dx * ax.live, g2, o2);
+    if (!vs.ok[j]) continue;
+    const int p = vs.p[j];
     if (it.prev_atomic) {
-      gadd(gpv + p, o0);
-      gadd(gpv + V + p, o1);
-      gadd(gpv + 2 * V + p, o2);
+      gadd(gpv + p, o[j][0]);
+      gadd(gpv + V + p, o[j][1]);
+      gadd(gpv + 2 * V + p, o[j][2]);
     } else {
-      gpv[p] += o0;
-      gpv[V + p] += o1;
-      gpv[2 * V + p] += o2;
+      gpv[p] += o[j][0];
+      gpv[V + p] += o[j][1];
+      gpv[2 * V + p] += o[j][2];
     }
-    sv[j].cz = az.i0; sv[j].cy = ay.i0; sv[j].cx = ax.i0;
-    sv[j].oz = z; sv[j].oy = y; sv[j].ox = x;
-    sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
-    sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
+    sv[j].cz = cs.az[j].i0; sv[j].cy = cs.ay[j].i0; sv[j].cx = cs.ax[j].i0;
+    sv[j].oz = vs.z[j]; sv[j].oy = vs.y[j]; sv[j].ox = vs.x[j];
+    sv[j].tz = cs.az[j].t; sv[j].ty = cs.ay[j].t; sv[j].tx = cs.ax[j].t;
+    sv[j].g[0] = g[j][0]; sv[j].g[1] = g[j][1]; sv[j].g[2] = g[j][2];
   }
   scatter_tile<false>(sv, gp(it.gc), D, H, W, acc, sbb, sred);
 }
