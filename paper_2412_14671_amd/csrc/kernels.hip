@@ -264,7 +264,8 @@ __device__ __forceinline__ void vox_set(const PTile& tc, int D, int H, int W, Vo
 }
 
 struct CellSet {
-  int base[VPT];
+  int base[VPT];        // linear index of the cell's lower corner
+  int l[VPT];           // index of the same corner in the staged LDS box
   Ax az[VPT], ay[VPT], ax[VPT];
 };
 
@@ -288,15 +289,76 @@ __device__ __forceinline__ void load_cells(const cgfloat* __restrict__ u, float 
   }
 }
 
-// Trilinear values of the three components of f at the cells.
+// Bounding box of the sampled cells (and of the owned voxels when own is set).
+__device__ __forceinline__ BBox cells_bbox(const VoxSet& vs, const CellSet& cs, bool own, int* sbb) {
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
+  int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vs.ok[j]) continue;
+    lo[0] = min(lo[0], cs.az[j].i0); hi[0] = max(hi[0], cs.az[j].i0 + 1);
+    lo[1] = min(lo[1], cs.ay[j].i0); hi[1] = max(hi[1], cs.ay[j].i0 + 1);
+    lo[2] = min(lo[2], cs.ax[j].i0); hi[2] = max(hi[2], cs.ax[j].i0 + 1);
+    if (own) {
+      lo[0] = min(lo[0], vs.z[j]); hi[0] = max(hi[0], vs.z[j]);
+      lo[1] = min(lo[1], vs.y[j]); hi[1] = max(hi[1], vs.y[j]);
+      lo[2] = min(lo[2], vs.x[j]); hi[2] = max(hi[2], vs.x[j]);
+    }
+  }
+  return block_bbox(lo, hi, sbb);
+}
+
+// Copies the three planes of f over the box into LDS ([3][cells], x fastest)
+// with coalesced row loads, and sets each voxel's corner index in the box.
+__device__ __forceinline__ void stage_box(const cgfloat* __restrict__ f, int V, int H, int W,
+                                          const BBox& bb, float* lds, const VoxSet& vs,
+                                          CellSet& cs) {
+  const int cells = bb.cells;
+  for (int i = threadIdx.x; i < cells; i += BLOCK) {
+    const int lx = i % bb.ex;
+    const int r = i / bb.ex;
+    const int ly = r % bb.ey;
+    const int lz = r / bb.ey;
+    const int g = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
+    lds[i] = f[g];
+    lds[cells + i] = f[V + g];
+    lds[2 * cells + i] = f[2 * V + g];
+  }
+#pragma unroll
+  for (int j = 0; j < VPT; ++j)
+    cs.l[j] = vs.ok[j] ? ((cs.az[j].i0 - bb.lz) * bb.ey + (cs.ay[j].i0 - bb.ly)) * bb.ex +
+                             (cs.ax[j].i0 - bb.lx)
+                       : 0;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void load8_lds(const float* f, int l, int sy, int sz, float (&v)[8]) {
+  v[0] = f[l];
+  v[1] = f[l + 1];
+  v[2] = f[l + sy];
+  v[3] = f[l + sy + 1];
+  v[4] = f[l + sz];
+  v[5] = f[l + sz + 1];
+  v[6] = f[l + sz + sy];
+  v[7] = f[l + sz + sy + 1];
+}
+
+// Trilinear values of the three components of f at the cells, from the
+// staged box when staged, else from global memory.
 __device__ __forceinline__ void sample_cells(const cgfloat* __restrict__ f, int V, int H, int W,
-                                             const CellSet& cs, float (&out)[VPT][3]) {
+                                             const CellSet& cs, const BBox& bb, const float* lds,
+                                             bool staged, float (&out)[VPT][3]) {
   const int HW = H * W;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     float v[VPT][8];
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) load8(f + c * V, cs.base[j], W, HW, v[j]);
+    for (int j = 0; j < VPT; ++j) {
+      if (staged)
+        load8_lds(lds + c * bb.cells, cs.l[j], bb.ex, bb.ex * bb.ey, v[j]);
+      else
+        load8(f + c * V, cs.base[j], W, HW, v[j]);
+    }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) out[j][c] = tri_val(v[j], cs.az[j].t, cs.ay[j].t, cs.ax[j].t);
   }
@@ -305,14 +367,20 @@ __device__ __forceinline__ void sample_cells(const cgfloat* __restrict__ f, int 
 // (J^T g) at the cells, J the Jacobian of a * f (rows: components of f,
 // columns: z, y, x; clamped axes contribute nothing).
 __device__ __forceinline__ void jt_cells(const cgfloat* __restrict__ f, float a, int V, int H,
-                                         int W, const CellSet& cs, const float (&g)[VPT][3],
+                                         int W, const CellSet& cs, const BBox& bb,
+                                         const float* lds, bool staged, const float (&g)[VPT][3],
                                          float (&acc)[VPT][3]) {
   const int HW = H * W;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     float v[VPT][8];
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) load8(f + c * V, cs.base[j], W, HW, v[j]);
+    for (int j = 0; j < VPT; ++j) {
+      if (staged)
+        load8_lds(lds + c * bb.cells, cs.l[j], bb.ex, bb.ex * bb.ey, v[j]);
+      else
+        load8(f + c * V, cs.base[j], W, HW, v[j]);
+    }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       float dz, dy, dx;
@@ -337,13 +405,18 @@ __global__ __launch_bounds__(BLOCK) void k_exp_fwd(const ExpFwdItem* __restrict_
   const float a = it.a;
   const cgfloat* __restrict__ s = gp(it.src);
   gfloat* __restrict__ d = gp(it.dst);
+  __shared__ float lds[3 * SCATTER_CELLS];
+  __shared__ int sbb[6];
   VoxSet vs;
   vox_set(tc, D, H, W, vs);
   float uu[VPT][3];
   CellSet cs;
   load_cells(s, a, D, H, W, vs, uu, cs);
+  const BBox bb = cells_bbox(vs, cs, false, sbb);
+  const bool staged = bb.cells > 0 && bb.cells <= SCATTER_CELLS;
+  if (staged) stage_box(s, V, H, W, bb, lds, vs, cs);
   float sm[VPT][3];
-  sample_cells(s, V, H, W, cs, sm);
+  sample_cells(s, V, H, W, cs, bb, lds, staged, sm);
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     if (!vs.ok[j]) continue;
@@ -365,13 +438,18 @@ __global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __rest
   const cgfloat* __restrict__ pr = gp(it.prev);
   const cgfloat* __restrict__ C = gp(it.C);
   gfloat* __restrict__ o = gp(it.out);
+  __shared__ float lds[3 * SCATTER_CELLS];
+  __shared__ int sbb[6];
   VoxSet vs;
   vox_set(tc, D, H, W, vs);
   float uu[VPT][3];
   CellSet cs;
   load_cells(pr, 1.f, D, H, W, vs, uu, cs);
+  const BBox bb = cells_bbox(vs, cs, false, sbb);
+  const bool staged = bb.cells > 0 && bb.cells <= SCATTER_CELLS;
+  if (staged) stage_box(C, V, H, W, bb, lds, vs, cs);
   float sm[VPT][3];
-  sample_cells(C, V, H, W, cs, sm);
+  sample_cells(C, V, H, W, cs, bb, lds, staged, sm);
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     if (!vs.ok[j]) continue;
@@ -548,7 +626,14 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     own[j][1] = g[j][1];
     own[j][2] = g[j][2];
   }
-  jt_cells(s, a, V, H, W, cs, g, own);
+  {
+    const BBox bb = cells_bbox(vs, cs, false, sbb);
+    const bool staged = bb.cells > 0 && bb.cells <= SCATTER_CELLS;
+    float* lds = reinterpret_cast<float*>(acc);
+    if (staged) stage_box(s, V, H, W, bb, lds, vs, cs);
+    jt_cells(s, a, V, H, W, cs, bb, lds, staged, g, own);
+    __syncthreads();  // the bins reuse the staging buffer
+  }
   double rval = 0.0;
   ScatterVox sv[VPT];
 #pragma unroll
@@ -615,7 +700,14 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
     o[j][1] = g[j][1];
     o[j][2] = g[j][2];
   }
-  jt_cells(C, 1.f, V, H, W, cs, g, o);
+  {
+    const BBox bb = cells_bbox(vs, cs, false, sbb);
+    const bool staged = bb.cells > 0 && bb.cells <= SCATTER_CELLS;
+    float* lds = reinterpret_cast<float*>(acc);
+    if (staged) stage_box(C, V, H, W, bb, lds, vs, cs);
+    jt_cells(C, 1.f, V, H, W, cs, bb, lds, staged, g, o);
+    __syncthreads();  // the bins reuse the staging buffer
+  }
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
