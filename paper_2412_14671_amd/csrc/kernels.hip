@@ -264,8 +264,7 @@ __device__ __forceinline__ void vox_set(const PTile& tc, int D, int H, int W, Vo
 }
 
 struct CellSet {
-  int base[VPT];        // linear index of the cell's lower corner
-  int l[VPT];           // index of the same corner in the staged LDS box
+  int base[VPT];
   Ax az[VPT], ay[VPT], ax[VPT];
 };
 
@@ -289,76 +288,15 @@ __device__ __forceinline__ void load_cells(const cgfloat* __restrict__ u, float 
   }
 }
 
-// Bounding box of the sampled cells (and of the owned voxels when own is set).
-__device__ __forceinline__ BBox cells_bbox(const VoxSet& vs, const CellSet& cs, bool own, int* sbb) {
-  int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
-  int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) {
-    if (!vs.ok[j]) continue;
-    lo[0] = min(lo[0], cs.az[j].i0); hi[0] = max(hi[0], cs.az[j].i0 + 1);
-    lo[1] = min(lo[1], cs.ay[j].i0); hi[1] = max(hi[1], cs.ay[j].i0 + 1);
-    lo[2] = min(lo[2], cs.ax[j].i0); hi[2] = max(hi[2], cs.ax[j].i0 + 1);
-    if (own) {
-      lo[0] = min(lo[0], vs.z[j]); hi[0] = max(hi[0], vs.z[j]);
-      lo[1] = min(lo[1], vs.y[j]); hi[1] = max(hi[1], vs.y[j]);
-      lo[2] = min(lo[2], vs.x[j]); hi[2] = max(hi[2], vs.x[j]);
-    }
-  }
-  return block_bbox(lo, hi, sbb);
-}
-
-// Copies the three planes of f over the box into LDS ([3][cells], x fastest)
-// with coalesced row loads, and sets each voxel's corner index in the box.
-__device__ __forceinline__ void stage_box(const cgfloat* __restrict__ f, int V, int H, int W,
-                                          const BBox& bb, float* lds, const VoxSet& vs,
-                                          CellSet& cs) {
-  const int cells = bb.cells;
-  for (int i = threadIdx.x; i < cells; i += BLOCK) {
-    const int lx = i % bb.ex;
-    const int r = i / bb.ex;
-    const int ly = r % bb.ey;
-    const int lz = r / bb.ey;
-    const int g = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
-    lds[i] = f[g];
-    lds[cells + i] = f[V + g];
-    lds[2 * cells + i] = f[2 * V + g];
-  }
-#pragma unroll
-  for (int j = 0; j < VPT; ++j)
-    cs.l[j] = vs.ok[j] ? ((cs.az[j].i0 - bb.lz) * bb.ey + (cs.ay[j].i0 - bb.ly)) * bb.ex +
-                             (cs.ax[j].i0 - bb.lx)
-                       : 0;
-  __syncthreads();
-}
-
-__device__ __forceinline__ void load8_lds(const float* f, int l, int sy, int sz, float (&v)[8]) {
-  v[0] = f[l];
-  v[1] = f[l + 1];
-  v[2] = f[l + sy];
-  v[3] = f[l + sy + 1];
-  v[4] = f[l + sz];
-  v[5] = f[l + sz + 1];
-  v[6] = f[l + sz + sy];
-  v[7] = f[l + sz + sy + 1];
-}
-
-// Trilinear values of the three components of f at the cells, from the
-// staged box when staged, else from global memory.
+// Trilinear values of the three components of f at the cells.
 __device__ __forceinline__ void sample_cells(const cgfloat* __restrict__ f, int V, int H, int W,
-                                             const CellSet& cs, const BBox& bb, const float* lds,
-                                             bool staged, float (&out)[VPT][3]) {
+                                             const CellSet& cs, float (&out)[VPT][3]) {
   const int HW = H * W;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     float v[VPT][8];
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      if (staged)
-        load8_lds(lds + c * bb.cells, cs.l[j], bb.ex, bb.ex * bb.ey, v[j]);
-      else
-        load8(f + c * V, cs.base[j], W, HW, v[j]);
-    }
+    for (int j = 0; j < VPT; ++j) load8(f + c * V, cs.base[j], W, HW, v[j]);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) out[j][c] = tri_val(v[j], cs.az[j].t, cs.ay[j].t, cs.ax[j].t);
   }
@@ -367,20 +305,14 @@ __device__ __forceinline__ void sample_cells(const cgfloat* __restrict__ f, int 
 // (J^T g) at the cells, J the Jacobian of a * f (rows: components of f,
 // columns: z, y, x; clamped axes contribute nothing).
 __device__ __forceinline__ void jt_cells(const cgfloat* __restrict__ f, float a, int V, int H,
-                                         int W, const CellSet& cs, const BBox& bb,
-                                         const float* lds, bool staged, const float (&g)[VPT][3],
+                                         int W, const CellSet& cs, const float (&g)[VPT][3],
                                          float (&acc)[VPT][3]) {
   const int HW = H * W;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     float v[VPT][8];
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      if (staged)
-        load8_lds(lds + c * bb.cells, cs.l[j], bb.ex, bb.ex * bb.ey, v[j]);
-      else
-        load8(f + c * V, cs.base[j], W, HW, v[j]);
-    }
+    for (int j = 0; j < VPT; ++j) load8(f + c * V, cs.base[j], W, HW, v[j]);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       float dz, dy, dx;
@@ -405,18 +337,13 @@ __global__ __launch_bounds__(BLOCK) void k_exp_fwd(const ExpFwdItem* __restrict_
   const float a = it.a;
   const cgfloat* __restrict__ s = gp(it.src);
   gfloat* __restrict__ d = gp(it.dst);
-  __shared__ float lds[3 * SCATTER_CELLS];
-  __shared__ int sbb[6];
   VoxSet vs;
   vox_set(tc, D, H, W, vs);
   float uu[VPT][3];
   CellSet cs;
   load_cells(s, a, D, H, W, vs, uu, cs);
-  const BBox bb = cells_bbox(vs, cs, false, sbb);
-  const bool staged = bb.cells > 0 && bb.cells <= SCATTER_CELLS;
-  if (staged) stage_box(s, V, H, W, bb, lds, vs, cs);
   float sm[VPT][3];
-  sample_cells(s, V, H, W, cs, bb, lds, staged, sm);
+  sample_cells(s, V, H, W, cs, sm);
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     if (!vs.ok[j]) continue;
@@ -438,18 +365,13 @@ __global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __rest
   const cgfloat* __restrict__ pr = gp(it.prev);
   const cgfloat* __restrict__ C = gp(it.C);
   gfloat* __restrict__ o = gp(it.out);
-  __shared__ float lds[3 * SCATTER_CELLS];
-  __shared__ int sbb[6];
   VoxSet vs;
   vox_set(tc, D, H, W, vs);
   float uu[VPT][3];
   CellSet cs;
   load_cells(pr, 1.f, D, H, W, vs, uu, cs);
-  const BBox bb = cells_bbox(vs, cs, false, sbb);
-  const bool staged = bb.cells > 0 && bb.cells <= SCATTER_CELLS;
-  if (staged) stage_box(C, V, H, W, bb, lds, vs, cs);
   float sm[VPT][3];
-  sample_cells(C, V, H, W, cs, bb, lds, staged, sm);
+  sample_cells(C, V, H, W, cs, sm);
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     if (!vs.ok[j]) continue;
@@ -599,7 +521,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   __shared__ double red[BLOCK / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ExpBwdItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const PTile tc = point_tile(tile - it.tile0, H, W);
   const float a = it.a;
   const cgfloat* __restrict__ s = gp(it.src);
@@ -607,56 +529,53 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   const bool reg = it.reg_w != 0.f;
   const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
               inv_mx = 1.f / (float)(D * H * (W - 1));
-  VoxSet vs;
-  vox_set(tc, D, H, W, vs);
-  float g[VPT][3];
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) {
-    g[j][0] = gin[vs.p[j]];
-    g[j][1] = gin[V + vs.p[j]];
-    g[j][2] = gin[2 * V + vs.p[j]];
-  }
-  float uu[VPT][3];
-  CellSet cs;
-  load_cells(s, a, D, H, W, vs, uu, cs);
-  float own[VPT][3];
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) {
-    own[j][0] = g[j][0];
-    own[j][1] = g[j][1];
-    own[j][2] = g[j][2];
-  }
-  {
-    const BBox bb = cells_bbox(vs, cs, false, sbb);
-    const bool staged = bb.cells > 0 && bb.cells <= SCATTER_CELLS;
-    float* lds = reinterpret_cast<float*>(acc);
-    if (staged) stage_box(s, V, H, W, bb, lds, vs, cs);
-    jt_cells(s, a, V, H, W, cs, bb, lds, staged, g, own);
-    __syncthreads();  // the bins reuse the staging buffer
-  }
   double rval = 0.0;
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     sv[j].cz = -1;
-    if (!vs.ok[j]) continue;
+    const int k = threadIdx.x + j * BLOCK;
+    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
+    if (x >= W || y >= H || z >= D) continue;
+    const int p = (z * H + y) * W + x;
+    const float uz = a * s[p], uy = a * s[V + p], ux = a * s[2 * V + p];
+    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
+    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+    const float g0 = gin[p], g1 = gin[V + p], g2 = gin[2 * V + p];
+    float own0 = g0, own1 = g1, own2 = g2;
+    float v[8], dz, dy, dx;
+    // row c of the Jacobian of a*src at q, times g_c, added to column terms
+    load8(s, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    own0 = fmaf(a * dz * az.live, g0, own0);
+    own1 = fmaf(a * dy * ay.live, g0, own1);
+    own2 = fmaf(a * dx * ax.live, g0, own2);
+    load8(s + V, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    own0 = fmaf(a * dz * az.live, g1, own0);
+    own1 = fmaf(a * dy * ay.live, g1, own1);
+    own2 = fmaf(a * dx * ax.live, g1, own2);
+    load8(s + 2 * V, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    own0 = fmaf(a * dz * az.live, g2, own0);
+    own1 = fmaf(a * dy * ay.live, g2, own1);
+    own2 = fmaf(a * dx * ax.live, g2, own2);
     if (reg) {
-      const int z = vs.z[j], y = vs.y[j], x = vs.x[j];
-      own[j][0] = fmaf(it.reg_w, reg_point(s, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own[j][0]);
-      own[j][1] = fmaf(it.reg_w, reg_point(s + V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own[j][1]);
-      own[j][2] = fmaf(it.reg_w, reg_point(s + 2 * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval),
-                       own[j][2]);
+      own0 = fmaf(it.reg_w, reg_point(s, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own0);
+      own1 = fmaf(it.reg_w, reg_point(s + V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own1);
+      own2 = fmaf(it.reg_w, reg_point(s + 2 * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval),
+                  own2);
     }
     if (it.zero_in) {
-      gin[vs.p[j]] = 0.f;
-      gin[V + vs.p[j]] = 0.f;
-      gin[2 * V + vs.p[j]] = 0.f;
+      gin[p] = 0.f;
+      gin[V + p] = 0.f;
+      gin[2 * V + p] = 0.f;
     }
-    sv[j].cz = cs.az[j].i0; sv[j].cy = cs.ay[j].i0; sv[j].cx = cs.ax[j].i0;
-    sv[j].oz = vs.z[j]; sv[j].oy = vs.y[j]; sv[j].ox = vs.x[j];
-    sv[j].tz = cs.az[j].t; sv[j].ty = cs.ay[j].t; sv[j].tx = cs.ax[j].t;
-    sv[j].g[0] = g[j][0]; sv[j].g[1] = g[j][1]; sv[j].g[2] = g[j][2];
-    sv[j].own[0] = own[j][0]; sv[j].own[1] = own[j][1]; sv[j].own[2] = own[j][2];
+    sv[j].cz = az.i0; sv[j].cy = ay.i0; sv[j].cx = ax.i0;
+    sv[j].oz = z; sv[j].oy = y; sv[j].ox = x;
+    sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
+    sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
+    sv[j].own[0] = own0; sv[j].own[1] = own1; sv[j].own[2] = own2;
   }
   scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sbb, sred);
   if (reg) {
@@ -675,58 +594,54 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
   __shared__ float sred[BLOCK / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ComposeBwdItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const PTile tc = point_tile(tile - it.tile0, H, W);
   const cgfloat* __restrict__ C = gp(it.C);
   const cgfloat* __restrict__ pr = gp(it.prev);
   const cgfloat* __restrict__ G = gp(it.g);
   gfloat* __restrict__ gpv = gp(it.gprev);
-  VoxSet vs;
-  vox_set(tc, D, H, W, vs);
-  float g[VPT][3];
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) {
-    g[j][0] = G[vs.p[j]];
-    g[j][1] = G[V + vs.p[j]];
-    g[j][2] = G[2 * V + vs.p[j]];
-  }
-  float uu[VPT][3];
-  CellSet cs;
-  load_cells(pr, 1.f, D, H, W, vs, uu, cs);
-  float o[VPT][3];
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) {
-    o[j][0] = g[j][0];
-    o[j][1] = g[j][1];
-    o[j][2] = g[j][2];
-  }
-  {
-    const BBox bb = cells_bbox(vs, cs, false, sbb);
-    const bool staged = bb.cells > 0 && bb.cells <= SCATTER_CELLS;
-    float* lds = reinterpret_cast<float*>(acc);
-    if (staged) stage_box(C, V, H, W, bb, lds, vs, cs);
-    jt_cells(C, 1.f, V, H, W, cs, bb, lds, staged, g, o);
-    __syncthreads();  // the bins reuse the staging buffer
-  }
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     sv[j].cz = -1;
-    if (!vs.ok[j]) continue;
-    const int p = vs.p[j];
+    const int k = threadIdx.x + j * BLOCK;
+    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
+    if (x >= W || y >= H || z >= D) continue;
+    const int p = (z * H + y) * W + x;
+    const float uz = pr[p], uy = pr[V + p], ux = pr[2 * V + p];
+    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
+    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+    const float g0 = G[p], g1 = G[V + p], g2 = G[2 * V + p];
+    float o0 = g0, o1 = g1, o2 = g2;
+    float v[8], dz, dy, dx;
+    load8(C, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    o0 = fmaf(dz * az.live, g0, o0);
+    o1 = fmaf(dy * ay.live, g0, o1);
+    o2 = fmaf(dx * ax.live, g0, o2);
+    load8(C + V, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    o0 = fmaf(dz * az.live, g1, o0);
+    o1 = fmaf(dy * ay.live, g1, o1);
+    o2 = fmaf(dx * ax.live, g1, o2);
+    load8(C + 2 * V, base, W, HW, v);
+    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
+    o0 = fmaf(dz * az.live, g2, o0);
+    o1 = fmaf(dy * ay.live, g2, o1);
+    o2 = fmaf(dx * ax.live, g2, o2);
     if (it.prev_atomic) {
-      gadd(gpv + p, o[j][0]);
-      gadd(gpv + V + p, o[j][1]);
-      gadd(gpv + 2 * V + p, o[j][2]);
+      gadd(gpv + p, o0);
+      gadd(gpv + V + p, o1);
+      gadd(gpv + 2 * V + p, o2);
     } else {
-      gpv[p] += o[j][0];
-      gpv[V + p] += o[j][1];
-      gpv[2 * V + p] += o[j][2];
+      gpv[p] += o0;
+      gpv[V + p] += o1;
+      gpv[2 * V + p] += o2;
     }
-    sv[j].cz = cs.az[j].i0; sv[j].cy = cs.ay[j].i0; sv[j].cx = cs.ax[j].i0;
-    sv[j].oz = vs.z[j]; sv[j].oy = vs.y[j]; sv[j].ox = vs.x[j];
-    sv[j].tz = cs.az[j].t; sv[j].ty = cs.ay[j].t; sv[j].tx = cs.ax[j].t;
-    sv[j].g[0] = g[j][0]; sv[j].g[1] = g[j][1]; sv[j].g[2] = g[j][2];
+    sv[j].cz = az.i0; sv[j].cy = ay.i0; sv[j].cx = ax.i0;
+    sv[j].oz = z; sv[j].oy = y; sv[j].ox = x;
+    sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
+    sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
   }
   scatter_tile<false>(sv, gp(it.gc), D, H, W, acc, sbb, sred);
 }
@@ -758,11 +673,19 @@ __device__ __forceinline__ STile stat_tile(int local, int D, int H, int W, int z
   return t;
 }
 
+// Column slots: a thread owns the patch columns threadIdx.x + k * BLOCK.
+template <int R>
+struct Patch {
+  static constexpr int WN = 2 * R + 1;
+  static constexpr int PY = ST_Y + 2 * R, PX = ST_X + 2 * R, P1 = PY * PX;
+  static constexpr int NS = (P1 + BLOCK - 1) / BLOCK;
+};
+
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__ items, int n_items,
                                                      int n_tiles, int metric) {
-  constexpr int WN = 2 * R + 1;
-  constexpr int PY = ST_Y + 2 * R, PX = ST_X + 2 * R, P1 = PY * PX;
+  using P = Patch<R>;
+  constexpr int WN = P::WN, PY = P::PY, PX = P::PX, P1 = P::P1, NS = P::NS;
   __shared__ float rF[WN][P1];
   __shared__ float rM[WN][P1];
   __shared__ float zs[5][P1];
@@ -784,26 +707,77 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
   const int y = tc.y0 + ty, x = tc.x0 + tx;
   const bool yx_in = (y < H) && (x < W);
   const bool yx_valid = yx_in && y >= R && y <= H - 1 - R && x >= R && x <= W - 1 - R;
+  // owned patch columns
+  int cyy[NS], cxx[NS];
+  bool cin[NS], cval[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int col = threadIdx.x + k * BLOCK;
+    cval[k] = col < P1;
+    cyy[k] = tc.y0 - R + col / PX;
+    cxx[k] = tc.x0 - R + col % PX;
+    cin[k] = cval[k] && cyy[k] >= 0 && cyy[k] < H && cxx[k] >= 0 && cxx[k] < W;
+  }
+  // software pipeline: U of slice zi+1 and the warped values of slice zi are
+  // in registers when iteration zi starts; the loads for the next slices are
+  // issued before this slice's sums so their latency overlaps the sums.
+  float u1[NS][3];
+  float fv0[NS], mv0[NS];
+  auto load_u = [&](int z, float (&u)[NS][3]) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const bool in = cin[k] && z >= 0 && z < D;
+      const int p = in ? (z * H + cyy[k]) * W + cxx[k] : 0;
+      u[k][0] = in ? U[p] : 0.f;
+      u[k][1] = in ? U[V + p] : 0.f;
+      u[k][2] = in ? U[2 * V + p] : 0.f;
+    }
+  };
+  // issue the loads of slice z (F and the 8 corners of I at the warped position)
+  auto issue = [&](int z, const float (&u)[NS][3], float (&fr)[NS], float (&v)[NS][8],
+                   Ax (&az)[NS], Ax (&ay)[NS], Ax (&ax)[NS]) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const bool in = cin[k] && z >= 0 && z < D;
+      const int zz = in ? z : 0, yy = in ? cyy[k] : 0, xx = in ? cxx[k] : 0;
+      az[k] = axis_disp(zz, u[k][0], D);
+      ay[k] = axis_disp(yy, u[k][1], H);
+      ax[k] = axis_disp(xx, u[k][2], W);
+      load8(I, (az[k].i0 * H + ay[k].i0) * W + ax[k].i0, W, HW, v[k]);
+      fr[k] = F[(zz * H + yy) * W + xx];
+    }
+  };
+  auto finish = [&](int z, const float (&fr)[NS], const float (&v)[NS][8], const Ax (&az)[NS],
+                    const Ax (&ay)[NS], const Ax (&ax)[NS], float (&fo)[NS], float (&mo)[NS]) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const bool in = cin[k] && z >= 0 && z < D;
+      mo[k] = in ? tri_val(v[k], az[k].t, ay[k].t, ax[k].t) - sM : 0.f;
+      fo[k] = in ? fr[k] - sF : 0.f;
+    }
+  };
+  {
+    float u0[NS][3], fr[NS], v[NS][8];
+    Ax az[NS], ay[NS], ax[NS];
+    load_u(tc.z0 - R, u0);
+    issue(tc.z0 - R, u0, fr, v, az, ay, ax);
+    finish(tc.z0 - R, fr, v, az, ay, ax, fv0, mv0);
+    load_u(tc.z0 - R + 1, u1);
+  }
   double lsum = 0.0;
   for (int zi = tc.z0 - R; zi < tc.z1 + R; ++zi) {
     const int slot = (zi + WN * 4096) % WN;
-    if (zi >= 0 && zi < D) {
-      for (int col = threadIdx.x; col < P1; col += BLOCK) {
-        const int yy = tc.y0 - R + col / PX, xx = tc.x0 - R + col % PX;
-        float fv = 0.f, mv = 0.f;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-          const int p = (zi * H + yy) * W + xx;
-          const Ax az = axis_disp(zi, U[p], D), ay = axis_disp(yy, U[V + p], H),
-                   ax = axis_disp(xx, U[2 * V + p], W);
-          float v[8];
-          load8(I, (az.i0 * H + ay.i0) * W + ax.i0, W, HW, v);
-          mv = tri_val(v, az.t, ay.t, ax.t) - sM;
-          fv = F[p] - sF;
-        }
-        rF[slot][col] = fv;
-        rM[slot][col] = mv;
-      }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (!cval[k]) continue;
+      const int col = threadIdx.x + k * BLOCK;
+      rF[slot][col] = fv0[k];
+      rM[slot][col] = mv0[k];
     }
+    float u2[NS][3], fr[NS], v[NS][8];
+    Ax az[NS], ay[NS], ax[NS];
+    load_u(zi + 2, u2);
+    issue(zi + 1, u1, fr, v, az, ay, ax);
     __syncthreads();
     const int zcen = zi - R;
     if (zcen >= tc.z0) {
@@ -888,6 +862,13 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
       }
     }
     __syncthreads();
+    finish(zi + 1, fr, v, az, ay, ax, fv0, mv0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      u1[k][0] = u2[k][0];
+      u1[k][1] = u2[k][1];
+      u1[k][2] = u2[k][2];
+    }
   }
   const double tot = block_sum(lsum, red);
   if (threadIdx.x == 0) {
@@ -900,11 +881,13 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
 // Gradient of Sim with respect to the pair field:
 //   dSim/dM(y) = (Box alpha + 2 M Box beta + F Box gamma)(y) / N_R,
 //   dSim/dU(y) = dSim/dM(y) * grad I_j(y + U(y)).
+// Pipelined like k_sim_stats: coefficients of the next slice and the output
+// voxel's loads are issued before the current slice's sums.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ items, int n_items,
                                                     int n_tiles) {
-  constexpr int WN = 2 * R + 1;
-  constexpr int PY = ST_Y + 2 * R, PX = ST_X + 2 * R, P1 = PY * PX;
+  using P = Patch<R>;
+  constexpr int WN = P::WN, PY = P::PY, PX = P::PX, P1 = P::P1, NS = P::NS;
   __shared__ float ring[3][WN][P1];
   __shared__ float zs[3][P1];
   __shared__ float xs[3][PY * ST_X];
@@ -920,25 +903,69 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
   const float inv_nr = (float)it.inv_nr;
   const int ty = threadIdx.x / ST_X, tx = threadIdx.x % ST_X;
   const int y = tc.y0 + ty, x = tc.x0 + tx;
+  const bool yx_in = y < H && x < W;
+  int cyy[NS], cxx[NS];
+  bool cin[NS], cval[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int col = threadIdx.x + k * BLOCK;
+    cval[k] = col < P1;
+    cyy[k] = tc.y0 - R + col / PX;
+    cxx[k] = tc.x0 - R + col % PX;
+    cin[k] = cval[k] && cyy[k] >= 0 && cyy[k] < H && cxx[k] >= 0 && cxx[k] < W;
+  }
+  auto load_coef = [&](int z, float (&c)[NS][3]) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const bool in = cin[k] && z >= 0 && z < D;
+      const int p = in ? (z * H + cyy[k]) * W + cxx[k] : 0;
+      c[k][0] = in ? coef[p] : 0.f;
+      c[k][1] = in ? coef[V + p] : 0.f;
+      c[k][2] = in ? coef[2 * V + p] : 0.f;
+    }
+  };
+  // output voxel (zo, y, x): U first, then F and the corners of I
+  auto load_uo = [&](int zo, float (&u)[3]) {
+    const bool in = yx_in && zo >= 0 && zo < D;
+    const int p = in ? (zo * H + y) * W + x : 0;
+    u[0] = in ? U[p] : 0.f;
+    u[1] = in ? U[V + p] : 0.f;
+    u[2] = in ? U[2 * V + p] : 0.f;
+  };
+  float c0[NS][3];
+  load_coef(tc.z0 - R, c0);
+  float uo[3];
+  load_uo(tc.z0, uo);
   for (int zi = tc.z0 - R; zi < tc.z1 + R; ++zi) {
     const int slot = (zi + WN * 4096) % WN;
-    const bool zin = zi >= 0 && zi < D;
-    for (int col = threadIdx.x; col < P1; col += BLOCK) {
-      const int yy = tc.y0 - R + col / PX, xx = tc.x0 - R + col % PX;
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-      if (zin && yy >= 0 && yy < H && xx >= 0 && xx < W) {
-        const int p = (zi * H + yy) * W + xx;
-        a0 = coef[p];
-        a1 = coef[V + p];
-        a2 = coef[2 * V + p];
-      }
-      ring[0][slot][col] = a0;
-      ring[1][slot][col] = a1;
-      ring[2][slot][col] = a2;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (!cval[k]) continue;
+      const int col = threadIdx.x + k * BLOCK;
+      ring[0][slot][col] = c0[k][0];
+      ring[1][slot][col] = c0[k][1];
+      ring[2][slot][col] = c0[k][2];
     }
-    __syncthreads();
+    float c1[NS][3];
+    load_coef(zi + 1, c1);
     const int zo = zi - R;
-    if (zo >= tc.z0) {
+    const bool out_now = zo >= tc.z0;
+    // loads of the output voxel of this iteration
+    float vI[8], fo = 0.f;
+    Ax az, ay, ax;
+    {
+      const bool in = yx_in && zo >= tc.z0 && zo < D;
+      const int zz = in ? zo : 0, yy = in ? y : 0, xx = in ? x : 0;
+      az = axis_disp(zz, uo[0], D);
+      ay = axis_disp(yy, uo[1], H);
+      ax = axis_disp(xx, uo[2], W);
+      load8(I, (az.i0 * H + ay.i0) * W + ax.i0, W, HW, vI);
+      fo = F[(zz * H + yy) * W + xx];
+    }
+    float un[3];
+    load_uo(out_now ? zo + 1 : tc.z0, un);
+    __syncthreads();
+    if (out_now) {
       for (int col = threadIdx.x; col < P1; col += BLOCK) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -961,7 +988,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
         }
       }
       __syncthreads();
-      if (y < H && x < W) {
+      if (yx_in) {
         float B[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -971,18 +998,26 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
           B[q] = acc;
         }
         const int p = (zo * H + y) * W + x;
-        const Ax az = axis_disp(zo, U[p], D), ay = axis_disp(y, U[V + p], H),
-                 ax = axis_disp(x, U[2 * V + p], W);
-        float v[8], dz, dy, dx;
-        load8(I, (az.i0 * H + ay.i0) * W + ax.i0, W, HW, v);
-        const float M = tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-        const float dM = (B[0] + 2.f * M * B[1] + F[p] * B[2]) * inv_nr;
+        float dz, dy, dx;
+        const float M = tri_grad(vI, az.t, ay.t, ax.t, dz, dy, dx);
+        const float dM = (B[0] + 2.f * M * B[1] + fo * B[2]) * inv_nr;
         gU[p] = dM * dz * az.live;
         gU[V + p] = dM * dy * ay.live;
         gU[2 * V + p] = dM * dx * ax.live;
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      c0[k][0] = c1[k][0];
+      c0[k][1] = c1[k][1];
+      c0[k][2] = c1[k][2];
+    }
+    if (out_now) {
+      uo[0] = un[0];
+      uo[1] = un[1];
+      uo[2] = un[2];
+    }
   }
 }
 
