@@ -404,19 +404,64 @@ struct ScatterVox {
   float own[3];        // value added at the own voxel
 };
 
-__device__ __forceinline__ float block_max(float v, float* sred) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = v;
+// Bounding box (lo/hi per axis) and largest magnitude over the block in one
+// reduction: wave shuffles, one LDS exchange, one barrier.
+struct ScatterBox {
+  BBox bb;
+  float bmax;
+};
+
+__device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], float mx,
+                                                  int* sred) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], o));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], o));
+    }
+    mx = fmaxf(mx, __shfl_xor(mx, o));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      sred[w * 8 + d] = lo[d];
+      sred[w * 8 + 3 + d] = hi[d];
+    }
+    sred[w * 8 + 6] = __float_as_int(mx);
+  }
   __syncthreads();
-  float m = sred[0];
-  for (int i = 1; i < BLOCK / 64; ++i) m = fmaxf(m, sred[i]);
-  return m;
+  int l[3] = {INT_MAX, INT_MAX, INT_MAX}, h[3] = {INT_MIN, INT_MIN, INT_MIN};
+  float m = 0.f;
+#pragma unroll
+  for (int i = 0; i < BLOCK / 64; ++i) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      l[d] = min(l[d], sred[i * 8 + d]);
+      h[d] = max(h[d], sred[i * 8 + 3 + d]);
+    }
+    m = fmaxf(m, __int_as_float(sred[i * 8 + 6]));
+  }
+  ScatterBox sb;
+  sb.bmax = m;
+  sb.bb.lz = l[0]; sb.bb.ly = l[1]; sb.bb.lx = l[2];
+  if (h[0] < l[0]) {
+    sb.bb.ez = sb.bb.ey = sb.bb.ex = 0;
+    sb.bb.cells = 0;
+    return sb;
+  }
+  sb.bb.ez = h[0] - l[0] + 1;
+  sb.bb.ey = h[1] - l[1] + 1;
+  sb.bb.ex = h[2] - l[2] + 1;
+  const long long c = (long long)sb.bb.ez * sb.bb.ey * sb.bb.ex;
+  sb.bb.cells = c > (long long)INT_MAX ? INT_MAX : (int)c;
+  return sb;
 }
 
 template <bool OWN>
 __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat* __restrict__ out,
-                                             int D, int H, int W, int* acc, int* sbb,
-                                             float* sred) {
+                                             int D, int H, int W, int* acc, int* sred) {
   const int HW = H * W, V = D * HW;
   int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
   int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
@@ -435,14 +480,19 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
       mx = fmaxf(mx, fmaxf(fabsf(sv[j].own[0]), fmaxf(fabsf(sv[j].own[1]), fabsf(sv[j].own[2]))));
     }
   }
-  const float bmax = block_max(mx, sred);
-  const BBox bb = block_bbox(lo, hi, sbb);
+  const ScatterBox sb = scatter_box(lo, hi, mx, sred);
+  const BBox& bb = sb.bb;
+  const float bmax = sb.bmax;
   if (bb.cells == 0) return;
   if (bb.cells <= SCATTER_CELLS && bmax > 0.f && bmax < 3.0e38f) {
     const float scale = FIX_SCALE / bmax;
     const float inv = bmax / FIX_SCALE;
     const int cells = bb.cells;
-    for (int i = threadIdx.x; i < 3 * cells; i += BLOCK) acc[i] = 0;
+    {
+      int4* a4 = reinterpret_cast<int4*>(acc);
+      const int n4 = (3 * cells + 3) >> 2;
+      for (int i = threadIdx.x; i < n4; i += BLOCK) a4[i] = make_int4(0, 0, 0, 0);
+    }
     __syncthreads();
     const int sy = bb.ex, sz = bb.ex * bb.ey;
 #pragma unroll
@@ -469,11 +519,13 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
       }
     }
     __syncthreads();
+    // i -> (lz, ly, lx) by float reciprocals: exact here since i < 2^22
+    const float inv_ex = 1.f / (float)bb.ex, inv_ey = 1.f / (float)bb.ey;
     for (int i = threadIdx.x; i < cells; i += BLOCK) {
-      const int lx = i % bb.ex;
-      const int r = i / bb.ex;
-      const int ly = r % bb.ey;
-      const int lz = r / bb.ey;
+      const int r = (int)(((float)i + 0.5f) * inv_ex);
+      const int lx = i - r * bb.ex;
+      const int lz = (int)(((float)r + 0.5f) * inv_ey);
+      const int ly = r - lz * bb.ey;
       const int gpos = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -515,9 +567,8 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict__ items,
                                                    int n_items, int n_tiles) {
-  __shared__ int acc[3 * SCATTER_CELLS];
-  __shared__ int sbb[6];
-  __shared__ float sred[BLOCK / 64];
+  __shared__ __align__(16) int acc[3 * SCATTER_CELLS];
+  __shared__ int sred[8 * (BLOCK / 64)];
   __shared__ double red[BLOCK / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ExpBwdItem it = items[find_item(items, n_items, tile)];
@@ -577,7 +628,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
     sv[j].own[0] = own0; sv[j].own[1] = own1; sv[j].own[2] = own2;
   }
-  scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sbb, sred);
+  scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred);
   if (reg) {
     const double tot = block_sum(rval, red);
     if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot * (double)it.reg_loss_w);
@@ -589,9 +640,8 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __restrict__ items,
                                                        int n_items, int n_tiles) {
-  __shared__ int acc[3 * SCATTER_CELLS];
-  __shared__ int sbb[6];
-  __shared__ float sred[BLOCK / 64];
+  __shared__ __align__(16) int acc[3 * SCATTER_CELLS];
+  __shared__ int sred[8 * (BLOCK / 64)];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ComposeBwdItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
@@ -643,7 +693,7 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
     sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
     sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
   }
-  scatter_tile<false>(sv, gp(it.gc), D, H, W, acc, sbb, sred);
+  scatter_tile<false>(sv, gp(it.gc), D, H, W, acc, sred);
 }
 
 // ---------------------------------------------------------------------------
