@@ -383,6 +383,39 @@ def reg_ss_grad(phi: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Gaussian smoothing of the flow (Sec. 2.4 and Appendix A: the flow field is
+# smoothed with a Gaussian kernel, applied through FFTs).  Reading: a periodic
+# (circular, as with the FFT) separable convolution with the sampled Gaussian
+# exp(-k^2 / (2 sigma^2)), normalised to unit sum and truncated at radius
+# int(4 sigma + 0.5).  The operator is symmetric, so its adjoint is itself.
+# ---------------------------------------------------------------------------
+
+def gaussian_taps(sigma: float) -> np.ndarray:
+    """Normalised taps w_{-r..r} of the truncated sampled Gaussian."""
+    r = int(4.0 * sigma + 0.5)
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-0.5 * (k / sigma) ** 2)
+    return w / w.sum()
+
+
+def smooth(phi: np.ndarray, sigma: float) -> np.ndarray:
+    """Circular Gaussian smoothing of every component along z, y and x."""
+    phi = np.asarray(phi, np.float64)
+    if sigma <= 0.0:
+        return phi.copy()
+    w = gaussian_taps(sigma)
+    r = (len(w) - 1) // 2
+    out = phi
+    for ax in (1, 2, 3):
+        acc = np.zeros_like(out)
+        for k in range(-r, r + 1):
+            # acc(x) += w_k * f(x + k), indices taken modulo the axis length
+            acc += w[k + r] * np.roll(out, -k, axis=ax)
+        out = acc
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Loss and gradient (Sec. 2.2 loss, Sec. 2.4 Eq. reg_sum)
 # ---------------------------------------------------------------------------
 
@@ -392,6 +425,7 @@ class Params:
     window: int = 5            # w, the window edge
     metric: int = LNCC         # LNCC or SILNCC
     alpha_ss: float = 1.0      # weight of L_ss
+    smooth_sigma: float = 0.0  # Gaussian smoothing of the flow (voxels of the level); 0 = none
     lr: float = 0.1            # peak learning rate (voxels per step)
     warmup: float = 0.2        # warm-up fraction of each stage
     betas: Tuple[float, float] = (0.9, 0.999)
@@ -402,11 +436,12 @@ class Params:
 def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: bool = False):
     """Evaluate L(phi) = sum_i sum_{j != i} Sim(I_i, I_j o Phi_ji^i) + alpha_ss L_ss.
 
-    Returns the loss and, with keep=True, every intermediate the backward pass
-    needs (Exp steps, pair fields, warped images)."""
+    The flow is first smoothed (smooth_sigma > 0); Exp and L_ss act on the
+    smoothed flow.  Returns the loss and, with keep=True, every intermediate
+    the backward pass needs (Exp steps, pair fields, warped images)."""
     N = len(images)
     imgs = [np.asarray(I, np.float64) for I in images]
-    phis = [np.asarray(ph, np.float64) for ph in phis]
+    phis = [smooth(ph, p.smooth_sigma) for ph in phis]
     fwd = [exp_fwd(ph, p.K) for ph in phis]
     bwd = [exp_fwd(-ph, p.K) for ph in phis]
     f = [us[-1] for us in fwd]
@@ -421,7 +456,7 @@ def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: b
     L = Lsim + Lreg
     if not keep:
         return L
-    return L, dict(fwd=fwd, bwd=bwd, f=f, b=b, U=U, sims=sims, Lsim=Lsim, Lreg=Lreg)
+    return L, dict(fwd=fwd, bwd=bwd, f=f, b=b, U=U, sims=sims, Lsim=Lsim, Lreg=Lreg, phis_s=phis)
 
 
 def pair_sim_grad(images, U, i, j, p: Params):
@@ -464,12 +499,13 @@ def loss_and_grad(phis: List[np.ndarray], images: List[np.ndarray], p: Params):
     aux["Gf"], aux["Gb"] = Gf, Gb
     grads = []
     scale = 2.0 ** -p.K
-    for i, ph in enumerate(phis):
+    for i in range(len(phis)):
         g0f = exp_bwd(aux["fwd"][i], Gf[i])
         g0b = exp_bwd(aux["bwd"][i], Gb[i])
         g = scale * (g0f - g0b)
-        g = g + p.alpha_ss / (N - 1) * reg_ss_grad(ph)
-        grads.append(g)
+        g = g + p.alpha_ss / (N - 1) * reg_ss_grad(aux["phis_s"][i])
+        # the smoothing is self-adjoint
+        grads.append(smooth(g, p.smooth_sigma))
     return L, grads, aux
 
 
@@ -521,11 +557,18 @@ def upsample2(phi: np.ndarray) -> np.ndarray:
     return 2.0 * sample(phi, (g - 0.5) / 2.0)
 
 
+def level_sigma(p: Params, level: int) -> float:
+    """Smoothing width at a pyramid level: smooth_sigma is given in voxels of
+    the finest level and halves with every coarser level."""
+    return p.smooth_sigma / 2.0 ** (len(p.iters) - 1 - level)
+
+
 def register(images: List[np.ndarray], p: Params, phis0: Optional[List[np.ndarray]] = None,
              record: bool = False):
     """The whole optimisation: pyramid levels coarse to fine, each running
     Adam on L(phi) for p.iters[level] steps from a schedule that restarts per
-    level.  Returns (phis at full resolution, pair fields, loss history)."""
+    level.  Returns (the smoothed flows that parameterise the final
+    deformations, at full resolution; pair fields; loss history)."""
     L_lv = len(p.iters)
     imgs_lv = [[np.asarray(I, np.float64) for I in images]]
     for _ in range(L_lv - 1):
@@ -544,17 +587,19 @@ def register(images: List[np.ndarray], p: Params, phis0: Optional[List[np.ndarra
         m = [np.zeros_like(x) for x in phis]
         v = [np.zeros_like(x) for x in phis]
         T = p.iters[lv]
+        pl = Params(**{**p.__dict__, "smooth_sigma": level_sigma(p, lv)})
         for t in range(1, T + 1):
-            L, grads, _ = loss_and_grad(phis, imgs, p)
+            L, grads, _ = loss_and_grad(phis, imgs, pl)
             hist.append(L)
             lr = lr_schedule(t, T, p.lr, p.warmup)
             for k in range(N - 1):
                 phis[k], m[k], v[k] = adam_step(phis[k], grads[k], m[k], v[k], t, lr,
                                                 p.betas, p.eps)
-    fwd = [exp_fwd(ph, p.K)[-1] for ph in phis]
-    bwd = [exp_fwd(-ph, p.K)[-1] for ph in phis]
+    sm = [smooth(ph, level_sigma(p, L_lv - 1)) for ph in phis]
+    fwd = [exp_fwd(ph, p.K)[-1] for ph in sm]
+    bwd = [exp_fwd(-ph, p.K)[-1] for ph in sm]
     U = all_pairs(fwd, bwd)
-    return phis, U, hist
+    return sm, U, hist
 
 
 # ---------------------------------------------------------------------------

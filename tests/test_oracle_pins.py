@@ -526,3 +526,43 @@ def test_loss_weights_the_regulariser_by_alpha_over_intervals():
     p = O.Params(K=4, window=3, metric=O.SILNCC, alpha_ss=0.7)
     want = 0.7 / (N - 1) * sum(np.sum(A * A) for A in As)
     assert abs(O.forward(phis, imgs, p) - want) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Gaussian smoothing of the flow (Sec. 2.4, Appendix A)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sigma", [0.5, 1.0, 1.7, 3.0])
+def test_smoothing_matches_scipy_gaussian_filter_wrap(sigma):
+    import scipy.ndimage as ndi
+    x = rng(100).standard_normal((3, 9, 12, 14))
+    want = np.stack([ndi.gaussian_filter(c, sigma, mode="wrap", truncate=4.0) for c in x])
+    assert np.abs(O.smooth(x, sigma) - want).max() < 1e-13
+
+
+def test_smoothing_is_self_adjoint_and_keeps_constants():
+    r = rng(101)
+    a = r.standard_normal((3, 8, 9, 10))
+    b = r.standard_normal((3, 8, 9, 10))
+    assert abs(np.sum(O.smooth(a, 1.3) * b) - np.sum(a * O.smooth(b, 1.3))) < 1e-10
+    c = np.full((3, 6, 7, 8), 2.5)
+    assert np.allclose(O.smooth(c, 2.0), c, atol=1e-14)
+    assert np.array_equal(O.smooth(a, 0.0), a)
+
+
+def test_T13_gradient_with_smoothing_matches_finite_differences():
+    imgs, phis = _tiny_problem(7, shape=(8, 9, 10), N=3)
+    p = O.Params(K=4, window=3, metric=O.SILNCC, alpha_ss=1.0, smooth_sigma=0.8)
+    L, grads, _ = O.loss_and_grad(phis, imgs, p)
+    r = rng(7)
+    gmax = max(np.abs(g).max() for g in grads)
+    h = 1e-5
+    for _ in range(40):
+        k = int(r.integers(0, 2))
+        idx = tuple(int(r.integers(0, n)) for n in phis[k].shape)
+        pp = [x.copy() for x in phis]
+        pm = [x.copy() for x in phis]
+        pp[k][idx] += h
+        pm[k][idx] -= h
+        fd = (O.forward(pp, imgs, p) - O.forward(pm, imgs, p)) / (2 * h)
+        assert abs(fd - grads[k][idx]) < 1e-6 * gmax + 1e-5 * abs(fd)
