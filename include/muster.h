@@ -85,6 +85,11 @@ typedef struct muster_params {
                                       recompute them from phi                     */
   int use_graph;                   /* 1: replay each level's iteration as a
                                       captured hipGraph; 0: eager launches        */
+  float smooth_sigma;              /* Gaussian smoothing of the flow before Exp
+                                      (Sec. 2.4, Appendix A), in voxels of the
+                                      finest level, halved per coarser level;
+                                      periodic, truncated at 4 sigma; 0 = off;
+                                      at most 15.8                                */
 } muster_params;
 
 /* Per-job result summary. */
@@ -126,7 +131,7 @@ const char* muster_version(void);
 
 /* Defaults (readings where the paper is silent): levels 1, iters {100}, K 7,
  * window 5, LNCC, alpha_ss 1, lr 0.1, warm-up 0.2 (Sec. 2.7), Adam
- * (0.9, 0.999, 1e-8), store mode, graphs on. */
+ * (0.9, 0.999, 1e-8), store mode, graphs on, no smoothing. */
 muster_status muster_params_default(muster_params* p);
 
 /* Device bytes a job of N sessions on grid dims needs under params
@@ -232,6 +237,12 @@ muster_status muster_reg(muster_ctx* ctx, void* stream, const int dims[3],
 /* 2x2x2 mean of a volume with even dims (one pyramid level down). */
 muster_status muster_pool2(muster_ctx* ctx, void* stream, const int dims[3],
                            const float* src_dev, float* dst_dev);
+/* Gaussian smoothing of a vector field [3][D][H][W] (Sec. 2.4, Appendix A):
+ * separable periodic convolution with the sampled Gaussian of width sigma
+ * voxels, normalised and truncated at radius int(4 sigma + 0.5) <= 64.
+ * src and dst must not overlap. */
+muster_status muster_smooth(muster_ctx* ctx, void* stream, const int dims[3], float sigma,
+                            const float* src_dev, float* dst_dev);
 /* Displacement field on the 2x finer grid: dst(x) = 2 * src((x - 0.5)/2);
  * dims are the coarse dims, dst is [3][2D][2H][2W]. */
 muster_status muster_upsample2(muster_ctx* ctx, void* stream, const int dims[3],
@@ -242,7 +253,7 @@ muster_status muster_upsample2(muster_ctx* ctx, void* stream, const int dims[3],
 enum {
   MUSTER_K_EXP_FWD = 0, MUSTER_K_COMPOSE_FWD, MUSTER_K_SIM_STATS, MUSTER_K_SIM_GRAD,
   MUSTER_K_COMPOSE_BWD, MUSTER_K_EXP_BWD, MUSTER_K_ADAM, MUSTER_K_FINISH,
-  MUSTER_K_POOL, MUSTER_K_UPSAMPLE, MUSTER_K_COUNT
+  MUSTER_K_POOL, MUSTER_K_UPSAMPLE, MUSTER_K_SMOOTH, MUSTER_K_COUNT
 };
 /* When enabled, eager launches (graphs off) of each kernel class are
  * bracketed by HIP events on the stream they run on. */

@@ -22,7 +22,7 @@ STATUS_NAMES = ["OK", "E_INVALID", "E_NOMEM", "E_DEVICE", "E_BUSY", "E_NONFINITE
 METRIC_LNCC, METRIC_SILNCC = 0, 1
 EXP_STORE, EXP_RECOMPUTE = 0, 1
 KERNELS = ["exp_fwd", "compose_fwd", "sim_stats", "sim_grad", "compose_bwd", "exp_bwd", "adam",
-           "finish", "pool2", "upsample2"]
+           "finish", "pool2", "upsample2", "smooth"]
 
 
 class MusterLibraryMissing(ImportError):
@@ -40,7 +40,7 @@ class Params(Structure):
     _fields_ = [("levels", c_int), ("iters", c_int * MAX_LEVELS), ("K", c_int), ("window", c_int),
                 ("metric", c_int), ("alpha_ss", c_float), ("lr", c_float), ("warmup", c_float),
                 ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("exp_mode", c_int),
-                ("use_graph", c_int)]
+                ("use_graph", c_int), ("smooth_sigma", c_float)]
 
 
 class Report(Structure):
@@ -93,6 +93,7 @@ SIGNATURES = {
     "muster_reg": (_ST, [_P, _P, DIMS, _P, POINTER(c_double), _P]),
     "muster_pool2": (_ST, [_P, _P, DIMS, _P, _P]),
     "muster_upsample2": (_ST, [_P, _P, DIMS, _P, _P]),
+    "muster_smooth": (_ST, [_P, _P, DIMS, c_float, _P, _P]),
     "muster_set_kernel_timing": (_ST, [_P, c_int]),
     "muster_kernel_stats": (_ST, [_P, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
     "muster_kernel_stats_reset": (_ST, [_P]),

@@ -30,6 +30,7 @@ class MusterParams:
     eps: float = 1e-8
     exp_mode: str = "store"           # "store" or "recompute"
     use_graph: bool = True
+    smooth_sigma: float = 0.0         # Gaussian smoothing of the flow, finest-level voxels
 
     def to_c(self) -> L.Params:
         p = L.Params()
@@ -48,6 +49,7 @@ class MusterParams:
         p.beta1, p.beta2, p.eps = float(self.beta1), float(self.beta2), float(self.eps)
         p.exp_mode = {"store": L.EXP_STORE, "recompute": L.EXP_RECOMPUTE}[self.exp_mode]
         p.use_graph = 1 if self.use_graph else 0
+        p.smooth_sigma = float(self.smooth_sigma)
         return p
 
 
@@ -140,6 +142,12 @@ class Context:
         D, H, W = img.shape
         out = torch.empty((D // 2, H // 2, W // 2), device=img.device)
         L.check(self.lib.muster_pool2(self.h, _stream(), _dims(img.shape), _ptr(img), _ptr(out)))
+        return out
+
+    def smooth(self, svf, sigma):
+        out = torch.empty_like(svf)
+        L.check(self.lib.muster_smooth(self.h, _stream(), _dims(svf.shape[1:]), float(sigma),
+                                       _ptr(svf), _ptr(out)))
         return out
 
     def upsample2(self, svf):

@@ -1088,18 +1088,24 @@ __global__ __launch_bounds__(BLOCK) void k_adam(const AdamItem* __restrict__ ite
   const AdamItem it = items[find_item(items, n_items, tile)];
   const int n = it.n;
   const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
-  if (it.mode == 1) {
+  gfloat* __restrict__ g0f = gp(it.g0f);
+  gfloat* __restrict__ g0b = gp(it.g0b);
+  const cgfloat* __restrict__ gs = gp(it.gsrc);
+  auto grad = [&](int i) -> float {
+    if (it.gsrc) return gs[i];
+    const float g = it.scale * (g0f[i] - g0b[i]);
+    g0f[i] = 0.f;
+    g0b[i] = 0.f;
+    return g;
+  };
+  if (it.mode != 0) {
+    gfloat* __restrict__ go = gp(it.gout);
+    const float sc = it.mode == 1 ? it.gscale : 1.f;
     for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
       const int q = q0 + k;
       if (q >= n) break;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int i = c * n + q;
-        const float g = it.scale * (it.g0f[i] - it.g0b[i]);
-        it.g0f[i] = 0.f;
-        it.g0b[i] = 0.f;
-        it.gout[i] = g * it.gscale;
-      }
+      for (int c = 0; c < 3; ++c) go[c * n + q] = grad(c * n + q) * sc;
     }
     return;
   }
@@ -1111,23 +1117,78 @@ __global__ __launch_bounds__(BLOCK) void k_adam(const AdamItem* __restrict__ ite
   const float step_size = (float)(lr / bc1);
   const float bc2s = (float)sqrt(bc2);
   const float b1 = js->b1, b2 = js->b2, eps = js->eps;
+  gfloat* __restrict__ phi = gp(it.phi);
+  gfloat* __restrict__ mm = gp(it.m);
+  gfloat* __restrict__ vv = gp(it.v);
   for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
     const int q = q0 + k;
     if (q >= n) break;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int i = c * n + q;
-      const float g = it.scale * (it.g0f[i] - it.g0b[i]);
-      it.g0f[i] = 0.f;
-      it.g0b[i] = 0.f;
-      float m = it.m[i], v = it.v[i];
+      const float g = grad(i);
+      float m = mm[i], v = vv[i];
       m = fmaf(1.f - b1, g - m, m);
       v = fmaf(1.f - b2, g * g, v * b2);
       const float den = sqrtf(v) / bc2s + eps;
-      it.phi[i] -= step_size * (m / den);
-      it.m[i] = m;
-      it.v[i] = v;
+      phi[i] -= step_size * (m / den);
+      mm[i] = m;
+      vv[i] = v;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian smoothing of the flow (Sec. 2.4, Appendix A): one separable pass of
+// the circular convolution with the sampled, normalised Gaussian truncated at
+// the item's radius, on the three components.  The filter is symmetric, so
+// the same pass is its own adjoint.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_smooth(const SmoothItem* __restrict__ items, int n_items,
+                                                  int n_tiles) {
+  __shared__ float w[2 * MAX_SMOOTH_RADIUS + 1];
+  __shared__ float wsum;
+  const int tile = blockIdx.x;
+  const SmoothItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const int r = it.radius;
+  for (int k = threadIdx.x; k <= 2 * r; k += BLOCK) {
+    const float d = (float)(k - r) / it.sigma;
+    w[k] = expf(-0.5f * d * d);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int k = 0; k <= 2 * r; ++k) t += w[k];
+    wsum = 1.f / t;
+  }
+  __syncthreads();
+  const float norm = wsum;
+  const int n = it.axis == 0 ? D : (it.axis == 1 ? H : W);
+  const int stride = it.axis == 0 ? HW : (it.axis == 1 ? W : 1);
+  const cgfloat* __restrict__ src = gp(it.src);
+  gfloat* __restrict__ dst = gp(it.dst);
+  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
+  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
+    const int q = q0 + k;
+    if (q >= V) break;
+    const int x = q % W, y = (q / W) % H, z = q / HW;
+    const int pos = it.axis == 0 ? z : (it.axis == 1 ? y : x);
+    const int row = q - pos * stride;  // the line's element at position 0
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int t = -r; t <= r; ++t) {
+      int j = pos + t;
+      j %= n;
+      if (j < 0) j += n;
+      const int idx = row + j * stride;
+      const float wt = w[t + r];
+      a0 = fmaf(wt, src[idx], a0);
+      a1 = fmaf(wt, src[V + idx], a1);
+      a2 = fmaf(wt, src[2 * V + idx], a2);
+    }
+    dst[q] = a0 * norm;
+    dst[V + q] = a1 * norm;
+    dst[2 * V + q] = a2 * norm;
   }
 }
 
@@ -1291,6 +1352,12 @@ hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int w
 hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adam, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_smooth, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 

@@ -101,21 +101,37 @@ struct SimItem {
   double* sim_out;  // optional per-pair accumulator
 };
 
-// Adam step (mode 0) or gradient output (mode 1) for one interval.
+// The gradient of one interval is g = scale * (g0f - g0b) (g0f, g0b are
+// cleared after they are read), or gsrc when gsrc is set.  Mode 0: Adam step
+// on phi.  Mode 1: gout = gscale * g.  Mode 2: gout = g (the combined
+// gradient, for smoothing before the step).
 struct AdamItem {
   int tile0;
   int n;          // voxels
   float* phi;
-  float* g0f;     // dL/du_0 of the forward direction (cleared after read)
-  float* g0b;     // dL/du_0 of the backward direction (cleared after read)
+  float* g0f;     // dL/du_0 of the forward direction
+  float* g0b;     // dL/du_0 of the backward direction
+  const float* gsrc;
   float* m;
   float* v;
-  float* gout;    // mode 1 output
+  float* gout;
   float scale;    // 2^-K
   float gscale;   // mode 1: grad_out
   int mode;
   int pad;
   JobState* js;
+};
+
+// One separable pass of the circular Gaussian smoothing along one axis.
+struct SmoothItem {
+  int tile0;
+  int D, H, W;
+  int axis;       // 0 = z, 1 = y, 2 = x
+  int radius;
+  float sigma;
+  int pad;
+  const float* src;
+  float* dst;
 };
 
 struct PoolItem {
@@ -160,6 +176,8 @@ hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int 
 hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window,
                            hipStream_t s);
 hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, hipStream_t s);
+constexpr int MAX_SMOOTH_RADIUS = 64;
 hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s);
 hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_upsample2(const UpItem* items, int n_items, int n_tiles, hipStream_t s);

@@ -122,6 +122,8 @@ void validate_params(const muster_params& p) {
     fail(MUSTER_E_INVALID, "bad Adam constants");
   if (p.exp_mode != MUSTER_EXP_STORE && p.exp_mode != MUSTER_EXP_RECOMPUTE)
     fail(MUSTER_E_INVALID, "unknown exp_mode %d", p.exp_mode);
+  if (!(p.smooth_sigma >= 0.f) || (int)(4.0f * p.smooth_sigma + 0.5f) > MAX_SMOOTH_RADIUS)
+    fail(MUSTER_E_INVALID, "smooth_sigma must be in [0, 15.8] (got %g)", (double)p.smooth_sigma);
 }
 
 void validate_problem(int N, const int dims[3], const muster_params& p, const double* times) {
@@ -160,6 +162,7 @@ uint64_t job_footprint(int N, const int dims[3], const muster_params& p) {
   const uint64_t F = 3 * V * sizeof(float);
   const uint64_t n1 = N - 1, P = (uint64_t)N * (N - 1), Pd = (uint64_t)(N - 1) * (N - 2);
   uint64_t fields = 3 * n1 + 2 * n1 * per_dir_fields(p) + std::max<uint64_t>(Pd, 1) + P + 4 * n1 + P;
+  if (p.smooth_sigma > 0.f) fields += 3 * n1;
   uint64_t bytes = fields * F;
   uint64_t imgs = 0;
   for (int l = 0; l < p.levels - 1; ++l) {
@@ -240,6 +243,11 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   J.m_gpair.alloc(ctx, P * F);
   J.m_pp.alloc(ctx, 4 * n1 * F);
   J.m_coef.alloc(ctx, P * F);
+  if (J.p.smooth_sigma > 0.f) {
+    J.m_phis.alloc(ctx, n1 * F);
+    J.m_t1.alloc(ctx, n1 * F);
+    J.m_t2.alloc(ctx, n1 * F);
+  }
   size_t img = 0;
   for (int l = 0; l < L - 1; ++l) img += (size_t)N * J.V(l);
   J.m_img.alloc(ctx, std::max<size_t>(img, 1) * sizeof(float));
@@ -263,7 +271,7 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   std::memset(J.host_state, 0, sizeof(JobState));
   J.footprint = J.m_phi.bytes + J.m_m.bytes + J.m_v.bytes + J.m_us.bytes + J.m_deep.bytes +
                 J.m_gpair.bytes + J.m_pp.bytes + J.m_coef.bytes + J.m_img.bytes +
-                J.m_state.bytes + J.m_hist.bytes;
+                J.m_state.bytes + J.m_hist.bytes + J.m_phis.bytes + J.m_t1.bytes + J.m_t2.bytes;
   return job;
 }
 
@@ -370,7 +378,7 @@ void job_final_outputs(Job& J, hipStream_t s) {
   plan->run(ctx, s);
   const size_t V = J.Vc();
   if (J.svf_out)
-    MUSTER_HIP(hipMemcpyAsync(J.svf_out, J.phi, (size_t)(J.N - 1) * 3 * V * sizeof(float),
+    MUSTER_HIP(hipMemcpyAsync(J.svf_out, J.flow(0), (size_t)(J.N - 1) * 3 * V * sizeof(float),
                               hipMemcpyDeviceToDevice, s));
   if (J.pairs_out) {
     for (int i = 0; i < J.N; ++i)
@@ -390,7 +398,7 @@ namespace {
 
 // Algorithmic bytes per voxel (the unique bytes each step must move).
 constexpr double B_EXP_FWD = 24, B_COMPOSE_FWD = 36, B_SIM_STATS = 20, B_SIM_GRAD = 32,
-                 B_COMPOSE_BWD = 84, B_EXP_BWD = 60, B_ADAM = 96;
+                 B_COMPOSE_BWD = 84, B_EXP_BWD = 60, B_ADAM = 96, B_SMOOTH = 24;
 
 struct Builder {
   Plan* plan;
@@ -414,6 +422,45 @@ struct Builder {
   }
 };
 
+// One separable smoothing pass (axis) for every interval of the smoothing
+// jobs: src(i) -> dst(i).
+template <class SrcF, class DstF>
+void add_smooth_pass(Builder& b, const std::vector<Job*>& jobs, int axis, SrcF src, DstF dst) {
+  std::vector<SmoothItem> items;
+  int tiles = 0;
+  double bytes = 0;
+  for (Job* J : jobs) {
+    if (!J->smoothing()) continue;
+    const int* d = J->ldims[J->level];
+    const size_t V = J->Vc();
+    for (int i = 0; i < J->N - 1; ++i) {
+      SmoothItem it{};
+      it.tile0 = tiles;
+      it.D = d[0]; it.H = d[1]; it.W = d[2];
+      it.axis = axis;
+      it.sigma = J->sigma();
+      it.radius = (int)(4.0f * it.sigma + 0.5f);
+      it.src = src(J, i);
+      it.dst = dst(J, i);
+      items.push_back(it);
+      tiles += (int)((V + ELEM_PER_BLOCK - 1) / ELEM_PER_BLOCK);
+      bytes += B_SMOOTH * V;
+    }
+  }
+  b.add(ST_SMOOTH, items, tiles, bytes);
+}
+
+// phi -> smoothed flow: z into t1, y into t2, x into the flow buffer
+void add_smooth_flow(Builder& b, const std::vector<Job*>& jobs) {
+  auto phi = [](Job* J, int i) { return (const float*)J->field(J->phi, i); };
+  auto t1 = [](Job* J, int i) { return J->field(J->m_t1.as<float>(), i); };
+  auto t2 = [](Job* J, int i) { return J->field(J->m_t2.as<float>(), i); };
+  auto fl = [](Job* J, int i) { return J->flow(i); };
+  add_smooth_pass(b, jobs, 0, phi, t1);
+  add_smooth_pass(b, jobs, 1, [&](Job* J, int i) { return (const float*)t1(J, i); }, t2);
+  add_smooth_pass(b, jobs, 2, [&](Job* J, int i) { return (const float*)t2(J, i); }, fl);
+}
+
 int sim_zc(const Job& J) { return std::min(32, J.ldims[J.level][0]); }
 
 void add_exp_fwd_step(Builder& b, const std::vector<Job*>& jobs, int s, bool recompute_only,
@@ -435,7 +482,7 @@ void add_exp_fwd_step(Builder& b, const std::vector<Job*>& jobs, int s, bool rec
       it.tile0 = tiles;
       it.D = d[0]; it.H = d[1]; it.W = d[2];
       if (s == 0) {
-        it.src = J->field(J->phi, i);
+        it.src = J->flow(i);
         it.a = sign * scale;
       } else {
         it.src = J->u_step(dir, s);
@@ -456,6 +503,7 @@ void add_forward(Builder& b, const std::vector<Job*>& jobs) {
     maxK = std::max(maxK, J->K());
     maxN = std::max(maxN, J->N);
   }
+  add_smooth_flow(b, jobs);
   for (int s = 0; s < maxK; ++s) add_exp_fwd_step(b, jobs, s, false, 0);
   for (int d = 2; d < maxN; ++d) {
     std::vector<ComposeItem> items;
@@ -589,7 +637,7 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
         it.tile0 = tiles;
         it.D = d[0]; it.H = d[1]; it.W = d[2];
         if (s == 0) {
-          it.src = J->field(J->phi, i);
+          it.src = J->flow(i);
           it.a = (fwd ? 1.f : -1.f) * scale;
         } else {
           it.src = J->u_step(dir, s);
@@ -614,6 +662,35 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
     b.add(ST_EXP_BWD, items, tiles, bytes);
   }
   {
+    // gradients of smoothing jobs: combine into t1, then smooth t1 -> t2 -> t1 -> t2
+    std::vector<AdamItem> items;
+    int tiles = 0;
+    double bytes = 0;
+    for (Job* J : jobs) {
+      if (!J->smoothing()) continue;
+      const size_t V = J->Vc();
+      for (int i = 0; i < J->N - 1; ++i) {
+        AdamItem it{};
+        it.tile0 = tiles;
+        it.n = (int)V;
+        it.g0f = J->pp(2 * i, 0);
+        it.g0b = J->pp(2 * i + 1, 0);
+        it.gout = J->field(J->m_t1.as<float>(), i);
+        it.scale = std::ldexp(1.f, -J->K());
+        it.mode = 2;
+        items.push_back(it);
+        tiles += elem_tiles(V);
+        bytes += 36.0 * V;
+      }
+    }
+    b.add(ST_ADAM, items, tiles, bytes);
+    auto t1 = [](Job* J, int i) { return J->field(J->m_t1.as<float>(), i); };
+    auto t2 = [](Job* J, int i) { return J->field(J->m_t2.as<float>(), i); };
+    add_smooth_pass(b, jobs, 0, [&](Job* J, int i) { return (const float*)t1(J, i); }, t2);
+    add_smooth_pass(b, jobs, 1, [&](Job* J, int i) { return (const float*)t2(J, i); }, t1);
+    add_smooth_pass(b, jobs, 2, [&](Job* J, int i) { return (const float*)t1(J, i); }, t2);
+  }
+  {
     std::vector<AdamItem> items;
     int tiles = 0;
     double bytes = 0;
@@ -626,6 +703,7 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
         it.phi = J->field(J->phi, i);
         it.g0f = J->pp(2 * i, 0);
         it.g0b = J->pp(2 * i + 1, 0);
+        it.gsrc = J->smoothing() ? J->field(J->m_t2.as<float>(), i) : nullptr;
         it.m = J->field(J->mbuf, i);
         it.v = J->field(J->vbuf, i);
         it.scale = std::ldexp(1.f, -J->K());
@@ -690,6 +768,7 @@ static int kclass(StageKind k) {
     case ST_EXP_BWD: return MUSTER_K_EXP_BWD;
     case ST_ADAM: return MUSTER_K_ADAM;
     case ST_FINISH: return MUSTER_K_FINISH;
+    case ST_SMOOTH: return MUSTER_K_SMOOTH;
   }
   return MUSTER_K_FINISH;
 }
@@ -708,6 +787,7 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_EXP_BWD: return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, s);
     case ST_ADAM: return launch_adam((const AdamItem*)p, st.n_items, st.n_tiles, s);
     case ST_FINISH: return launch_finish((JobState* const*)p, st.n_items, s);
+    case ST_SMOOTH: return launch_smooth((const SmoothItem*)p, st.n_items, st.n_tiles, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1121,6 +1201,7 @@ muster_status muster_params_default(muster_params* p) {
     p->eps = 1e-8f;
     p->exp_mode = MUSTER_EXP_STORE;
     p->use_graph = 1;
+    p->smooth_sigma = 0.0f;
   });
 }
 
@@ -1306,8 +1387,8 @@ muster_status muster_loss_forward(muster_ctx* h, void* stream, int N, const int 
     plan->run(ctx, s);
     const size_t V = J.Vc();
     for (int i = 0; i < N - 1; ++i)
-      MUSTER_HIP(launch_reg(GridDims{dims[0], dims[1], dims[2]}, svf_dev + (size_t)i * 3 * V,
-                            &J.js->loss_reg, nullptr, s));
+      MUSTER_HIP(launch_reg(GridDims{dims[0], dims[1], dims[2]}, J.flow(i), &J.js->loss_reg,
+                            nullptr, s));
     read_state(J, s);
     if (ctx->timing) resolve_timing(ctx);
     *loss_host = J.host_state->loss_sim + (double)params->alpha_ss / (N - 1) * J.host_state->loss_reg;
@@ -1596,6 +1677,40 @@ muster_status muster_pool2(muster_ctx* h, void* stream, const int dims[3], const
   });
 }
 
+muster_status muster_smooth(muster_ctx* h, void* stream, const int dims[3], float sigma,
+                            const float* src, float* dst) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && src && dst, "NULL argument");
+    NEED(src != dst, "src and dst must differ");
+    check_dims(dims, 1);
+    NEED(sigma > 0.f && (int)(4.0f * sigma + 0.5f) <= MAX_SMOOTH_RADIUS, "sigma must be in (0, 15.8]");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2];
+    DevMem t1, t2;
+    t1.alloc(ctx, 3 * V * sizeof(float));
+    t2.alloc(ctx, 3 * V * sizeof(float));
+    const float* srcs[3] = {src, t1.as<float>(), t2.as<float>()};
+    float* dsts[3] = {t1.as<float>(), t2.as<float>(), dst};
+    size_t offs[3];
+    for (int a = 0; a < 3; ++a) {
+      SmoothItem it{};
+      it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+      it.axis = a;
+      it.sigma = sigma;
+      it.radius = (int)(4.0f * sigma + 0.5f);
+      it.src = srcs[a];
+      it.dst = dsts[a];
+      offs[a] = sc.add(it);
+    }
+    sc.upload();
+    for (int a = 0; a < 3; ++a)
+      MUSTER_HIP(launch_smooth((const SmoothItem*)(sc.dev() + offs[a]), 1, elem_tiles(V), sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
 muster_status muster_upsample2(muster_ctx* h, void* stream, const int dims[3], const float* src,
                                float* dst) {
   Ctx* ctx = C(h);
@@ -1653,7 +1768,7 @@ muster_status muster_kernel_stats_reset(muster_ctx* h) {
 const char* muster_kernel_name(int k) {
   static const char* names[MUSTER_K_COUNT] = {"exp_fwd", "compose_fwd", "sim_stats", "sim_grad",
                                               "compose_bwd", "exp_bwd", "adam", "finish",
-                                              "pool2", "upsample2"};
+                                              "pool2", "upsample2", "smooth"};
   if (k < 0 || k >= MUSTER_K_COUNT) return "";
   return names[k];
 }

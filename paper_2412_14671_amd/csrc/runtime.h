@@ -117,6 +117,7 @@ struct Job {
   std::vector<int> deep_slot;        // N*N -> slot of |i-j| >= 2 pairs, -1 otherwise
 
   DevMem m_phi, m_m, m_v, m_us, m_deep, m_gpair, m_pp, m_coef, m_img, m_state, m_hist;
+  DevMem m_phis, m_t1, m_t2;         // smoothed flow and gradient ping-pong (smoothing on)
   float* phi = nullptr;              // may alias the caller's field in grad_mode
   float* mbuf = nullptr;
   float* vbuf = nullptr;
@@ -129,6 +130,10 @@ struct Job {
 
   ~Job();
   size_t V(int l) const { return (size_t)ldims[l][0] * ldims[l][1] * ldims[l][2]; }
+  float sigma() const { return p.smooth_sigma / (float)(1 << (p.levels - 1 - level)); }
+  bool smoothing() const { return sigma() > 0.f; }
+  // the flow Exp integrates: the smoothed field when smoothing is on
+  float* flow(int i) const { return field(smoothing() ? m_phis.as<float>() : phi, (size_t)i); }
   size_t Vc() const { return V(level); }
   int K() const { return p.K; }
   float* field(float* base, size_t idx) const { return base + idx * 3 * Vc(); }
@@ -152,7 +157,7 @@ void job_final_outputs(Job& job, hipStream_t s);           // final forward + co
 // A launch plan: one iteration (or a forward pass) of a set of jobs.
 enum StageKind {
   ST_EXP_FWD, ST_COMPOSE_FWD, ST_SIM_STATS, ST_SIM_GRAD, ST_COMPOSE_BWD, ST_EXP_BWD, ST_ADAM,
-  ST_FINISH
+  ST_FINISH, ST_SMOOTH
 };
 
 struct Stage {

@@ -67,7 +67,7 @@ def test_params_default(lib):
     assert lib.muster_params_default(ctypes.byref(p)) == L.OK
     assert (p.levels, p.iters[0], p.K, p.window, p.metric) == (1, 100, 7, 5, L.METRIC_LNCC)
     assert abs(p.warmup - 0.2) < 1e-7 and abs(p.alpha_ss - 1.0) < 1e-7
-    assert p.exp_mode == L.EXP_STORE and p.use_graph == 1
+    assert p.exp_mode == L.EXP_STORE and p.use_graph == 1 and p.smooth_sigma == 0.0
 
 
 def _fp(lib, N, dims, **kw):
@@ -95,6 +95,8 @@ def test_footprint_counts_fields(lib):
     assert st2 == L.OK and b2 == b - 4 * (7 - 3) * F
     st3, b3 = _fp(lib, 10, (160, 192, 160))
     assert st3 == L.OK and 20e9 < b3 < 40e9
+    st4, b4 = _fp(lib, 3, (32, 32, 32), smooth_sigma=1.5)
+    assert st4 == L.OK and b4 == b + 3 * 2 * F
 
 
 @pytest.mark.parametrize("N,dims,kw", [
@@ -108,6 +110,8 @@ def test_footprint_counts_fields(lib):
     (3, (32, 32, 32), {"metric": 7}),
     (3, (32, 32, 32), {"levels": 0}),
     (3, (32, 32, 32), {"warmup": 1.5}),
+    (3, (32, 32, 32), {"smooth_sigma": -1.0}),
+    (3, (32, 32, 32), {"smooth_sigma": 20.0}),
 ])
 def test_footprint_rejects_invalid_problems(lib, N, dims, kw):
     st, _ = _fp(lib, N, dims, **kw)

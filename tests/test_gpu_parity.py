@@ -246,3 +246,39 @@ def test_loss_and_gradient_match_oracle(ctx, case, mode):
     L_ref, g_ref, _ = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
     assert abs(float(loss) - L_ref) < 1e-3 * abs(L_ref)
     assert_grad_close(host(svf.grad), np.stack(g_ref))
+
+
+# ---------------------------------------------------------------------------
+# Gaussian smoothing of the flow (Sec. 2.4, Appendix A)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,sigma", [((20, 27, 35), 0.6), ((32, 32, 32), 1.5),
+                                         ((9, 40, 23), 3.0), ((6, 7, 5), 2.0)])
+def test_smooth_matches_oracle(ctx, shape, sigma):
+    log(f"smooth {shape} sigma={sigma}")
+    f = smooth_field(shape, 1.0, seed=int(10 * sigma), sigma=1.0)
+    got = host(ctx.smooth(gpu(f), sigma))
+    assert np.abs(got - O.smooth(f.astype(np.float64), sigma)).max() < 1e-6
+
+
+@pytest.mark.parametrize("case", [
+    dict(shape=(32, 32, 32), N=3, K=7, w=5, metric="lncc", sigma=1.0),
+    dict(shape=(24, 30, 36), N=4, K=5, w=3, metric="silncc", sigma=2.0),
+])
+def test_loss_and_gradient_with_smoothing_match_oracle(ctx, case):
+    from paper_2412_14671_amd import MusterLoss, MusterParams
+    log(f"loss+smooth {case}")
+    shape, N = case["shape"], case["N"]
+    imgs = np.stack([smooth_image(shape, seed=30 + k) for k in range(N)])
+    phis = np.stack([smooth_field(shape, 1.5, seed=40 + k, sigma=1.0) for k in range(N - 1)])
+    svf = gpu(phis).requires_grad_(True)
+    params = MusterParams(K=case["K"], window=case["w"], metric=case["metric"], alpha_ss=0.8,
+                          smooth_sigma=case["sigma"])
+    loss = MusterLoss.apply(svf, gpu(imgs), params, ctx)
+    loss.backward()
+    p = O.Params(K=case["K"], window=case["w"],
+                 metric=O.LNCC if case["metric"] == "lncc" else O.SILNCC, alpha_ss=0.8,
+                 smooth_sigma=case["sigma"])
+    L_ref, g_ref, _ = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
+    assert abs(float(loss.detach()) - L_ref) < 1e-3 * abs(L_ref)
+    assert_grad_close(host(svf.grad), np.stack(g_ref))
