@@ -2,8 +2,9 @@
 
 Default workload: one subject of six 160x192x160 phantom sessions registered
 over a three-level pyramid (40x48x40, 80x96x80, 160x192x160; 200/100/50 Adam
-steps), SiLNCC with a 7^3 window, K = 7 squarings.  A step is one complete
-registration (every step of the path at every level).  The metric counts
+steps), SiLNCC with a 7^3 window, K = 7 squarings, alpha_ss = 0.1 and a
+Gaussian smoothing of the flow with sigma 3 finest-level voxels.  A step is
+one complete registration (every step of the path at every level).  The metric counts
 session-voxel-iterations: sum over levels of N * V_level * steps_level,
 divided by the wall time of a step, with the input series already resident in
 device memory.
@@ -50,6 +51,9 @@ def parse():
     ap.add_argument("--shape", default="160,192,160")
     ap.add_argument("--sessions", type=int, default=6)
     ap.add_argument("--iters", default="200,100,50")
+    ap.add_argument("--alpha", type=float, default=0.1, help="alpha_ss")
+    ap.add_argument("--smooth", type=float, default=3.0,
+                    help="Gaussian smoothing width of the flow, finest-level voxels")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2.0)
     ap.add_argument("--batch-subjects", type=int, default=16)
@@ -144,8 +148,8 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
     log(f"generating {N} sessions of {shape}")
     s = synth.phantom_series(shape, N, seed=2, device=dev)
     images = s.images.contiguous()
-    params = MusterParams(iters=iters, K=7, window=7, metric="silncc", alpha_ss=1.0, lr=0.1,
-                          use_graph=args.graph)
+    params = MusterParams(iters=iters, K=7, window=7, metric="silncc", alpha_ss=args.alpha, lr=0.1,
+                          smooth_sigma=args.smooth, use_graph=args.graph)
     L = len(iters)
     vox_iters = sum(N * np.prod([d // 2 ** (L - 1 - l) for d in shape]) * iters[l]
                     for l in range(L))
@@ -181,7 +185,7 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"one subject, {N} phantom sessions {shape[0]}x{shape[1]}x{shape[2]}, "
                                 f"{L}-level pyramid {'/'.join(map(str, iters))} steps, "
-                                "SiLNCC w7, K7, alpha_ss 1"),
+                                f"SiLNCC w7, K7, alpha_ss {args.alpha:g}, smoothing sigma {args.smooth:g}"),
                    "sessions": N, "dims": list(shape), "levels": L, "iters": iters,
                    "graphs": bool(args.graph)},
         "roofline": roof,
@@ -196,8 +200,9 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
     if not args.no_cpu_baseline:
         from oracle import muster_oracle as O
         log("cpu baseline (oracle)")
-        p = O.Params(K=7, window=7, metric=O.SILNCC, alpha_ss=1.0, lr=0.1)
         coarse = tuple(d // 2 ** (L - 1) for d in shape)
+        p = O.Params(K=7, window=7, metric=O.SILNCC, alpha_ss=args.alpha, lr=0.1,
+                     smooth_sigma=args.smooth / 2 ** (L - 1))
         out["cpu_baseline"] = cpu_baseline_register(s.images.cpu().numpy(), p, coarse)
     return out
 
@@ -209,9 +214,9 @@ def bench_batch(args, ctx, dev, torch, synth, MusterParams):
         log(f"subject {k}: N={N} {shape}")
         subjects.append(synth.batch_subject(100 + k, device=dev))
     params_b = MusterParams(iters=[args.batch_iters], K=7, window=7, metric="silncc", lr=0.1,
-                            use_graph=True)
+                            alpha_ss=args.alpha, smooth_sigma=args.smooth, use_graph=True)
     params_p = MusterParams(iters=[args.batch_iters], K=7, window=7, metric="silncc", lr=0.1,
-                            use_graph=False)
+                            alpha_ss=args.alpha, smooth_sigma=args.smooth, use_graph=False)
     vox = sum(s.images.shape[0] * s.images[0].numel() for s in subjects) * args.batch_iters
     imgs = [s.images for s in subjects]
     torch.cuda.synchronize()
@@ -245,7 +250,8 @@ def bench_serve(args, ctx, dev, torch, synth, MusterParams):
     for k in range(12):
         N, shape = synth.subject_draw(500 + k)
         pool.append(synth.batch_subject(500 + k, device=dev))
-    params = MusterParams(iters=[200, 100, 50], K=7, window=7, metric="silncc", lr=0.1)
+    params = MusterParams(iters=[200, 100, 50], K=7, window=7, metric="silncc", lr=0.1,
+                          alpha_ss=args.alpha, smooth_sigma=args.smooth)
     srv = Server(ctx)
     arrivals = []
     t = 0.0

@@ -89,7 +89,8 @@ typedef struct muster_params {
                                       (Sec. 2.4, Appendix A), in voxels of the
                                       finest level, halved per coarser level;
                                       periodic, truncated at 4 sigma; 0 = off;
-                                      at most 15.8                                */
+                                      at most 15.8; with smoothing on, each
+                                      dimension is at most 4096                   */
 } muster_params;
 
 /* Per-job result summary. */
@@ -240,7 +241,8 @@ muster_status muster_pool2(muster_ctx* ctx, void* stream, const int dims[3],
 /* Gaussian smoothing of a vector field [3][D][H][W] (Sec. 2.4, Appendix A):
  * separable periodic convolution with the sampled Gaussian of width sigma
  * voxels, normalised and truncated at radius int(4 sigma + 0.5) <= 64.
- * src and dst must not overlap. */
+ * Each dimension is at most 4096 (a whole line is staged on chip).
+ * src and dst must not overlap; MUSTER_E_INVALID otherwise. */
 muster_status muster_smooth(muster_ctx* ctx, void* stream, const int dims[3], float sigma,
                             const float* src_dev, float* dst_dev);
 /* Displacement field on the 2x finer grid: dst(x) = 2 * src((x - 0.5)/2);

@@ -1144,51 +1144,127 @@ __global__ __launch_bounds__(BLOCK) void k_adam(const AdamItem* __restrict__ ite
 // the item's radius, on the three components.  The filter is symmetric, so
 // the same pass is its own adjoint.
 // ---------------------------------------------------------------------------
+// SMOOTH_S consecutive outputs, from p0 on, of the circular convolution of a
+// line of n samples held in LDS at line[pos * ls] with the taps w.  The line
+// is read once per chunk; each sample feeds every output it reaches (taps
+// outside 0..2r are zero), so output p0+o sums its taps in the order k = 0..2r.
+__device__ __forceinline__ void smooth_chunk(const float* line, int ls, int n, int p0, int r,
+                                             const float* __restrict__ w,
+                                             float (&acc)[SMOOTH_S]) {
+#pragma unroll
+  for (int o = 0; o < SMOOTH_S; ++o) acc[o] = 0.f;
+  int pos = (p0 - r) % n;
+  if (pos < 0) pos += n;
+  const int m = SMOOTH_S + 2 * r;
+  for (int j = 0; j < m; ++j) {
+    const float v = line[pos * ls];
+#pragma unroll
+    for (int o = 0; o < SMOOTH_S; ++o) acc[o] = fmaf(w[SMOOTH_WPAD + j - o], v, acc[o]);
+    if (++pos == n) pos = 0;
+  }
+}
+
+// One pass of the separable circular Gaussian (Appendix A reading: periodic
+// boundary, truncated sampled kernel of radius int(4 sigma + 0.5)).  A block
+// stages whole lines of one component in LDS, so every sample is read from
+// HBM once and written once.
 __global__ __launch_bounds__(BLOCK) void k_smooth(const SmoothItem* __restrict__ items, int n_items,
                                                   int n_tiles) {
-  __shared__ float w[2 * MAX_SMOOTH_RADIUS + 1];
-  __shared__ float wsum;
-  const int tile = blockIdx.x;
-  const SmoothItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
-  const int r = it.radius;
-  for (int k = threadIdx.x; k <= 2 * r; k += BLOCK) {
-    const float d = (float)(k - r) / it.sigma;
-    w[k] = expf(-0.5f * d * d);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float t = 0.f;
-    for (int k = 0; k <= 2 * r; ++k) t += w[k];
-    wsum = 1.f / t;
-  }
-  __syncthreads();
-  const float norm = wsum;
-  const int n = it.axis == 0 ? D : (it.axis == 1 ? H : W);
-  const int stride = it.axis == 0 ? HW : (it.axis == 1 ? W : 1);
-  const cgfloat* __restrict__ src = gp(it.src);
-  gfloat* __restrict__ dst = gp(it.dst);
-  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
-  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
-    const int q = q0 + k;
-    if (q >= V) break;
-    const int x = q % W, y = (q / W) % H, z = q / HW;
-    const int pos = it.axis == 0 ? z : (it.axis == 1 ? y : x);
-    const int row = q - pos * stride;  // the line's element at position 0
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    for (int t = -r; t <= r; ++t) {
-      int j = pos + t;
-      j %= n;
-      if (j < 0) j += n;
-      const int idx = row + j * stride;
-      const float wt = w[t + r];
-      a0 = fmaf(wt, src[idx], a0);
-      a1 = fmaf(wt, src[V + idx], a1);
-      a2 = fmaf(wt, src[2 * V + idx], a2);
+  extern __shared__ float lds[];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const SmoothItem& it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W;
+  const int V = D * H * W;
+  const int local = tile - it.tile0;
+  const int comp = local / it.tiles_comp;
+  const int t = local - comp * it.tiles_comp;
+  const cgfloat* __restrict__ src = gp(it.src) + comp * V;
+  gfloat* __restrict__ dst = gp(it.dst) + comp * V;
+  const int r = it.radius, L = it.lines, ls = it.lshift;
+  if (it.axis < 2) {
+    // lines along z (axis 0) or y (axis 1); the tile is L adjacent x columns
+    const int n = it.axis == 0 ? D : H;
+    const int stride = it.axis == 0 ? H * W : W;
+    const int nxc = (W + L - 1) >> ls;
+    const int outer = t / nxc;
+    const int x0 = (t - outer * nxc) << ls;
+    const int width = min(L, W - x0);
+    const int base = (it.axis == 0 ? outer * W : outer * H * W) + x0;
+    // SMOOTH_U loads in flight per thread before they land in LDS
+    const int total = n << ls;
+    for (int e0 = threadIdx.x; e0 < total; e0 += BLOCK * SMOOTH_U) {
+      float v[SMOOTH_U];
+#pragma unroll
+      for (int u = 0; u < SMOOTH_U; ++u) {
+        const int e = e0 + u * BLOCK;
+        const int p = e >> ls, c = e & (L - 1);
+        v[u] = (e < total && c < width) ? src[base + p * stride + c] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < SMOOTH_U; ++u) {
+        const int e = e0 + u * BLOCK;
+        if (e < total) lds[e] = v[u];
+      }
     }
-    dst[q] = a0 * norm;
-    dst[V + q] = a1 * norm;
-    dst[2 * V + q] = a2 * norm;
+    __syncthreads();
+    const int c = threadIdx.x & (L - 1);
+    if (c < width) {
+      const int chunks = (n + SMOOTH_S - 1) / SMOOTH_S;
+      for (int q = threadIdx.x >> ls; q < chunks; q += BLOCK >> ls) {
+        const int p0 = q * SMOOTH_S;
+        float acc[SMOOTH_S];
+        smooth_chunk(lds + c, L, n, p0, r, it.w, acc);
+#pragma unroll
+        for (int o = 0; o < SMOOTH_S; ++o)
+          if (p0 + o < n) dst[base + (p0 + o) * stride + c] = acc[o];
+      }
+    }
+  } else {
+    // lines along x: the tile is L consecutive rows, staged with an odd row
+    // pitch so lanes on different rows hit different banks
+    const int Wp = W | 1;
+    const int row0 = t << ls;
+    const int rows = min(L, D * H - row0);
+    float* in = lds;
+    float* out = lds + L * Wp;
+    // the tile is rows * W contiguous floats; e -> (e / W, e % W) through a
+    // float reciprocal, exact here since e < 2^14 leaves a wide margin
+    const int total = rows * W;
+    const float invW = 1.f / (float)W;
+    const cgfloat* __restrict__ tsrc = src + row0 * W;
+    for (int e0 = threadIdx.x; e0 < total; e0 += BLOCK * SMOOTH_U) {
+      float v[SMOOTH_U];
+#pragma unroll
+      for (int u = 0; u < SMOOTH_U; ++u) {
+        const int e = e0 + u * BLOCK;
+        v[u] = e < total ? tsrc[e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < SMOOTH_U; ++u) {
+        const int e = e0 + u * BLOCK;
+        const int row = (int)(((float)e + 0.5f) * invW);
+        if (e < total) in[e + row * (Wp - W)] = v[u];
+      }
+    }
+    __syncthreads();
+    const int rr = threadIdx.x & (L - 1);
+    if (rr < rows) {
+      const int chunks = (W + SMOOTH_S - 1) / SMOOTH_S;
+      for (int q = threadIdx.x >> ls; q < chunks; q += BLOCK >> ls) {
+        const int p0 = q * SMOOTH_S;
+        float acc[SMOOTH_S];
+        smooth_chunk(in + rr * Wp, 1, W, p0, r, it.w, acc);
+#pragma unroll
+        for (int o = 0; o < SMOOTH_S; ++o)
+          if (p0 + o < W) out[rr * Wp + p0 + o] = acc[o];
+      }
+    }
+    __syncthreads();
+    gfloat* __restrict__ tdst = dst + row0 * W;
+    for (int e = threadIdx.x; e < total; e += BLOCK) {
+      const int row = (int)(((float)e + 0.5f) * invW);
+      tdst[e] = out[e + row * (Wp - W)];
+    }
   }
 }
 
@@ -1355,9 +1431,12 @@ hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, hipStream_t s) {
+hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, int lds_floats,
+                         hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_smooth, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  if (lds_floats <= 0 || lds_floats > SMOOTH_LDS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_smooth, dim3(n_tiles), dim3(BLOCK), lds_floats * sizeof(float), s, items,
+                     n_items, n_tiles);
   return hipGetLastError();
 }
 

@@ -122,16 +122,32 @@ struct AdamItem {
   JobState* js;
 };
 
-// One separable pass of the circular Gaussian smoothing along one axis.
+// One separable pass of the circular Gaussian smoothing along one axis, for
+// one field of three components.  A tile holds whole lines of one component
+// in LDS: `lines` adjacent x columns of lines along z or y, or `lines`
+// consecutive rows along x.  Taps w[SMOOTH_WPAD + k] for k = 0..2*radius are
+// the normalised Gaussian weights; every other entry is zero.
+constexpr int MAX_SMOOTH_RADIUS = 64;
+constexpr int SMOOTH_S = 8;                    // outputs per thread along a line
+constexpr int SMOOTH_WPAD = SMOOTH_S;
+constexpr int SMOOTH_U = 8;                    // loads in flight per thread when staging
+constexpr int SMOOTH_WLEN = 2 * MAX_SMOOTH_RADIUS + 1 + 2 * SMOOTH_WPAD;
+constexpr int SMOOTH_LDS = 16384;              // floats of LDS per block, at most
+constexpr int SMOOTH_LDS_TARGET = 8192;        // preferred, for occupancy
+constexpr int SMOOTH_MAX_DIM = 4096;
+
 struct SmoothItem {
   int tile0;
   int D, H, W;
-  int axis;       // 0 = z, 1 = y, 2 = x
+  int axis;        // 0 = z, 1 = y, 2 = x
   int radius;
-  float sigma;
-  int pad;
+  int lines;       // lines per tile, a power of two in 1..64
+  int lshift;      // log2(lines)
+  int tiles_comp;  // tiles per component
+  int pad[3];
   const float* src;
   float* dst;
+  float w[SMOOTH_WLEN];
 };
 
 struct PoolItem {
@@ -176,8 +192,11 @@ hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int 
 hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window,
                            hipStream_t s);
 hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s);
-hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, hipStream_t s);
-constexpr int MAX_SMOOTH_RADIUS = 64;
+hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, int lds_floats,
+                         hipStream_t s);
+// Fills the geometry and taps of a smoothing item; returns its tile count and
+// raises *lds_floats to the LDS the item needs.
+int smooth_item_setup(SmoothItem& it, const int dims[3], int axis, float sigma, int* lds_floats);
 hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s);
 hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_upsample2(const UpItem* items, int n_items, int n_tiles, hipStream_t s);

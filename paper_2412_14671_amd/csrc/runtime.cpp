@@ -139,6 +139,9 @@ void validate_problem(int N, const int dims[3], const muster_params& p, const do
     if (dims[d] / f < p.window)
       fail(MUSTER_E_INVALID, "dims[%d] = %d is smaller than the window at the coarsest level", d,
            dims[d]);
+    if (p.smooth_sigma > 0.f && dims[d] > SMOOTH_MAX_DIM)
+      fail(MUSTER_E_INVALID, "dims[%d] = %d exceeds %d, the longest line smoothing supports", d,
+           dims[d], SMOOTH_MAX_DIM);
     V *= (uint64_t)dims[d];
   }
   if (V * 3 >= (uint64_t)INT32_MAX) fail(MUSTER_E_INVALID, "volume too large (%llu voxels)",
@@ -422,32 +425,58 @@ struct Builder {
   }
 };
 
+}  // namespace
+
+int smooth_item_setup(SmoothItem& it, const int dims[3], int axis, float sigma, int* lds_floats) {
+  it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+  it.axis = axis;
+  const double sg = sigma;
+  const int r = (int)(4.0 * sg + 0.5);
+  it.radius = r;
+  for (int k = 0; k < SMOOTH_WLEN; ++k) it.w[k] = 0.f;
+  double tot = 0.0;
+  for (int k = -r; k <= r; ++k) tot += std::exp(-0.5 * (k / sg) * (k / sg));
+  for (int k = -r; k <= r; ++k)
+    it.w[SMOOTH_WPAD + k + r] = (float)(std::exp(-0.5 * (k / sg) * (k / sg)) / tot);
+  // LDS floats a tile of L lines needs, and the number of lines on offer
+  const int n = dims[axis];
+  const int avail = axis == 2 ? dims[0] * dims[1] : dims[2];
+  auto need = [&](int L) { return axis == 2 ? 2 * L * (dims[2] | 1) : n * L; };
+  int L = 64;
+  while (L > 1 && (L / 2 >= avail || need(L) > SMOOTH_LDS_TARGET)) L /= 2;
+  while (L > 1 && need(L) > SMOOTH_LDS) L /= 2;
+  it.lines = L;
+  it.lshift = 0;
+  while ((1 << it.lshift) < L) ++it.lshift;
+  it.tiles_comp = axis == 2 ? (avail + L - 1) / L
+                            : (axis == 0 ? dims[1] : dims[0]) * ((dims[2] + L - 1) / L);
+  *lds_floats = std::max(*lds_floats, need(L));
+  return 3 * it.tiles_comp;
+}
+
+namespace {
+
 // One separable smoothing pass (axis) for every interval of the smoothing
 // jobs: src(i) -> dst(i).
 template <class SrcF, class DstF>
 void add_smooth_pass(Builder& b, const std::vector<Job*>& jobs, int axis, SrcF src, DstF dst) {
   std::vector<SmoothItem> items;
-  int tiles = 0;
+  int tiles = 0, lds = 0;
   double bytes = 0;
   for (Job* J : jobs) {
     if (!J->smoothing()) continue;
-    const int* d = J->ldims[J->level];
-    const size_t V = J->Vc();
     for (int i = 0; i < J->N - 1; ++i) {
       SmoothItem it{};
       it.tile0 = tiles;
-      it.D = d[0]; it.H = d[1]; it.W = d[2];
-      it.axis = axis;
-      it.sigma = J->sigma();
-      it.radius = (int)(4.0f * it.sigma + 0.5f);
+      tiles += smooth_item_setup(it, J->ldims[J->level], axis, J->sigma(), &lds);
       it.src = src(J, i);
       it.dst = dst(J, i);
       items.push_back(it);
-      tiles += (int)((V + ELEM_PER_BLOCK - 1) / ELEM_PER_BLOCK);
-      bytes += B_SMOOTH * V;
+      bytes += B_SMOOTH * J->Vc();
     }
   }
   b.add(ST_SMOOTH, items, tiles, bytes);
+  if (!items.empty()) b.plan->stages.back().lds = lds;
 }
 
 // phi -> smoothed flow: z into t1, y into t2, x into the flow buffer
@@ -787,7 +816,7 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_EXP_BWD: return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, s);
     case ST_ADAM: return launch_adam((const AdamItem*)p, st.n_items, st.n_tiles, s);
     case ST_FINISH: return launch_finish((JobState* const*)p, st.n_items, s);
-    case ST_SMOOTH: return launch_smooth((const SmoothItem*)p, st.n_items, st.n_tiles, s);
+    case ST_SMOOTH: return launch_smooth((const SmoothItem*)p, st.n_items, st.n_tiles, st.lds, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1685,6 +1714,8 @@ muster_status muster_smooth(muster_ctx* h, void* stream, const int dims[3], floa
     NEED(src != dst, "src and dst must differ");
     check_dims(dims, 1);
     NEED(sigma > 0.f && (int)(4.0f * sigma + 0.5f) <= MAX_SMOOTH_RADIUS, "sigma must be in (0, 15.8]");
+    NEED(dims[0] <= SMOOTH_MAX_DIM && dims[1] <= SMOOTH_MAX_DIM && dims[2] <= SMOOTH_MAX_DIM,
+         "every dimension must be at most 4096");
     std::lock_guard<std::mutex> lk(ctx->mu);
     StepCall sc{ctx, (hipStream_t)stream, {}};
     const size_t V = (size_t)dims[0] * dims[1] * dims[2];
@@ -1694,19 +1725,17 @@ muster_status muster_smooth(muster_ctx* h, void* stream, const int dims[3], floa
     const float* srcs[3] = {src, t1.as<float>(), t2.as<float>()};
     float* dsts[3] = {t1.as<float>(), t2.as<float>(), dst};
     size_t offs[3];
+    int tiles[3], lds[3] = {0, 0, 0};
     for (int a = 0; a < 3; ++a) {
       SmoothItem it{};
-      it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
-      it.axis = a;
-      it.sigma = sigma;
-      it.radius = (int)(4.0f * sigma + 0.5f);
+      tiles[a] = smooth_item_setup(it, dims, a, sigma, &lds[a]);
       it.src = srcs[a];
       it.dst = dsts[a];
       offs[a] = sc.add(it);
     }
     sc.upload();
     for (int a = 0; a < 3; ++a)
-      MUSTER_HIP(launch_smooth((const SmoothItem*)(sc.dev() + offs[a]), 1, elem_tiles(V), sc.s));
+      MUSTER_HIP(launch_smooth((const SmoothItem*)(sc.dev() + offs[a]), 1, tiles[a], lds[a], sc.s));
     MUSTER_HIP(hipStreamSynchronize(sc.s));
   });
 }

@@ -166,6 +166,7 @@ struct Stage {
   int n_items;
   int n_tiles;
   int window = 0, metric = 0, zc = 32;
+  int lds = 0;       // dynamic LDS floats (smoothing)
   double bytes = 0;  // algorithmic bytes of the launch
 };
 

@@ -15,7 +15,8 @@ Recipes (sizes, value ranges) follow the workloads the method is evaluated on:
   * blobs(): a sum of random Gaussian blobs plus Gaussian noise, sessions 2..N
     obtained by flowing one velocity field for times 1, 2, ...;
   * phantom(): a brain-like phantom of three nested smoothed ellipsoids
-    (intensities 0.3/0.6/0.9), a smooth multiplicative bias field of +-10 %
+    (intensities 0.3/0.6/0.9) with a folded texture of amplitude 0.15 inside
+    the outer one, a smooth multiplicative bias field of +-10 %
     per session, Rician noise, unevenly spaced acquisition times and one
     velocity field per interval.
 
@@ -76,16 +77,16 @@ def _grid(shape, device) -> torch.Tensor:
 
 
 def _eval_field(v: torch.Tensor, pts: torch.Tensor) -> torch.Tensor:
-    """Value of the gridded field v (3, D, H, W) at positions pts (3, ...)
+    """Value of the gridded field v (C, D, H, W) at positions pts (3, ...)
     through torch.nn.functional.grid_sample (border padding)."""
-    D, H, W = v.shape[1:]
+    C, D, H, W = v.shape
     shp = pts.shape[1:]
     p = pts.reshape(3, -1)
     # grid_sample wants (x, y, z) in [-1, 1] with align_corners=True
     g = torch.stack([2 * p[2] / (W - 1) - 1, 2 * p[1] / (H - 1) - 1, 2 * p[0] / (D - 1) - 1], -1)
     out = torch.nn.functional.grid_sample(v[None], g[None, None, None], mode="bilinear",
                                           padding_mode="border", align_corners=True)
-    return out.reshape(3, *shp)
+    return out.reshape(C, *shp)
 
 
 def flow(v: torch.Tensor, pts: torch.Tensor, t: float = 1.0, steps: int = 8) -> torch.Tensor:
@@ -124,23 +125,37 @@ class Blobs:
 
 class Phantom:
     """Three nested ellipsoids (outer to inner 0.3, 0.6, 0.9 over a zero
-    background) whose edges are smoothed over about 1.5 voxels."""
+    background) whose edges are smoothed over about 1.5 voxels, plus a folded
+    texture inside the outer ellipsoid: a Gaussian-smoothed random field
+    (sigma 2 voxels) passed through tanh, amplitude 0.15, standing in for the
+    grey/white-matter folding that gives a brain scan features everywhere.
+    The texture is a gridded field read trilinearly, so it is one continuous
+    function of position like the ellipsoids."""
 
-    def __init__(self, shape, rng, edge=1.5):
+    def __init__(self, shape, rng, edge=1.5, texture=0.15, texture_sigma=2.0, device="cpu"):
         dims = np.asarray(shape, np.float64)
         self.centre = dims / 2.0 - 0.5 + rng.uniform(-0.03, 0.03, 3) * dims
         self.axes = []
         for frac in (0.42, 0.32, 0.20):
             self.axes.append(frac * dims * rng.uniform(0.9, 1.1, 3))
         self.edge = edge
+        self.texture = texture
+        t = gaussian_smooth(torch.from_numpy(rng.standard_normal(tuple(shape))).to(device),
+                            texture_sigma)
+        self.tex = torch.tanh(t / t.std())[None].contiguous()
+
+    def _layer(self, pts, a):
+        rho = torch.sqrt(sum(((pts[k] - self.centre[k]) / a[k]) ** 2 for k in range(3)))
+        d = (1.0 - rho) * float(np.exp(np.log(a).mean()))
+        return 0.5 * (1.0 + torch.erf(d / (math.sqrt(2.0) * self.edge)))
 
     def __call__(self, pts: torch.Tensor) -> torch.Tensor:
         out = torch.zeros(pts.shape[1:], dtype=torch.float64, device=pts.device)
         for a in self.axes:
-            rho = torch.sqrt(sum(((pts[k] - self.centre[k]) / a[k]) ** 2 for k in range(3)))
-            d = (1.0 - rho) * float(np.exp(np.log(a).mean()))
-            out += 0.3 * 0.5 * (1.0 + torch.erf(d / (math.sqrt(2.0) * self.edge)))
-        return out
+            out += 0.3 * self._layer(pts, a)
+        if self.texture:
+            out += self.texture * self._layer(pts, self.axes[0]) * _eval_field(self.tex, pts)[0]
+        return out.clamp_min(0.0)
 
 
 def _series_positions(vs: List[torch.Tensor], k: int, g: torch.Tensor, steps: int) -> torch.Tensor:
@@ -181,7 +196,7 @@ def phantom_series(shape=(64, 64, 64), N=4, seed=2, sigma_v=6.0, amp=(0.5, 1.5),
     """Phantom series with per-interval velocity fields, unevenly spaced times,
     a per-session smooth multiplicative bias and Rician noise."""
     rng = _rng(seed)
-    P = Phantom(shape, rng)
+    P = Phantom(shape, rng, device=device)
     gaps = rng.uniform(interval[0], interval[1], N - 1)
     times = np.concatenate([[0.0], np.cumsum(gaps)])
     amps = rng.uniform(amp[0], amp[1], N - 1)
@@ -200,7 +215,7 @@ def phantom_series(shape=(64, 64, 64), N=4, seed=2, sigma_v=6.0, amp=(0.5, 1.5),
         imgs.append(torch.sqrt((x + n1) ** 2 + n2 ** 2))
     images = torch.stack(imgs).float().contiguous()
     svf = torch.stack([-v for v in vs]).float().contiguous()
-    roi = (P(g) > 0.15)
+    roi = P._layer(g, P.axes[0]) > 0.5
     return Series(images, times, svf, roi, f"phantom{shape}")
 
 
