@@ -10,8 +10,9 @@ divided by the wall time of a step, with the input series already resident in
 device memory.
 
 Other workloads (--workload): "batch" (16 subjects of uneven size and session
-count, 100 steps at the finest level, batched graph-replayed loop against the
-per-subject plain loop) and "serve" (Poisson arrivals into the
+count, 100 steps at the finest level, batched graph-replayed loop against two
+per-subject plain loops: this library's kernels launched eagerly, and the same
+loss written op by op in PyTorch eager with autograd) and "serve" (Poisson arrivals into the
 continuous-batching server; p50/p99 latency).
 
 The JSON line carries the roofline of the dominant kernel (algorithmic bytes
@@ -94,6 +95,129 @@ def cpu_baseline_register(series, params_np, level_shape):
             "kind": "oracle",
             "sample": (f"one Adam step of the same {N}-session subject at the coarsest level "
                        f"{tuple(imgs[0].shape)} (NumPy float64, single-threaded), {dt:.1f} s")}
+
+
+# ---------------------------------------------------------------------------
+# Plain per-subject loop in PyTorch eager ops with autograd: the same loss
+# (border-clamped trilinear sampling, scaling and squaring, outward
+# composition, valid-window ML moments, SiLNCC/LNCC, diffusion regulariser,
+# circular Gaussian smoothing) and the same Adam schedule, one op at a time,
+# as the method is written in a tensor framework.  A baseline for the batched
+# path only; nothing in the library uses it.
+# ---------------------------------------------------------------------------
+
+def _torch_sample(torch, f, q):
+    """Border-clamped trilinear sample of f (C, D, H, W) at voxel positions
+    q (3, D', H', W') through grid_sample (align_corners, border padding)."""
+    C, D, H, W = f.shape
+    g = torch.stack([2 * q[2] / (W - 1) - 1, 2 * q[1] / (H - 1) - 1, 2 * q[0] / (D - 1) - 1], -1)
+    return torch.nn.functional.grid_sample(f[None], g[None], mode="bilinear",
+                                           padding_mode="border", align_corners=True)[0]
+
+
+def _torch_smooth(torch, phi, sigma):
+    if sigma <= 0:
+        return phi
+    F = torch.nn.functional
+    r = int(4.0 * sigma + 0.5)
+    k = torch.arange(-r, r + 1, device=phi.device, dtype=torch.float64)
+    w = torch.exp(-0.5 * (k / sigma) ** 2)
+    w = (w / w.sum()).float()
+    x = phi[None]
+    for ax in range(3):
+        shape = [1, 1, 1]
+        shape[ax] = 2 * r + 1
+        pad = [0, 0, 0, 0, 0, 0]
+        pad[2 * (2 - ax)] = pad[2 * (2 - ax) + 1] = r
+        xp = x
+        n = x.shape[2 + ax]
+        while pad[2 * (2 - ax)] > 0:
+            step = min(pad[2 * (2 - ax)], n)
+            pp = [0] * 6
+            pp[2 * (2 - ax)] = pp[2 * (2 - ax) + 1] = step
+            xp = F.pad(xp, pp, mode="circular")
+            pad[2 * (2 - ax)] -= step
+            pad[2 * (2 - ax) + 1] -= step
+            n = xp.shape[2 + ax]
+        x = F.conv3d(xp, w.view(1, 1, *shape).expand(3, 1, *shape).contiguous(), groups=3)
+    return x[0]
+
+
+def torch_loss(torch, phis, images, K=7, window=7, metric="silncc", alpha_ss=1.0,
+               smooth_sigma=0.0):
+    """L(phi) for the list of (3, D, H, W) flows and (N, D, H, W) images."""
+    N = images.shape[0]
+    D, H, W = images.shape[1:]
+    dev = images.device
+    grid = torch.stack(torch.meshgrid(*[torch.arange(n, device=dev, dtype=torch.float32)
+                                        for n in (D, H, W)], indexing="ij"))
+    flows = [_torch_smooth(torch, ph, smooth_sigma) for ph in phis]
+
+    def expo(v):
+        u = v / 2.0 ** K
+        for _ in range(K):
+            u = u + _torch_sample(torch, u, grid + u)
+        return u
+
+    f = [expo(v) for v in flows]
+    b = [expo(-v) for v in flows]
+    pool = torch.nn.functional.avg_pool3d
+    loss = 0.0
+    for i in range(N):
+        U = None
+        for j in range(i + 1, N):
+            U = f[j - 1] if U is None else U + _torch_sample(torch, f[j - 1], grid + U)
+            loss = loss + _torch_sim(torch, pool, images[i], images[j], U, grid, window, metric)
+        U = None
+        for j in range(i - 1, -1, -1):
+            U = b[j] if U is None else U + _torch_sample(torch, b[j], grid + U)
+            loss = loss + _torch_sim(torch, pool, images[i], images[j], U, grid, window, metric)
+    reg = 0.0
+    for ph in flows:
+        for d in range(3):
+            reg = reg + (torch.diff(ph, dim=1 + d) ** 2).mean(dim=(1, 2, 3)).sum()
+    return loss + alpha_ss * reg / (N - 1)
+
+
+def _torch_sim(torch, pool, Fi, Ij, U, grid, w, metric):
+    M = _torch_sample(torch, Ij[None], grid + U)[0]
+    F = Fi
+    st = [pool(x[None, None], w, stride=1)[0, 0] for x in (F, M, F * F, M * M, F * M)]
+    mF, mM = st[0], st[1]
+    vF = torch.clamp(st[2] - mF * mF, min=0.0)
+    vM = torch.clamp(st[3] - mM * mM, min=0.0)
+    c = st[4] - mF * mM
+    if metric == "lncc":
+        ell = 1.0 - c / torch.sqrt(torch.clamp(vF * vM, min=1e-10))
+    else:
+        ell = vM - c * c / torch.clamp(vF, min=1e-6)
+    return ell.mean()
+
+
+def torch_register(torch, images, iters, lr=0.1, warmup=0.2, timed_iters=None, **kw):
+    """Single-level Adam loop on torch_loss; returns (phis, seconds per iteration)."""
+    N = images.shape[0]
+    phis = [torch.zeros((3,) + tuple(images.shape[1:]), device=images.device, requires_grad=True)
+            for _ in range(N - 1)]
+    opt = torch.optim.Adam(phis, lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    T = iters
+    Wu = max(1, math.ceil(warmup * T))
+    n = T if timed_iters is None else min(T, timed_iters)
+    t0 = None
+    for t in range(1, n + 1):
+        if t == 2:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        lr_t = lr * t / Wu if t <= Wu else lr * 0.5 * (1 + math.cos(math.pi * (t - Wu) / (T - Wu)))
+        for g in opt.param_groups:
+            g["lr"] = lr_t
+        opt.zero_grad(set_to_none=True)
+        L = torch_loss(torch, phis, images, **kw)
+        L.backward()
+        opt.step()
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / max(1, n - 1) if t0 is not None else float("nan")
+    return [p.detach() for p in phis], per
 
 
 def roofline_from_stats(stats, traffic=None):
@@ -231,6 +355,24 @@ def bench_batch(args, ctx, dev, torch, synth, MusterParams):
         plain.append(svf)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    # PyTorch-eager plain loop: per-iteration time of every subject (first
+    # iteration untimed), scaled to the same iteration count; one subject runs
+    # the whole schedule to compare the final error
+    t_eager = 0.0
+    for k, s in enumerate(subjects):
+        log(f"torch eager loop, subject {k}")
+        _, per = torch_register(torch, s.images, args.batch_iters, lr=0.1, timed_iters=3, K=7,
+                                window=7, metric="silncc", alpha_ss=args.alpha,
+                                smooth_sigma=args.smooth)
+        t_eager += per * args.batch_iters
+        torch.cuda.empty_cache()
+    kc = min(range(len(subjects)), key=lambda k: subjects[k].images.numel())
+    log(f"torch eager loop, full schedule on subject {kc}")
+    ph_e, _ = torch_register(torch, subjects[kc].images, args.batch_iters, lr=0.1, K=7, window=7,
+                             metric="silncc", alpha_ss=args.alpha, smooth_sigma=args.smooth)
+    sv_e = torch.stack([_torch_smooth(torch, p, args.smooth) for p in ph_e])
+    eu_e = eu(subjects[kc].svf_true.cpu().numpy(), sv_e.cpu().numpy(), subjects[kc].roi.cpu().numpy())
+    torch.cuda.empty_cache()
     eu_b = [eu(s.svf_true.cpu().numpy(), o.cpu().numpy(), s.roi.cpu().numpy()) for s, o in zip(subjects, outs)]
     eu_p = [eu(s.svf_true.cpu().numpy(), o.cpu().numpy(), s.roi.cpu().numpy()) for s, o in zip(subjects, plain)]
     return {"metric": "voxel-iterations/sec (fwd+bwd) batched vs plain loop",
@@ -240,6 +382,10 @@ def bench_batch(args, ctx, dev, torch, synth, MusterParams):
             "config": {"workload": f"{len(subjects)} subjects, N in 3..10, sizes from 96^3/128^3/160x192x160, "
                                    f"{args.batch_iters} steps at the finest level, SiLNCC w7, K7"},
             "plain_loop_value": round(vox / tp, 1), "batched_over_plain": round(tp / tb, 3),
+            "torch_eager_loop_value": round(vox / t_eager, 1),
+            "batched_over_torch_eager": round(t_eager / tb, 3),
+            "torch_eager_eu_check": {"subject": kc, "eu_torch_eager": round(eu_e, 4),
+                                     "eu_batched": round(eu_b[kc], 4)},
             "eu_batched": [round(x, 4) for x in eu_b], "eu_plain": [round(x, 4) for x in eu_p]}
 
 
@@ -270,6 +416,8 @@ def bench_serve(args, ctx, dev, torch, synth, MusterParams):
     reps = [srv.wait(tk) for tk, _, _ in tickets]
     wall = time.perf_counter() - t0
     lat = np.array([r["seconds"] for r in reps])
+    eus = [eu(pool[k].svf_true.cpu().numpy(), out.cpu().numpy(), pool[k].roi.cpu().numpy())
+           for (_, k, out), r in zip(tickets, reps) if r["status"] == 0]
     vox = sum(pool[k].images.shape[0] * sum(pool[k].images[0].numel() // 8 ** (2 - l) * it
                                             for l, it in enumerate([200, 100, 50]))
               for _, k, _ in tickets)
@@ -282,7 +430,12 @@ def bench_serve(args, ctx, dev, torch, synth, MusterParams):
                                    "N in 3..10, sizes from 96^3/128^3/160x192x160, pyramid 200/100/50"},
             "jobs_per_s": round(len(tickets) / wall, 3), "p50_s": round(float(np.percentile(lat, 50)), 3),
             "p99_s": round(float(np.percentile(lat, 99)), 3),
-            "failed": int(sum(r["status"] != 0 for r in reps))}
+            "eu_mean": round(float(np.mean(eus)), 4) if eus else None,
+            "eu_max": round(float(np.max(eus)), 4) if eus else None,
+            "queue_p50_s": round(float(np.percentile([r["queue_seconds"] for r in reps], 50)), 3),
+            "service_mean_s": round(float(np.mean([r["seconds"] - r["queue_seconds"] for r in reps])), 3),
+            "failed": int(sum(r["status"] != 0 for r in reps)),
+            "failed_status": sorted({int(r["status"]) for r in reps if r["status"] != 0})}
 
 
 if __name__ == "__main__":

@@ -120,7 +120,8 @@ typedef struct muster_job {
 /* ---- context -------------------------------------------------------------- */
 
 /* Create a context on HIP device `device`.  hbm_budget bounds the device
- * bytes the context may hold for workspaces (0 = no bound beyond the device).
+ * bytes the context may hold for workspaces (0 = 80 % of the device memory
+ * free at creation).  The server admits jobs while their footprints fit it.
  * The context owns its arena, internal streams, graphs and autotune cache. */
 muster_status muster_ctx_create(int device, uint64_t hbm_budget, muster_ctx** out);
 /* Destroy a context (waits for its work; stops its server thread). */

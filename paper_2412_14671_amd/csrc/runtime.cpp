@@ -1178,6 +1178,13 @@ muster_status muster_ctx_create(int device, uint64_t hbm_budget, muster_ctx** ou
     MUSTER_HIP(hipGetDeviceCount(&n));
     NEED(device >= 0 && device < n, "device %d out of range (%d devices)", device, n);
     MUSTER_HIP(hipSetDevice(device));
+    if (hbm_budget == 0) {
+      // no bound given: 80 % of what is free on the device now, so that
+      // admission by footprint never runs the device out of memory
+      size_t free_b = 0, total_b = 0;
+      MUSTER_HIP(hipMemGetInfo(&free_b, &total_b));
+      hbm_budget = (uint64_t)(0.8 * (double)free_b);
+    }
     auto c = std::make_unique<Ctx>(hbm_budget);
     c->device = device;
     MUSTER_HIP(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking));
