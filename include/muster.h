@@ -126,6 +126,30 @@ typedef struct muster_job {
 muster_status muster_ctx_create(int device, uint64_t hbm_budget, muster_ctx** out);
 /* Destroy a context (waits for its work; stops its server thread). */
 muster_status muster_ctx_destroy(muster_ctx* ctx);
+
+/* Tiling of the window-statistics kernels (warp + moments + Sim, and their
+ * adjoint; Sec. 2.6).  A block owns a tile of window centres of shape
+ * 0 = 8 x 32, 1 = 16 x 32 or 2 = 8 x 64 (y x x) and marches through a chunk
+ * of `zchunk` slices in z.  Modes:
+ *   MUSTER_TILES_DEFAULT  shape 0, zchunk 32;
+ *   MUSTER_TILES_AUTOTUNE (the default) the fastest of every shape and
+ *                         zchunk in {16, 32, 64}, timed once per problem
+ *                         shape (D, H, W, window, metric) on scratch data of
+ *                         that shape, then cached in the context (and, when
+ *                         the environment variable MUSTER_TUNE_CACHE names a
+ *                         file, appended to it and read back by later
+ *                         contexts);
+ *   MUSTER_TILES_FIXED    the given shape and zchunk.
+ * zchunk is capped at D.  Results do not depend on the tiling beyond float
+ * rounding.  MUSTER_E_INVALID for an unknown mode, shape or zchunk < 1. */
+#define MUSTER_TILES_DEFAULT 0
+#define MUSTER_TILES_AUTOTUNE 1
+#define MUSTER_TILES_FIXED 2
+muster_status muster_ctx_set_tiling(muster_ctx* ctx, int mode, int shape, int zchunk);
+/* The tiling the context uses for one problem shape (tuning it now, on
+ * `stream`, if the mode is AUTOTUNE and it is not cached). */
+muster_status muster_ctx_sim_tiling(muster_ctx* ctx, void* stream, const int dims[3], int window,
+                                    int metric, int* shape, int* zchunk);
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* muster_last_error(void);
 /* Library version string. */

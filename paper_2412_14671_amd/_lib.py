@@ -20,6 +20,8 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_BUSY, E_NONFINITE, E_CANCELLED, E_INTERNAL =
 STATUS_NAMES = ["OK", "E_INVALID", "E_NOMEM", "E_DEVICE", "E_BUSY", "E_NONFINITE",
                 "E_CANCELLED", "E_INTERNAL"]
 METRIC_LNCC, METRIC_SILNCC = 0, 1
+TILES_DEFAULT, TILES_AUTOTUNE, TILES_FIXED = 0, 1, 2
+SIM_SHAPES = [(8, 32), (16, 32), (8, 64)]
 EXP_STORE, EXP_RECOMPUTE = 0, 1
 KERNELS = ["exp_fwd", "compose_fwd", "sim_stats", "sim_grad", "compose_bwd", "exp_bwd", "adam",
            "finish", "pool2", "upsample2", "smooth"]
@@ -94,6 +96,8 @@ SIGNATURES = {
     "muster_pool2": (_ST, [_P, _P, DIMS, _P, _P]),
     "muster_upsample2": (_ST, [_P, _P, DIMS, _P, _P]),
     "muster_smooth": (_ST, [_P, _P, DIMS, c_float, _P, _P]),
+    "muster_ctx_set_tiling": (_ST, [_P, c_int, c_int, c_int]),
+    "muster_ctx_sim_tiling": (_ST, [_P, _P, DIMS, c_int, c_int, POINTER(c_int), POINTER(c_int)]),
     "muster_set_kernel_timing": (_ST, [_P, c_int]),
     "muster_kernel_stats": (_ST, [_P, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
     "muster_kernel_stats_reset": (_ST, [_P]),

@@ -119,6 +119,20 @@ class Context:
                                             _ptr(U_prev), _ptr(C), _ptr(G), _ptr(G_prev),
                                             _ptr(G_C)))
 
+    # -- tiling of the window statistics ---------------------------------------------
+    def set_tiling(self, mode: str = "autotune", shape: int = 0, zchunk: int = 32):
+        """mode "default" (8x32 centres, 32 slices), "autotune" or "fixed"."""
+        m = {"default": L.TILES_DEFAULT, "autotune": L.TILES_AUTOTUNE, "fixed": L.TILES_FIXED}[mode]
+        L.check(self.lib.muster_ctx_set_tiling(self.h, m, shape, zchunk))
+
+    def sim_tiling(self, dims, window=7, metric="silncc"):
+        """(shape index, z chunk) the context uses for this problem shape."""
+        m = {"lncc": L.METRIC_LNCC, "silncc": L.METRIC_SILNCC}[metric]
+        sh, zc = c_int(), c_int()
+        L.check(self.lib.muster_ctx_sim_tiling(self.h, _stream(), _dims(dims), window, m, byref(sh),
+                                               byref(zc)))
+        return sh.value, zc.value
+
     def sim(self, F, I, U, window, metric="lncc", grad=False):
         m = {"lncc": L.METRIC_LNCC, "silncc": L.METRIC_SILNCC}[metric]
         val = c_double()

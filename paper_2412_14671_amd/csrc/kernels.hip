@@ -160,13 +160,15 @@ __device__ __forceinline__ PTile point_tile(int local, int H, int W) {
   return t;
 }
 
+// Sum over a block of NT threads; the result is valid in thread 0.
+template <int NT = BLOCK>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < BLOCK / 64; ++i) s += red[i];
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
   return s;
 }
 
@@ -711,49 +713,53 @@ struct STile {
   int z0, z1, y0, x0;
 };
 
+template <int TY, int TX>
 __device__ __forceinline__ STile stat_tile(int local, int D, int H, int W, int zc) {
-  const int ntx = (W + ST_X - 1) / ST_X;
-  const int nty = (H + ST_Y - 1) / ST_Y;
+  const int ntx = (W + TX - 1) / TX;
+  const int nty = (H + TY - 1) / TY;
   STile t;
-  t.x0 = (local % ntx) * ST_X;
+  t.x0 = (local % ntx) * TX;
   const int r = local / ntx;
-  t.y0 = (r % nty) * ST_Y;
+  t.y0 = (r % nty) * TY;
   t.z0 = (r / nty) * zc;
   t.z1 = min(t.z0 + zc, D);
   return t;
 }
 
-// Column slots: a thread owns the patch columns threadIdx.x + k * BLOCK.
-template <int R>
+// A block of TY x TX threads owns TY x TX window centres; its patch of
+// columns is (TY + 2R) x (TX + 2R), and a thread owns the patch columns
+// threadIdx.x + k * NT.
+template <int R, int TY, int TX>
 struct Patch {
+  static constexpr int NT = TY * TX;
   static constexpr int WN = 2 * R + 1;
-  static constexpr int PY = ST_Y + 2 * R, PX = ST_X + 2 * R, P1 = PY * PX;
-  static constexpr int NS = (P1 + BLOCK - 1) / BLOCK;
+  static constexpr int PY = TY + 2 * R, PX = TX + 2 * R, P1 = PY * PX;
+  static constexpr int NS = (P1 + NT - 1) / NT;
 };
 
-template <int R>
-__global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__ items, int n_items,
-                                                     int n_tiles, int metric) {
-  using P = Patch<R>;
-  constexpr int WN = P::WN, PY = P::PY, PX = P::PX, P1 = P::P1, NS = P::NS;
+template <int R, int TY, int TX>
+__global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict__ items, int n_items,
+                                                       int n_tiles, int metric) {
+  using P = Patch<R, TY, TX>;
+  constexpr int WN = P::WN, PY = P::PY, PX = P::PX, P1 = P::P1, NS = P::NS, NT = P::NT;
   __shared__ float rF[WN][P1];
   __shared__ float rM[WN][P1];
   __shared__ float zs[5][P1];
-  __shared__ float xs[5][PY * ST_X];
-  __shared__ double red[BLOCK / 64];
+  __shared__ float xs[5][PY * TX];
+  __shared__ double red[NT / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const SimItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
-  const STile tc = stat_tile(tile - it.tile0, D, H, W, it.zc);
+  const STile tc = stat_tile<TY, TX>(tile - it.tile0, D, H, W, it.zc);
   const cgfloat* __restrict__ F = gp(it.F);
   const cgfloat* __restrict__ I = gp(it.I);
   const cgfloat* __restrict__ U = gp(it.U);
   gfloat* __restrict__ coef = gp(it.coef);
-  const int pm = (min((tc.z0 + tc.z1) / 2, D - 1) * H + min(tc.y0 + ST_Y / 2, H - 1)) * W +
-                 min(tc.x0 + ST_X / 2, W - 1);
+  const int pm = (min((tc.z0 + tc.z1) / 2, D - 1) * H + min(tc.y0 + TY / 2, H - 1)) * W +
+                 min(tc.x0 + TX / 2, W - 1);
   const float sF = F[pm], sM = I[pm];
   const float inv_n = 1.f / (float)(WN * WN * WN);
-  const int ty = threadIdx.x / ST_X, tx = threadIdx.x % ST_X;
+  const int ty = threadIdx.x / TX, tx = threadIdx.x % TX;
   const int y = tc.y0 + ty, x = tc.x0 + tx;
   const bool yx_in = (y < H) && (x < W);
   const bool yx_valid = yx_in && y >= R && y <= H - 1 - R && x >= R && x <= W - 1 - R;
@@ -762,7 +768,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
   bool cin[NS], cval[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    const int col = threadIdx.x + k * BLOCK;
+    const int col = threadIdx.x + k * NT;
     cval[k] = col < P1;
     cyy[k] = tc.y0 - R + col / PX;
     cxx[k] = tc.x0 - R + col % PX;
@@ -820,7 +826,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (!cval[k]) continue;
-      const int col = threadIdx.x + k * BLOCK;
+      const int col = threadIdx.x + k * NT;
       rF[slot][col] = fv0[k];
       rM[slot][col] = mv0[k];
     }
@@ -833,7 +839,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
     if (zcen >= tc.z0) {
       const bool zvalid = zcen >= R && zcen <= D - 1 - R;
       if (zvalid) {
-        for (int col = threadIdx.x; col < P1; col += BLOCK) {
+        for (int col = threadIdx.x; col < P1; col += NT) {
           float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
           for (int k = 0; k < WN; ++k) {
@@ -847,8 +853,8 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
           zs[0][col] = s0; zs[1][col] = s1; zs[2][col] = s2; zs[3][col] = s3; zs[4][col] = s4;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < PY * ST_X; e += BLOCK) {
-          const int row = e / ST_X, c = e % ST_X;
+        for (int e = threadIdx.x; e < PY * TX; e += NT) {
+          const int row = e / TX, c = e % TX;
           const int b = row * PX + c;
 #pragma unroll
           for (int q = 0; q < 5; ++q) {
@@ -869,7 +875,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
           for (int q = 0; q < 5; ++q) {
             float acc = 0.f;
 #pragma unroll
-            for (int k = 0; k < WN; ++k) acc += xs[q][(ty + k) * ST_X + tx];
+            for (int k = 0; k < WN; ++k) acc += xs[q][(ty + k) * TX + tx];
             S[q] = acc;
           }
           const float mF = S[0] * inv_n, mM = S[1] * inv_n;
@@ -920,7 +926,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
       u1[k][2] = u2[k][2];
     }
   }
-  const double tot = block_sum(lsum, red);
+  const double tot = block_sum<NT>(lsum, red);
   if (threadIdx.x == 0) {
     const double v = tot * it.inv_nr;
     if (it.js) unsafeAtomicAdd(&it.js->loss_sim, v);
@@ -933,32 +939,32 @@ __global__ __launch_bounds__(BLOCK) void k_sim_stats(const SimItem* __restrict__
 //   dSim/dU(y) = dSim/dM(y) * grad I_j(y + U(y)).
 // Pipelined like k_sim_stats: coefficients of the next slice and the output
 // voxel's loads are issued before the current slice's sums.
-template <int R>
-__global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ items, int n_items,
-                                                    int n_tiles) {
-  using P = Patch<R>;
-  constexpr int WN = P::WN, PY = P::PY, PX = P::PX, P1 = P::P1, NS = P::NS;
+template <int R, int TY, int TX>
+__global__ __launch_bounds__(TY * TX) void k_sim_grad(const SimItem* __restrict__ items, int n_items,
+                                                      int n_tiles) {
+  using P = Patch<R, TY, TX>;
+  constexpr int WN = P::WN, PY = P::PY, PX = P::PX, P1 = P::P1, NS = P::NS, NT = P::NT;
   __shared__ float ring[3][WN][P1];
   __shared__ float zs[3][P1];
-  __shared__ float xs[3][PY * ST_X];
+  __shared__ float xs[3][PY * TX];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const SimItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
-  const STile tc = stat_tile(tile - it.tile0, D, H, W, it.zc);
+  const STile tc = stat_tile<TY, TX>(tile - it.tile0, D, H, W, it.zc);
   const cgfloat* __restrict__ F = gp(it.F);
   const cgfloat* __restrict__ I = gp(it.I);
   const cgfloat* __restrict__ U = gp(it.U);
   const cgfloat* __restrict__ coef = gp(it.coef);
   gfloat* __restrict__ gU = gp(it.gU);
   const float inv_nr = (float)it.inv_nr;
-  const int ty = threadIdx.x / ST_X, tx = threadIdx.x % ST_X;
+  const int ty = threadIdx.x / TX, tx = threadIdx.x % TX;
   const int y = tc.y0 + ty, x = tc.x0 + tx;
   const bool yx_in = y < H && x < W;
   int cyy[NS], cxx[NS];
   bool cin[NS], cval[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    const int col = threadIdx.x + k * BLOCK;
+    const int col = threadIdx.x + k * NT;
     cval[k] = col < P1;
     cyy[k] = tc.y0 - R + col / PX;
     cxx[k] = tc.x0 - R + col % PX;
@@ -991,7 +997,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (!cval[k]) continue;
-      const int col = threadIdx.x + k * BLOCK;
+      const int col = threadIdx.x + k * NT;
       ring[0][slot][col] = c0[k][0];
       ring[1][slot][col] = c0[k][1];
       ring[2][slot][col] = c0[k][2];
@@ -1016,7 +1022,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
     load_uo(out_now ? zo + 1 : tc.z0, un);
     __syncthreads();
     if (out_now) {
-      for (int col = threadIdx.x; col < P1; col += BLOCK) {
+      for (int col = threadIdx.x; col < P1; col += NT) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           float acc = 0.f;
@@ -1026,8 +1032,8 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
         }
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < PY * ST_X; e += BLOCK) {
-        const int row = e / ST_X, c = e % ST_X;
+      for (int e = threadIdx.x; e < PY * TX; e += NT) {
+        const int row = e / TX, c = e % TX;
         const int b = row * PX + c;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -1044,7 +1050,7 @@ __global__ __launch_bounds__(BLOCK) void k_sim_grad(const SimItem* __restrict__ 
         for (int q = 0; q < 3; ++q) {
           float acc = 0.f;
 #pragma unroll
-          for (int k = 0; k < WN; ++k) acc += xs[q][(ty + k) * ST_X + tx];
+          for (int k = 0; k < WN; ++k) acc += xs[q][(ty + k) * TX + tx];
           B[q] = acc;
         }
         const int p = (zo * H + y) * W + x;
@@ -1401,28 +1407,48 @@ hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_ti
   return hipGetLastError();
 }
 
-hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,
-                            hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  switch (window) {
-    case 3: hipLaunchKernelGGL(k_sim_stats<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, metric); break;
-    case 5: hipLaunchKernelGGL(k_sim_stats<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, metric); break;
-    case 7: hipLaunchKernelGGL(k_sim_stats<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles, metric); break;
+template <int R, int TY, int TX>
+static void sim_launch(bool grad, const SimItem* items, int n_items, int n_tiles, int metric,
+                       hipStream_t s) {
+  if (grad)
+    hipLaunchKernelGGL((k_sim_grad<R, TY, TX>), dim3(n_tiles), dim3(TY * TX), 0, s, items, n_items,
+                       n_tiles);
+  else
+    hipLaunchKernelGGL((k_sim_stats<R, TY, TX>), dim3(n_tiles), dim3(TY * TX), 0, s, items,
+                       n_items, n_tiles, metric);
+}
+
+template <int R>
+static hipError_t sim_shape(bool grad, const SimItem* items, int n_items, int n_tiles, int metric,
+                            int shape, hipStream_t s) {
+  switch (shape) {
+    case 0: sim_launch<R, 8, 32>(grad, items, n_items, n_tiles, metric, s); break;
+    case 1: sim_launch<R, 16, 32>(grad, items, n_items, n_tiles, metric, s); break;
+    case 2: sim_launch<R, 8, 64>(grad, items, n_items, n_tiles, metric, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window,
-                           hipStream_t s) {
+static hipError_t sim_window(bool grad, const SimItem* items, int n_items, int n_tiles, int window,
+                             int metric, int shape, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   switch (window) {
-    case 3: hipLaunchKernelGGL(k_sim_grad<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
-    case 5: hipLaunchKernelGGL(k_sim_grad<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
-    case 7: hipLaunchKernelGGL(k_sim_grad<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 3: return sim_shape<1>(grad, items, n_items, n_tiles, metric, shape, s);
+    case 5: return sim_shape<2>(grad, items, n_items, n_tiles, metric, shape, s);
+    case 7: return sim_shape<3>(grad, items, n_items, n_tiles, metric, shape, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+}
+
+hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,
+                            int shape, hipStream_t s) {
+  return sim_window(false, items, n_items, n_tiles, window, metric, shape, s);
+}
+
+hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window, int shape,
+                           hipStream_t s) {
+  return sim_window(true, items, n_items, n_tiles, window, 0, shape, s);
 }
 
 hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s) {
@@ -1437,6 +1463,26 @@ hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, int 
   if (lds_floats <= 0 || lds_floats > SMOOTH_LDS) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_smooth, dim3(n_tiles), dim3(BLOCK), lds_floats * sizeof(float), s, items,
                      n_items, n_tiles);
+  return hipGetLastError();
+}
+
+__global__ void k_pattern(float* __restrict__ p, int64_t n, int D, int H, int W, float off,
+                          float amp, float phase) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t V = (int64_t)D * H * W;
+  const int c = (int)(i / V);
+  const int q = (int)(i - c * V);
+  const int x = q % W, y = (q / W) % H, z = q / (W * H);
+  p[i] = off + amp * sinf(0.21f * x + 0.13f * y + 0.17f * z + phase + 1.7f * c) *
+                   cosf(0.05f * x - 0.09f * z + phase);
+}
+
+hipError_t launch_pattern(float* p, int64_t n, const int dims[3], float off, float amp,
+                          float phase, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pattern, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, dims[0],
+                     dims[1], dims[2], off, amp, phase);
   return hipGetLastError();
 }
 

@@ -170,15 +170,19 @@ constexpr int PT_VOX = PT_Z * PT_Y * PT_X;
 constexpr int BLOCK = 256;
 constexpr int SCATTER_CELLS = 3072;            // LDS bins per component
 // Tiles of the windowed-statistics kernels: TY x TX columns, z chunks.
-constexpr int ST_Y = 8, ST_X = 32;
+// Tile shapes (centres in y x x) of the window-statistics kernels; the block
+// has one thread per centre.
+constexpr int SIM_SHAPES = 3;
+constexpr int SIM_SHAPE_Y[SIM_SHAPES] = {8, 16, 8};
+constexpr int SIM_SHAPE_X[SIM_SHAPES] = {32, 32, 64};
 constexpr int ELEM_PER_BLOCK = 1024;           // elementwise kernels
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 inline int point_tiles(int D, int H, int W) {
   return ceil_div(D, PT_Z) * ceil_div(H, PT_Y) * ceil_div(W, PT_X);
 }
-inline int stat_tiles(int D, int H, int W, int zc) {
-  return ceil_div(D, zc) * ceil_div(H, ST_Y) * ceil_div(W, ST_X);
+inline int stat_tiles(int D, int H, int W, int zc, int shape) {
+  return ceil_div(D, zc) * ceil_div(H, SIM_SHAPE_Y[shape]) * ceil_div(W, SIM_SHAPE_X[shape]);
 }
 
 // Launchers (kernels.hip).  All return hipError_t of the launch.
@@ -188,8 +192,8 @@ hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, hip
 hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
                               hipStream_t s);
 hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,
-                            hipStream_t s);
-hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window,
+                            int shape, hipStream_t s);
+hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window, int shape,
                            hipStream_t s);
 hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, int lds_floats,
@@ -204,5 +208,9 @@ hipError_t launch_adam_flat(int64_t n, float* x, const float* g, float* m, float
                             float lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+// p[c][z][y][x] = off + amp * (a smooth periodic pattern); scratch data for
+// the autotuner.
+hipError_t launch_pattern(float* p, int64_t n, const int dims[3], float off, float amp,
+                          float phase, hipStream_t s);
 
 }  // namespace muster

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace muster {
@@ -365,6 +366,7 @@ void job_begin_level(Job& J, int level, hipStream_t s) {
   st.hist_base = base;
   *J.host_state = st;
   MUSTER_HIP(hipMemcpyAsync(J.js, J.host_state, sizeof(JobState), hipMemcpyHostToDevice, s));
+  J.sim_tile[level] = choose_sim_tile(ctx, J.ldims[level], J.p.window, J.p.metric, s);
   MUSTER_HIP(hipStreamSynchronize(s));
 }
 
@@ -490,7 +492,6 @@ void add_smooth_flow(Builder& b, const std::vector<Job*>& jobs) {
   add_smooth_pass(b, jobs, 2, [&](Job* J, int i) { return (const float*)t2(J, i); }, fl);
 }
 
-int sim_zc(const Job& J) { return std::min(32, J.ldims[J.level][0]); }
 
 void add_exp_fwd_step(Builder& b, const std::vector<Job*>& jobs, int s, bool recompute_only,
                       int upto) {
@@ -566,15 +567,17 @@ void add_forward(Builder& b, const std::vector<Job*>& jobs) {
   }
 }
 
-std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int& tiles, double& vox) {
+// The pair items of the jobs whose window statistics use tile shape `shape`.
+std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int shape, int& tiles, double& vox) {
   std::vector<SimItem> items;
   tiles = 0;
   vox = 0;
   for (Job* J : jobs) {
+    const SimTile& tl = J->sim_tile[J->level];
+    if (tl.shape != shape) continue;
     const int N = J->N;
     const int* d = J->ldims[J->level];
     const int r = (J->p.window - 1) / 2;
-    const int zc = sim_zc(*J);
     const double nr = (double)(d[0] - 2 * r) * (d[1] - 2 * r) * (d[2] - 2 * r);
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) {
@@ -582,7 +585,7 @@ std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int& tiles, double
         SimItem it{};
         it.tile0 = tiles;
         it.D = d[0]; it.H = d[1]; it.W = d[2];
-        it.zc = zc;
+        it.zc = tl.zc;
         it.F = J->image(i);
         it.I = J->image(j);
         it.U = J->pair_field(i, j);
@@ -592,11 +595,25 @@ std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int& tiles, double
         it.js = J->js;
         it.sim_out = nullptr;
         items.push_back(it);
-        tiles += stat_tiles(d[0], d[1], d[2], zc);
+        tiles += stat_tiles(d[0], d[1], d[2], tl.zc, shape);
         vox += (double)J->Vc();
       }
   }
   return items;
+}
+
+// One window-statistics stage per tile shape in use.
+void add_sim_stages(Builder& b, const std::vector<Job*>& jobs, StageKind kind) {
+  const int window = jobs[0]->p.window, metric = jobs[0]->p.metric;
+  for (int shape = 0; shape < SIM_SHAPES; ++shape) {
+    int tiles;
+    double vox;
+    auto items = sim_items(jobs, shape, tiles, vox);
+    if (items.empty()) continue;
+    const double per = kind == ST_SIM_STATS ? B_SIM_STATS : B_SIM_GRAD;
+    b.add(kind, items, tiles, per * vox, window, kind == ST_SIM_STATS ? metric : 0);
+    b.plan->stages.back().shape = shape;
+  }
 }
 
 void add_backward(Builder& b, const std::vector<Job*>& jobs) {
@@ -605,13 +622,7 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
     maxK = std::max(maxK, J->K());
     maxN = std::max(maxN, J->N);
   }
-  const int window = jobs[0]->p.window;
-  {
-    int tiles;
-    double vox;
-    auto items = sim_items(jobs, tiles, vox);
-    b.add(ST_SIM_GRAD, items, tiles, B_SIM_GRAD * vox, window, 0);
-  }
+  add_sim_stages(b, jobs, ST_SIM_GRAD);
   for (int d = maxN - 1; d >= 2; --d) {
     std::vector<ComposeBwdItem> items;
     int tiles = 0;
@@ -760,12 +771,7 @@ std::unique_ptr<Plan> build_plan(const std::vector<Job*>& jobs, PlanScope scope)
     if (J->p.window != window || J->p.metric != metric)
       fail(MUSTER_E_INVALID, "jobs batched together must share window and metric");
   if (scope == PLAN_ITERATION || scope == PLAN_FORWARD || scope == PLAN_LOSS_FWD) add_forward(b, jobs);
-  if (scope == PLAN_ITERATION || scope == PLAN_LOSS_FWD) {
-    int tiles;
-    double vox;
-    auto items = sim_items(jobs, tiles, vox);
-    b.add(ST_SIM_STATS, items, tiles, B_SIM_STATS * vox, window, metric);
-  }
+  if (scope == PLAN_ITERATION || scope == PLAN_LOSS_FWD) add_sim_stages(b, jobs, ST_SIM_STATS);
   if (scope == PLAN_ITERATION || scope == PLAN_LOSS_BWD) add_backward(b, jobs);
   if (scope == PLAN_ITERATION) {
     std::vector<JobState*> st;
@@ -808,9 +814,10 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_EXP_FWD: return launch_exp_fwd((const ExpFwdItem*)p, st.n_items, st.n_tiles, s);
     case ST_COMPOSE_FWD: return launch_compose_fwd((const ComposeItem*)p, st.n_items, st.n_tiles, s);
     case ST_SIM_STATS:
-      return launch_sim_stats((const SimItem*)p, st.n_items, st.n_tiles, st.window, st.metric, s);
+      return launch_sim_stats((const SimItem*)p, st.n_items, st.n_tiles, st.window, st.metric,
+                              st.shape, s);
     case ST_SIM_GRAD:
-      return launch_sim_grad((const SimItem*)p, st.n_items, st.n_tiles, st.window, s);
+      return launch_sim_grad((const SimItem*)p, st.n_items, st.n_tiles, st.window, st.shape, s);
     case ST_COMPOSE_BWD:
       return launch_compose_bwd((const ComposeBwdItem*)p, st.n_items, st.n_tiles, s);
     case ST_EXP_BWD: return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, s);
@@ -1109,6 +1116,161 @@ void Server::loop() {
   (void)hipStreamDestroy(s);
 }
 
+
+// ---------------------------------------------------------------------------
+// Autotuner of the window-statistics tiling.  Each candidate (tile shape,
+// z chunk) runs the statistics and gradient kernels on a scratch problem of
+// the same shape (two patterned images and a patterned pair field), one
+// untimed and three timed repetitions; the fastest median wins.  Results are
+// kept per context and, with MUSTER_TUNE_CACHE set, appended to that file and
+// read back by later contexts.
+// ---------------------------------------------------------------------------
+namespace {
+
+std::vector<int> tune_key(const int d[3], int window, int metric) {
+  return {d[0], d[1], d[2], window, metric};
+}
+
+void save_tune_entry(Ctx* ctx, const std::vector<int>& k, const SimTile& t) {
+  if (ctx->tune_path.empty()) return;
+  FILE* f = std::fopen(ctx->tune_path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4], t.shape, t.zc);
+  std::fclose(f);
+}
+
+SimTile default_sim_tile(const int dims[3]) {
+  SimTile t;
+  t.shape = 0;
+  t.zc = std::min(32, dims[0]);
+  return t;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    MUSTER_HIP(hipEventCreate(&a));
+    MUSTER_HIP(hipEventCreate(&b));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+SimTile tune_sim_tile(Ctx* ctx, const int dims[3], int window, int metric, hipStream_t s) {
+  // A launch of the real path carries every pair of a job (6 to 90), so the
+  // scratch launch carries several pairs with distinct fields, as many as
+  // fit 1.5 GB, at most 8.
+  const size_t V = (size_t)dims[0] * dims[1] * dims[2];
+  const size_t per_pair = 9 * V * sizeof(float);
+  const int P = (int)std::max<size_t>(1, std::min<size_t>(8, ((size_t)1536 << 20) / per_pair));
+  DevMem img, fld, acc, item;
+  img.alloc(ctx, 2 * V * sizeof(float));
+  fld.alloc(ctx, (size_t)P * per_pair);
+  acc.alloc(ctx, sizeof(double));
+  item.alloc(ctx, (size_t)P * sizeof(SimItem));
+  MUSTER_HIP(launch_pattern(img.as<float>(), (int64_t)(2 * V), dims, 0.5f, 0.4f, 0.3f, s));
+  MUSTER_HIP(launch_pattern(fld.as<float>(), (int64_t)(9 * V * P), dims, 0.f, 1.5f, 1.1f, s));
+  const int r = (window - 1) / 2;
+  std::vector<SimItem> its(P);
+  for (int k = 0; k < P; ++k) {
+    SimItem& it = its[k];
+    float* base = fld.as<float>() + (size_t)k * 9 * V;
+    it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.F = img.as<float>();
+    it.I = img.as<float>() + V;
+    it.U = base;
+    it.coef = base + 3 * V;
+    it.gU = base + 6 * V;
+    it.inv_nr = 1.0 / ((double)(dims[0] - 2 * r) * (dims[1] - 2 * r) * (dims[2] - 2 * r));
+    it.js = nullptr;
+    it.sim_out = acc.as<double>();
+  }
+  std::vector<int> zcs;
+  for (int z : {16, 32, 64}) {
+    const int zc = std::min(z, dims[0]);
+    if (std::find(zcs.begin(), zcs.end(), zc) == zcs.end()) zcs.push_back(zc);
+  }
+  EventPair ev;
+  SimTile best = default_sim_tile(dims);
+  float best_ms = 1e30f;
+  for (int shape = 0; shape < SIM_SHAPES; ++shape)
+    for (int zc : zcs) {
+      const int per = stat_tiles(dims[0], dims[1], dims[2], zc, shape);
+      for (int k = 0; k < P; ++k) {
+        its[k].zc = zc;
+        its[k].tile0 = k * per;
+      }
+      MUSTER_HIP(hipMemcpyAsync(item.p, its.data(), (size_t)P * sizeof(SimItem),
+                                hipMemcpyHostToDevice, s));
+      const SimItem* d_it = item.as<SimItem>();
+      auto once = [&] {
+        MUSTER_HIP(launch_sim_stats(d_it, P, P * per, window, metric, shape, s));
+        MUSTER_HIP(launch_sim_grad(d_it, P, P * per, window, shape, s));
+      };
+      once();
+      float t[3];
+      for (float& x : t) {
+        MUSTER_HIP(hipEventRecord(ev.a, s));
+        once();
+        MUSTER_HIP(hipEventRecord(ev.b, s));
+        MUSTER_HIP(hipEventSynchronize(ev.b));
+        MUSTER_HIP(hipEventElapsedTime(&x, ev.a, ev.b));
+      }
+      std::sort(t, t + 3);
+      if (std::getenv("MUSTER_TUNE_VERBOSE"))
+        std::fprintf(stderr, "muster tune %dx%dx%d w%d m%d (%d pairs): shape %d zchunk %d  %.4f ms\n",
+                     dims[0], dims[1], dims[2], window, metric, P, shape, zc, (double)t[1]);
+      if (t[1] < best_ms) {
+        best_ms = t[1];
+        best.shape = shape;
+        best.zc = zc;
+      }
+    }
+  MUSTER_HIP(hipStreamSynchronize(s));
+  return best;
+}
+
+}  // namespace
+
+void load_tune_cache(Ctx* ctx) {
+  const char* path = std::getenv("MUSTER_TUNE_CACHE");
+  if (!path || !*path) return;
+  ctx->tune_path = path;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int D, H, W, w, m, sh, zc;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d", &D, &H, &W, &w, &m, &sh, &zc) == 7)
+    if (sh >= 0 && sh < SIM_SHAPES && zc >= 1 && zc <= D) ctx->tuned[{D, H, W, w, m}] = SimTile{sh, zc};
+  std::fclose(f);
+}
+
+SimTile choose_sim_tile(Ctx* ctx, const int dims[3], int window, int metric, hipStream_t s) {
+  if (ctx->tile_mode == MUSTER_TILES_DEFAULT) return default_sim_tile(dims);
+  if (ctx->tile_mode == MUSTER_TILES_FIXED) {
+    SimTile t = ctx->fixed_tile;
+    t.zc = std::min(t.zc, dims[0]);
+    return t;
+  }
+  const auto key = tune_key(dims, window, metric);
+  {
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    auto f = ctx->tuned.find(key);
+    if (f != ctx->tuned.end()) return f->second;
+  }
+  SimTile t;
+  try {
+    t = tune_sim_tile(ctx, dims, window, metric, s);
+  } catch (const Error& e) {
+    if (e.st != MUSTER_E_NOMEM) throw;
+    return default_sim_tile(dims);  // no room for the scratch problem now: do not cache
+  }
+  std::lock_guard<std::mutex> lk(ctx->tune_mu);
+  if (ctx->tuned.emplace(key, t).second) save_tune_entry(ctx, key, t);
+  return t;
+}
+
 }  // namespace muster
 
 // ===========================================================================
@@ -1187,6 +1349,7 @@ muster_status muster_ctx_create(int device, uint64_t hbm_budget, muster_ctx** ou
     }
     auto c = std::make_unique<Ctx>(hbm_budget);
     c->device = device;
+    load_tune_cache(c.get());
     MUSTER_HIP(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking));
     c->step_items_bytes = 1 << 20;
     c->step_items = c->arena.try_alloc(c->step_items_bytes);
@@ -1421,7 +1584,6 @@ muster_status muster_loss_forward(muster_ctx* h, void* stream, int N, const int 
     auto plan = build_plan(one, PLAN_LOSS_FWD);
     plan->upload(ctx, s);
     plan->run(ctx, s);
-    const size_t V = J.Vc();
     for (int i = 0; i < N - 1; ++i)
       MUSTER_HIP(launch_reg(GridDims{dims[0], dims[1], dims[2]}, J.flow(i), &J.js->loss_reg,
                             nullptr, s));
@@ -1639,10 +1801,10 @@ muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int win
     DevMem coef;
     if (grad_U) coef.alloc(ctx, 3 * V * sizeof(float));
     const int r = (window - 1) / 2;
-    const int zc = std::min(32, dims[0]);
+    const SimTile tl = choose_sim_tile(ctx, dims, window, metric, sc.s);
     SimItem it{};
     it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
-    it.zc = zc;
+    it.zc = tl.zc;
     it.F = F;
     it.I = I;
     it.U = U;
@@ -1654,10 +1816,12 @@ muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int win
     const size_t off = sc.add(it);
     sc.upload();
     MUSTER_HIP(hipMemsetAsync(ctx->step_acc, 0, sizeof(double), sc.s));
-    const int tiles = stat_tiles(dims[0], dims[1], dims[2], zc);
-    MUSTER_HIP(launch_sim_stats((const SimItem*)(sc.dev() + off), 1, tiles, window, metric, sc.s));
+    const int tiles = stat_tiles(dims[0], dims[1], dims[2], tl.zc, tl.shape);
+    MUSTER_HIP(launch_sim_stats((const SimItem*)(sc.dev() + off), 1, tiles, window, metric,
+                                tl.shape, sc.s));
     if (grad_U)
-      MUSTER_HIP(launch_sim_grad((const SimItem*)(sc.dev() + off), 1, tiles, window, sc.s));
+      MUSTER_HIP(launch_sim_grad((const SimItem*)(sc.dev() + off), 1, tiles, window, tl.shape,
+                                 sc.s));
     MUSTER_HIP(hipMemcpyAsync(sim_host, ctx->step_acc, sizeof(double), hipMemcpyDeviceToHost, sc.s));
     MUSTER_HIP(hipStreamSynchronize(sc.s));
   });
@@ -1769,6 +1933,37 @@ muster_status muster_upsample2(muster_ctx* h, void* stream, const int dims[3], c
 }
 
 // ---- measurement ----------------------------------------------------------------
+
+muster_status muster_ctx_set_tiling(muster_ctx* h, int mode, int shape, int zchunk) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx, "NULL context");
+    NEED(mode == MUSTER_TILES_DEFAULT || mode == MUSTER_TILES_AUTOTUNE || mode == MUSTER_TILES_FIXED,
+         "unknown tiling mode %d", mode);
+    if (mode == MUSTER_TILES_FIXED) {
+      NEED(shape >= 0 && shape < SIM_SHAPES, "shape must be in 0..%d", SIM_SHAPES - 1);
+      NEED(zchunk >= 1, "zchunk must be positive");
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tile_mode = mode;
+    if (mode == MUSTER_TILES_FIXED) ctx->fixed_tile = SimTile{shape, zchunk};
+  });
+}
+
+muster_status muster_ctx_sim_tiling(muster_ctx* h, void* stream, const int dims[3], int window,
+                                    int metric, int* shape, int* zchunk) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && shape && zchunk, "NULL argument");
+    NEED(window == 3 || window == 5 || window == 7, "window must be 3, 5 or 7");
+    NEED(metric == MUSTER_METRIC_LNCC || metric == MUSTER_METRIC_SILNCC, "unknown metric");
+    check_dims(dims, window);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const SimTile t = choose_sim_tile(ctx, dims, window, metric, (hipStream_t)stream);
+    *shape = t.shape;
+    *zchunk = t.zc;
+  });
+}
 
 muster_status muster_set_kernel_timing(muster_ctx* h, int enable) {
   Ctx* ctx = C(h);

@@ -63,6 +63,13 @@ struct KernelStats {
 
 struct Server;
 
+// Tile choice of the window-statistics kernels (shape index into
+// SIM_SHAPE_Y/X, and the z extent of a block's chunk).
+struct SimTile {
+  int shape = 0;
+  int zc = 32;
+};
+
 struct Ctx {
   int device = 0;
   Arena arena;
@@ -75,6 +82,13 @@ struct Ctx {
   size_t step_items_bytes = 0;
   double* step_acc = nullptr;        // device doubles for single-step results
   std::unique_ptr<Server> server;
+  // tiling of the window statistics: MUSTER_TILES_* mode, the fixed choice,
+  // and the autotuner's results keyed by (D, H, W, window, metric)
+  int tile_mode = MUSTER_TILES_AUTOTUNE;
+  SimTile fixed_tile;
+  std::map<std::vector<int>, SimTile> tuned;
+  std::string tune_path;             // optional on-disk cache (MUSTER_TUNE_CACHE)
+  std::mutex tune_mu;
   explicit Ctx(uint64_t budget) : arena(budget) {}
 };
 
@@ -115,6 +129,7 @@ struct Job {
   int level = 0;                     // current pyramid level (0 = coarsest)
   int ldims[MUSTER_MAX_LEVELS][3];
   std::vector<int> deep_slot;        // N*N -> slot of |i-j| >= 2 pairs, -1 otherwise
+  SimTile sim_tile[MUSTER_MAX_LEVELS];
 
   DevMem m_phi, m_m, m_v, m_us, m_deep, m_gpair, m_pp, m_coef, m_img, m_state, m_hist;
   DevMem m_phis, m_t1, m_t2;         // smoothed flow and gradient ping-pong (smoothing on)
@@ -153,6 +168,10 @@ void validate_problem(int N, const int dims[3], const muster_params& p, const do
 std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& j);
 void job_begin_level(Job& job, int level, hipStream_t s);   // pyramid, init/upsample, zero state
 void job_final_outputs(Job& job, hipStream_t s);           // final forward + copies to the caller
+// The window-statistics tiling for one problem shape under the context's
+// mode; autotuning times every candidate once on scratch data on stream s.
+SimTile choose_sim_tile(Ctx* ctx, const int dims[3], int window, int metric, hipStream_t s);
+void load_tune_cache(Ctx* ctx);
 
 // A launch plan: one iteration (or a forward pass) of a set of jobs.
 enum StageKind {
@@ -167,6 +186,7 @@ struct Stage {
   int n_tiles;
   int window = 0, metric = 0, zc = 32;
   int lds = 0;       // dynamic LDS floats (smoothing)
+  int shape = 0;     // window-statistics tile shape
   double bytes = 0;  // algorithmic bytes of the launch
 };
 

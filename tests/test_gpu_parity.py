@@ -282,3 +282,28 @@ def test_loss_and_gradient_with_smoothing_match_oracle(ctx, case):
     L_ref, g_ref, _ = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
     assert abs(float(loss.detach()) - L_ref) < 1e-3 * abs(L_ref)
     assert_grad_close(host(svf.grad), np.stack(g_ref))
+
+
+# ---------------------------------------------------------------------------
+# Every tile shape and z chunk of the window statistics (the autotuner's
+# candidates, plus chunks that leave ragged tails) against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape_id,zc", [(1, 32), (2, 16), (0, 5), (1, 7), (2, 64)])
+@pytest.mark.parametrize("w,metric", [(3, "lncc"), (5, "silncc"), (7, "silncc")])
+def test_sim_every_tiling_matches_oracle(ctx, shape_id, zc, w, metric):
+    log(f"sim tiling shape={shape_id} zc={zc} w={w} {metric}")
+    shape = (21, 26, 45) if shape_id != 2 else (40, 17, 70)
+    F = smooth_image(shape, seed=w + 10)
+    I = smooth_image(shape, seed=w + 11)
+    U = smooth_field(shape, 2.0, seed=w + 12)
+    ctx.set_tiling("fixed", shape_id, zc)
+    try:
+        val, g = ctx.sim(gpu(F), gpu(I), gpu(U), w, metric, grad=True)
+    finally:
+        ctx.set_tiling("autotune")
+    p = O.Params(window=w, metric=O.LNCC if metric == "lncc" else O.SILNCC)
+    s_ref, g_ref = O.pair_sim_grad([F.astype(np.float64), I.astype(np.float64)],
+                                   U.astype(np.float64), 0, 1, p)
+    assert abs(val - s_ref) < 1e-3 * abs(s_ref)
+    assert_grad_close(host(g), g_ref)

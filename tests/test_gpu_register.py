@@ -185,3 +185,25 @@ def test_server_results_match_alone(ctx):
     st = srv.stats()
     assert st["resident"] == 0 and st["queued"] == 0
     c2.close()
+
+
+def test_autotuned_tiling_is_valid_cached_and_reproducible():
+    """The autotuner returns a valid tiling, caches it, and a registration
+    under it equals one under the same tiling fixed by hand."""
+    from paper_2412_14671_amd import Context, MusterParams, synth
+    c = Context(0)
+    try:
+        sh, zc = c.sim_tiling((48, 40, 56), 7, "silncc")
+        log(f"autotuned tiling for 48x40x56 w7: shape {sh}, zchunk {zc}")
+        assert 0 <= sh < 3 and 1 <= zc <= 48
+        assert c.sim_tiling((48, 40, 56), 7, "silncc") == (sh, zc)
+        s = synth.phantom_series((48, 40, 56), 3, seed=21)
+        imgs = s.images.to(DEV)
+        params = MusterParams(iters=[15], K=7, window=7, metric="silncc", use_graph=False)
+        a, _, ra = c.register(imgs, s.times, params)
+        c.set_tiling("fixed", sh, zc)
+        b, _, rb = c.register(imgs, s.times, params)
+        assert_same_run(a, b, "autotuned vs fixed")
+        assert abs(ra["loss_last"] - rb["loss_last"]) <= 1e-6 * abs(ra["loss_last"])
+    finally:
+        c.close()
