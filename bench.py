@@ -45,8 +45,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured graphs in the timed region (no per-kernel timing)")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON with HBM traffic per launch of the dominant kernel from rocprofv3 counters")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
+                                                     "exp_bwd_phantom6_160x192x160_traffic.txt"),
+                    help="JSON summary of rocprofv3 FETCH_SIZE/WRITE_SIZE passes for the dominant "
+                         "kernel (per grid size); used only if it matches the current kernels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter calibration)")
     ap.add_argument("--shape", default="160,192,160")
@@ -220,15 +222,36 @@ def torch_register(torch, images, iters, lr=0.1, warmup=0.2, timed_iters=None, *
     return [p.detach() for p in phis], per
 
 
+def traffic_per_launch(path, kernel, launch_grids):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    weighted like the timed launches ({grid in blocks: launches}); None if the
+    summary is absent, covers another kernel or predates the current kernels."""
+    import hashlib
+    if not path or not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2412_14671_amd", "csrc", "kernels.hip")
+    if t.get("kernel") != kernel or t.get("kernels_hip_sha256") != hashlib.sha256(
+            open(src, "rb").read()).hexdigest():
+        return None
+    ff, wf = t["calibration"]["fetch_factor"], t["calibration"]["write_factor"]
+    tot = n = 0
+    for grid, launches in launch_grids.items():
+        e = t["per_grid"].get(str(grid))
+        if e is None:
+            return None
+        tot += launches * (e["fetch_kib"] * ff + e["write_kib"] * wf) * 1024.0
+        n += launches
+    return round(tot / n) if n else None
+
+
 def roofline_from_stats(stats, traffic=None):
     best = max(stats.items(), key=lambda kv: kv[1]["ms"])
     name, st = best
     if st["launches"] == 0 or st["ms"] <= 0:
         return name, None
     achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
-    tr = None
-    if traffic and traffic.get("kernel") == name:
-        tr = traffic.get("bytes_per_launch")
+    tr = traffic.get(name) if traffic else None
     return name, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
                   "kernel": name, "launches": st["launches"],
@@ -297,7 +320,13 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
     roi = s.roi.cpu().numpy()
     svf_np = svf.cpu().numpy()
     true_np = s.svf_true.cpu().numpy()
-    traffic = json.load(open(args.traffic)) if args.traffic else None
+    # exp_bwd launches per level: K per iteration, tiles 2(N-1) x point tiles (8x8x16)
+    grids = {}
+    for l in range(L):
+        d = [x // 2 ** (L - 1 - l) for x in shape]
+        g = 2 * (N - 1) * (-(-d[0] // 8)) * (-(-d[1] // 8)) * (-(-d[2] // 16))
+        grids[g] = grids.get(g, 0) + 7 * iters[l] * args.steps
+    traffic = {"exp_bwd": traffic_per_launch(args.traffic, "exp_bwd", grids)}
     kname, roof = roofline_from_stats(stats, traffic)
     out = {
         "metric": "voxel-iterations/sec (fwd+bwd)",

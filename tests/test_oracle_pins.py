@@ -540,6 +540,20 @@ def test_smoothing_matches_scipy_gaussian_filter_wrap(sigma):
     assert np.abs(O.smooth(x, sigma) - want).max() < 1e-13
 
 
+@pytest.mark.parametrize("sigma", [1.5, 2.0, 3.0])
+def test_smoothing_matches_the_fourier_domain_gaussian_of_appendix_a(sigma):
+    """Appendix A filters with the transfer function exp(-(omega sigma)^2 / 2)
+    (omega_s = 1/sigma) on the periodic grid.  The truncated sampled kernel
+    differs from it only by the tail mass beyond 4 sigma (about 6e-5) and the
+    aliasing of the sampled Gaussian (exp(-pi^2 sigma^2 / 2))."""
+    x = rng(102).standard_normal((3, 16, 20, 24))
+    w = [2 * np.pi * np.fft.fftfreq(n) for n in x.shape[1:]]
+    tf = np.exp(-0.5 * sigma ** 2 * (w[0][:, None, None] ** 2 + w[1][None, :, None] ** 2
+                                      + w[2][None, None, :] ** 2))
+    want = np.real(np.fft.ifftn(np.fft.fftn(x, axes=(1, 2, 3)) * tf, axes=(1, 2, 3)))
+    assert np.abs(O.smooth(x, sigma) - want).max() < 3e-4 * np.abs(x).max()
+
+
 def test_smoothing_is_self_adjoint_and_keeps_constants():
     r = rng(101)
     a = r.standard_normal((3, 8, 9, 10))
@@ -547,6 +561,7 @@ def test_smoothing_is_self_adjoint_and_keeps_constants():
     assert abs(np.sum(O.smooth(a, 1.3) * b) - np.sum(a * O.smooth(b, 1.3))) < 1e-10
     c = np.full((3, 6, 7, 8), 2.5)
     assert np.allclose(O.smooth(c, 2.0), c, atol=1e-14)
+    assert np.allclose(O.smooth(a, 1.3).mean(axis=(1, 2, 3)), a.mean(axis=(1, 2, 3)), atol=1e-13)
     assert np.array_equal(O.smooth(a, 0.0), a)
 
 
