@@ -39,7 +39,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -419,12 +419,62 @@ def smooth(phi: np.ndarray, sigma: float) -> np.ndarray:
 # Loss and gradient (Sec. 2.2 loss, Sec. 2.4 Eq. reg_sum)
 # ---------------------------------------------------------------------------
 
+def reg_l2(phi: np.ndarray) -> float:
+    """Squared L2 norm of one flow (the second form of Eq. reg_ss): the mean
+    over voxels of the squared vector norm, so that its weight does not
+    depend on the grid size (the same reading as L_ss)."""
+    phi = np.asarray(phi, np.float64)
+    return float((phi ** 2).sum(axis=0).mean())
+
+
+def reg_l2_grad(phi: np.ndarray) -> np.ndarray:
+    phi = np.asarray(phi, np.float64)
+    return 2.0 * phi / phi[0].size
+
+
+def reg_ts(phis: List[np.ndarray], times: Sequence[float]) -> float:
+    """Temporal smoothness (Eq. reg_ts): for each inner session k the flow of
+    the interval before it and the flow of the interval after it, each divided
+    by its interval length, should agree; the mean over voxels of the squared
+    vector norm of their difference, averaged over the N-2 inner sessions.
+    The earlier interval's flow is read as phi_{k-1,k} (the flow forward in
+    time), under which a flow proportional to the interval length costs
+    nothing.  Zero for N = 2."""
+    N = len(phis) + 1
+    if N < 3:
+        return 0.0
+    dt = np.diff(np.asarray(times, np.float64))
+    tot = 0.0
+    for k in range(1, N - 1):
+        a = np.asarray(phis[k - 1], np.float64) / dt[k - 1] - np.asarray(phis[k], np.float64) / dt[k]
+        tot += float((a ** 2).sum(axis=0).mean())
+    return tot / (N - 2)
+
+
+def reg_ts_grad(phis: List[np.ndarray], times: Sequence[float]) -> List[np.ndarray]:
+    """d reg_ts / d phi_i for every interval i."""
+    N = len(phis) + 1
+    g = [np.zeros_like(np.asarray(x, np.float64)) for x in phis]
+    if N < 3:
+        return g
+    dt = np.diff(np.asarray(times, np.float64))
+    V = np.asarray(phis[0])[0].size
+    for k in range(1, N - 1):
+        a = np.asarray(phis[k - 1], np.float64) / dt[k - 1] - np.asarray(phis[k], np.float64) / dt[k]
+        g[k - 1] += 2.0 * a / (dt[k - 1] * V * (N - 2))
+        g[k] -= 2.0 * a / (dt[k] * V * (N - 2))
+    return g
+
+
 @dataclass
 class Params:
     K: int = 7                 # squarings in Exp
     window: int = 5            # w, the window edge
     metric: int = LNCC         # LNCC or SILNCC
     alpha_ss: float = 1.0      # weight of L_ss
+    alpha_l2: float = 0.0      # weight of L_L2
+    alpha_ts: float = 0.0      # weight of L_ts (needs times)
+    times: Optional[Tuple[float, ...]] = None  # acquisition times t_1..t_N
     smooth_sigma: float = 0.0  # Gaussian smoothing of the flow (voxels of the level); 0 = none
     lr: float = 0.1            # peak learning rate (voxels per step)
     warmup: float = 0.2        # warm-up fraction of each stage
@@ -434,7 +484,8 @@ class Params:
 
 
 def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: bool = False):
-    """Evaluate L(phi) = sum_i sum_{j != i} Sim(I_i, I_j o Phi_ji^i) + alpha_ss L_ss.
+    """Evaluate L(phi) = sum_i sum_{j != i} Sim(I_i, I_j o Phi_ji^i) + alpha_ss L_ss
+    + alpha_L2 L_L2 + alpha_ts L_ts (Eq. reg_sum).
 
     The flow is first smoothed (smooth_sigma > 0); Exp and L_ss act on the
     smoothed flow.  Returns the loss and, with keep=True, every intermediate
@@ -453,6 +504,10 @@ def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: b
         sims[(i, j)] = similarity(imgs[i], M, p.window, p.metric)
     Lsim = float(sum(sims.values()))
     Lreg = p.alpha_ss * sum(reg_ss(ph) for ph in phis) / (N - 1)
+    if p.alpha_l2:
+        Lreg += p.alpha_l2 * sum(reg_l2(ph) for ph in phis) / (N - 1)
+    if p.alpha_ts:
+        Lreg += p.alpha_ts * reg_ts(phis, p.times)
     L = Lsim + Lreg
     if not keep:
         return L
@@ -499,11 +554,16 @@ def loss_and_grad(phis: List[np.ndarray], images: List[np.ndarray], p: Params):
     aux["Gf"], aux["Gb"] = Gf, Gb
     grads = []
     scale = 2.0 ** -p.K
+    gts = reg_ts_grad(aux["phis_s"], p.times) if p.alpha_ts else None
     for i in range(len(phis)):
         g0f = exp_bwd(aux["fwd"][i], Gf[i])
         g0b = exp_bwd(aux["bwd"][i], Gb[i])
         g = scale * (g0f - g0b)
         g = g + p.alpha_ss / (N - 1) * reg_ss_grad(aux["phis_s"][i])
+        if p.alpha_l2:
+            g = g + p.alpha_l2 / (N - 1) * reg_l2_grad(aux["phis_s"][i])
+        if p.alpha_ts:
+            g = g + p.alpha_ts * gts[i]
         # the smoothing is self-adjoint
         grads.append(smooth(g, p.smooth_sigma))
     return L, grads, aux

@@ -581,3 +581,77 @@ def test_T13_gradient_with_smoothing_matches_finite_differences():
         pm[k][idx] -= h
         fd = (O.forward(pp, imgs, p) - O.forward(pm, imgs, p)) / (2 * h)
         assert abs(fd - grads[k][idx]) < 1e-6 * gmax + 1e-5 * abs(fd)
+
+
+# --------------------------------------------------------------------------
+# L_L2 and L_ts (Sec. 2.4, the second form of Eq. reg_ss, Eq. reg_ts, Eq. reg_sum)
+# --------------------------------------------------------------------------
+
+def test_l2_and_ts_of_constant_fields_have_closed_forms():
+    shape = (5, 6, 7)
+    a = np.array([0.3, -1.2, 0.5])
+    b = np.array([1.0, 0.25, -0.75])
+    fa = np.broadcast_to(a[:, None, None, None], (3,) + shape).copy()
+    fb = np.broadcast_to(b[:, None, None, None], (3,) + shape).copy()
+    assert abs(O.reg_l2(fa) - (a ** 2).sum()) < 1e-14
+    # N = 3, intervals 0.5 and 2: the single inner session compares a/0.5 with b/2
+    times = (1.0, 1.5, 3.5)
+    assert abs(O.reg_ts([fa, fb], times) - ((a / 0.5 - b / 2.0) ** 2).sum()) < 1e-13
+    assert O.reg_ts([fa], (0.0, 1.0)) == 0.0
+
+
+def test_ts_is_zero_for_flow_proportional_to_the_interval_and_not_for_the_sign_flip():
+    """The premise of Eq. reg_ts: a deformation flow proportional to time costs
+    nothing.  Under the literal phi_{i,i-1} = -phi_{i-1,i} reading it would
+    cost 4 |v|^2 instead; this pins the reading."""
+    v = smooth_field((6, 7, 8), 1.0, seed=3)
+    times = (0.0, 0.7, 2.2, 2.9, 4.0)
+    dt = np.diff(times)
+    phis = [v * d for d in dt]
+    assert O.reg_ts(phis, times) < 1e-28
+    literal = np.mean([(((-phis[k - 1]) / dt[k - 1] - phis[k] / dt[k]) ** 2).sum(axis=0).mean()
+                       for k in range(1, 4)])
+    assert abs(literal - 4 * (v ** 2).sum(axis=0).mean()) < 1e-12
+
+
+def test_l2_and_ts_gradients_match_finite_differences():
+    r = rng(7)
+    phis = [0.5 * r.standard_normal((3, 4, 5, 6)) for _ in range(3)]
+    times = (0.0, 1.3, 1.9, 3.4)
+    h = 1e-6
+    g_ts = O.reg_ts_grad(phis, times)
+    for trial in range(12):
+        i = int(r.integers(0, 3))
+        idx = tuple(int(r.integers(0, n)) for n in phis[i].shape)
+        up = [x.copy() for x in phis]
+        dn = [x.copy() for x in phis]
+        up[i][idx] += h
+        dn[i][idx] -= h
+        fd = (O.reg_ts(up, times) - O.reg_ts(dn, times)) / (2 * h)
+        assert abs(fd - g_ts[i][idx]) < 1e-7 * max(1.0, abs(fd))
+        fd2 = (O.reg_l2(up[i]) - O.reg_l2(dn[i])) / (2 * h)
+        assert abs(fd2 - O.reg_l2_grad(phis[i])[idx]) < 1e-8
+
+
+def test_total_loss_gradient_with_l2_and_ts_matches_finite_differences():
+    """Whole loss (similarity + all three regularisers + smoothing) against
+    central differences on sampled parameters."""
+    shape = (8, 9, 10)
+    r = rng(11)
+    import scipy.ndimage as ndi
+    imgs = [ndi.gaussian_filter(rng(40 + k).uniform(0, 1, shape), 1.0) for k in range(4)]
+    phis = [smooth_field(shape, 0.8, seed=50 + k, sigma=1.5) for k in range(3)]
+    p = O.Params(K=4, window=3, metric=O.SILNCC, alpha_ss=0.5, alpha_l2=0.3, alpha_ts=0.7,
+                 times=(0.0, 0.6, 2.0, 2.5), smooth_sigma=0.7)
+    L, grads, _ = O.loss_and_grad(phis, imgs, p)
+    assert abs(L - O.forward(phis, imgs, p)) < 1e-12 * abs(L)
+    h = 1e-5
+    for trial in range(10):
+        i = int(r.integers(0, 3))
+        idx = tuple(int(r.integers(1, n - 1)) for n in phis[i].shape)
+        up = [x.copy() for x in phis]
+        dn = [x.copy() for x in phis]
+        up[i][idx] += h
+        dn[i][idx] -= h
+        fd = (O.forward(up, imgs, p) - O.forward(dn, imgs, p)) / (2 * h)
+        assert abs(fd - grads[i][idx]) < 2e-5 * max(1.0, np.abs(grads[i]).max())
