@@ -91,6 +91,14 @@ typedef struct muster_params {
                                       periodic, truncated at 4 sigma; 0 = off;
                                       at most 15.8; with smoothing on, each
                                       dimension is at most 4096                   */
+  float alpha_l2;                  /* weight of L_L2 (second form of Eq. reg_ss):
+                                      (1/(N-1)) sum_i mean_p |phi_i(p)|^2; 0 = off */
+  float alpha_ts;                  /* weight of L_ts (Eq. reg_ts):
+                                      (1/(N-2)) sum_k mean_p |phi_{k-1}/dt_{k-1}
+                                      - phi_k/dt_k|^2 with dt_k = t_{k+1} - t_k;
+                                      needs the acquisition times; 0 = off.
+                                      Both act on the flow Exp integrates (the
+                                      smoothed flow when smoothing is on)         */
 } muster_params;
 
 /* Per-job result summary. */
@@ -211,15 +219,17 @@ muster_status muster_server_stats(muster_ctx* ctx, int* resident, int* queued,
 
 /* ---- differentiable loss (autograd) -------------------------------------- */
 
-/* L(phi) at one grid: Sec. 2.2 loss with alpha_ss L_ss (Eq. reg_sum), for
- * images [N][D][H][W] and svf [N-1][3][D][H][W] (only K, window, metric and
- * alpha_ss of params are used).  Writes *loss_host (synchronises the stream)
- * and returns in *saved the state the backward pass needs; the caller's
- * buffers must stay valid until muster_saved_free. */
+/* L(phi) at one grid: Sec. 2.2 loss with alpha_ss L_ss + alpha_l2 L_L2 +
+ * alpha_ts L_ts (Eq. reg_sum), for images [N][D][H][W] and svf
+ * [N-1][3][D][H][W] (K, window, metric, the alphas and smooth_sigma of params
+ * are used).  times_host (N doubles, strictly increasing) is required when
+ * alpha_ts > 0 and N >= 3, else it may be NULL.  Writes *loss_host
+ * (synchronises the stream) and returns in *saved the state the backward pass
+ * needs; the caller's buffers must stay valid until muster_saved_free. */
 muster_status muster_loss_forward(muster_ctx* ctx, void* stream, int N, const int dims[3],
-                                  const float* images_dev, const float* svf_dev,
-                                  const muster_params* params, double* loss_host,
-                                  muster_saved** saved);
+                                  const float* images_dev, const double* times_host,
+                                  const float* svf_dev, const muster_params* params,
+                                  double* loss_host, muster_saved** saved);
 /* grad_svf_dev[N-1][3][D][H][W] = grad_out * dL/dphi by the hand-written
  * adjoints of every step.  The saved state can be used once. */
 muster_status muster_loss_backward(muster_ctx* ctx, void* stream, muster_saved* saved,

@@ -42,7 +42,8 @@ class Params(Structure):
     _fields_ = [("levels", c_int), ("iters", c_int * MAX_LEVELS), ("K", c_int), ("window", c_int),
                 ("metric", c_int), ("alpha_ss", c_float), ("lr", c_float), ("warmup", c_float),
                 ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("exp_mode", c_int),
-                ("use_graph", c_int), ("smooth_sigma", c_float)]
+                ("use_graph", c_int), ("smooth_sigma", c_float), ("alpha_l2", c_float),
+                ("alpha_ts", c_float)]
 
 
 class Report(Structure):
@@ -81,8 +82,8 @@ SIGNATURES = {
     "muster_wait": (_ST, [_P, c_uint64, POINTER(Report)]),
     "muster_cancel": (_ST, [_P, c_uint64]),
     "muster_server_stats": (_ST, [_P, POINTER(c_int), POINTER(c_int), POINTER(c_uint64)]),
-    "muster_loss_forward": (_ST, [_P, _P, c_int, DIMS, _P, _P, POINTER(Params), POINTER(c_double),
-                                  POINTER(_P)]),
+    "muster_loss_forward": (_ST, [_P, _P, c_int, DIMS, _P, POINTER(c_double), _P, POINTER(Params),
+                                  POINTER(c_double), POINTER(_P)]),
     "muster_loss_backward": (_ST, [_P, _P, _P, c_double, _P]),
     "muster_saved_free": (_ST, [_P]),
     "muster_exp": (_ST, [_P, _P, DIMS, c_int, c_int, _P, _P, _P]),

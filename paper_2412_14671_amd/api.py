@@ -31,6 +31,8 @@ class MusterParams:
     exp_mode: str = "store"           # "store" or "recompute"
     use_graph: bool = True
     smooth_sigma: float = 0.0         # Gaussian smoothing of the flow, finest-level voxels
+    alpha_l2: float = 0.0             # weight of L_L2 (flow magnitude)
+    alpha_ts: float = 0.0             # weight of L_ts (temporal smoothness; needs times)
 
     def to_c(self) -> L.Params:
         p = L.Params()
@@ -50,6 +52,8 @@ class MusterParams:
         p.exp_mode = {"store": L.EXP_STORE, "recompute": L.EXP_RECOMPUTE}[self.exp_mode]
         p.use_graph = 1 if self.use_graph else 0
         p.smooth_sigma = float(self.smooth_sigma)
+        p.alpha_l2 = float(self.alpha_l2)
+        p.alpha_ts = float(self.alpha_ts)
         return p
 
 
@@ -258,15 +262,18 @@ class MusterLoss(torch.autograd.Function):
     adjoints)."""
 
     @staticmethod
-    def forward(ctx, svf, images, params: MusterParams, lib_ctx: Context):
+    def forward(ctx, svf, images, params: MusterParams, lib_ctx: Context, times=None):
         svf_c = svf.detach().contiguous()
         img_c = images.detach().contiguous()
         loss = c_double()
         saved = c_void_p()
         p = params.to_c()
+        tarr = None
+        if times is not None:
+            tarr = (c_double * img_c.shape[0])(*[float(t) for t in times])
         L.check(lib_ctx.lib.muster_loss_forward(lib_ctx.h, _stream(), img_c.shape[0],
-                                                _dims(img_c.shape[1:]), _ptr(img_c), _ptr(svf_c),
-                                                byref(p), byref(loss), byref(saved)))
+                                                _dims(img_c.shape[1:]), _ptr(img_c), tarr,
+                                                _ptr(svf_c), byref(p), byref(loss), byref(saved)))
         ctx.lib_ctx = lib_ctx
         ctx.saved_handle = saved
         ctx.keep = (svf_c, img_c)
@@ -283,7 +290,7 @@ class MusterLoss(torch.autograd.Function):
         finally:
             lib.muster_saved_free(ctx.saved_handle)
             ctx.saved_handle = None
-        return g, None, None, None
+        return g, None, None, None, None
 
 
 class Server:

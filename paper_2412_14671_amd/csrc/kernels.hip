@@ -579,10 +579,10 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   const float a = it.a;
   const cgfloat* __restrict__ s = gp(it.src);
   gfloat* __restrict__ gin = gp(it.gin);
-  const bool reg = it.reg_w != 0.f;
+  const bool reg = it.reg_w != 0.f || it.ext;
   const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
               inv_mx = 1.f / (float)(D * H * (W - 1));
-  double rval = 0.0;
+  double rval = 0.0, rext = 0.0;
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
@@ -613,11 +613,37 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     own0 = fmaf(a * dz * az.live, g2, own0);
     own1 = fmaf(a * dy * ay.live, g2, own1);
     own2 = fmaf(a * dx * ax.live, g2, own2);
-    if (reg) {
+    if (it.reg_w != 0.f) {
       own0 = fmaf(it.reg_w, reg_point(s, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own0);
       own1 = fmaf(it.reg_w, reg_point(s + V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own1);
       own2 = fmaf(it.reg_w, reg_point(s + 2 * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval),
                   own2);
+    }
+    if (it.ext) {
+      // L_L2 and L_ts (Sec. 2.4): linear in the flows of this interval and its neighbours
+      const float f0 = s[p], f1 = s[V + p], f2 = s[2 * V + p];
+      own0 = fmaf(it.w_self, f0, own0);
+      own1 = fmaf(it.w_self, f1, own1);
+      own2 = fmaf(it.w_self, f2, own2);
+      double e = (double)it.l2_loss_w * ((double)f0 * f0 + (double)f1 * f1 + (double)f2 * f2);
+      if (it.flow_prev) {
+        const cgfloat* __restrict__ fp = gp(it.flow_prev);
+        const float p0 = fp[p], p1 = fp[V + p], p2 = fp[2 * V + p];
+        own0 = fmaf(it.w_prev, p0, own0);
+        own1 = fmaf(it.w_prev, p1, own1);
+        own2 = fmaf(it.w_prev, p2, own2);
+        const double a0 = (double)p0 * it.inv_dprev - (double)f0 * it.inv_dself;
+        const double a1 = (double)p1 * it.inv_dprev - (double)f1 * it.inv_dself;
+        const double a2 = (double)p2 * it.inv_dprev - (double)f2 * it.inv_dself;
+        e += (double)it.ts_loss_w * (a0 * a0 + a1 * a1 + a2 * a2);
+      }
+      if (it.flow_next) {
+        const cgfloat* __restrict__ fn = gp(it.flow_next);
+        own0 = fmaf(it.w_next, fn[p], own0);
+        own1 = fmaf(it.w_next, fn[V + p], own1);
+        own2 = fmaf(it.w_next, fn[2 * V + p], own2);
+      }
+      rext += e;
     }
     if (it.zero_in) {
       gin[p] = 0.f;
@@ -632,8 +658,8 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   }
   scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred);
   if (reg) {
-    const double tot = block_sum(rval, red);
-    if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot * (double)it.reg_loss_w);
+    const double tot = block_sum(rval * (double)it.reg_loss_w + rext, red);
+    if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot);
   }
 }
 
@@ -1278,12 +1304,13 @@ __global__ void k_finish(JobState* const* __restrict__ states, int n_jobs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_jobs) return;
   JobState* js = states[i];
-  const double L = js->loss_sim + js->loss_reg;
+  const double L = js->loss_sim + js->loss_reg + js->loss_ext;
   const int h = js->hist_base + js->t;
   if (js->history && h >= 0 && h < js->hist_len) js->history[h] = L;
   if (!isfinite(L)) js->nonfinite = 1;
   js->loss_sim = 0.0;
   js->loss_reg = 0.0;
+  js->loss_ext = 0.0;
   js->t += 1;
 }
 
@@ -1483,6 +1510,39 @@ hipError_t launch_pattern(float* p, int64_t n, const int dims[3], float off, flo
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pattern, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, dims[0],
                      dims[1], dims[2], off, amp, phase);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reg_ext(GridDims d, const float* __restrict__ f_,
+                                                   const float* __restrict__ fprev_, float l2w,
+                                                   float tsw, float inv_dp, float inv_ds,
+                                                   double* out) {
+  __shared__ double red[BLOCK / 64];
+  const int V = d.D * d.H * d.W;
+  const cgfloat* __restrict__ f = gp(f_);
+  const cgfloat* __restrict__ fprev = fprev_ ? gp(fprev_) : nullptr;
+  double acc = 0.0;
+  for (int p = blockIdx.x * BLOCK + threadIdx.x; p < V; p += gridDim.x * BLOCK) {
+    const float f0 = f[p], f1 = f[V + p], f2 = f[2 * V + p];
+    acc += (double)l2w * ((double)f0 * f0 + (double)f1 * f1 + (double)f2 * f2);
+    if (fprev) {
+      const double a0 = (double)fprev[p] * inv_dp - (double)f0 * inv_ds;
+      const double a1 = (double)fprev[V + p] * inv_dp - (double)f1 * inv_ds;
+      const double a2 = (double)fprev[2 * V + p] * inv_dp - (double)f2 * inv_ds;
+      acc += (double)tsw * (a0 * a0 + a1 * a1 + a2 * a2);
+    }
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) unsafeAtomicAdd(out, tot);
+}
+
+hipError_t launch_reg_ext(GridDims d, const float* f, const float* fprev, float l2w, float tsw,
+                          float inv_dp, float inv_ds, double* out, hipStream_t s) {
+  const int V = d.D * d.H * d.W;
+  if (V <= 0) return hipSuccess;
+  const int blocks = ceil_div(V, BLOCK) < 2048 ? ceil_div(V, BLOCK) : 2048;
+  hipLaunchKernelGGL(k_reg_ext, dim3(blocks), dim3(BLOCK), 0, s, d, f, fprev, l2w, tsw, inv_dp,
+                     inv_ds, out);
   return hipGetLastError();
 }
 

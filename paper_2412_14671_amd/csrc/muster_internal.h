@@ -23,7 +23,8 @@ struct JobState {
   int nonfinite;    // set once the loss is not finite
   float lr0, b1, b2, eps;
   double loss_sim;  // accumulated over the current iteration
-  double loss_reg;
+  double loss_reg;  // weighted regularisers
+  double loss_ext;  // weighted L_L2 + L_ts of a loss-only forward pass
   double* history;  // loss per step (device), length hist_len
   int hist_len;
   int hist_base;    // index of this level's first step in history
@@ -65,9 +66,18 @@ struct ExpBwdItem {
   float* gout;
   float a;
   int zero_in;
-  float reg_w;
-  float reg_loss_w;
+  float reg_w;       // weight of the L_ss gradient (0 = none)
+  float reg_loss_w;  // weight of the L_ss value
   JobState* js;
+  // L_L2 and L_ts at step 0 of a forward direction: the own term gains
+  // w_self f_i + w_prev f_{i-1} + w_next f_{i+1} (flows of the neighbouring
+  // intervals, NULL where absent), and the loss l2_loss_w |f_i|^2 +
+  // ts_loss_w |f_{i-1} inv_dprev - f_i inv_dself|^2 per voxel.
+  int ext;
+  float w_self, w_prev, w_next;
+  float l2_loss_w, ts_loss_w, inv_dprev, inv_dself;
+  const float* flow_prev;
+  const float* flow_next;
 };
 
 // Backward of one composition out = prev + C o (Omega + prev): given
@@ -207,6 +217,9 @@ hipError_t launch_upsample2(const UpItem* items, int n_items, int n_tiles, hipSt
 hipError_t launch_adam_flat(int64_t n, float* x, const float* g, float* m, float* v, int t,
                             float lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hipStream_t s);
+// out += l2w sum_p |f(p)|^2 + tsw sum_p |fprev(p) inv_dp - f(p) inv_ds|^2 (fprev may be NULL)
+hipError_t launch_reg_ext(GridDims d, const float* f, const float* fprev, float l2w, float tsw,
+                          float inv_dp, float inv_ds, double* out, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 // p[c][z][y][x] = off + amp * (a smooth periodic pattern); scratch data for
 // the autotuner.

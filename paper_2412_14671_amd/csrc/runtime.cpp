@@ -125,6 +125,8 @@ void validate_params(const muster_params& p) {
     fail(MUSTER_E_INVALID, "unknown exp_mode %d", p.exp_mode);
   if (!(p.smooth_sigma >= 0.f) || (int)(4.0f * p.smooth_sigma + 0.5f) > MAX_SMOOTH_RADIUS)
     fail(MUSTER_E_INVALID, "smooth_sigma must be in [0, 15.8] (got %g)", (double)p.smooth_sigma);
+  if (!(p.alpha_l2 >= 0.f) || !std::isfinite(p.alpha_l2)) fail(MUSTER_E_INVALID, "alpha_l2 must be >= 0");
+  if (!(p.alpha_ts >= 0.f) || !std::isfinite(p.alpha_ts)) fail(MUSTER_E_INVALID, "alpha_ts must be >= 0");
 }
 
 void validate_problem(int N, const int dims[3], const muster_params& p, const double* times) {
@@ -214,6 +216,8 @@ float* Job::coef(int i, int j) const {
 std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   validate_problem(jd.N, jd.dims, jd.params, jd.times_host);
   if (!jd.images_dev) fail(MUSTER_E_INVALID, "images is NULL");
+  if (jd.params.alpha_ts > 0.f && jd.N >= 3 && !jd.times_host)
+    fail(MUSTER_E_INVALID, "alpha_ts > 0 needs the acquisition times");
   auto job = std::make_unique<Job>();
   Job& J = *job;
   J.ctx = ctx;
@@ -224,6 +228,7 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   J.svf_init = jd.svf_init_dev;
   J.svf_out = jd.svf_out_dev;
   J.pairs_out = jd.pairs_out_dev;
+  if (jd.times_host) J.times.assign(jd.times_host, jd.times_host + jd.N);
   const int L = J.p.levels;
   for (int l = 0; l < L; ++l) {
     const int f = 1 << (L - 1 - l);
@@ -616,6 +621,46 @@ void add_sim_stages(Builder& b, const std::vector<Job*>& jobs, StageKind kind) {
   }
 }
 
+// L_L2 and L_ts terms of interval i (Sec. 2.4), on the flows Exp integrates.
+// Gradient weights carry 2^K: the step-0 own term is scaled by 2^-K when the
+// two directions are combined.
+void set_reg_ext(ExpBwdItem& it, const Job& J, int i) {
+  const int N = J.N;
+  const double V = (double)J.Vc();
+  const bool l2 = J.p.alpha_l2 > 0.f;
+  const bool ts = J.p.alpha_ts > 0.f && N >= 3;
+  if (!l2 && !ts) return;
+  const double k2 = std::ldexp(1.0, J.K());
+  double w_self = 0, w_prev = 0, w_next = 0;
+  it.ext = 1;
+  if (l2) {
+    w_self += 2.0 * J.p.alpha_l2 / ((N - 1) * V);
+    it.l2_loss_w = (float)(J.p.alpha_l2 / ((N - 1) * V));
+  }
+  if (ts) {
+    const double c = 2.0 * J.p.alpha_ts / ((N - 2) * V);
+    const double di = J.times[i + 1] - J.times[i];
+    if (i >= 1) {
+      const double dp = J.times[i] - J.times[i - 1];
+      w_self += c / (di * di);
+      w_prev = -c / (dp * di);
+      it.flow_prev = J.flow(i - 1);
+      it.ts_loss_w = (float)(J.p.alpha_ts / ((N - 2) * V));
+      it.inv_dprev = (float)(1.0 / dp);
+      it.inv_dself = (float)(1.0 / di);
+    }
+    if (i <= N - 3) {
+      const double dn = J.times[i + 2] - J.times[i + 1];
+      w_self += c / (di * di);
+      w_next = -c / (di * dn);
+      it.flow_next = J.flow(i + 1);
+    }
+  }
+  it.w_self = (float)(k2 * w_self);
+  it.w_prev = (float)(k2 * w_prev);
+  it.w_next = (float)(k2 * w_next);
+}
+
 void add_backward(Builder& b, const std::vector<Job*>& jobs) {
   int maxK = 0, maxN = 0;
   for (Job* J : jobs) {
@@ -693,6 +738,7 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
           it.reg_w = std::ldexp(1.f, K) * J->p.alpha_ss / (float)(J->N - 1);
           it.reg_loss_w = J->p.alpha_ss / (float)(J->N - 1);
         }
+        if (s == 0 && fwd) set_reg_ext(it, *J, i);
         it.js = J->js;
         items.push_back(it);
         tiles += point_tiles(d[0], d[1], d[2]);
@@ -1559,9 +1605,9 @@ muster_status muster_server_stats(muster_ctx* h, int* resident, int* queued, uin
 // ---- autograd ---------------------------------------------------------------
 
 muster_status muster_loss_forward(muster_ctx* h, void* stream, int N, const int dims[3],
-                                  const float* images_dev, const float* svf_dev,
-                                  const muster_params* params, double* loss_host,
-                                  muster_saved** saved) {
+                                  const float* images_dev, const double* times_host,
+                                  const float* svf_dev, const muster_params* params,
+                                  double* loss_host, muster_saved** saved) {
   Ctx* ctx = C(h);
   return guard(ctx, [&] {
     NEED(ctx && params && images_dev && svf_dev && loss_host && saved, "NULL argument");
@@ -1572,6 +1618,7 @@ muster_status muster_loss_forward(muster_ctx* h, void* stream, int N, const int 
     jd.N = N;
     std::memcpy(jd.dims, dims, sizeof jd.dims);
     jd.images_dev = images_dev;
+    jd.times_host = times_host;
     jd.params = *params;
     jd.params.levels = 1;
     jd.params.iters[0] = 0;
@@ -1587,9 +1634,18 @@ muster_status muster_loss_forward(muster_ctx* h, void* stream, int N, const int 
     for (int i = 0; i < N - 1; ++i)
       MUSTER_HIP(launch_reg(GridDims{dims[0], dims[1], dims[2]}, J.flow(i), &J.js->loss_reg,
                             nullptr, s));
+    for (int i = 0; i < N - 1; ++i) {
+      ExpBwdItem e{};
+      set_reg_ext(e, J, i);
+      if (e.ext)
+        MUSTER_HIP(launch_reg_ext(GridDims{dims[0], dims[1], dims[2]}, J.flow(i), e.flow_prev,
+                                  e.l2_loss_w, e.ts_loss_w, e.inv_dprev, e.inv_dself,
+                                  &J.js->loss_ext, s));
+    }
     read_state(J, s);
     if (ctx->timing) resolve_timing(ctx);
-    *loss_host = J.host_state->loss_sim + (double)params->alpha_ss / (N - 1) * J.host_state->loss_reg;
+    *loss_host = J.host_state->loss_sim +
+                 (double)params->alpha_ss / (N - 1) * J.host_state->loss_reg + J.host_state->loss_ext;
     auto* sv = new muster_saved;
     sv->ctx = h;
     sv->job = std::move(job);

@@ -129,6 +129,7 @@ struct Job {
   int level = 0;                     // current pyramid level (0 = coarsest)
   int ldims[MUSTER_MAX_LEVELS][3];
   std::vector<int> deep_slot;        // N*N -> slot of |i-j| >= 2 pairs, -1 otherwise
+  std::vector<double> times;         // acquisition times (empty if not given)
   SimTile sim_tile[MUSTER_MAX_LEVELS];
 
   DevMem m_phi, m_m, m_v, m_us, m_deep, m_gpair, m_pp, m_coef, m_img, m_state, m_hist;

@@ -68,6 +68,7 @@ def test_params_default(lib):
     assert (p.levels, p.iters[0], p.K, p.window, p.metric) == (1, 100, 7, 5, L.METRIC_LNCC)
     assert abs(p.warmup - 0.2) < 1e-7 and abs(p.alpha_ss - 1.0) < 1e-7
     assert p.exp_mode == L.EXP_STORE and p.use_graph == 1 and p.smooth_sigma == 0.0
+    assert p.alpha_l2 == 0.0 and p.alpha_ts == 0.0
 
 
 def _fp(lib, N, dims, **kw):
@@ -112,6 +113,8 @@ def test_footprint_counts_fields(lib):
     (3, (32, 32, 32), {"warmup": 1.5}),
     (3, (32, 32, 32), {"smooth_sigma": -1.0}),
     (3, (32, 32, 32), {"smooth_sigma": 20.0}),
+    (3, (32, 32, 32), {"alpha_l2": -0.5}),
+    (3, (32, 32, 32), {"alpha_ts": float("nan")}),
 ])
 def test_footprint_rejects_invalid_problems(lib, N, dims, kw):
     st, _ = _fp(lib, N, dims, **kw)

@@ -307,3 +307,45 @@ def test_sim_every_tiling_matches_oracle(ctx, shape_id, zc, w, metric):
                                    U.astype(np.float64), 0, 1, p)
     assert abs(val - s_ref) < 1e-3 * abs(s_ref)
     assert_grad_close(host(g), g_ref)
+
+
+# ---------------------------------------------------------------------------
+# L_L2 and L_ts (Sec. 2.4, Eq. reg_ts, reg_sum) in the whole loss and gradient
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", [
+    dict(shape=(24, 28, 20), N=4, K=6, w=5, metric="silncc", sigma=0.0, l2=0.4, ts=0.8,
+         times=(0.0, 0.7, 2.1, 2.6)),
+    dict(shape=(20, 22, 26), N=5, K=5, w=3, metric="lncc", sigma=1.2, l2=0.0, ts=1.5,
+         times=(0.0, 1.0, 1.4, 3.0, 3.5)),
+    dict(shape=(16, 18, 20), N=2, K=6, w=3, metric="silncc", sigma=0.0, l2=2.0, ts=1.0,
+         times=(0.0, 1.3)),
+])
+def test_loss_and_gradient_with_l2_and_ts_match_oracle(ctx, case):
+    from paper_2412_14671_amd import MusterLoss, MusterParams
+    log(f"loss+l2/ts {case}")
+    shape, N = case["shape"], case["N"]
+    imgs = np.stack([smooth_image(shape, seed=60 + k) for k in range(N)])
+    phis = np.stack([smooth_field(shape, 1.2, seed=70 + k, sigma=1.5) for k in range(N - 1)])
+    svf = gpu(phis).requires_grad_(True)
+    params = MusterParams(K=case["K"], window=case["w"], metric=case["metric"], alpha_ss=0.3,
+                          smooth_sigma=case["sigma"], alpha_l2=case["l2"], alpha_ts=case["ts"])
+    loss = MusterLoss.apply(svf, gpu(imgs), params, ctx, case["times"])
+    loss.backward()
+    p = O.Params(K=case["K"], window=case["w"],
+                 metric=O.LNCC if case["metric"] == "lncc" else O.SILNCC, alpha_ss=0.3,
+                 smooth_sigma=case["sigma"], alpha_l2=case["l2"], alpha_ts=case["ts"],
+                 times=case["times"])
+    L_ref, g_ref, aux = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
+    log(f"  loss {float(loss.detach()):.6f} oracle {L_ref:.6f} (reg part {aux['Lreg']:.6f})")
+    assert abs(float(loss.detach()) - L_ref) < 1e-3 * abs(L_ref)
+    assert_grad_close(host(svf.grad), np.stack(g_ref))
+
+
+def test_loss_forward_needs_times_for_ts(ctx):
+    from paper_2412_14671_amd import MusterLoss, MusterParams, MusterError
+    shape = (12, 12, 12)
+    imgs = gpu(np.stack([smooth_image(shape, seed=k) for k in range(3)]))
+    svf = gpu(np.zeros((2, 3) + shape))
+    with pytest.raises(MusterError):
+        MusterLoss.apply(svf, imgs, MusterParams(K=4, window=3, alpha_ts=1.0), ctx)

@@ -207,3 +207,37 @@ def test_autotuned_tiling_is_valid_cached_and_reproducible():
         assert abs(ra["loss_last"] - rb["loss_last"]) <= 1e-6 * abs(ra["loss_last"])
     finally:
         c.close()
+
+
+def test_solver_steps_with_l2_and_ts_match_oracle(ctx):
+    """Three Adam steps with every regulariser on (the schedule's last rate is
+    0, so the output is phi_2): the recorded losses are the oracle's L(0) and
+    L(phi_2), and phi_2 follows the oracle's updates, whose second gradient
+    carries the L_L2 and L_ts terms of phi_1."""
+    from paper_2412_14671_amd import MusterParams, synth
+    s = synth.phantom_series((20, 24, 28), 4, seed=13)
+    imgs = [x.numpy() for x in s.images]
+    params = MusterParams(iters=[3], K=6, window=5, metric="silncc", alpha_ss=0.5, alpha_l2=0.5,
+                          alpha_ts=2.0, lr=0.05, use_graph=False)
+    svf, _, rep = ctx.register(s.images.to(DEV), s.times, params)
+    p = O.Params(K=6, window=5, metric=O.SILNCC, alpha_ss=0.5, alpha_l2=0.5, alpha_ts=2.0,
+                 times=tuple(s.times))
+    phi = [np.zeros((3, 20, 24, 28)) for _ in range(3)]
+    m = [np.zeros_like(x) for x in phi]
+    v = [np.zeros_like(x) for x in phi]
+    losses, gs = [], []
+    for t in (1, 2, 3):
+        L, g, aux = O.loss_and_grad(phi, imgs, p)
+        losses.append(L)
+        gs.append(np.stack(g))
+        lr = O.lr_schedule(t, 3, 0.05)
+        for k in range(3):
+            phi[k], m[k], v[k] = O.adam_step(phi[k], g[k], m[k], v[k], t, lr)
+    log(f"losses gpu {rep['loss_first']:.6f} {rep['loss_last']:.6f} oracle {losses}")
+    assert abs(rep["loss_first"] - losses[0]) < 1e-3 * abs(losses[0])
+    assert abs(rep["loss_last"] - losses[2]) < 1e-3 * abs(losses[2])
+    got = svf.cpu().numpy().astype(np.float64)
+    want = np.stack(phi)
+    big = (np.abs(gs[0]) > 1e-2 * np.abs(gs[0]).max()) & (np.abs(gs[1]) > 1e-2 * np.abs(gs[1]).max())
+    assert big.mean() > 0.02
+    assert np.abs(got[big] - want[big]).max() < 2e-3 * 0.05 * 2
