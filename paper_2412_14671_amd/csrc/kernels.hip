@@ -461,9 +461,19 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
   return sb;
 }
 
-template <bool OWN>
+// Staged output of a scatter: this tile's slot ([3][STAGE_CAP]) and
+// descriptor in the staging buffers, the overflow flag, and the tile origin.
+struct StageOut {
+  gfloat* slot;
+  int* desc;
+  int* flag;
+  int z0, y0, x0;
+};
+
+template <bool OWN, bool STAGE = false>
 __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat* __restrict__ out,
-                                             int D, int H, int W, int* acc, int* sred) {
+                                             int D, int H, int W, int* acc, int* sred,
+                                             const StageOut& so = StageOut{}) {
   const int HW = H * W, V = D * HW;
   int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
   int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
@@ -485,6 +495,22 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
   const ScatterBox sb = scatter_box(lo, hi, mx, sred);
   const BBox& bb = sb.bb;
   const float bmax = sb.bmax;
+  bool staged = false;
+  if (STAGE) {
+    // the box goes to the staging slot if it fits and reaches no farther than
+    // the 26 neighbouring tiles (where the reading step looks for it)
+    staged = bb.cells > 0 && bb.cells <= STAGE_CAP && bmax > 0.f && bmax < 3.0e38f &&
+             bb.lz >= so.z0 - PT_Z && bb.lz + bb.ez <= so.z0 + 2 * PT_Z &&
+             bb.ly >= so.y0 - PT_Y && bb.ly + bb.ey <= so.y0 + 2 * PT_Y &&
+             bb.lx >= so.x0 - PT_X && bb.lx + bb.ex <= so.x0 + 2 * PT_X;
+    if (threadIdx.x == 0) {
+      so.desc[0] = bb.lz; so.desc[1] = bb.ly; so.desc[2] = bb.lx;
+      so.desc[3] = staged ? bb.ez : 0;
+      so.desc[4] = bb.ey; so.desc[5] = bb.ex;
+      // anything the flat path adds must be picked up by the reading step
+      if (!staged && bb.cells > 0 && !(bmax == 0.f)) *so.flag = 1;
+    }
+  }
   if (bb.cells == 0) return;
   if (bb.cells <= SCATTER_CELLS && bmax > 0.f && bmax < 3.0e38f) {
     const float scale = FIX_SCALE / bmax;
@@ -521,6 +547,30 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
       }
     }
     __syncthreads();
+    if (STAGE && staged) {
+      // plain stores of the whole box (zeros included): the slot is this
+      // tile's alone.  The descriptor also records the largest cell
+      // magnitude, from which the reading step sizes its fixed point.
+      int amax = 0;
+      for (int i = threadIdx.x; i < cells; i += BLOCK) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int v = acc[c * cells + i];
+          amax = max(amax, abs(v));
+          so.slot[c * STAGE_CAP + i] = (float)v * inv;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) amax = max(amax, __shfl_xor(amax, o));
+      if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = amax;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int m = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) m = max(m, sred[w]);
+        so.desc[6] = __float_as_int((float)m * inv);
+      }
+      return;
+    }
     // i -> (lz, ly, lx) by float reciprocals: exact here since i < 2^22
     const float inv_ex = 1.f / (float)bb.ex, inv_ey = 1.f / (float)bb.ey;
     for (int i = threadIdx.x; i < cells; i += BLOCK) {
@@ -567,15 +617,20 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
 // Exp backward: one squaring, dL/du_s from dL/du_{s+1}
 //   G_s(p) = G(p) + J_u(q)^T G(p) + sum_{p': corners of q(p') contain p} w G(p')
 // ---------------------------------------------------------------------------
+// MODE: 0 flat G_{s+1} in, flat G_s out; 1 flat in, staged out; 2 staged
+// in, staged out; 3 staged in, flat out (see ExpBwdItem).
+template <int MODE>
 __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict__ items,
                                                    int n_items, int n_tiles) {
+  constexpr bool IN_ST = MODE >= 2, OUT_ST = MODE == 1 || MODE == 2;
   __shared__ __align__(16) int acc[3 * SCATTER_CELLS];
   __shared__ int sred[8 * (BLOCK / 64)];
   __shared__ double red[BLOCK / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ExpBwdItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
-  const PTile tc = point_tile(tile - it.tile0, H, W);
+  const int local = tile - it.tile0;
+  const PTile tc = point_tile(local, H, W);
   const float a = it.a;
   const cgfloat* __restrict__ s = gp(it.src);
   gfloat* __restrict__ gin = gp(it.gin);
@@ -583,18 +638,174 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
               inv_mx = 1.f / (float)(D * H * (W - 1));
   double rval = 0.0, rext = 0.0;
+  // G_{s+1} at the owned voxels
+  float gv[VPT][3];
+  int vz[VPT], vy[VPT], vx[VPT];
+  bool vok[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int k = threadIdx.x + j * BLOCK;
+    vx[j] = tc.x0 + (k % PT_X);
+    vy[j] = tc.y0 + (k / PT_X) % PT_Y;
+    vz[j] = tc.z0 + k / (PT_X * PT_Y);
+    vok[j] = vx[j] < W && vy[j] < H && vz[j] < D;
+    gv[j][0] = gv[j][1] = gv[j][2] = 0.f;
+  }
+  if (IN_ST) {
+    // G_{s+1} over this tile from the staged boxes of the previous step.  The
+    // tile's own box (which holds every owned voxel) is read straight into
+    // registers.  The parts of the 26 neighbours' boxes that reach into the
+    // tile form one list of cells, which the block reads with all its loads in
+    // flight and adds into LDS bins (neighbouring boxes overlap) in 32-bit
+    // fixed point, scaled so that the sum of the boxes' largest cell
+    // magnitudes maps to 2^30: no bin can overflow.  Then the flat overflow,
+    // if any block of the previous step used it.
+    __shared__ int nbd[27][12];
+    __shared__ int pre[28];
+    __shared__ float nbm[27];
+    __shared__ float nbmax;
+    int* gacc = acc;  // [3][PT_VOX], before the scatter reuses acc
+    const int ntz = (D + PT_Z - 1) / PT_Z, nty = (H + PT_Y - 1) / PT_Y, ntx = (W + PT_X - 1) / PT_X;
+    const int tz = tc.z0 / PT_Z, ty = tc.y0 / PT_Y, tx = tc.x0 / PT_X;
+    const cgfloat* __restrict__ st = gp(it.stage_in);
+    // own box, straight into registers
+    {
+      const int* dsc = it.desc_in + local * 8;
+      const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
+      if (ez > 0) {
+        const cgfloat* __restrict__ sl = st + (size_t)local * 3 * STAGE_CAP;
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+          if (!vok[j]) continue;
+          const int idx = ((vz[j] - bz) * ey + (vy[j] - by)) * ex + (vx[j] - bx);
+          gv[j][0] = sl[idx];
+          gv[j][1] = sl[STAGE_CAP + idx];
+          gv[j][2] = sl[2 * STAGE_CAP + idx];
+        }
+      }
+    }
+    if (threadIdx.x < 27) {
+      const int d = threadIdx.x;
+      const int nz = tz + d / 9 - 1, ny = ty + (d / 3) % 3 - 1, nx = tx + d % 3 - 1;
+      int n = 0;
+      float bm = 0.f;
+      int* e = nbd[d];
+      if (d != 13 && nz >= 0 && nz < ntz && ny >= 0 && ny < nty && nx >= 0 && nx < ntx) {
+        const int nb = (nz * nty + ny) * ntx + nx;
+        const int* dsc = it.desc_in + nb * 8;
+        const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
+        // intersection with this tile, in global coordinates
+        const int z0 = max(bz, tc.z0), z1 = min(bz + ez, min(tc.z0 + PT_Z, D));
+        const int y0 = max(by, tc.y0), y1 = min(by + ey, min(tc.y0 + PT_Y, H));
+        const int x0 = max(bx, tc.x0), x1 = min(bx + ex, min(tc.x0 + PT_X, W));
+        if (ez > 0 && z1 > z0 && y1 > y0 && x1 > x0) {
+          n = (z1 - z0) * (y1 - y0) * (x1 - x0);
+          bm = __int_as_float(dsc[6]);
+          e[0] = z0; e[1] = y0; e[2] = x0;
+          e[3] = y1 - y0; e[4] = x1 - x0;
+          e[5] = bz; e[6] = by; e[7] = bx; e[8] = ey; e[9] = ex;
+          e[10] = nb;
+        }
+      }
+      e[11] = n;
+      nbm[d] = bm;
+    }
+    for (int i = threadIdx.x; i < 3 * PT_VOX; i += BLOCK) gacc[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      float m = 0.f;
+      for (int d = 0; d < 27; ++d) {
+        pre[d] = t;
+        t += nbd[d][11];
+        m += nbm[d];
+      }
+      pre[27] = t;
+      nbmax = m;
+    }
+    __syncthreads();
+    const int total = pre[27];
+    const float qscale = nbmax > 0.f ? 1073741824.0f / nbmax : 0.f;  // 2^30 / sum of maxima
+    const float qinv = nbmax / 1073741824.0f;
+    constexpr int U = 4;
+    for (int w0 = threadIdx.x; w0 < total; w0 += BLOCK * U) {
+      float v0[U], v1[U], v2[U];
+      int loc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int w = w0 + u * BLOCK;
+        loc[u] = -1;
+        if (w < total) {
+          int d = 0;  // the last d with pre[d] <= w: the non-empty entry holding w
+#pragma unroll
+          for (int step = 16; step > 0; step >>= 1)
+            if (d + step < 27 && pre[d + step] <= w) d += step;
+          const int* e = nbd[d];
+          const int r = w - pre[d];
+          const int nyx = e[3] * e[4];
+          const int iz = r / nyx, rr = r - iz * nyx, iy = rr / e[4], ix = rr - iy * e[4];
+          const int gz = e[0] + iz, gy = e[1] + iy, gx = e[2] + ix;
+          const int idx = ((gz - e[5]) * e[8] + (gy - e[6])) * e[9] + (gx - e[7]);
+          const cgfloat* __restrict__ sl = st + (size_t)e[10] * 3 * STAGE_CAP;
+          v0[u] = sl[idx];
+          v1[u] = sl[STAGE_CAP + idx];
+          v2[u] = sl[2 * STAGE_CAP + idx];
+          loc[u] = ((gz - tc.z0) * PT_Y + (gy - tc.y0)) * PT_X + (gx - tc.x0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (loc[u] < 0) continue;
+        atomicAdd(&gacc[loc[u]], __float2int_rn(v0[u] * qscale));
+        atomicAdd(&gacc[PT_VOX + loc[u]], __float2int_rn(v1[u] * qscale));
+        atomicAdd(&gacc[2 * PT_VOX + loc[u]], __float2int_rn(v2[u] * qscale));
+      }
+    }
+    __syncthreads();
+    const bool flat = *it.flag_in != 0;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      if (!vok[j]) continue;
+      const int k = threadIdx.x + j * BLOCK;
+      gv[j][0] += (float)gacc[k] * qinv;
+      gv[j][1] += (float)gacc[PT_VOX + k] * qinv;
+      gv[j][2] += (float)gacc[2 * PT_VOX + k] * qinv;
+      if (flat) {
+        const int p = (vz[j] * H + vy[j]) * W + vx[j];
+        gv[j][0] += gin[p];
+        gv[j][1] += gin[V + p];
+        gv[j][2] += gin[2 * V + p];
+        gin[p] = 0.f;
+        gin[V + p] = 0.f;
+        gin[2 * V + p] = 0.f;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      if (!vok[j]) continue;
+      const int p = (vz[j] * H + vy[j]) * W + vx[j];
+      gv[j][0] = gin[p];
+      gv[j][1] = gin[V + p];
+      gv[j][2] = gin[2 * V + p];
+      if (it.zero_in) {
+        gin[p] = 0.f;
+        gin[V + p] = 0.f;
+        gin[2 * V + p] = 0.f;
+      }
+    }
+  }
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     sv[j].cz = -1;
-    const int k = threadIdx.x + j * BLOCK;
-    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
-    if (x >= W || y >= H || z >= D) continue;
+    if (!vok[j]) continue;
+    const int x = vx[j], y = vy[j], z = vz[j];
     const int p = (z * H + y) * W + x;
     const float uz = a * s[p], uy = a * s[V + p], ux = a * s[2 * V + p];
     const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
     const int base = (az.i0 * H + ay.i0) * W + ax.i0;
-    const float g0 = gin[p], g1 = gin[V + p], g2 = gin[2 * V + p];
+    const float g0 = gv[j][0], g1 = gv[j][1], g2 = gv[j][2];
     float own0 = g0, own1 = g1, own2 = g2;
     float v[8], dz, dy, dx;
     // row c of the Jacobian of a*src at q, times g_c, added to column terms
@@ -645,18 +856,22 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
       }
       rext += e;
     }
-    if (it.zero_in) {
-      gin[p] = 0.f;
-      gin[V + p] = 0.f;
-      gin[2 * V + p] = 0.f;
-    }
     sv[j].cz = az.i0; sv[j].cy = ay.i0; sv[j].cx = ax.i0;
     sv[j].oz = z; sv[j].oy = y; sv[j].ox = x;
     sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
     sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
     sv[j].own[0] = own0; sv[j].own[1] = own1; sv[j].own[2] = own2;
   }
-  scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred);
+  if (OUT_ST) {
+    StageOut so;
+    so.slot = gp(it.stage_out) + (size_t)local * 3 * STAGE_CAP;
+    so.desc = it.desc_out + local * 8;
+    so.flag = it.flag_out;
+    so.z0 = tc.z0; so.y0 = tc.y0; so.x0 = tc.x0;
+    scatter_tile<true, true>(sv, gp(it.gout), D, H, W, acc, sred, so);
+  } else {
+    scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred);
+  }
   if (reg) {
     const double tot = block_sum(rval * (double)it.reg_loss_w + rext, red);
     if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot);
@@ -1311,6 +1526,7 @@ __global__ void k_finish(JobState* const* __restrict__ states, int n_jobs) {
   js->loss_sim = 0.0;
   js->loss_reg = 0.0;
   js->loss_ext = 0.0;
+  for (int k = 0; k < js->n_flags; ++k) js->flags[k] = 0;
   js->t += 1;
 }
 
@@ -1421,9 +1637,16 @@ hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles
   return hipGetLastError();
 }
 
-hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s) {
+hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int staged,
+                          hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_exp_bwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  switch (staged) {
+    case 0: hipLaunchKernelGGL(k_exp_bwd<0>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 1: hipLaunchKernelGGL(k_exp_bwd<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 2: hipLaunchKernelGGL(k_exp_bwd<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 3: hipLaunchKernelGGL(k_exp_bwd<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

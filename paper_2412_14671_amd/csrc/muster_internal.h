@@ -27,6 +27,8 @@ struct JobState {
   double loss_ext;  // weighted L_L2 + L_ts of a loss-only forward pass
   double* history;  // loss per step (device), length hist_len
   int hist_len;
+  int* flags;       // overflow flags of the staged Exp backward, cleared per iteration
+  int n_flags;
   int hist_base;    // index of this level's first step in history
 };
 
@@ -78,6 +80,20 @@ struct ExpBwdItem {
   float l2_loss_w, ts_loss_w, inv_dprev, inv_dself;
   const float* flow_prev;
   const float* flow_next;
+  // Staged accumulation between squaring steps.  A block that scatters
+  // G_s with a box of bins that fits STAGE_CAP cells and stays within its
+  // tile's 26 neighbours writes the box, plain, to its own slot of stage_out
+  // ([tiles][3][STAGE_CAP]) and its extent to desc_out ([tiles][8]);
+  // otherwise it adds into the flat gout with atomics, marks its descriptor
+  // empty and sets *flag_out.  A step reading a staged G_{s+1} sums, at each
+  // voxel, the boxes of its own tile and its neighbours that contain the
+  // voxel, plus the flat gin where *flag_in is set (then clears it).
+  const float* stage_in;
+  const int* desc_in;
+  const int* flag_in;
+  float* stage_out;
+  int* desc_out;
+  int* flag_out;
 };
 
 // Backward of one composition out = prev + C o (Omega + prev): given
@@ -178,7 +194,8 @@ struct UpItem {
 constexpr int PT_Z = 8, PT_Y = 8, PT_X = 16;   // 1024 voxels, 256 threads
 constexpr int PT_VOX = PT_Z * PT_Y * PT_X;
 constexpr int BLOCK = 256;
-constexpr int SCATTER_CELLS = 3072;            // LDS bins per component
+constexpr int SCATTER_CELLS = 3072;          // LDS bins per component
+constexpr int STAGE_CAP = SCATTER_CELLS;      // cells per component of a staging slot
 // Tiles of the windowed-statistics kernels: TY x TX columns, z chunks.
 // Tile shapes (centres in y x x) of the window-statistics kernels; the block
 // has one thread per centre.
@@ -198,7 +215,10 @@ inline int stat_tiles(int D, int H, int W, int zc, int shape) {
 // Launchers (kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_exp_fwd(const ExpFwdItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles, hipStream_t s);
-hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s);
+// staged: 0 flat in / flat out, 1 flat in / staged out, 2 staged in / staged out,
+// 3 staged in / flat out
+hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int staged,
+                          hipStream_t s);
 hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
                               hipStream_t s);
 hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,

@@ -170,6 +170,12 @@ uint64_t job_footprint(int N, const int dims[3], const muster_params& p) {
   uint64_t fields = 3 * n1 + 2 * n1 * per_dir_fields(p) + std::max<uint64_t>(Pd, 1) + P + 4 * n1 + P;
   if (p.smooth_sigma > 0.f) fields += 3 * n1;
   uint64_t bytes = fields * F;
+  if (p.K >= 2) {
+    // staging slots and descriptors of the Exp backward, per direction, two steps
+    const uint64_t tiles = (uint64_t)point_tiles(dims[0], dims[1], dims[2]);
+    bytes += 2 * 2 * n1 * tiles * (3 * STAGE_CAP * sizeof(float) + 8 * sizeof(int));
+    bytes += 2 * n1 * p.K * sizeof(int) + 2 * 256;
+  }
   uint64_t imgs = 0;
   for (int l = 0; l < p.levels - 1; ++l) {
     const int f = 1 << (p.levels - 1 - l);
@@ -257,6 +263,12 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
     J.m_t1.alloc(ctx, n1 * F);
     J.m_t2.alloc(ctx, n1 * F);
   }
+  J.tiles_fine = point_tiles(J.ldims[L - 1][0], J.ldims[L - 1][1], J.ldims[L - 1][2]);
+  if (J.staged()) {
+    J.m_stage.alloc(ctx, 2 * 2 * n1 * (size_t)J.tiles_fine * 3 * STAGE_CAP * sizeof(float));
+    J.m_desc.alloc(ctx, 2 * 2 * n1 * (size_t)J.tiles_fine * 8 * sizeof(int));
+    J.m_flags.alloc(ctx, 2 * n1 * (size_t)J.p.K * sizeof(int));
+  }
   size_t img = 0;
   for (int l = 0; l < L - 1; ++l) img += (size_t)N * J.V(l);
   J.m_img.alloc(ctx, std::max<size_t>(img, 1) * sizeof(float));
@@ -280,7 +292,8 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   std::memset(J.host_state, 0, sizeof(JobState));
   J.footprint = J.m_phi.bytes + J.m_m.bytes + J.m_v.bytes + J.m_us.bytes + J.m_deep.bytes +
                 J.m_gpair.bytes + J.m_pp.bytes + J.m_coef.bytes + J.m_img.bytes +
-                J.m_state.bytes + J.m_hist.bytes + J.m_phis.bytes + J.m_t1.bytes + J.m_t2.bytes;
+                J.m_state.bytes + J.m_hist.bytes + J.m_phis.bytes + J.m_t1.bytes + J.m_t2.bytes +
+                J.m_stage.bytes + J.m_desc.bytes + J.m_flags.bytes;
   return job;
 }
 
@@ -354,6 +367,8 @@ void job_begin_level(Job& J, int level, hipStream_t s) {
     MUSTER_HIP(launch_fill(J.vbuf, (int64_t)(n1 * 3 * V), 0.f, s));
   }
   MUSTER_HIP(launch_fill(J.m_pp.as<float>(), (int64_t)(4 * n1 * 3 * V), 0.f, s));
+  if (J.staged())  // the flags are ints; 0.0f has the same bits as 0
+    MUSTER_HIP(launch_fill((float*)J.m_flags.p, (int64_t)(2 * n1 * J.p.K), 0.f, s));
   JobState st{};
   const int prev_nonfinite = level > 0 ? J.host_state->nonfinite : 0;
   st.t = 0;
@@ -366,6 +381,8 @@ void job_begin_level(Job& J, int level, hipStream_t s) {
   st.eps = J.p.eps;
   st.history = J.hist;
   st.hist_len = J.hist_len;
+  st.flags = J.staged() ? J.m_flags.as<int>() : nullptr;
+  st.n_flags = J.staged() ? (int)(2 * n1 * J.p.K) : 0;
   int base = 0;
   for (int l = 0; l < level; ++l) base += J.p.iters[l];
   st.hist_base = base;
@@ -707,19 +724,22 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
     // recompute u_s where needed
     if (s >= 1)
       for (int k = 0; k < s; ++k) add_exp_fwd_step(b, jobs, k, true, s);
-    std::vector<ExpBwdItem> items;
-    int tiles = 0;
-    double bytes = 0;
+    // one launch per staging mode in use (jobs with different K differ)
+    std::vector<ExpBwdItem> items[4];
+    int tiles[4] = {0, 0, 0, 0};
+    double bytes[4] = {0, 0, 0, 0};
     for (Job* J : jobs) {
       const int K = J->K();
       if (s >= K) continue;
       const int* d = J->ldims[J->level];
       const float scale = std::ldexp(1.f, -K);
+      const bool in_st = J->staged() && s < K - 1, out_st = J->staged() && s > 0;
+      const int mode = in_st ? (out_st ? 2 : 3) : (out_st ? 1 : 0);
       for (int dir = 0; dir < 2 * (J->N - 1); ++dir) {
         const int i = dir / 2;
         const bool fwd = dir % 2 == 0;
         ExpBwdItem it{};
-        it.tile0 = tiles;
+        it.tile0 = tiles[mode];
         it.D = d[0]; it.H = d[1]; it.W = d[2];
         if (s == 0) {
           it.src = J->flow(i);
@@ -734,18 +754,31 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
           it.gin = J->pp(dir, (s + 1) % 2);
         it.gout = J->pp(dir, s % 2);
         it.zero_in = (s < K - 1) ? 1 : 0;
+        if (in_st) {
+          it.stage_in = J->stage(dir, (s + 1) % 2);
+          it.desc_in = J->desc(dir, (s + 1) % 2);
+          it.flag_in = J->flag(dir, s + 1);
+        }
+        if (out_st) {
+          it.stage_out = J->stage(dir, s % 2);
+          it.desc_out = J->desc(dir, s % 2);
+          it.flag_out = J->flag(dir, s);
+        }
         if (s == 0 && fwd && J->p.alpha_ss > 0.f) {
           it.reg_w = std::ldexp(1.f, K) * J->p.alpha_ss / (float)(J->N - 1);
           it.reg_loss_w = J->p.alpha_ss / (float)(J->N - 1);
         }
         if (s == 0 && fwd) set_reg_ext(it, *J, i);
         it.js = J->js;
-        items.push_back(it);
-        tiles += point_tiles(d[0], d[1], d[2]);
-        bytes += B_EXP_BWD * J->Vc();
+        items[mode].push_back(it);
+        tiles[mode] += point_tiles(d[0], d[1], d[2]);
+        bytes[mode] += B_EXP_BWD * J->Vc();
       }
     }
-    b.add(ST_EXP_BWD, items, tiles, bytes);
+    for (int mode = 0; mode < 4; ++mode) {
+      b.add(ST_EXP_BWD, items[mode], tiles[mode], bytes[mode]);
+      if (!items[mode].empty()) b.plan->stages.back().staged = mode;
+    }
   }
   {
     // gradients of smoothing jobs: combine into t1, then smooth t1 -> t2 -> t1 -> t2
@@ -866,7 +899,8 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
       return launch_sim_grad((const SimItem*)p, st.n_items, st.n_tiles, st.window, st.shape, s);
     case ST_COMPOSE_BWD:
       return launch_compose_bwd((const ComposeBwdItem*)p, st.n_items, st.n_tiles, s);
-    case ST_EXP_BWD: return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, s);
+    case ST_EXP_BWD:
+      return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, st.staged, s);
     case ST_ADAM: return launch_adam((const AdamItem*)p, st.n_items, st.n_tiles, s);
     case ST_FINISH: return launch_finish((JobState* const*)p, st.n_items, s);
     case ST_SMOOTH: return launch_smooth((const SmoothItem*)p, st.n_items, st.n_tiles, st.lds, s);
@@ -1790,7 +1824,7 @@ muster_status muster_exp_bwd(muster_ctx* h, void* stream, const int dims[3], int
     for (auto& l : seq) {
       const unsigned char* p = sc.dev() + l.off;
       if (l.kind == 0) MUSTER_HIP(launch_exp_fwd((const ExpFwdItem*)p, 1, tiles, sc.s));
-      if (l.kind == 1) MUSTER_HIP(launch_exp_bwd((const ExpBwdItem*)p, 1, tiles, sc.s));
+      if (l.kind == 1) MUSTER_HIP(launch_exp_bwd((const ExpBwdItem*)p, 1, tiles, 0, sc.s));
       if (l.kind == 2) MUSTER_HIP(launch_adam((const AdamItem*)p, 1, elem_tiles(V), sc.s));
     }
     MUSTER_HIP(hipStreamSynchronize(sc.s));

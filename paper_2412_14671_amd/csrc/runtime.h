@@ -134,6 +134,7 @@ struct Job {
 
   DevMem m_phi, m_m, m_v, m_us, m_deep, m_gpair, m_pp, m_coef, m_img, m_state, m_hist;
   DevMem m_phis, m_t1, m_t2;         // smoothed flow and gradient ping-pong (smoothing on)
+  DevMem m_stage, m_desc, m_flags;   // staged Exp-backward accumulation (K >= 2)
   float* phi = nullptr;              // may alias the caller's field in grad_mode
   float* mbuf = nullptr;
   float* vbuf = nullptr;
@@ -159,6 +160,13 @@ struct Job {
   float* pair_field(int i, int j) const;        // U[j->i]
   float* pair_grad(int i, int j) const;
   float* pp(int dir, int k) const { return field(m_pp.as<float>(), (size_t)dir * 2 + k); }
+  bool staged() const { return p.K >= 2; }
+  int tiles_fine = 0;                // point tiles of the finest grid
+  float* stage(int dir, int k) const {
+    return m_stage.as<float>() + ((size_t)dir * 2 + k) * tiles_fine * 3 * STAGE_CAP;
+  }
+  int* desc(int dir, int k) const { return m_desc.as<int>() + ((size_t)dir * 2 + k) * tiles_fine * 8; }
+  int* flag(int dir, int s) const { return m_flags.as<int>() + (size_t)dir * p.K + s; }
   float* coef(int i, int j) const;
   const float* image(int i) const { return level_images[level] + (size_t)i * Vc(); }
 };
@@ -186,6 +194,7 @@ struct Stage {
   int n_items;
   int n_tiles;
   int window = 0, metric = 0, zc = 32;
+  int staged = 0;    // Exp-backward staging mode
   int lds = 0;       // dynamic LDS floats (smoothing)
   int shape = 0;     // window-statistics tile shape
   double bytes = 0;  // algorithmic bytes of the launch

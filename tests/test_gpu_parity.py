@@ -349,3 +349,23 @@ def test_loss_forward_needs_times_for_ts(ctx):
     svf = gpu(np.zeros((2, 3) + shape))
     with pytest.raises(MusterError):
         MusterLoss.apply(svf, imgs, MusterParams(K=4, window=3, alpha_ts=1.0), ctx)
+
+
+def test_large_displacements_take_the_overflow_path_and_match_oracle(ctx):
+    """Exp-backward blocks whose box of bins does not fit a staging slot fall
+    back to atomics on the flat field and flag it; the next step adds it.  A
+    rough field of amplitude 5 voxels makes many blocks do so."""
+    from paper_2412_14671_amd import MusterLoss, MusterParams
+    shape = (24, 32, 48)
+    N = 3
+    imgs = np.stack([smooth_image(shape, seed=90 + k) for k in range(N)])
+    phis = np.stack([smooth_field(shape, 5.0, seed=95 + k, sigma=1.2) for k in range(N - 1)])
+    for mode in ("store", "recompute"):
+        svf = gpu(phis).requires_grad_(True)
+        params = MusterParams(K=6, window=5, metric="silncc", alpha_ss=0.2, exp_mode=mode)
+        loss = MusterLoss.apply(svf, gpu(imgs), params, ctx)
+        loss.backward()
+        p = O.Params(K=6, window=5, metric=O.SILNCC, alpha_ss=0.2)
+        L_ref, g_ref, _ = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
+        assert abs(float(loss.detach()) - L_ref) < 1e-3 * abs(L_ref)
+        assert_grad_close(host(svf.grad), np.stack(g_ref))
