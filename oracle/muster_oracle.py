@@ -475,6 +475,7 @@ class Params:
     alpha_l2: float = 0.0      # weight of L_L2
     alpha_ts: float = 0.0      # weight of L_ts (needs times)
     times: Optional[Tuple[float, ...]] = None  # acquisition times t_1..t_N
+    flow_factor: int = 1       # 1: flows on the image grid; 2: on a grid twice as coarse
     smooth_sigma: float = 0.0  # Gaussian smoothing of the flow (voxels of the level); 0 = none
     lr: float = 0.1            # peak learning rate (voxels per step)
     warmup: float = 0.2        # warm-up fraction of each stage
@@ -498,8 +499,11 @@ def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: b
     f = [us[-1] for us in fwd]
     b = [us[-1] for us in bwd]
     U = all_pairs(f, b)
+    # the pair fields act on the image grid: with a coarser flow grid they are
+    # carried up by the same map as between pyramid levels (Sec. 2.7)
+    Ui = U if p.flow_factor == 1 else {k: upsample2(v) for k, v in U.items()}
     sims = {}
-    for (i, j), Uij in U.items():
+    for (i, j), Uij in Ui.items():
         M = warp(imgs[j], Uij)
         sims[(i, j)] = similarity(imgs[i], M, p.window, p.metric)
     Lsim = float(sum(sims.values()))
@@ -511,7 +515,8 @@ def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: b
     L = Lsim + Lreg
     if not keep:
         return L
-    return L, dict(fwd=fwd, bwd=bwd, f=f, b=b, U=U, sims=sims, Lsim=Lsim, Lreg=Lreg, phis_s=phis)
+    return L, dict(fwd=fwd, bwd=bwd, f=f, b=b, U=U, U_img=Ui, sims=sims, Lsim=Lsim, Lreg=Lreg,
+                   phis_s=phis)
 
 
 def pair_sim_grad(images, U, i, j, p: Params):
@@ -530,8 +535,10 @@ def loss_and_grad(phis: List[np.ndarray], images: List[np.ndarray], p: Params):
     U = aux["U"]
     f, b = aux["f"], aux["b"]
     G = {}
-    for (i, j), Uij in U.items():
+    for (i, j), Uij in aux["U_img"].items():
         _, G[(i, j)] = pair_sim_grad(imgs, Uij, i, j, p)
+        if p.flow_factor != 1:
+            G[(i, j)] = upsample2_adjoint(G[(i, j)], U[(i, j)].shape[1:])
     aux["G_pair_sim"] = {k: v.copy() for k, v in G.items()}
     Gf = [np.zeros_like(x) for x in f]
     Gb = [np.zeros_like(x) for x in b]
@@ -617,9 +624,18 @@ def upsample2(phi: np.ndarray) -> np.ndarray:
     return 2.0 * sample(phi, (g - 0.5) / 2.0)
 
 
+def upsample2_adjoint(g: np.ndarray, shape) -> np.ndarray:
+    """Adjoint of upsample2 for a coarse grid of the given shape: each fine
+    voxel hands twice its value back to the corners of the coarse cell it
+    sampled, with the same trilinear weights."""
+    g = np.asarray(g, np.float64)
+    fine = identity_grid(g.shape[1:])
+    return 2.0 * sample_adjoint(g, (fine - 0.5) / 2.0, shape)
+
+
 def level_sigma(p: Params, level: int) -> float:
     """Smoothing width at a pyramid level: smooth_sigma is given in voxels of
-    the finest level and halves with every coarser level."""
+    the finest level's flow grid and halves with every coarser level."""
     return p.smooth_sigma / 2.0 ** (len(p.iters) - 1 - level)
 
 
@@ -628,7 +644,8 @@ def register(images: List[np.ndarray], p: Params, phis0: Optional[List[np.ndarra
     """The whole optimisation: pyramid levels coarse to fine, each running
     Adam on L(phi) for p.iters[level] steps from a schedule that restarts per
     level.  Returns (the smoothed flows that parameterise the final
-    deformations, at full resolution; pair fields; loss history)."""
+    deformations, on the finest flow grid; pair fields on that grid; loss
+    history).""" 
     L_lv = len(p.iters)
     imgs_lv = [[np.asarray(I, np.float64) for I in images]]
     for _ in range(L_lv - 1):
@@ -638,7 +655,7 @@ def register(images: List[np.ndarray], p: Params, phis0: Optional[List[np.ndarra
     hist = []
     for lv in range(L_lv):
         imgs = imgs_lv[lv]
-        shape = imgs[0].shape
+        shape = tuple(n // p.flow_factor for n in imgs[0].shape)
         if phis is None:
             phis = phis0 if phis0 is not None else [np.zeros((3,) + shape) for _ in range(N - 1)]
             phis = [np.asarray(x, np.float64) for x in phis]

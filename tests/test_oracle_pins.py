@@ -655,3 +655,54 @@ def test_total_loss_gradient_with_l2_and_ts_matches_finite_differences():
         dn[i][idx] -= h
         fd = (O.forward(up, imgs, p) - O.forward(dn, imgs, p)) / (2 * h)
         assert abs(fd - grads[i][idx]) < 2e-5 * max(1.0, np.abs(grads[i]).max())
+
+
+# --------------------------------------------------------------------------
+# Flow grid twice as coarse as the images (Sec. 2.7 stage geometry)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(2, 3, 4), (5, 6, 7), (8, 8, 8)])
+def test_upsample2_adjoint_is_the_transpose_of_upsample2(shape):
+    r = rng(200 + sum(shape))
+    a = r.standard_normal((3,) + shape)
+    b = r.standard_normal((3,) + tuple(2 * n for n in shape))
+    lhs = float(np.sum(O.upsample2(a) * b))
+    rhs = float(np.sum(a * O.upsample2_adjoint(b, shape)))
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
+
+
+def test_coarse_flow_of_a_constant_svf_translates_the_images_by_twice_it():
+    """A constant SVF c on the flow grid is a translation by c flow voxels,
+    i.e. 2c image voxels: the warped image of the pair is the image sampled
+    2c away, exactly."""
+    shape = (12, 14, 16)
+    c = np.array([0.25, -0.5, 0.375])
+    phi = np.broadcast_to(c[:, None, None, None], (3, 6, 7, 8)).copy()
+    p = O.Params(K=5, window=3, metric=O.SILNCC, alpha_ss=0.0, flow_factor=2)
+    z, y, x = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    imgs = [np.sin(0.3 * z) + np.cos(0.2 * y) + 0.1 * x, np.sin(0.25 * x + 0.1 * y)]
+    _, aux = O.forward([phi], imgs, p, keep=True)
+    U = aux["U_img"][(0, 1)]
+    assert np.allclose(U, 2 * c[:, None, None, None], atol=1e-12)
+
+
+def test_loss_gradient_with_a_coarse_flow_grid_matches_finite_differences():
+    r = rng(12)
+    fshape = (5, 6, 7)
+    shape = tuple(2 * n for n in fshape)
+    import scipy.ndimage as ndi
+    imgs = [ndi.gaussian_filter(rng(60 + k).uniform(0, 1, shape), 1.0) for k in range(3)]
+    phis = [smooth_field(fshape, 0.6, seed=70 + k, sigma=1.2) for k in range(2)]
+    p = O.Params(K=4, window=3, metric=O.LNCC, alpha_ss=0.5, flow_factor=2, smooth_sigma=0.6)
+    L, grads, _ = O.loss_and_grad(phis, imgs, p)
+    assert abs(L - O.forward(phis, imgs, p)) < 1e-12 * abs(L)
+    h = 1e-5
+    for trial in range(10):
+        i = int(r.integers(0, 2))
+        idx = tuple(int(r.integers(0, n)) for n in phis[i].shape)
+        up = [x.copy() for x in phis]
+        dn = [x.copy() for x in phis]
+        up[i][idx] += h
+        dn[i][idx] -= h
+        fd = (O.forward(up, imgs, p) - O.forward(dn, imgs, p)) / (2 * h)
+        assert abs(fd - grads[i][idx]) < 2e-5 * max(1.0, np.abs(grads[i]).max())
