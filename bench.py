@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--iters", default="200,100,50")
     ap.add_argument("--alpha", type=float, default=0.1, help="alpha_ss")
     ap.add_argument("--smooth", type=float, default=3.0,
-                    help="Gaussian smoothing width of the flow, finest-level voxels")
+                    help="Gaussian smoothing width of the flow, finest-level flow-grid voxels")
+    ap.add_argument("--flow-factor", type=int, default=1,
+                    help="2: flows on a grid twice as coarse as the images")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2.0)
     ap.add_argument("--batch-subjects", type=int, default=16)
@@ -296,7 +298,8 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
     s = synth.phantom_series(shape, N, seed=2, device=dev)
     images = s.images.contiguous()
     params = MusterParams(iters=iters, K=7, window=7, metric="silncc", alpha_ss=args.alpha, lr=0.1,
-                          smooth_sigma=args.smooth, use_graph=args.graph)
+                          smooth_sigma=args.smooth, use_graph=args.graph,
+                          flow_factor=args.flow_factor)
     L = len(iters)
     vox_iters = sum(N * np.prod([d // 2 ** (L - 1 - l) for d in shape]) * iters[l]
                     for l in range(L))
@@ -338,7 +341,9 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"one subject, {N} phantom sessions {shape[0]}x{shape[1]}x{shape[2]}, "
                                 f"{L}-level pyramid {'/'.join(map(str, iters))} steps, "
-                                f"SiLNCC w7, K7, alpha_ss {args.alpha:g}, smoothing sigma {args.smooth:g}"),
+                                f"SiLNCC w7, K7, alpha_ss {args.alpha:g}, smoothing sigma {args.smooth:g}"
+                                + (f", flows on a grid {args.flow_factor}x coarser"
+                                   if args.flow_factor > 1 else "")),
                    "sessions": N, "dims": list(shape), "levels": L, "iters": iters,
                    "graphs": bool(args.graph)},
         "roofline": roof,

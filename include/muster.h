@@ -99,6 +99,18 @@ typedef struct muster_params {
                                       needs the acquisition times; 0 = off.
                                       Both act on the flow Exp integrates (the
                                       smoothed flow when smoothing is on)         */
+  int flow_factor;                 /* 1: the flows live on the image grid; 2: on
+                                      a grid twice as coarse (the paper's stage
+                                      geometry, Sec. 2.7).  Exp and the
+                                      compositions run on the flow grid; the pair
+                                      fields are carried up to the image grid
+                                      for the similarity.  dims must then be
+                                      divisible by 2^levels; smooth_sigma is in
+                                      voxels of the finest flow grid; svf_out
+                                      and pairs_out stay on the image grid (the
+                                      flows carried up, in image voxels), while
+                                      svf_init and the autograd svf are on the
+                                      flow grid.  0 is read as 1.              */
 } muster_params;
 
 /* Per-job result summary. */
@@ -284,13 +296,18 @@ muster_status muster_smooth(muster_ctx* ctx, void* stream, const int dims[3], fl
  * dims are the coarse dims, dst is [3][2D][2H][2W]. */
 muster_status muster_upsample2(muster_ctx* ctx, void* stream, const int dims[3],
                                const float* src_dev, float* dst_dev);
+/* Adjoint of muster_upsample2 (how a gradient on the fine grid reaches the
+ * coarse field; Sec. 2.7 with a flow grid coarser than the images): src is
+ * [3][2D][2H][2W], dst [3][D][H][W] is overwritten; dims are the coarse dims. */
+muster_status muster_upsample2_adjoint(muster_ctx* ctx, void* stream, const int dims[3],
+                                       const float* src_dev, float* dst_dev);
 
 /* ---- measurement --------------------------------------------------------- */
 
 enum {
   MUSTER_K_EXP_FWD = 0, MUSTER_K_COMPOSE_FWD, MUSTER_K_SIM_STATS, MUSTER_K_SIM_GRAD,
   MUSTER_K_COMPOSE_BWD, MUSTER_K_EXP_BWD, MUSTER_K_ADAM, MUSTER_K_FINISH,
-  MUSTER_K_POOL, MUSTER_K_UPSAMPLE, MUSTER_K_SMOOTH, MUSTER_K_COUNT
+  MUSTER_K_POOL, MUSTER_K_UPSAMPLE, MUSTER_K_SMOOTH, MUSTER_K_UPSAMPLE_ADJ, MUSTER_K_COUNT
 };
 /* When enabled, eager launches (graphs off) of each kernel class are
  * bracketed by HIP events on the stream they run on. */

@@ -24,7 +24,7 @@ TILES_DEFAULT, TILES_AUTOTUNE, TILES_FIXED = 0, 1, 2
 SIM_SHAPES = [(8, 32), (16, 32), (8, 64)]
 EXP_STORE, EXP_RECOMPUTE = 0, 1
 KERNELS = ["exp_fwd", "compose_fwd", "sim_stats", "sim_grad", "compose_bwd", "exp_bwd", "adam",
-           "finish", "pool2", "upsample2", "smooth"]
+           "finish", "pool2", "upsample2", "smooth", "upsample2_adj"]
 
 
 class MusterLibraryMissing(ImportError):
@@ -43,7 +43,7 @@ class Params(Structure):
                 ("metric", c_int), ("alpha_ss", c_float), ("lr", c_float), ("warmup", c_float),
                 ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("exp_mode", c_int),
                 ("use_graph", c_int), ("smooth_sigma", c_float), ("alpha_l2", c_float),
-                ("alpha_ts", c_float)]
+                ("alpha_ts", c_float), ("flow_factor", c_int)]
 
 
 class Report(Structure):
@@ -96,6 +96,7 @@ SIGNATURES = {
     "muster_reg": (_ST, [_P, _P, DIMS, _P, POINTER(c_double), _P]),
     "muster_pool2": (_ST, [_P, _P, DIMS, _P, _P]),
     "muster_upsample2": (_ST, [_P, _P, DIMS, _P, _P]),
+    "muster_upsample2_adjoint": (_ST, [_P, _P, DIMS, _P, _P]),
     "muster_smooth": (_ST, [_P, _P, DIMS, c_float, _P, _P]),
     "muster_ctx_set_tiling": (_ST, [_P, c_int, c_int, c_int]),
     "muster_ctx_sim_tiling": (_ST, [_P, _P, DIMS, c_int, c_int, POINTER(c_int), POINTER(c_int)]),

@@ -33,6 +33,7 @@ class MusterParams:
     smooth_sigma: float = 0.0         # Gaussian smoothing of the flow, finest-level voxels
     alpha_l2: float = 0.0             # weight of L_L2 (flow magnitude)
     alpha_ts: float = 0.0             # weight of L_ts (temporal smoothness; needs times)
+    flow_factor: int = 1              # 2: flows on a grid twice as coarse as the images
 
     def to_c(self) -> L.Params:
         p = L.Params()
@@ -54,6 +55,7 @@ class MusterParams:
         p.smooth_sigma = float(self.smooth_sigma)
         p.alpha_l2 = float(self.alpha_l2)
         p.alpha_ts = float(self.alpha_ts)
+        p.flow_factor = int(self.flow_factor)
         return p
 
 
@@ -173,6 +175,14 @@ class Context:
         out = torch.empty((3, 2 * D, 2 * H, 2 * W), device=svf.device)
         L.check(self.lib.muster_upsample2(self.h, _stream(), _dims(svf.shape[1:]), _ptr(svf),
                                           _ptr(out)))
+        return out
+
+    def upsample2_adjoint(self, g):
+        """Adjoint of upsample2: g [3, 2D, 2H, 2W] -> [3, D, H, W]."""
+        _, D2, H2, W2 = g.shape
+        out = torch.empty((3, D2 // 2, H2 // 2, W2 // 2), device=g.device)
+        L.check(self.lib.muster_upsample2_adjoint(self.h, _stream(), _dims(out.shape[1:]), _ptr(g),
+                                                  _ptr(out)))
         return out
 
     # -- whole registrations -----------------------------------------------------

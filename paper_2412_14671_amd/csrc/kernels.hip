@@ -1577,6 +1577,66 @@ __global__ __launch_bounds__(BLOCK) void k_upsample2(const UpItem* __restrict__ 
   }
 }
 
+// Adjoint of k_upsample2 (flow grid -> image grid, values doubled): each
+// coarse voxel gathers, with weight 2 w, the fine voxels whose sample cell has
+// it as a corner.  Along an axis those are the fine indices 2c-1 .. 2c+2; the
+// weight is evaluated with the forward's own clamp and cell rules, so borders
+// match it exactly.  A gather, so no atomics and a fixed summation order.
+__device__ __forceinline__ float up_weight(int f, int c, int n) {
+  const Ax a = axis_pos(((float)f - 0.5f) * 0.5f, n);
+  return c == a.i0 ? 1.f - a.t : (c == a.i0 + 1 ? a.t : 0.f);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_upsample2_adj(const UpItem* __restrict__ items,
+                                                         int n_items, int n_tiles) {
+  const int tile = blockIdx.x;
+  const UpItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
+  const int H2 = 2 * H, W2 = 2 * W, n2 = 8 * V;
+  const cgfloat* __restrict__ g = gp(it.src);
+  gfloat* __restrict__ out = gp(it.dst);
+  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
+  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
+    const int q = q0 + k;
+    if (q >= V) break;
+    const int x = q % W, y = (q / W) % H, z = q / (W * H);
+    float wz[4], wy[4], wx[4];
+    int fz[4], fy[4], fx[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      fz[t] = 2 * z - 1 + t;
+      fy[t] = 2 * y - 1 + t;
+      fx[t] = 2 * x - 1 + t;
+      wz[t] = (fz[t] >= 0 && fz[t] < 2 * D) ? up_weight(fz[t], z, D) : 0.f;
+      wy[t] = (fy[t] >= 0 && fy[t] < H2) ? up_weight(fy[t], y, H) : 0.f;
+      wx[t] = (fx[t] >= 0 && fx[t] < W2) ? up_weight(fx[t], x, W) : 0.f;
+    }
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (wz[i] == 0.f) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (wy[j] == 0.f) continue;
+        const float wzy = wz[i] * wy[j];
+        const int row = (fz[i] * H2 + fy[j]) * W2;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          if (wx[l] == 0.f) continue;
+          const float w = wzy * wx[l];
+          const int p = row + fx[l];
+          a0 = fmaf(w, g[p], a0);
+          a1 = fmaf(w, g[n2 + p], a1);
+          a2 = fmaf(w, g[2 * n2 + p], a2);
+        }
+      }
+    }
+    out[q] = 2.f * a0;
+    out[V + q] = 2.f * a1;
+    out[2 * V + q] = 2.f * a2;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Single-step helpers for the unit entry points
 // ---------------------------------------------------------------------------
@@ -1778,6 +1838,12 @@ hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s) {
 hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pool2, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_upsample2_adj(const UpItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_upsample2_adj, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 

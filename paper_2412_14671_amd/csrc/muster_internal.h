@@ -234,6 +234,8 @@ int smooth_item_setup(SmoothItem& it, const int dims[3], int axis, float sigma, 
 hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s);
 hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_upsample2(const UpItem* items, int n_items, int n_tiles, hipStream_t s);
+// adjoint: src [3][2D][2H][2W] (fine), dst [3][D][H][W] (coarse), tiles over the coarse grid
+hipError_t launch_upsample2_adj(const UpItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_adam_flat(int64_t n, float* x, const float* g, float* m, float* v, int t,
                             float lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hipStream_t s);

@@ -125,6 +125,8 @@ void validate_params(const muster_params& p) {
     fail(MUSTER_E_INVALID, "unknown exp_mode %d", p.exp_mode);
   if (!(p.smooth_sigma >= 0.f) || (int)(4.0f * p.smooth_sigma + 0.5f) > MAX_SMOOTH_RADIUS)
     fail(MUSTER_E_INVALID, "smooth_sigma must be in [0, 15.8] (got %g)", (double)p.smooth_sigma);
+  if (p.flow_factor != 0 && p.flow_factor != 1 && p.flow_factor != 2)
+    fail(MUSTER_E_INVALID, "flow_factor must be 1 or 2 (got %d)", p.flow_factor);
   if (!(p.alpha_l2 >= 0.f) || !std::isfinite(p.alpha_l2)) fail(MUSTER_E_INVALID, "alpha_l2 must be >= 0");
   if (!(p.alpha_ts >= 0.f) || !std::isfinite(p.alpha_ts)) fail(MUSTER_E_INVALID, "alpha_ts must be >= 0");
 }
@@ -136,9 +138,14 @@ void validate_problem(int N, const int dims[3], const muster_params& p, const do
   validate_params(p);
   const int f = 1 << (p.levels - 1);
   uint64_t V = 1;
+  const int ff = p.flow_factor == 2 ? 2 : 1;
   for (int d = 0; d < 3; ++d) {
-    if (dims[d] % f != 0)
-      fail(MUSTER_E_INVALID, "dims[%d] = %d is not divisible by 2^(levels-1) = %d", d, dims[d], f);
+    if (dims[d] % (f * ff) != 0)
+      fail(MUSTER_E_INVALID, "dims[%d] = %d is not divisible by 2^(levels-1) * flow_factor = %d",
+           d, dims[d], f * ff);
+    if (dims[d] / (f * ff) < 2)
+      fail(MUSTER_E_INVALID, "dims[%d] = %d leaves fewer than 2 flow-grid points at the coarsest level",
+           d, dims[d]);
     if (dims[d] / f < p.window)
       fail(MUSTER_E_INVALID, "dims[%d] = %d is smaller than the window at the coarsest level", d,
            dims[d]);
@@ -164,15 +171,23 @@ static int per_dir_fields(const muster_params& p) {
 }
 
 uint64_t job_footprint(int N, const int dims[3], const muster_params& p) {
-  const uint64_t V = (uint64_t)dims[0] * dims[1] * dims[2];
-  const uint64_t F = 3 * V * sizeof(float);
+  const int ff = p.flow_factor == 2 ? 2 : 1;
+  const int fd[3] = {dims[0] / ff, dims[1] / ff, dims[2] / ff};
+  const uint64_t VI = (uint64_t)dims[0] * dims[1] * dims[2];
+  const uint64_t V = (uint64_t)fd[0] * fd[1] * fd[2];
+  const uint64_t F = 3 * V * sizeof(float), FI = 3 * VI * sizeof(float);
   const uint64_t n1 = N - 1, P = (uint64_t)N * (N - 1), Pd = (uint64_t)(N - 1) * (N - 2);
-  uint64_t fields = 3 * n1 + 2 * n1 * per_dir_fields(p) + std::max<uint64_t>(Pd, 1) + P + 4 * n1 + P;
+  // flow grid: phi, m, v, Exp steps, composed pairs, pair gradients, ping-pong
+  uint64_t fields = 3 * n1 + 2 * n1 * per_dir_fields(p) + std::max<uint64_t>(Pd, 1) + P + 4 * n1;
   if (p.smooth_sigma > 0.f) fields += 3 * n1;
   uint64_t bytes = fields * F;
+  // image grid: window coefficients, and with a coarser flow grid the pair
+  // fields and their gradients
+  bytes += P * FI;
+  if (ff > 1) bytes += 2 * P * FI;
   if (p.K >= 2) {
     // staging slots and descriptors of the Exp backward, per direction, two steps
-    const uint64_t tiles = (uint64_t)point_tiles(dims[0], dims[1], dims[2]);
+    const uint64_t tiles = (uint64_t)point_tiles(fd[0], fd[1], fd[2]);
     bytes += 2 * 2 * n1 * tiles * (3 * STAGE_CAP * sizeof(float) + 8 * sizeof(int));
     bytes += 2 * n1 * p.K * sizeof(int) + 2 * 256;
   }
@@ -216,7 +231,17 @@ float* Job::pair_grad(int i, int j) const {
 }
 
 float* Job::coef(int i, int j) const {
-  return field(m_coef.as<float>(), (size_t)pair_index(i, j, N));
+  return fieldI(m_coef.as<float>(), (size_t)pair_index(i, j, N));
+}
+
+float* Job::pair_img(int i, int j) const {
+  if (ff == 1) return pair_field(i, j);
+  return fieldI(m_pimg.as<float>(), (size_t)pair_index(i, j, N));
+}
+
+float* Job::pair_grad_img(int i, int j) const {
+  if (ff == 1) return pair_grad(i, j);
+  return fieldI(m_gimg.as<float>(), (size_t)pair_index(i, j, N));
 }
 
 std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
@@ -236,9 +261,13 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   J.pairs_out = jd.pairs_out_dev;
   if (jd.times_host) J.times.assign(jd.times_host, jd.times_host + jd.N);
   const int L = J.p.levels;
+  J.ff = J.p.flow_factor == 2 ? 2 : 1;
   for (int l = 0; l < L; ++l) {
     const int f = 1 << (L - 1 - l);
-    for (int d = 0; d < 3; ++d) J.ldims[l][d] = jd.dims[d] / f;
+    for (int d = 0; d < 3; ++d) {
+      J.idims[l][d] = jd.dims[d] / f;
+      J.ldims[l][d] = jd.dims[d] / (f * J.ff);
+    }
   }
   const int N = J.N;
   J.deep_slot.assign((size_t)N * N, -1);
@@ -248,6 +277,7 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
       if (std::abs(i - j) >= 2) J.deep_slot[i * N + j] = slot++;
   const size_t V0 = J.V(L - 1);
   const size_t F = 3 * V0 * sizeof(float);
+  const size_t FI = 3 * J.VI(L - 1) * sizeof(float);
   const size_t n1 = N - 1;
   const size_t P = (size_t)N * (N - 1);
   J.m_phi.alloc(ctx, n1 * F);
@@ -257,7 +287,11 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   J.m_deep.alloc(ctx, std::max<size_t>(slot, 1) * F);
   J.m_gpair.alloc(ctx, P * F);
   J.m_pp.alloc(ctx, 4 * n1 * F);
-  J.m_coef.alloc(ctx, P * F);
+  J.m_coef.alloc(ctx, P * FI);
+  if (J.ff > 1) {
+    J.m_pimg.alloc(ctx, P * FI);
+    J.m_gimg.alloc(ctx, P * FI);
+  }
   if (J.p.smooth_sigma > 0.f) {
     J.m_phis.alloc(ctx, n1 * F);
     J.m_t1.alloc(ctx, n1 * F);
@@ -270,7 +304,7 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
     J.m_flags.alloc(ctx, 2 * n1 * (size_t)J.p.K * sizeof(int));
   }
   size_t img = 0;
-  for (int l = 0; l < L - 1; ++l) img += (size_t)N * J.V(l);
+  for (int l = 0; l < L - 1; ++l) img += (size_t)N * J.VI(l);
   J.m_img.alloc(ctx, std::max<size_t>(img, 1) * sizeof(float));
   J.m_state.alloc(ctx, sizeof(JobState));
   J.hist_len = 0;
@@ -285,7 +319,7 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   size_t off = 0;
   for (int l = 0; l < L - 1; ++l) {
     J.level_images[l] = J.m_img.as<float>() + off;
-    off += (size_t)N * J.V(l);
+    off += (size_t)N * J.VI(l);
   }
   J.level_images[L - 1] = const_cast<float*>(J.images_fine);
   MUSTER_HIP(hipHostMalloc((void**)&J.host_state, sizeof(JobState), hipHostMallocDefault));
@@ -293,7 +327,8 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
   J.footprint = J.m_phi.bytes + J.m_m.bytes + J.m_v.bytes + J.m_us.bytes + J.m_deep.bytes +
                 J.m_gpair.bytes + J.m_pp.bytes + J.m_coef.bytes + J.m_img.bytes +
                 J.m_state.bytes + J.m_hist.bytes + J.m_phis.bytes + J.m_t1.bytes + J.m_t2.bytes +
-                J.m_stage.bytes + J.m_desc.bytes + J.m_flags.bytes;
+                J.m_stage.bytes + J.m_desc.bytes + J.m_flags.bytes + J.m_pimg.bytes +
+                J.m_gimg.bytes;
   return job;
 }
 
@@ -321,8 +356,8 @@ void job_begin_level(Job& J, int level, hipStream_t s) {
     for (int l = L - 2; l >= 0; --l) {
       std::vector<PoolItem> items;
       int tiles = 0;
-      const int* dd = J.ldims[l + 1];
-      const size_t Vs = J.V(l + 1), Vd = J.V(l);
+      const int* dd = J.idims[l + 1];
+      const size_t Vs = J.VI(l + 1), Vd = J.VI(l);
       for (int i = 0; i < N; ++i) {
         PoolItem it{};
         it.tile0 = tiles;
@@ -388,7 +423,7 @@ void job_begin_level(Job& J, int level, hipStream_t s) {
   st.hist_base = base;
   *J.host_state = st;
   MUSTER_HIP(hipMemcpyAsync(J.js, J.host_state, sizeof(JobState), hipMemcpyHostToDevice, s));
-  J.sim_tile[level] = choose_sim_tile(ctx, J.ldims[level], J.p.window, J.p.metric, s);
+  J.sim_tile[level] = choose_sim_tile(ctx, J.idims[level], J.p.window, J.p.metric, s);
   MUSTER_HIP(hipStreamSynchronize(s));
 }
 
@@ -403,16 +438,33 @@ void job_final_outputs(Job& J, hipStream_t s) {
   auto plan = build_plan(one, PLAN_FORWARD);
   plan->upload(ctx, s);
   plan->run(ctx, s);
-  const size_t V = J.Vc();
-  if (J.svf_out)
-    MUSTER_HIP(hipMemcpyAsync(J.svf_out, J.flow(0), (size_t)(J.N - 1) * 3 * V * sizeof(float),
-                              hipMemcpyDeviceToDevice, s));
+  const size_t VI = J.VIc();
+  if (J.svf_out) {
+    if (J.ff == 1) {
+      MUSTER_HIP(hipMemcpyAsync(J.svf_out, J.flow(0), (size_t)(J.N - 1) * 3 * VI * sizeof(float),
+                                hipMemcpyDeviceToDevice, s));
+    } else {
+      // the flows carried up to the image grid (image voxel units)
+      std::vector<UpItem> items;
+      int tiles = 0;
+      for (int i = 0; i < J.N - 1; ++i) {
+        UpItem it{};
+        it.tile0 = tiles;
+        it.D = J.ldims[J.level][0]; it.H = J.ldims[J.level][1]; it.W = J.ldims[J.level][2];
+        it.src = J.flow(i);
+        it.dst = J.svf_out + (size_t)i * 3 * VI;
+        items.push_back(it);
+        tiles += elem_tiles(VI);
+      }
+      run_items(ctx, items, tiles, s, launch_upsample2);
+    }
+  }
   if (J.pairs_out) {
     for (int i = 0; i < J.N; ++i)
       for (int j = 0; j < J.N; ++j)
         if (i != j)
-          MUSTER_HIP(hipMemcpyAsync(J.pairs_out + (size_t)pair_index(i, j, J.N) * 3 * V,
-                                    J.pair_field(i, j), 3 * V * sizeof(float),
+          MUSTER_HIP(hipMemcpyAsync(J.pairs_out + (size_t)pair_index(i, j, J.N) * 3 * VI,
+                                    J.pair_img(i, j), 3 * VI * sizeof(float),
                                     hipMemcpyDeviceToDevice, s));
   }
   MUSTER_HIP(hipStreamSynchronize(s));
@@ -549,6 +601,40 @@ void add_exp_fwd_step(Builder& b, const std::vector<Job*>& jobs, int s, bool rec
   b.add(ST_EXP_FWD, items, tiles, bytes);
 }
 
+// Jobs whose flow grid is coarser than the image grid: the pair fields
+// carried up to the image grid for the similarity (forward), or the pair
+// gradients carried back down by the adjoint (backward).
+constexpr double B_UPSAMPLE = 12 + 12 * 8, B_UPSAMPLE_ADJ = 12 * 8 + 12;  // per coarse voxel
+void add_pair_resampling(Builder& b, const std::vector<Job*>& jobs, bool adjoint) {
+  std::vector<UpItem> items;
+  int tiles = 0;
+  double bytes = 0;
+  for (Job* J : jobs) {
+    if (J->ff == 1) continue;
+    const int* d = J->ldims[J->level];
+    for (int i = 0; i < J->N; ++i)
+      for (int j = 0; j < J->N; ++j) {
+        if (i == j) continue;
+        UpItem it{};
+        it.tile0 = tiles;
+        it.D = d[0]; it.H = d[1]; it.W = d[2];
+        if (adjoint) {
+          it.src = J->pair_grad_img(i, j);
+          it.dst = J->pair_grad(i, j);
+          tiles += elem_tiles(J->Vc());
+          bytes += B_UPSAMPLE_ADJ * J->Vc();
+        } else {
+          it.src = J->pair_field(i, j);
+          it.dst = J->pair_img(i, j);
+          tiles += elem_tiles(J->VIc());
+          bytes += B_UPSAMPLE * J->Vc();
+        }
+        items.push_back(it);
+      }
+  }
+  b.add(adjoint ? ST_UPSAMPLE_ADJ : ST_UPSAMPLE, items, tiles, bytes);
+}
+
 void add_forward(Builder& b, const std::vector<Job*>& jobs) {
   int maxK = 0, maxN = 0;
   for (Job* J : jobs) {
@@ -587,6 +673,7 @@ void add_forward(Builder& b, const std::vector<Job*>& jobs) {
     }
     b.add(ST_COMPOSE_FWD, items, tiles, bytes);
   }
+  add_pair_resampling(b, jobs, false);
 }
 
 // The pair items of the jobs whose window statistics use tile shape `shape`.
@@ -598,7 +685,7 @@ std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int shape, int& ti
     const SimTile& tl = J->sim_tile[J->level];
     if (tl.shape != shape) continue;
     const int N = J->N;
-    const int* d = J->ldims[J->level];
+    const int* d = J->idims[J->level];
     const int r = (J->p.window - 1) / 2;
     const double nr = (double)(d[0] - 2 * r) * (d[1] - 2 * r) * (d[2] - 2 * r);
     for (int i = 0; i < N; ++i)
@@ -610,15 +697,15 @@ std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int shape, int& ti
         it.zc = tl.zc;
         it.F = J->image(i);
         it.I = J->image(j);
-        it.U = J->pair_field(i, j);
+        it.U = J->pair_img(i, j);
         it.coef = J->coef(i, j);
-        it.gU = J->pair_grad(i, j);
+        it.gU = J->pair_grad_img(i, j);
         it.inv_nr = 1.0 / nr;
         it.js = J->js;
         it.sim_out = nullptr;
         items.push_back(it);
         tiles += stat_tiles(d[0], d[1], d[2], tl.zc, shape);
-        vox += (double)J->Vc();
+        vox += (double)J->VIc();
       }
   }
   return items;
@@ -685,6 +772,7 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
     maxN = std::max(maxN, J->N);
   }
   add_sim_stages(b, jobs, ST_SIM_GRAD);
+  add_pair_resampling(b, jobs, true);
   for (int d = maxN - 1; d >= 2; --d) {
     std::vector<ComposeBwdItem> items;
     int tiles = 0;
@@ -883,6 +971,8 @@ static int kclass(StageKind k) {
     case ST_ADAM: return MUSTER_K_ADAM;
     case ST_FINISH: return MUSTER_K_FINISH;
     case ST_SMOOTH: return MUSTER_K_SMOOTH;
+    case ST_UPSAMPLE: return MUSTER_K_UPSAMPLE;
+    case ST_UPSAMPLE_ADJ: return MUSTER_K_UPSAMPLE_ADJ;
   }
   return MUSTER_K_FINISH;
 }
@@ -904,6 +994,8 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_ADAM: return launch_adam((const AdamItem*)p, st.n_items, st.n_tiles, s);
     case ST_FINISH: return launch_finish((JobState* const*)p, st.n_items, s);
     case ST_SMOOTH: return launch_smooth((const SmoothItem*)p, st.n_items, st.n_tiles, st.lds, s);
+    case ST_UPSAMPLE: return launch_upsample2((const UpItem*)p, st.n_items, st.n_tiles, s);
+    case ST_UPSAMPLE_ADJ: return launch_upsample2_adj((const UpItem*)p, st.n_items, st.n_tiles, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1481,6 +1573,7 @@ muster_status muster_params_default(muster_params* p) {
     p->exp_mode = MUSTER_EXP_STORE;
     p->use_graph = 1;
     p->smooth_sigma = 0.0f;
+    p->flow_factor = 1;
   });
 }
 
@@ -1665,16 +1758,15 @@ muster_status muster_loss_forward(muster_ctx* h, void* stream, int N, const int 
     auto plan = build_plan(one, PLAN_LOSS_FWD);
     plan->upload(ctx, s);
     plan->run(ctx, s);
+    const GridDims fd{J.ldims[0][0], J.ldims[0][1], J.ldims[0][2]};  // the flow grid
     for (int i = 0; i < N - 1; ++i)
-      MUSTER_HIP(launch_reg(GridDims{dims[0], dims[1], dims[2]}, J.flow(i), &J.js->loss_reg,
-                            nullptr, s));
+      MUSTER_HIP(launch_reg(fd, J.flow(i), &J.js->loss_reg, nullptr, s));
     for (int i = 0; i < N - 1; ++i) {
       ExpBwdItem e{};
       set_reg_ext(e, J, i);
       if (e.ext)
-        MUSTER_HIP(launch_reg_ext(GridDims{dims[0], dims[1], dims[2]}, J.flow(i), e.flow_prev,
-                                  e.l2_loss_w, e.ts_loss_w, e.inv_dprev, e.inv_dself,
-                                  &J.js->loss_ext, s));
+        MUSTER_HIP(launch_reg_ext(fd, J.flow(i), e.flow_prev, e.l2_loss_w, e.ts_loss_w, e.inv_dprev,
+                                  e.inv_dself, &J.js->loss_ext, s));
     }
     read_state(J, s);
     if (ctx->timing) resolve_timing(ctx);
@@ -2022,6 +2114,27 @@ muster_status muster_upsample2(muster_ctx* h, void* stream, const int dims[3], c
   });
 }
 
+muster_status muster_upsample2_adjoint(muster_ctx* h, void* stream, const int dims[3],
+                                       const float* src, float* dst) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && src && dst, "NULL argument");
+    check_dims(dims, 2);
+    NEED((uint64_t)dims[0] * dims[1] * dims[2] * 8 * 3 < (uint64_t)INT32_MAX, "volume too large");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    UpItem it{};
+    it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.src = src;
+    it.dst = dst;
+    const size_t off = sc.add(it);
+    sc.upload();
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2];
+    MUSTER_HIP(launch_upsample2_adj((const UpItem*)(sc.dev() + off), 1, elem_tiles(V), sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
 // ---- measurement ----------------------------------------------------------------
 
 muster_status muster_ctx_set_tiling(muster_ctx* h, int mode, int shape, int zchunk) {
@@ -2089,7 +2202,7 @@ muster_status muster_kernel_stats_reset(muster_ctx* h) {
 const char* muster_kernel_name(int k) {
   static const char* names[MUSTER_K_COUNT] = {"exp_fwd", "compose_fwd", "sim_stats", "sim_grad",
                                               "compose_bwd", "exp_bwd", "adam", "finish",
-                                              "pool2", "upsample2", "smooth"};
+                                              "pool2", "upsample2", "smooth", "upsample2_adj"};
   if (k < 0 || k >= MUSTER_K_COUNT) return "";
   return names[k];
 }

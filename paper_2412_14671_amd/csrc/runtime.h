@@ -127,13 +127,16 @@ struct Job {
   float grad_scale = 1.f;
 
   int level = 0;                     // current pyramid level (0 = coarsest)
-  int ldims[MUSTER_MAX_LEVELS][3];
+  int ff = 1;                        // flow grid factor: flows on the image grid / ff
+  int ldims[MUSTER_MAX_LEVELS][3];   // flow grid per level (fields)
+  int idims[MUSTER_MAX_LEVELS][3];   // image grid per level
   std::vector<int> deep_slot;        // N*N -> slot of |i-j| >= 2 pairs, -1 otherwise
   std::vector<double> times;         // acquisition times (empty if not given)
   SimTile sim_tile[MUSTER_MAX_LEVELS];
 
   DevMem m_phi, m_m, m_v, m_us, m_deep, m_gpair, m_pp, m_coef, m_img, m_state, m_hist;
   DevMem m_phis, m_t1, m_t2;         // smoothed flow and gradient ping-pong (smoothing on)
+  DevMem m_pimg, m_gimg;             // pair fields and their gradients on the image grid (ff > 1)
   DevMem m_stage, m_desc, m_flags;   // staged Exp-backward accumulation (K >= 2)
   float* phi = nullptr;              // may alias the caller's field in grad_mode
   float* mbuf = nullptr;
@@ -147,6 +150,9 @@ struct Job {
 
   ~Job();
   size_t V(int l) const { return (size_t)ldims[l][0] * ldims[l][1] * ldims[l][2]; }
+  size_t VI(int l) const { return (size_t)idims[l][0] * idims[l][1] * idims[l][2]; }
+  size_t VIc() const { return VI(level); }
+  float* fieldI(float* base, size_t idx) const { return base + idx * 3 * VIc(); }
   float sigma() const { return p.smooth_sigma / (float)(1 << (p.levels - 1 - level)); }
   bool smoothing() const { return sigma() > 0.f; }
   // the flow Exp integrates: the smoothed field when smoothing is on
@@ -157,8 +163,10 @@ struct Job {
   float* us_field(int dir, int slot) const;     // see runtime.cpp
   float* u_step(int dir, int s) const;          // u_s for s in 1..K (store or recompute layout)
   float* u_final(int dir) const { return u_step(dir, p.K); }
-  float* pair_field(int i, int j) const;        // U[j->i]
+  float* pair_field(int i, int j) const;        // U[j->i] on the flow grid
   float* pair_grad(int i, int j) const;
+  float* pair_img(int i, int j) const;          // U[j->i] on the image grid
+  float* pair_grad_img(int i, int j) const;
   float* pp(int dir, int k) const { return field(m_pp.as<float>(), (size_t)dir * 2 + k); }
   bool staged() const { return p.K >= 2; }
   int tiles_fine = 0;                // point tiles of the finest grid
@@ -168,7 +176,7 @@ struct Job {
   int* desc(int dir, int k) const { return m_desc.as<int>() + ((size_t)dir * 2 + k) * tiles_fine * 8; }
   int* flag(int dir, int s) const { return m_flags.as<int>() + (size_t)dir * p.K + s; }
   float* coef(int i, int j) const;
-  const float* image(int i) const { return level_images[level] + (size_t)i * Vc(); }
+  const float* image(int i) const { return level_images[level] + (size_t)i * VIc(); }
 };
 
 uint64_t job_footprint(int N, const int dims[3], const muster_params& p);
@@ -185,7 +193,7 @@ void load_tune_cache(Ctx* ctx);
 // A launch plan: one iteration (or a forward pass) of a set of jobs.
 enum StageKind {
   ST_EXP_FWD, ST_COMPOSE_FWD, ST_SIM_STATS, ST_SIM_GRAD, ST_COMPOSE_BWD, ST_EXP_BWD, ST_ADAM,
-  ST_FINISH, ST_SMOOTH
+  ST_FINISH, ST_SMOOTH, ST_UPSAMPLE, ST_UPSAMPLE_ADJ
 };
 
 struct Stage {

@@ -369,3 +369,42 @@ def test_large_displacements_take_the_overflow_path_and_match_oracle(ctx):
         L_ref, g_ref, _ = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
         assert abs(float(loss.detach()) - L_ref) < 1e-3 * abs(L_ref)
         assert_grad_close(host(svf.grad), np.stack(g_ref))
+
+
+# ---------------------------------------------------------------------------
+# Flow grid twice as coarse as the images (Sec. 2.7 stage geometry)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (16, 12, 20), (2, 9, 33)])
+def test_upsample2_and_adjoint_match_oracle(ctx, shape):
+    f = smooth_field(shape, 1.5, seed=sum(shape), sigma=1.0)
+    g = smooth_field(tuple(2 * n for n in shape), 1.0, seed=sum(shape) + 1, sigma=1.0)
+    up = host(ctx.upsample2(gpu(f)))
+    assert np.abs(up - O.upsample2(f.astype(np.float64))).max() < 1e-5
+    adj = host(ctx.upsample2_adjoint(gpu(g)))
+    want = O.upsample2_adjoint(g.astype(np.float64), shape)
+    assert np.abs(adj - want).max() < 1e-5 * max(1.0, np.abs(want).max())
+
+
+@pytest.mark.parametrize("case", [
+    dict(fshape=(12, 14, 16), N=3, K=6, w=5, metric="silncc", sigma=0.0),
+    dict(fshape=(10, 12, 9), N=4, K=5, w=3, metric="lncc", sigma=1.0),
+])
+def test_loss_and_gradient_on_a_coarse_flow_grid_match_oracle(ctx, case):
+    from paper_2412_14671_amd import MusterLoss, MusterParams
+    log(f"loss coarse flow {case}")
+    fshape, N = case["fshape"], case["N"]
+    shape = tuple(2 * n for n in fshape)
+    imgs = np.stack([smooth_image(shape, seed=110 + k) for k in range(N)])
+    phis = np.stack([smooth_field(fshape, 1.0, seed=120 + k, sigma=1.2) for k in range(N - 1)])
+    svf = gpu(phis).requires_grad_(True)
+    params = MusterParams(K=case["K"], window=case["w"], metric=case["metric"], alpha_ss=0.5,
+                          smooth_sigma=case["sigma"], flow_factor=2)
+    loss = MusterLoss.apply(svf, gpu(imgs), params, ctx)
+    loss.backward()
+    p = O.Params(K=case["K"], window=case["w"],
+                 metric=O.LNCC if case["metric"] == "lncc" else O.SILNCC, alpha_ss=0.5,
+                 smooth_sigma=case["sigma"], flow_factor=2)
+    L_ref, g_ref, _ = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
+    assert abs(float(loss.detach()) - L_ref) < 1e-3 * abs(L_ref)
+    assert_grad_close(host(svf.grad), np.stack(g_ref))

