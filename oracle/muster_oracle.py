@@ -683,6 +683,51 @@ def register(images: List[np.ndarray], p: Params, phis0: Optional[List[np.ndarra
 # Evaluation (Sec. 2.8)
 # ---------------------------------------------------------------------------
 
+def jacobian_det(U: np.ndarray) -> np.ndarray:
+    """det(d(Omega + U)/dx) per voxel for a displacement field U (3, D, H, W):
+    the determinant of I + grad U, with the derivatives by central
+    differences inside the grid and one-sided differences at its faces."""
+    U = np.asarray(U, np.float64)
+    J = np.empty((3, 3) + U.shape[1:])
+    for c in range(3):
+        g = np.gradient(U[c], axis=(0, 1, 2))
+        for d in range(3):
+            J[c, d] = g[d] + (1.0 if c == d else 0.0)
+    return (J[0, 0] * (J[1, 1] * J[2, 2] - J[1, 2] * J[2, 1])
+            - J[0, 1] * (J[1, 0] * J[2, 2] - J[1, 2] * J[2, 0])
+            + J[0, 2] * (J[1, 0] * J[2, 1] - J[1, 1] * J[2, 0]))
+
+
+def _roi_vectors(phi: np.ndarray, roi: Optional[np.ndarray]) -> np.ndarray:
+    phi = np.asarray(phi, np.float64)
+    v = phi.reshape(3, -1)
+    if roi is not None:
+        v = v[:, np.asarray(roi, bool).ravel()]
+    return v
+
+
+def pcc(phi_true: np.ndarray, phi: np.ndarray, roi: Optional[np.ndarray] = None) -> float:
+    """Pearson correlation of two vector fields over the region of interest
+    (Sec. 2.8): centre each field by its mean vector, then the sum of the
+    per-voxel dot products over the product of the two root sums of squares."""
+    a = _roi_vectors(phi_true, roi)
+    b = _roi_vectors(phi, roi)
+    a = a - a.mean(axis=1, keepdims=True)
+    b = b - b.mean(axis=1, keepdims=True)
+    return float((a * b).sum() / np.sqrt((a * a).sum() * (b * b).sum()))
+
+
+def slope(phi_true: np.ndarray, phi: np.ndarray, roi: Optional[np.ndarray] = None) -> float:
+    """Bias B (Sec. 2.8): fit phi = A phi_true + b by least squares over the
+    region of interest (A 3x3, b a vector) and return trace(A) / 3."""
+    a = _roi_vectors(phi_true, roi)
+    b = _roi_vectors(phi, roi)
+    X = np.vstack([a, np.ones((1, a.shape[1]))]).T        # regressors with intercept
+    coef, *_ = np.linalg.lstsq(X, b.T, rcond=None)        # (4, 3): rows of A^T, then b
+    A = coef[:3].T
+    return float(np.trace(A) / 3.0)
+
+
 def euclidean_error(phi_true: np.ndarray, phi: np.ndarray, roi: Optional[np.ndarray] = None) -> float:
     """Eu: mean over the region of interest of the point-wise vector distance."""
     d = np.sqrt(((np.asarray(phi_true, np.float64) - np.asarray(phi, np.float64)) ** 2).sum(0))

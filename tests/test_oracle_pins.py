@@ -706,3 +706,36 @@ def test_loss_gradient_with_a_coarse_flow_grid_matches_finite_differences():
         dn[i][idx] -= h
         fd = (O.forward(up, imgs, p) - O.forward(dn, imgs, p)) / (2 * h)
         assert abs(fd - grads[i][idx]) < 2e-5 * max(1.0, np.abs(grads[i]).max())
+
+
+# --------------------------------------------------------------------------
+# Outputs and evaluation: Jacobian determinants, Eu, PCC, slope (Sec. 2.8)
+# --------------------------------------------------------------------------
+
+def test_jacobian_det_of_affine_and_translation_fields_is_exact():
+    shape = (6, 7, 8)
+    g = np.stack(np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij"))
+    M = np.array([[0.1, -0.05, 0.02], [0.03, -0.2, 0.04], [0.0, 0.06, 0.15]])
+    U = np.einsum("cd,d...->c...", M, g) + np.array([1.0, -2.0, 0.5])[:, None, None, None]
+    # finite differences (central and one-sided) are exact on linear fields
+    assert np.allclose(O.jacobian_det(U), np.linalg.det(np.eye(3) + M), atol=1e-13)
+    T = np.broadcast_to(np.array([0.3, 0.1, -0.7])[:, None, None, None], (3,) + shape)
+    assert np.allclose(O.jacobian_det(T), 1.0, atol=1e-15)
+
+
+def test_pcc_and_slope_closed_forms():
+    r = rng(300)
+    shape = (5, 6, 7)
+    a = r.standard_normal((3,) + shape)
+    roi = r.uniform(size=shape) > 0.3
+    assert abs(O.pcc(a, a, roi) - 1.0) < 1e-12
+    assert abs(O.pcc(a, 2.5 * a + np.array([1.0, 2.0, -3.0])[:, None, None, None], roi) - 1.0) < 1e-12
+    assert abs(O.pcc(a, -a, roi) + 1.0) < 1e-12
+    assert abs(O.slope(a, 0.7 * a + 0.2, roi) - 0.7) < 1e-12
+    # a general linear map: the slope is the mean diagonal of the map
+    M = np.array([[0.9, 0.1, 0.0], [0.2, 1.3, -0.1], [0.0, 0.05, 0.5]])
+    b = np.einsum("cd,d...->c...", M, a) + np.array([0.1, 0.0, -0.2])[:, None, None, None]
+    assert abs(O.slope(a, b, roi) - np.trace(M) / 3) < 1e-12
+    # independent noise decorrelates
+    n = r.standard_normal((3,) + shape)
+    assert abs(O.pcc(a, n)) < 0.15
