@@ -350,6 +350,11 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
         "cpu_baseline": None,
         "eu_voxels": round(eu(true_np, svf_np, roi), 4),
         "eu_at_zero": round(eu(true_np, np.zeros_like(svf_np), roi), 4),
+        # Sec. 2.8 metrics per interval, by the library's evaluation kernel
+        "pcc_per_interval": [round(ctx.field_metrics(s.svf_true[k].contiguous(), svf[k].contiguous(),
+                                                     s.roi)[1], 4) for k in range(N - 1)],
+        "slope_per_interval": [round(ctx.field_metrics(s.svf_true[k].contiguous(), svf[k].contiguous(),
+                                                       s.roi)[2], 4) for k in range(N - 1)],
         "loss_first": rep["loss_first"], "loss_last": rep["loss_last"],
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                         "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}

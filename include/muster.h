@@ -302,6 +302,25 @@ muster_status muster_upsample2(muster_ctx* ctx, void* stream, const int dims[3],
 muster_status muster_upsample2_adjoint(muster_ctx* ctx, void* stream, const int dims[3],
                                        const float* src_dev, float* dst_dev);
 
+/* ---- outputs and evaluation (Sec. 2.8) ------------------------------------ */
+
+/* Jacobian determinant of Omega + U at every voxel: det(I + grad U), the
+ * derivatives by central differences inside the grid and one-sided
+ * differences at its faces.  U [3][D][H][W] in voxels, det [D][H][W].  Every
+ * dimension must be at least 2. */
+muster_status muster_jacobian_det(muster_ctx* ctx, void* stream, const int dims[3],
+                                  const float* U_dev, float* det_dev);
+/* Metrics of an estimated displacement field against a reference over a
+ * region of interest (roi_dev: one byte per voxel, non-zero = inside; NULL =
+ * every voxel): eu = mean |est - ref|; pcc = the vector Pearson correlation
+ * (both fields centred by their mean vectors); slope = trace(A) / 3 for the
+ * least-squares fit est = A ref + b.  Sums are accumulated in FP64.
+ * MUSTER_E_INVALID for an empty region. */
+muster_status muster_field_metrics(muster_ctx* ctx, void* stream, const int dims[3],
+                                   const float* ref_dev, const float* est_dev,
+                                   const unsigned char* roi_dev, double* eu, double* pcc,
+                                   double* slope);
+
 /* ---- measurement --------------------------------------------------------- */
 
 enum {

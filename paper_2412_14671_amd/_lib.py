@@ -97,6 +97,9 @@ SIGNATURES = {
     "muster_pool2": (_ST, [_P, _P, DIMS, _P, _P]),
     "muster_upsample2": (_ST, [_P, _P, DIMS, _P, _P]),
     "muster_upsample2_adjoint": (_ST, [_P, _P, DIMS, _P, _P]),
+    "muster_jacobian_det": (_ST, [_P, _P, DIMS, _P, _P]),
+    "muster_field_metrics": (_ST, [_P, _P, DIMS, _P, _P, _P, POINTER(c_double), POINTER(c_double),
+                                   POINTER(c_double)]),
     "muster_smooth": (_ST, [_P, _P, DIMS, c_float, _P, _P]),
     "muster_ctx_set_tiling": (_ST, [_P, c_int, c_int, c_int]),
     "muster_ctx_sim_tiling": (_ST, [_P, _P, DIMS, c_int, c_int, POINTER(c_int), POINTER(c_int)]),

@@ -185,6 +185,25 @@ class Context:
                                                   _ptr(out)))
         return out
 
+    # -- outputs and evaluation -------------------------------------------------------
+    def jacobian_det(self, U):
+        """det(I + grad U) per voxel for a displacement field U [3, D, H, W]."""
+        out = torch.empty(tuple(U.shape[1:]), device=U.device)
+        L.check(self.lib.muster_jacobian_det(self.h, _stream(), _dims(U.shape[1:]), _ptr(U),
+                                             _ptr(out)))
+        return out
+
+    def field_metrics(self, ref, est, roi=None):
+        """(Eu, PCC, slope) of est against ref over roi (bool [D, H, W] or None)."""
+        r = None
+        if roi is not None:
+            r = roi.to(device=ref.device, dtype=torch.uint8).contiguous()
+        eu, pcc, sl = c_double(), c_double(), c_double()
+        L.check(self.lib.muster_field_metrics(self.h, _stream(), _dims(ref.shape[1:]), _ptr(ref),
+                                              _ptr(est), None if r is None else c_void_p(r.data_ptr()),
+                                              byref(eu), byref(pcc), byref(sl)))
+        return eu.value, pcc.value, sl.value
+
     # -- whole registrations -----------------------------------------------------
     def footprint(self, N, dims, params: MusterParams) -> int:
         b = c_uint64()

@@ -1841,6 +1841,99 @@ hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStre
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Outputs and evaluation (Sec. 2.8): Jacobian determinants of Omega + U, and
+// the sums from which Eu, the vector PCC and the regression slope follow.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float fd_axis(const cgfloat* __restrict__ f, int p, int i, int n,
+                                         int stride) {
+  // central difference inside, one-sided at the two faces
+  if (i == 0) return f[p + stride] - f[p];
+  if (i == n - 1) return f[p] - f[p - stride];
+  return 0.5f * (f[p + stride] - f[p - stride]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_jacobian_det(GridDims d, const float* __restrict__ U_,
+                                                        float* __restrict__ out) {
+  const int D = d.D, H = d.H, W = d.W, HW = H * W, V = D * HW;
+  const cgfloat* __restrict__ U = gp(U_);
+  for (int p = blockIdx.x * BLOCK + threadIdx.x; p < V; p += gridDim.x * BLOCK) {
+    const int x = p % W, y = (p / W) % H, z = p / HW;
+    float J[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cgfloat* __restrict__ f = U + (size_t)c * V;
+      J[c][0] = fd_axis(f, p, z, D, HW) + (c == 0 ? 1.f : 0.f);
+      J[c][1] = fd_axis(f, p, y, H, W) + (c == 1 ? 1.f : 0.f);
+      J[c][2] = fd_axis(f, p, x, W, 1) + (c == 2 ? 1.f : 0.f);
+    }
+    gp(out)[p] = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  }
+}
+
+// Sums over the region of interest (roi may be NULL: every voxel): count,
+// sum |b - a|, sum a (3), sum b (3), sum a a^T (9), sum b a^T (9), sum b.b.
+constexpr int FIELD_STATS = 27;
+
+__global__ __launch_bounds__(BLOCK) void k_field_stats(int V, const float* __restrict__ a_,
+                                                       const float* __restrict__ b_,
+                                                       const unsigned char* __restrict__ roi,
+                                                       double* __restrict__ out) {
+  __shared__ double red[BLOCK / 64];
+  const cgfloat* __restrict__ a = gp(a_);
+  const cgfloat* __restrict__ b = gp(b_);
+  double acc[FIELD_STATS];
+#pragma unroll
+  for (int k = 0; k < FIELD_STATS; ++k) acc[k] = 0.0;
+  for (int p = blockIdx.x * BLOCK + threadIdx.x; p < V; p += gridDim.x * BLOCK) {
+    if (roi && !roi[p]) continue;
+    double av[3], bv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      av[c] = a[(size_t)c * V + p];
+      bv[c] = b[(size_t)c * V + p];
+    }
+    acc[0] += 1.0;
+    acc[1] += sqrt((bv[0] - av[0]) * (bv[0] - av[0]) + (bv[1] - av[1]) * (bv[1] - av[1]) +
+                   (bv[2] - av[2]) * (bv[2] - av[2]));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      acc[2 + c] += av[c];
+      acc[5 + c] += bv[c];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        acc[8 + 3 * c + e] += av[c] * av[e];
+        acc[17 + 3 * c + e] += bv[c] * av[e];
+      }
+    }
+    acc[26] += bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2];
+  }
+#pragma unroll
+  for (int k = 0; k < FIELD_STATS; ++k) {
+    const double t = block_sum(acc[k], red);
+    if (threadIdx.x == 0) unsafeAtomicAdd(out + k, t);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_jacobian_det(GridDims d, const float* U, float* out, hipStream_t s) {
+  const int V = d.D * d.H * d.W;
+  if (V <= 0) return hipSuccess;
+  const int blocks = ceil_div(V, BLOCK) < 4096 ? ceil_div(V, BLOCK) : 4096;
+  hipLaunchKernelGGL(k_jacobian_det, dim3(blocks), dim3(BLOCK), 0, s, d, U, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_stats(int V, const float* a, const float* b, const unsigned char* roi,
+                              double* out, hipStream_t s) {
+  if (V <= 0) return hipSuccess;
+  const int blocks = ceil_div(V, BLOCK) < 1024 ? ceil_div(V, BLOCK) : 1024;
+  hipLaunchKernelGGL(k_field_stats, dim3(blocks), dim3(BLOCK), 0, s, V, a, b, roi, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_upsample2_adj(const UpItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_upsample2_adj, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);

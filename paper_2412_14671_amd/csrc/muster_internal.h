@@ -243,6 +243,10 @@ hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hi
 hipError_t launch_reg_ext(GridDims d, const float* f, const float* fprev, float l2w, float tsw,
                           float inv_dp, float inv_ds, double* out, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_jacobian_det(GridDims d, const float* U, float* out, hipStream_t s);
+// 27 sums over the voxels with roi[p] != 0 (all if roi is NULL), added to out
+hipError_t launch_field_stats(int V, const float* a, const float* b, const unsigned char* roi,
+                              double* out, hipStream_t s);
 // p[c][z][y][x] = off + amp * (a smooth periodic pattern); scratch data for
 // the autotuner.
 hipError_t launch_pattern(float* p, int64_t n, const int dims[3], float off, float amp,

@@ -2137,6 +2137,74 @@ muster_status muster_upsample2_adjoint(muster_ctx* h, void* stream, const int di
 
 // ---- measurement ----------------------------------------------------------------
 
+muster_status muster_jacobian_det(muster_ctx* h, void* stream, const int dims[3], const float* U,
+                                  float* det) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && U && det, "NULL argument");
+    check_dims(dims, 2);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = (hipStream_t)stream;
+    MUSTER_HIP(launch_jacobian_det(GridDims{dims[0], dims[1], dims[2]}, U, det, s));
+    MUSTER_HIP(hipStreamSynchronize(s));
+  });
+}
+
+muster_status muster_field_metrics(muster_ctx* h, void* stream, const int dims[3], const float* ref,
+                                   const float* est, const unsigned char* roi, double* eu,
+                                   double* pcc, double* slope) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && ref && est && eu && pcc && slope, "NULL argument");
+    check_dims(dims, 1);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = (hipStream_t)stream;
+    const int V = dims[0] * dims[1] * dims[2];
+    double* acc = ctx->step_acc;  // 64 doubles
+    MUSTER_HIP(hipMemsetAsync(acc, 0, 27 * sizeof(double), s));
+    MUSTER_HIP(launch_field_stats(V, ref, est, roi, acc, s));
+    double t[27];
+    MUSTER_HIP(hipMemcpyAsync(t, acc, sizeof t, hipMemcpyDeviceToHost, s));
+    MUSTER_HIP(hipStreamSynchronize(s));
+    const double n = t[0];
+    NEED(n > 0, "the region of interest is empty");
+    *eu = t[1] / n;
+    double ma[3], mb[3], Saa[3][3], Sba[3][3];
+    for (int c = 0; c < 3; ++c) {
+      ma[c] = t[2 + c] / n;
+      mb[c] = t[5 + c] / n;
+    }
+    for (int c = 0; c < 3; ++c)
+      for (int e = 0; e < 3; ++e) {
+        Saa[c][e] = t[8 + 3 * c + e] - n * ma[c] * ma[e];
+        Sba[c][e] = t[17 + 3 * c + e] - n * mb[c] * ma[e];
+      }
+    const double Sbb = t[26] - n * (mb[0] * mb[0] + mb[1] * mb[1] + mb[2] * mb[2]);
+    const double tr_ba = Sba[0][0] + Sba[1][1] + Sba[2][2];
+    const double tr_aa = Saa[0][0] + Saa[1][1] + Saa[2][2];
+    *pcc = tr_ba / std::sqrt(tr_aa * Sbb);
+    // A = Sba Saa^-1 (least squares of est on ref with an intercept); B = tr(A) / 3
+    const double (&m)[3][3] = Saa;
+    const double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                       m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                       m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+    double inv[3][3];
+    inv[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) / det;
+    inv[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) / det;
+    inv[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) / det;
+    inv[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) / det;
+    inv[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) / det;
+    inv[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) / det;
+    inv[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) / det;
+    inv[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) / det;
+    inv[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) / det;
+    double tr = 0.0;
+    for (int c = 0; c < 3; ++c)
+      for (int e = 0; e < 3; ++e) tr += Sba[c][e] * inv[e][c];
+    *slope = tr / 3.0;
+  });
+}
+
 muster_status muster_ctx_set_tiling(muster_ctx* h, int mode, int shape, int zchunk) {
   Ctx* ctx = C(h);
   return guard(ctx, [&] {

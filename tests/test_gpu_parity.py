@@ -408,3 +408,27 @@ def test_loss_and_gradient_on_a_coarse_flow_grid_match_oracle(ctx, case):
     L_ref, g_ref, _ = O.loss_and_grad(list(phis.astype(np.float64)), list(imgs), p)
     assert abs(float(loss.detach()) - L_ref) < 1e-3 * abs(L_ref)
     assert_grad_close(host(svf.grad), np.stack(g_ref))
+
+
+# ---------------------------------------------------------------------------
+# Outputs and evaluation (Sec. 2.8)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(17, 20, 23), (2, 5, 40)])
+def test_jacobian_det_matches_oracle(ctx, shape):
+    U = smooth_field(shape, 1.5, seed=400 + shape[0], sigma=1.5)
+    got = host(ctx.jacobian_det(gpu(U)))
+    assert np.abs(got - O.jacobian_det(U.astype(np.float64))).max() < 1e-5
+
+
+@pytest.mark.parametrize("with_roi", [False, True])
+def test_field_metrics_match_oracle(ctx, with_roi):
+    shape = (24, 30, 36)
+    a = smooth_field(shape, 1.0, seed=410, sigma=2.0)
+    b = (0.8 * a + 0.3 * smooth_field(shape, 1.0, seed=411, sigma=2.0)).astype(np.float32)
+    roi = (rng(412).uniform(size=shape) > 0.4) if with_roi else None
+    eu_, pcc_, sl_ = ctx.field_metrics(gpu(a), gpu(b), None if roi is None else torch.from_numpy(roi))
+    A, B = a.astype(np.float64), b.astype(np.float64)
+    assert abs(eu_ - O.euclidean_error(A, B, roi)) < 1e-9
+    assert abs(pcc_ - O.pcc(A, B, roi)) < 1e-9
+    assert abs(sl_ - O.slope(A, B, roi)) < 1e-8
