@@ -466,6 +466,57 @@ def reg_ts_grad(phis: List[np.ndarray], times: Sequence[float]) -> List[np.ndarr
     return g
 
 
+# ---------------------------------------------------------------------------
+# Rigid adjustment (Sec. 2.5): Euler angles and a translation per session
+# ---------------------------------------------------------------------------
+
+def _rot(axis_a: int, axis_b: int, t: float, deriv: bool = False) -> np.ndarray:
+    """Rotation by t in the plane of components (axis_a, axis_b), turning a
+    towards b (or its derivative with respect to t)."""
+    R = np.zeros((3, 3)) if deriv else np.eye(3)
+    c, s_ = math.cos(t), math.sin(t)
+    if deriv:
+        c, s_ = -s_, c
+    R[axis_a, axis_a] = c
+    R[axis_b, axis_b] = c
+    R[axis_a, axis_b] = -s_
+    R[axis_b, axis_a] = s_
+    return R
+
+
+def rigid_matrix(theta, deriv: Optional[int] = None) -> np.ndarray:
+    """R = Rz Ry Rx in (z, y, x) components: Rz turns y towards x, Ry turns x
+    towards z, Rx turns z towards y.  With deriv = k, dR/dtheta_k."""
+    tz, ty, tx = (float(v) for v in theta)
+    f = [_rot(1, 2, tz, deriv == 0), _rot(2, 0, ty, deriv == 1), _rot(0, 1, tx, deriv == 2)]
+    return f[0] @ f[1] @ f[2]
+
+
+def rigid_displacement(params, shape) -> np.ndarray:
+    """L(p) - p for the linear map L(p) = R (p - c) + c + t of one session;
+    params = (theta_z, theta_y, theta_x, t_z, t_y, t_x), c the centre of the
+    grid, all in voxels of that grid."""
+    R = rigid_matrix(params[:3])
+    g = identity_grid(shape)
+    c = np.array([(n - 1) / 2.0 for n in shape])[:, None, None, None]
+    q = np.einsum("cd,d...->c...", R, g - c) + c + np.asarray(params[3:], np.float64)[:, None, None, None]
+    return q - g
+
+
+def rigid_grad(G: np.ndarray, params) -> np.ndarray:
+    """d/d params of sum_p G(p) . (L(p) - p) for a field G on the grid."""
+    G = np.asarray(G, np.float64)
+    shape = G.shape[1:]
+    g = identity_grid(shape)
+    c = np.array([(n - 1) / 2.0 for n in shape])[:, None, None, None]
+    M = G.reshape(3, -1) @ (g - c).reshape(3, -1).T   # sum_p G(p) (p - c)^T
+    out = np.zeros(6)
+    for k in range(3):
+        out[k] = float(np.sum(rigid_matrix(params[:3], deriv=k) * M))
+    out[3:] = G.reshape(3, -1).sum(axis=1)
+    return out
+
+
 @dataclass
 class Params:
     K: int = 7                 # squarings in Exp
@@ -476,6 +527,7 @@ class Params:
     alpha_ts: float = 0.0      # weight of L_ts (needs times)
     times: Optional[Tuple[float, ...]] = None  # acquisition times t_1..t_N
     flow_factor: int = 1       # 1: flows on the image grid; 2: on a grid twice as coarse
+    rigid: bool = False        # rigid adjustment of every session but the first
     smooth_sigma: float = 0.0  # Gaussian smoothing of the flow (voxels of the level); 0 = none
     lr: float = 0.1            # peak learning rate (voxels per step)
     warmup: float = 0.2        # warm-up fraction of each stage
@@ -484,7 +536,8 @@ class Params:
     iters: Tuple[int, ...] = (50,)   # iterations per pyramid level, coarse to fine
 
 
-def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: bool = False):
+def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: bool = False,
+            rigid: Optional[List[np.ndarray]] = None):
     """Evaluate L(phi) = sum_i sum_{j != i} Sim(I_i, I_j o Phi_ji^i) + alpha_ss L_ss
     + alpha_L2 L_L2 + alpha_ts L_ts (Eq. reg_sum).
 
@@ -502,6 +555,11 @@ def forward(phis: List[np.ndarray], images: List[np.ndarray], p: Params, keep: b
     # the pair fields act on the image grid: with a coarser flow grid they are
     # carried up by the same map as between pyramid levels (Sec. 2.7)
     Ui = U if p.flow_factor == 1 else {k: upsample2(v) for k, v in U.items()}
+    if p.rigid and rigid is not None:
+        # Sec. 2.5: the pair field that samples session j >= 1 gains the
+        # displacement of that session's linear map
+        Lj = [None] + [rigid_displacement(r, imgs[0].shape) for r in rigid]
+        Ui = {(i, j): (v + Lj[j] if j >= 1 else v) for (i, j), v in Ui.items()}
     sims = {}
     for (i, j), Uij in Ui.items():
         M = warp(imgs[j], Uij)
@@ -527,16 +585,22 @@ def pair_sim_grad(images, U, i, j, p: Params):
     return s, dM[None] * warp_grad(images[j], U)
 
 
-def loss_and_grad(phis: List[np.ndarray], images: List[np.ndarray], p: Params):
-    """Return (L, [dL/dphi_i], aux) by hand-written adjoints of every step."""
+def loss_and_grad(phis: List[np.ndarray], images: List[np.ndarray], p: Params,
+                  rigid: Optional[List[np.ndarray]] = None):
+    """Return (L, [dL/dphi_i], aux) by hand-written adjoints of every step;
+    with a rigid adjustment, aux["rigid_grad"] holds dL/d(params of session j)
+    for j = 1..N-1."""
     N = len(images)
     imgs = [np.asarray(I, np.float64) for I in images]
-    L, aux = forward(phis, imgs, p, keep=True)
+    L, aux = forward(phis, imgs, p, keep=True, rigid=rigid)
     U = aux["U"]
     f, b = aux["f"], aux["b"]
     G = {}
+    rg = [np.zeros(6) for _ in range(N - 1)]
     for (i, j), Uij in aux["U_img"].items():
         _, G[(i, j)] = pair_sim_grad(imgs, Uij, i, j, p)
+        if p.rigid and rigid is not None and j >= 1:
+            rg[j - 1] += rigid_grad(G[(i, j)], rigid[j - 1])
         if p.flow_factor != 1:
             G[(i, j)] = upsample2_adjoint(G[(i, j)], U[(i, j)].shape[1:])
     aux["G_pair_sim"] = {k: v.copy() for k, v in G.items()}
@@ -559,6 +623,7 @@ def loss_and_grad(phis: List[np.ndarray], images: List[np.ndarray], p: Params):
         Gf[i] += G[(i, i + 1)]
         Gb[i] += G[(i + 1, i)]
     aux["Gf"], aux["Gb"] = Gf, Gb
+    aux["rigid_grad"] = rg
     grads = []
     scale = 2.0 ** -p.K
     gts = reg_ts_grad(aux["phis_s"], p.times) if p.alpha_ts else None
@@ -639,19 +704,30 @@ def level_sigma(p: Params, level: int) -> float:
     return p.smooth_sigma / 2.0 ** (len(p.iters) - 1 - level)
 
 
+def rigid_lr(lr: float, shape) -> np.ndarray:
+    """Step sizes of the rigid parameters: lr voxels for the translations and
+    lr / r for the angles, r the largest half-extent of the grid, so that a
+    step of either moves the farthest voxel by about lr."""
+    r = max((n - 1) / 2.0 for n in shape)
+    return np.array([lr / r] * 3 + [lr] * 3)
+
+
 def register(images: List[np.ndarray], p: Params, phis0: Optional[List[np.ndarray]] = None,
              record: bool = False):
     """The whole optimisation: pyramid levels coarse to fine, each running
-    Adam on L(phi) for p.iters[level] steps from a schedule that restarts per
-    level.  Returns (the smoothed flows that parameterise the final
-    deformations, on the finest flow grid; pair fields on that grid; loss
-    history).""" 
+    Adam on L(phi) (and on the rigid parameters when p.rigid) for
+    p.iters[level] steps from a schedule that restarts per level.  Returns
+    (the smoothed flows that parameterise the final deformations, on the
+    finest flow grid; pair fields on that grid; loss history); with p.rigid
+    the rigid parameters of sessions 1..N-1 (finest grid) follow as a fourth
+    item."""
     L_lv = len(p.iters)
     imgs_lv = [[np.asarray(I, np.float64) for I in images]]
     for _ in range(L_lv - 1):
         imgs_lv.insert(0, [pool2(I) for I in imgs_lv[0]])
     N = len(images)
     phis = None
+    rig = [np.zeros(6) for _ in range(N - 1)]
     hist = []
     for lv in range(L_lv):
         imgs = imgs_lv[lv]
@@ -661,21 +737,38 @@ def register(images: List[np.ndarray], p: Params, phis0: Optional[List[np.ndarra
             phis = [np.asarray(x, np.float64) for x in phis]
         else:
             phis = [upsample2(x) for x in phis]
+            # translations are in voxels of the level: twice as many one level up
+            rig = [np.concatenate([r[:3], 2.0 * r[3:]]) for r in rig]
         m = [np.zeros_like(x) for x in phis]
         v = [np.zeros_like(x) for x in phis]
+        rm = [np.zeros(6) for _ in range(N - 1)]
+        rv = [np.zeros(6) for _ in range(N - 1)]
+        rlr = rigid_lr(1.0, imgs[0].shape)
         T = p.iters[lv]
         pl = Params(**{**p.__dict__, "smooth_sigma": level_sigma(p, lv)})
         for t in range(1, T + 1):
-            L, grads, _ = loss_and_grad(phis, imgs, pl)
+            L, grads, aux = loss_and_grad(phis, imgs, pl, rigid=rig if p.rigid else None)
             hist.append(L)
             lr = lr_schedule(t, T, p.lr, p.warmup)
             for k in range(N - 1):
                 phis[k], m[k], v[k] = adam_step(phis[k], grads[k], m[k], v[k], t, lr,
                                                 p.betas, p.eps)
+            if p.rigid:
+                for k in range(N - 1):
+                    # Adam per parameter with its own step size
+                    b1, b2 = p.betas
+                    g = aux["rigid_grad"][k]
+                    rm[k] = b1 * rm[k] + (1 - b1) * g
+                    rv[k] = b2 * rv[k] + (1 - b2) * g * g
+                    mh = rm[k] / (1 - b1 ** t)
+                    vh = rv[k] / (1 - b2 ** t)
+                    rig[k] = rig[k] - lr * rlr * mh / (np.sqrt(vh) + p.eps)
     sm = [smooth(ph, level_sigma(p, L_lv - 1)) for ph in phis]
     fwd = [exp_fwd(ph, p.K)[-1] for ph in sm]
     bwd = [exp_fwd(-ph, p.K)[-1] for ph in sm]
     U = all_pairs(fwd, bwd)
+    if p.rigid:
+        return sm, U, hist, rig
     return sm, U, hist
 
 

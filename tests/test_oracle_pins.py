@@ -739,3 +739,60 @@ def test_pcc_and_slope_closed_forms():
     # independent noise decorrelates
     n = r.standard_normal((3,) + shape)
     assert abs(O.pcc(a, n)) < 0.15
+
+
+# --------------------------------------------------------------------------
+# Rigid adjustment (Sec. 2.5)
+# --------------------------------------------------------------------------
+
+def test_rigid_matrix_is_a_rotation_and_its_derivatives_are_exact():
+    th = np.array([0.3, -0.2, 0.45])
+    R = O.rigid_matrix(th)
+    assert np.allclose(R @ R.T, np.eye(3), atol=1e-14) and abs(np.linalg.det(R) - 1) < 1e-14
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1e-6
+        fd = (O.rigid_matrix(th + e) - O.rigid_matrix(th - e)) / 2e-6
+        assert np.abs(fd - O.rigid_matrix(th, deriv=k)).max() < 1e-9
+    # each factor fixes its own axis: a rotation about z leaves the z component
+    Rz = O.rigid_matrix([0.7, 0.0, 0.0])
+    assert np.allclose(Rz[0], [1, 0, 0]) and np.allclose(Rz[:, 0], [1, 0, 0])
+
+
+def test_rigid_translation_of_a_translated_series_is_exact_and_zero_params_change_nothing():
+    """Session 1 is session 0 read 2 voxels further along x: with phi = 0 and
+    a rigid translation of 2 voxels for session 1, pair (0, 1) warps session
+    1 exactly onto session 0, so that pair's SiLNCC is zero."""
+    shape = (10, 12, 24)
+    z, y, x = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    base = lambda xx: np.sin(0.3 * z) * np.cos(0.2 * y) + np.sin(0.15 * xx)
+    imgs = [base(x), base(x - 2.0)]
+    phi = [np.zeros((3,) + shape)]
+    p = O.Params(K=4, window=3, metric=O.SILNCC, alpha_ss=0.0, rigid=True)
+    _, aux = O.forward(phi, imgs, p, keep=True, rigid=[np.array([0, 0, 0, 0, 0, 2.0])])
+    # interior windows see exact copies; the clamped border strip does not
+    U = aux["U_img"][(0, 1)]
+    assert np.allclose(U[2], 2.0) and np.allclose(U[:2], 0.0)
+    M = O.warp(imgs[1], U)
+    assert np.abs(M[:, :, :20] - imgs[0][:, :, :20]).max() < 1e-12
+    p0 = O.Params(K=4, window=3, metric=O.SILNCC, alpha_ss=0.0)
+    assert O.forward(phi, imgs, p0) == O.forward(phi, imgs, p, rigid=[np.zeros(6)])
+
+
+def test_rigid_gradient_matches_finite_differences():
+    shape = (8, 9, 10)
+    import scipy.ndimage as ndi
+    imgs = [ndi.gaussian_filter(rng(80 + k).uniform(0, 1, shape), 1.2) for k in range(3)]
+    phis = [smooth_field(shape, 0.5, seed=90 + k, sigma=1.5) for k in range(2)]
+    rig = [np.array([0.05, -0.03, 0.02, 0.3, -0.2, 0.1]), np.array([-0.02, 0.04, 0.01, -0.1, 0.25, 0.2])]
+    p = O.Params(K=4, window=3, metric=O.LNCC, alpha_ss=0.3, rigid=True)
+    L, grads, aux = O.loss_and_grad(phis, imgs, p, rigid=rig)
+    h = 1e-6
+    for j in range(2):
+        for k in range(6):
+            up = [r.copy() for r in rig]
+            dn = [r.copy() for r in rig]
+            up[j][k] += h
+            dn[j][k] -= h
+            fd = (O.forward(phis, imgs, p, rigid=up) - O.forward(phis, imgs, p, rigid=dn)) / (2 * h)
+            assert abs(fd - aux["rigid_grad"][j][k]) < 1e-5 * max(1.0, abs(fd))
