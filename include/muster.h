@@ -111,6 +111,13 @@ typedef struct muster_params {
                                       flows carried up, in image voxels), while
                                       svf_init and the autograd svf are on the
                                       flow grid.  0 is read as 1.              */
+  int rigid;                       /* 1: a rigid adjustment (Euler angles about
+                                      z, y, x and a translation, in voxels, about
+                                      the grid centre) per session but the first,
+                                      optimised with the flows; its displacement
+                                      is added to every pair field that samples
+                                      that session (Sec. 2.5).  Registration
+                                      entry points only (not the autograd ones) */
 } muster_params;
 
 /* Per-job result summary. */
@@ -133,8 +140,13 @@ typedef struct muster_job {
   const float* svf_init_dev;       /* optional [N-1][3] fields at the coarsest
                                       level; NULL starts from phi = 0              */
   float* svf_out_dev;              /* [N-1][3][D][H][W] result                    */
-  float* pairs_out_dev;            /* optional [N(N-1)][3][D][H][W] result        */
+  float* pairs_out_dev;            /* optional [N(N-1)][3][D][H][W] result; with
+                                      a rigid adjustment these are the total
+                                      deformations (pair field + rigid part)      */
   muster_params params;
+  float* rigid_out_dev;            /* optional [N-1][6] result with params.rigid:
+                                      angles (z, y, x; radians) and translation
+                                      (voxels) of sessions 1..N-1                 */
 } muster_job;
 
 /* ---- context -------------------------------------------------------------- */
@@ -326,7 +338,8 @@ muster_status muster_field_metrics(muster_ctx* ctx, void* stream, const int dims
 enum {
   MUSTER_K_EXP_FWD = 0, MUSTER_K_COMPOSE_FWD, MUSTER_K_SIM_STATS, MUSTER_K_SIM_GRAD,
   MUSTER_K_COMPOSE_BWD, MUSTER_K_EXP_BWD, MUSTER_K_ADAM, MUSTER_K_FINISH,
-  MUSTER_K_POOL, MUSTER_K_UPSAMPLE, MUSTER_K_SMOOTH, MUSTER_K_UPSAMPLE_ADJ, MUSTER_K_COUNT
+  MUSTER_K_POOL, MUSTER_K_UPSAMPLE, MUSTER_K_SMOOTH, MUSTER_K_UPSAMPLE_ADJ, MUSTER_K_RIGID,
+  MUSTER_K_COUNT
 };
 /* When enabled, eager launches (graphs off) of each kernel class are
  * bracketed by HIP events on the stream they run on. */

@@ -24,7 +24,7 @@ TILES_DEFAULT, TILES_AUTOTUNE, TILES_FIXED = 0, 1, 2
 SIM_SHAPES = [(8, 32), (16, 32), (8, 64)]
 EXP_STORE, EXP_RECOMPUTE = 0, 1
 KERNELS = ["exp_fwd", "compose_fwd", "sim_stats", "sim_grad", "compose_bwd", "exp_bwd", "adam",
-           "finish", "pool2", "upsample2", "smooth", "upsample2_adj"]
+           "finish", "pool2", "upsample2", "smooth", "upsample2_adj", "rigid"]
 
 
 class MusterLibraryMissing(ImportError):
@@ -43,7 +43,7 @@ class Params(Structure):
                 ("metric", c_int), ("alpha_ss", c_float), ("lr", c_float), ("warmup", c_float),
                 ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("exp_mode", c_int),
                 ("use_graph", c_int), ("smooth_sigma", c_float), ("alpha_l2", c_float),
-                ("alpha_ts", c_float), ("flow_factor", c_int)]
+                ("alpha_ts", c_float), ("flow_factor", c_int), ("rigid", c_int)]
 
 
 class Report(Structure):
@@ -58,7 +58,8 @@ class Report(Structure):
 class Job(Structure):
     _fields_ = [("N", c_int), ("dims", c_int * 3), ("images_dev", c_void_p),
                 ("times_host", POINTER(c_double)), ("svf_init_dev", c_void_p),
-                ("svf_out_dev", c_void_p), ("pairs_out_dev", c_void_p), ("params", Params)]
+                ("svf_out_dev", c_void_p), ("pairs_out_dev", c_void_p), ("params", Params),
+                ("rigid_out_dev", c_void_p)]
 
 
 DIMS = c_int * 3

@@ -34,6 +34,7 @@ class MusterParams:
     alpha_l2: float = 0.0             # weight of L_L2 (flow magnitude)
     alpha_ts: float = 0.0             # weight of L_ts (temporal smoothness; needs times)
     flow_factor: int = 1              # 2: flows on a grid twice as coarse as the images
+    rigid: bool = False               # rigid adjustment of every session but the first
 
     def to_c(self) -> L.Params:
         p = L.Params()
@@ -56,6 +57,7 @@ class MusterParams:
         p.alpha_l2 = float(self.alpha_l2)
         p.alpha_ts = float(self.alpha_ts)
         p.flow_factor = int(self.flow_factor)
+        p.rigid = 1 if self.rigid else 0
         return p
 
 
@@ -214,8 +216,25 @@ class Context:
     def register(self, images: torch.Tensor, times=None, params: Optional[MusterParams] = None,
                  pairs: bool = False):
         """Register a series images[N, D, H, W]; returns (svf, pairs or None,
-        report dict)."""
+        report dict).  With params.rigid the report also holds "rigid": the
+        [N-1, 6] angles (radians) and translations (voxels) of sessions
+        1..N-1, and the pairs are the total deformations."""
         params = params or MusterParams()
+        if params.rigid:
+            N = images.shape[0]
+            svf = torch.empty((N - 1, 3) + tuple(images.shape[1:]), device=images.device)
+            pr = torch.empty((N * (N - 1), 3) + tuple(images.shape[1:]), device=images.device) \
+                if pairs else None
+            rig = torch.empty((N - 1, 6), device=images.device)
+            keep = []
+            jobs = (L.Job * 1)()
+            jobs[0] = self._job(images, times, params, svf, pr, keep=keep)
+            jobs[0].rigid_out_dev = _ptr(rig)
+            reps = (L.Report * 1)()
+            L.check(self.lib.muster_register_batch(self.h, _stream(), 1, jobs, reps))
+            rep = reps[0].as_dict()
+            rep["rigid"] = rig
+            return svf, pr, rep
         N = images.shape[0]
         svf = torch.empty((N - 1, 3) + tuple(images.shape[1:]), device=images.device)
         pr = torch.empty((N * (N - 1), 3) + tuple(images.shape[1:]), device=images.device) \

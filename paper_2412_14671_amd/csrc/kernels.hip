@@ -1020,6 +1020,15 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
   // issued before this slice's sums so their latency overlaps the sums.
   float u1[NS][3];
   float fv0[NS], mv0[NS];
+  // the rigid adjustment of the source session adds A p + off (Sec. 2.5)
+  float rA[9], rO[3];
+  const bool rigid = it.rigid != nullptr;
+  if (rigid) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) rA[k] = it.rigid->A[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rO[k] = it.rigid->off[k];
+  }
   auto load_u = [&](int z, float (&u)[NS][3]) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -1028,6 +1037,12 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
       u[k][0] = in ? U[p] : 0.f;
       u[k][1] = in ? U[V + p] : 0.f;
       u[k][2] = in ? U[2 * V + p] : 0.f;
+      if (rigid && in) {
+        const float fz = (float)z, fy = (float)cyy[k], fx = (float)cxx[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          u[k][c] += fmaf(rA[3 * c], fz, fmaf(rA[3 * c + 1], fy, fmaf(rA[3 * c + 2], fx, rO[c])));
+      }
     }
   };
   // issue the loads of slice z (F and the 8 corners of I at the warped position)
@@ -1222,12 +1237,26 @@ __global__ __launch_bounds__(TY * TX) void k_sim_grad(const SimItem* __restrict_
     }
   };
   // output voxel (zo, y, x): U first, then F and the corners of I
+  float rA[9], rO[3];
+  const bool rigid = it.rigid != nullptr;
+  if (rigid) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) rA[k] = it.rigid->A[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rO[k] = it.rigid->off[k];
+  }
   auto load_uo = [&](int zo, float (&u)[3]) {
     const bool in = yx_in && zo >= 0 && zo < D;
     const int p = in ? (zo * H + y) * W + x : 0;
     u[0] = in ? U[p] : 0.f;
     u[1] = in ? U[V + p] : 0.f;
     u[2] = in ? U[2 * V + p] : 0.f;
+    if (rigid && in) {
+      const float fz = (float)zo, fy = (float)y, fx = (float)x;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        u[c] += fmaf(rA[3 * c], fz, fmaf(rA[3 * c + 1], fy, fmaf(rA[3 * c + 2], fx, rO[c])));
+    }
   };
   float c0[NS][3];
   load_coef(tc.z0 - R, c0);
@@ -1931,6 +1960,136 @@ hipError_t launch_field_stats(int V, const float* a, const float* b, const unsig
   if (V <= 0) return hipSuccess;
   const int blocks = ceil_div(V, BLOCK) < 1024 ? ceil_div(V, BLOCK) : 1024;
   hipLaunchKernelGGL(k_field_stats, dim3(blocks), dim3(BLOCK), 0, s, V, a, b, roi, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Rigid adjustment (Sec. 2.5)
+// ---------------------------------------------------------------------------
+// sum_p G(p) and sum_p G(p) (p - c)^T over one pair's gradient, into the
+// source session's accumulators.
+__global__ __launch_bounds__(BLOCK) void k_rigid_grad(const RigidGradItem* __restrict__ items,
+                                                      int n_items, int n_tiles) {
+  __shared__ double red[BLOCK / 64][12];
+  const int tile = blockIdx.x;
+  const RigidGradItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
+  const float cz = 0.5f * (D - 1), cy = 0.5f * (H - 1), cx = 0.5f * (W - 1);
+  const cgfloat* __restrict__ G = gp(it.G);
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
+  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
+    const int q = q0 + k;
+    if (q >= V) break;
+    const int x = q % W, y = (q / W) % H, z = q / (W * H);
+    const double pz = (double)z - cz, py = (double)y - cy, px = (double)x - cx;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double g = G[(size_t)c * V + q];
+      acc[c] += g;
+      acc[3 + 3 * c] += g * pz;
+      acc[4 + 3 * c] += g * py;
+      acc[5 + 3 * c] += g * px;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k)
+    for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) red[threadIdx.x >> 6][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    double t = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) t += red[w][threadIdx.x];
+    double* dst = threadIdx.x < 3 ? &it.rg->gsum[threadIdx.x] : &it.rg->gmom[threadIdx.x - 3];
+    unsafeAtomicAdd(dst, t);
+  }
+}
+
+// One Adam step of a session's rigid parameters (PyTorch semantics, the
+// job's schedule; the angles' step scaled by rot_lr), then the displacement
+// the kernels apply, and the sums cleared for the next iteration.
+__global__ void k_rigid_step(const RigidStepItem* __restrict__ items, int n_items) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const RigidStepItem it = items[i];
+  RigidState* rg = it.rg;
+  const JobState* js = it.js;
+  const int step = js->t + 1;
+  const double lr = schedule_lr(js, step);
+  const double bc1 = 1.0 - pow((double)js->b1, (double)step);
+  const double bc2 = 1.0 - pow((double)js->b2, (double)step);
+  float g[6];
+  for (int k = 0; k < 3; ++k) {
+    float dR[9];
+    rigid_rotation(rg->theta, k, dR);
+    double acc = 0.0;
+    for (int e = 0; e < 9; ++e) acc += (double)dR[e] * rg->gmom[e];
+    g[k] = (float)acc;
+    g[3 + k] = (float)rg->gsum[k];
+  }
+  const float b1 = js->b1, b2 = js->b2, eps = js->eps;
+  float prm[6] = {rg->theta[0], rg->theta[1], rg->theta[2], rg->t[0], rg->t[1], rg->t[2]};
+  for (int k = 0; k < 6; ++k) {
+    const float m = fmaf(1.f - b1, g[k] - rg->m[k], rg->m[k]);
+    const float v = fmaf(1.f - b2, g[k] * g[k], rg->v[k] * b2);
+    rg->m[k] = m;
+    rg->v[k] = v;
+    const float scale = k < 3 ? it.rot_lr : 1.f;
+    const float den = sqrtf(v) / (float)sqrt(bc2) + eps;
+    prm[k] -= (float)(lr * scale / bc1) * (m / den);
+  }
+  for (int k = 0; k < 3; ++k) {
+    rg->theta[k] = prm[k];
+    rg->t[k] = prm[3 + k];
+  }
+  float R[9];
+  rigid_rotation(rg->theta, -1, R);
+  for (int a = 0; a < 3; ++a) {
+    float rc = 0.f;
+    for (int b = 0; b < 3; ++b) {
+      rg->A[3 * a + b] = R[3 * a + b] - (a == b ? 1.f : 0.f);
+      rc += R[3 * a + b] * it.c[b];
+    }
+    rg->off[a] = it.c[a] + rg->t[a] - rc;
+  }
+  for (int k = 0; k < 3; ++k) rg->gsum[k] = 0.0;
+  for (int k = 0; k < 9; ++k) rg->gmom[k] = 0.0;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_add_rigid(GridDims d, float* __restrict__ f_,
+                                                     const RigidState* __restrict__ rg) {
+  const int V = d.D * d.H * d.W;
+  gfloat* __restrict__ f = gp(f_);
+  for (int p = blockIdx.x * BLOCK + threadIdx.x; p < V; p += gridDim.x * BLOCK) {
+    const float x = (float)(p % d.W), y = (float)((p / d.W) % d.H), z = (float)(p / (d.W * d.H));
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      f[(size_t)c * V + p] += fmaf(rg->A[3 * c], z, fmaf(rg->A[3 * c + 1], y,
+                                                         fmaf(rg->A[3 * c + 2], x, rg->off[c])));
+  }
+}
+
+hipError_t launch_rigid_grad(const RigidGradItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rigid_grad, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_rigid_step(const RigidStepItem* items, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rigid_step, dim3(ceil_div(n_items, 64)), dim3(64), 0, s, items, n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_rigid(GridDims d, float* field, const RigidState* rg, hipStream_t s) {
+  const int V = d.D * d.H * d.W;
+  if (V <= 0) return hipSuccess;
+  const int blocks = ceil_div(V, BLOCK) < 2048 ? ceil_div(V, BLOCK) : 2048;
+  hipLaunchKernelGGL(k_add_rigid, dim3(blocks), dim3(BLOCK), 0, s, d, field, rg);
   return hipGetLastError();
 }
 

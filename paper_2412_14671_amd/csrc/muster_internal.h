@@ -112,6 +112,56 @@ struct ComposeBwdItem {
 };
 
 // One session pair (target F = I_i, source I_j, field U = U[j->i]).
+// Rigid adjustment of one session (Sec. 2.5): parameters (angles about z, y,
+// x; translation), their Adam moments, the displacement the similarity
+// kernels add, d(p) = A p + off with A = R - I and off = c + t - R c, and the
+// gradient sums of the current iteration.
+struct RigidState {
+  float theta[3], t[3];
+  float m[6], v[6];
+  float A[9], off[3];
+  double gsum[3];   // sum_p G(p)
+  double gmom[9];   // sum_p G(p) (p - c)^T, row-major
+};
+
+// R = Rz Ry Rx in (z, y, x) components (Rz turns y towards x, Ry turns x
+// towards z, Rx turns z towards y), or its derivative with respect to one
+// angle (deriv = 0, 1, 2).
+__host__ __device__ inline void rigid_rotation(const float th[3], int deriv, float R[9]) {
+  float f[3][9];
+  const int ax[3][2] = {{1, 2}, {2, 0}, {0, 1}};
+  for (int k = 0; k < 3; ++k) {
+    float c = cosf(th[k]), s = sinf(th[k]);
+    const bool d = deriv == k;
+    for (int e = 0; e < 9; ++e) f[k][e] = 0.f;
+    if (d) {
+      const float cc = -s;
+      s = c;
+      c = cc;
+    } else {
+      for (int e = 0; e < 3; ++e) f[k][4 * e] = 1.f;
+    }
+    const int a = ax[k][0], b = ax[k][1];
+    f[k][3 * a + a] = c;
+    f[k][3 * b + b] = c;
+    f[k][3 * a + b] = -s;
+    f[k][3 * b + a] = s;
+  }
+  float t[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      float acc = 0.f;
+      for (int l = 0; l < 3; ++l) acc += f[0][3 * i + l] * f[1][3 * l + j];
+      t[3 * i + j] = acc;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      float acc = 0.f;
+      for (int l = 0; l < 3; ++l) acc += t[3 * i + l] * f[2][3 * l + j];
+      R[3 * i + j] = acc;
+    }
+}
+
 struct SimItem {
   int tile0;
   int D, H, W;
@@ -125,6 +175,23 @@ struct SimItem {
   double inv_nr; // 1 / number of windows
   JobState* js;  // loss accumulator (may be null)
   double* sim_out;  // optional per-pair accumulator
+  const RigidState* rigid;  // rigid adjustment of the source session, or null
+};
+
+// Gradient sums of a rigid adjustment from one pair's dSim/dU on the image grid.
+struct RigidGradItem {
+  int tile0;
+  int D, H, W;
+  const float* G;
+  RigidState* rg;
+};
+
+// Adam step of one session's rigid parameters.
+struct RigidStepItem {
+  RigidState* rg;
+  const JobState* js;
+  float c[3];       // centre of the image grid
+  float rot_lr;     // step scale of the angles (1 / largest half-extent)
 };
 
 // The gradient of one interval is g = scale * (g0f - g0b) (g0f, g0b are
@@ -244,6 +311,10 @@ hipError_t launch_reg_ext(GridDims d, const float* f, const float* fprev, float 
                           float inv_dp, float inv_ds, double* out, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_jacobian_det(GridDims d, const float* U, float* out, hipStream_t s);
+hipError_t launch_rigid_grad(const RigidGradItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_rigid_step(const RigidStepItem* items, int n_items, hipStream_t s);
+// field [3][D][H][W] += the displacement of a rigid state
+hipError_t launch_add_rigid(GridDims d, float* field, const RigidState* rg, hipStream_t s);
 // 27 sums over the voxels with roi[p] != 0 (all if roi is NULL), added to out
 hipError_t launch_field_stats(int V, const float* a, const float* b, const unsigned char* roi,
                               double* out, hipStream_t s);

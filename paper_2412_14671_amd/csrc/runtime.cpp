@@ -185,6 +185,7 @@ uint64_t job_footprint(int N, const int dims[3], const muster_params& p) {
   // fields and their gradients
   bytes += P * FI;
   if (ff > 1) bytes += 2 * P * FI;
+  if (p.rigid) bytes += n1 * sizeof(RigidState) + 256;
   if (p.K >= 2) {
     // staging slots and descriptors of the Exp backward, per direction, two steps
     const uint64_t tiles = (uint64_t)point_tiles(fd[0], fd[1], fd[2]);
@@ -298,6 +299,13 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
     J.m_t2.alloc(ctx, n1 * F);
   }
   J.tiles_fine = point_tiles(J.ldims[L - 1][0], J.ldims[L - 1][1], J.ldims[L - 1][2]);
+  J.rigid_out = jd.rigid_out_dev;
+  if (J.p.rigid) {
+    J.m_rigid.alloc(ctx, n1 * sizeof(RigidState));
+    std::vector<RigidState> z(n1);
+    std::memset(z.data(), 0, n1 * sizeof(RigidState));
+    MUSTER_HIP(hipMemcpy(J.m_rigid.p, z.data(), n1 * sizeof(RigidState), hipMemcpyHostToDevice));
+  }
   if (J.staged()) {
     J.m_stage.alloc(ctx, 2 * 2 * n1 * (size_t)J.tiles_fine * 3 * STAGE_CAP * sizeof(float));
     J.m_desc.alloc(ctx, 2 * 2 * n1 * (size_t)J.tiles_fine * 8 * sizeof(int));
@@ -328,7 +336,7 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
                 J.m_gpair.bytes + J.m_pp.bytes + J.m_coef.bytes + J.m_img.bytes +
                 J.m_state.bytes + J.m_hist.bytes + J.m_phis.bytes + J.m_t1.bytes + J.m_t2.bytes +
                 J.m_stage.bytes + J.m_desc.bytes + J.m_flags.bytes + J.m_pimg.bytes +
-                J.m_gimg.bytes;
+                J.m_gimg.bytes + J.m_rigid.bytes;
   return job;
 }
 
@@ -346,6 +354,39 @@ static void run_items(Ctx* ctx, std::vector<Item>& items, int n_tiles, hipStream
 }
 
 static int elem_tiles(size_t n) { return (int)((n + ELEM_PER_BLOCK - 1) / ELEM_PER_BLOCK); }
+
+// Rigid states at the start of a level: translations doubled when the grid
+// doubles, Adam moments and sums cleared, the applied displacement
+// recomputed about the level's centre.
+static void rigid_begin_level(Job& J, int level, hipStream_t s) {
+  const size_t n1 = J.N - 1;
+  std::vector<RigidState> st(n1);
+  MUSTER_HIP(hipMemcpyAsync(st.data(), J.m_rigid.p, n1 * sizeof(RigidState),
+                            hipMemcpyDeviceToHost, s));
+  MUSTER_HIP(hipStreamSynchronize(s));
+  const int* d = J.idims[level];
+  const float c[3] = {0.5f * (d[0] - 1), 0.5f * (d[1] - 1), 0.5f * (d[2] - 1)};
+  for (RigidState& r : st) {
+    if (level > 0)
+      for (int k = 0; k < 3; ++k) r.t[k] *= 2.f;
+    for (int k = 0; k < 6; ++k) r.m[k] = r.v[k] = 0.f;
+    for (int k = 0; k < 3; ++k) r.gsum[k] = 0.0;
+    for (int k = 0; k < 9; ++k) r.gmom[k] = 0.0;
+    float R[9];
+    rigid_rotation(r.theta, -1, R);
+    for (int a = 0; a < 3; ++a) {
+      float rc = 0.f;
+      for (int b = 0; b < 3; ++b) {
+        r.A[3 * a + b] = R[3 * a + b] - (a == b ? 1.f : 0.f);
+        rc += R[3 * a + b] * c[b];
+      }
+      r.off[a] = c[a] + r.t[a] - rc;
+    }
+  }
+  MUSTER_HIP(hipMemcpyAsync(J.m_rigid.p, st.data(), n1 * sizeof(RigidState),
+                            hipMemcpyHostToDevice, s));
+  MUSTER_HIP(hipStreamSynchronize(s));
+}
 
 void job_begin_level(Job& J, int level, hipStream_t s) {
   Ctx* ctx = J.ctx;
@@ -402,6 +443,7 @@ void job_begin_level(Job& J, int level, hipStream_t s) {
     MUSTER_HIP(launch_fill(J.vbuf, (int64_t)(n1 * 3 * V), 0.f, s));
   }
   MUSTER_HIP(launch_fill(J.m_pp.as<float>(), (int64_t)(4 * n1 * 3 * V), 0.f, s));
+  if (J.p.rigid) rigid_begin_level(J, level, s);
   if (J.staged())  // the flags are ints; 0.0f has the same bits as 0
     MUSTER_HIP(launch_fill((float*)J.m_flags.p, (int64_t)(2 * n1 * J.p.K), 0.f, s));
   JobState st{};
@@ -460,12 +502,32 @@ void job_final_outputs(Job& J, hipStream_t s) {
     }
   }
   if (J.pairs_out) {
+    const int* d = J.idims[J.level];
     for (int i = 0; i < J.N; ++i)
-      for (int j = 0; j < J.N; ++j)
-        if (i != j)
-          MUSTER_HIP(hipMemcpyAsync(J.pairs_out + (size_t)pair_index(i, j, J.N) * 3 * VI,
-                                    J.pair_img(i, j), 3 * VI * sizeof(float),
-                                    hipMemcpyDeviceToDevice, s));
+      for (int j = 0; j < J.N; ++j) {
+        if (i == j) continue;
+        float* dst = J.pairs_out + (size_t)pair_index(i, j, J.N) * 3 * VI;
+        MUSTER_HIP(hipMemcpyAsync(dst, J.pair_img(i, j), 3 * VI * sizeof(float),
+                                  hipMemcpyDeviceToDevice, s));
+        // the total deformation: the rigid part of the source session added
+        if (J.p.rigid && j >= 1)
+          MUSTER_HIP(launch_add_rigid(GridDims{d[0], d[1], d[2]}, dst, J.rigid(j), s));
+      }
+  }
+  if (J.p.rigid && J.rigid_out) {
+    const size_t n1 = J.N - 1;
+    std::vector<RigidState> st(n1);
+    MUSTER_HIP(hipMemcpyAsync(st.data(), J.m_rigid.p, n1 * sizeof(RigidState),
+                              hipMemcpyDeviceToHost, s));
+    MUSTER_HIP(hipStreamSynchronize(s));
+    std::vector<float> out(6 * n1);
+    for (size_t j = 0; j < n1; ++j)
+      for (int k = 0; k < 3; ++k) {
+        out[6 * j + k] = st[j].theta[k];
+        out[6 * j + 3 + k] = st[j].t[k];
+      }
+    MUSTER_HIP(hipMemcpyAsync(J.rigid_out, out.data(), out.size() * sizeof(float),
+                              hipMemcpyHostToDevice, s));
   }
   MUSTER_HIP(hipStreamSynchronize(s));
 }
@@ -676,6 +738,43 @@ void add_forward(Builder& b, const std::vector<Job*>& jobs) {
   add_pair_resampling(b, jobs, false);
 }
 
+// Rigid adjustment (Sec. 2.5): the gradient sums of every pair whose source
+// is session j >= 1 (its dSim/dU on the image grid, before the composition
+// adjoints add to it), then one Adam step per session.
+void add_rigid_stages(Builder& b, const std::vector<Job*>& jobs) {
+  std::vector<RigidGradItem> gi;
+  std::vector<RigidStepItem> si;
+  int tiles = 0;
+  double bytes = 0;
+  for (Job* J : jobs) {
+    if (!J->p.rigid) continue;
+    const int* d = J->idims[J->level];
+    for (int i = 0; i < J->N; ++i)
+      for (int j = 1; j < J->N; ++j) {
+        if (i == j) continue;
+        RigidGradItem it{};
+        it.tile0 = tiles;
+        it.D = d[0]; it.H = d[1]; it.W = d[2];
+        it.G = J->pair_grad_img(i, j);
+        it.rg = J->rigid(j);
+        gi.push_back(it);
+        tiles += elem_tiles(J->VIc());
+        bytes += 12.0 * J->VIc();
+      }
+    const float rmax = 0.5f * (float)(std::max(d[0], std::max(d[1], d[2])) - 1);
+    for (int j = 1; j < J->N; ++j) {
+      RigidStepItem it{};
+      it.rg = J->rigid(j);
+      it.js = J->js;
+      for (int k = 0; k < 3; ++k) it.c[k] = 0.5f * (d[k] - 1);
+      it.rot_lr = 1.f / rmax;
+      si.push_back(it);
+    }
+  }
+  b.add(ST_RIGID_GRAD, gi, tiles, bytes);
+  b.add(ST_RIGID_STEP, si, (int)si.size(), 0.0);
+}
+
 // The pair items of the jobs whose window statistics use tile shape `shape`.
 std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int shape, int& tiles, double& vox) {
   std::vector<SimItem> items;
@@ -703,6 +802,7 @@ std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int shape, int& ti
         it.inv_nr = 1.0 / nr;
         it.js = J->js;
         it.sim_out = nullptr;
+        it.rigid = (J->p.rigid && j >= 1) ? J->rigid(j) : nullptr;
         items.push_back(it);
         tiles += stat_tiles(d[0], d[1], d[2], tl.zc, shape);
         vox += (double)J->VIc();
@@ -772,6 +872,7 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
     maxN = std::max(maxN, J->N);
   }
   add_sim_stages(b, jobs, ST_SIM_GRAD);
+  add_rigid_stages(b, jobs);
   add_pair_resampling(b, jobs, true);
   for (int d = maxN - 1; d >= 2; --d) {
     std::vector<ComposeBwdItem> items;
@@ -973,6 +1074,8 @@ static int kclass(StageKind k) {
     case ST_SMOOTH: return MUSTER_K_SMOOTH;
     case ST_UPSAMPLE: return MUSTER_K_UPSAMPLE;
     case ST_UPSAMPLE_ADJ: return MUSTER_K_UPSAMPLE_ADJ;
+    case ST_RIGID_GRAD: return MUSTER_K_RIGID;
+    case ST_RIGID_STEP: return MUSTER_K_RIGID;
   }
   return MUSTER_K_FINISH;
 }
@@ -996,6 +1099,9 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_SMOOTH: return launch_smooth((const SmoothItem*)p, st.n_items, st.n_tiles, st.lds, s);
     case ST_UPSAMPLE: return launch_upsample2((const UpItem*)p, st.n_items, st.n_tiles, s);
     case ST_UPSAMPLE_ADJ: return launch_upsample2_adj((const UpItem*)p, st.n_items, st.n_tiles, s);
+    case ST_RIGID_GRAD:
+      return launch_rigid_grad((const RigidGradItem*)p, st.n_items, st.n_tiles, s);
+    case ST_RIGID_STEP: return launch_rigid_step((const RigidStepItem*)p, st.n_items, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1738,6 +1844,7 @@ muster_status muster_loss_forward(muster_ctx* h, void* stream, int N, const int 
   Ctx* ctx = C(h);
   return guard(ctx, [&] {
     NEED(ctx && params && images_dev && svf_dev && loss_host && saved, "NULL argument");
+    NEED(!params->rigid, "the rigid adjustment is available through the registration entry points only");
     NEED(dims, "dims is NULL");
     std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t s = (hipStream_t)stream;
@@ -2270,7 +2377,8 @@ muster_status muster_kernel_stats_reset(muster_ctx* h) {
 const char* muster_kernel_name(int k) {
   static const char* names[MUSTER_K_COUNT] = {"exp_fwd", "compose_fwd", "sim_stats", "sim_grad",
                                               "compose_bwd", "exp_bwd", "adam", "finish",
-                                              "pool2", "upsample2", "smooth", "upsample2_adj"};
+                                              "pool2", "upsample2", "smooth", "upsample2_adj",
+                                              "rigid"};
   if (k < 0 || k >= MUSTER_K_COUNT) return "";
   return names[k];
 }

@@ -137,6 +137,8 @@ struct Job {
   DevMem m_phi, m_m, m_v, m_us, m_deep, m_gpair, m_pp, m_coef, m_img, m_state, m_hist;
   DevMem m_phis, m_t1, m_t2;         // smoothed flow and gradient ping-pong (smoothing on)
   DevMem m_pimg, m_gimg;             // pair fields and their gradients on the image grid (ff > 1)
+  DevMem m_rigid;                    // RigidState of sessions 1..N-1 (params.rigid)
+  float* rigid_out = nullptr;
   DevMem m_stage, m_desc, m_flags;   // staged Exp-backward accumulation (K >= 2)
   float* phi = nullptr;              // may alias the caller's field in grad_mode
   float* mbuf = nullptr;
@@ -166,6 +168,7 @@ struct Job {
   float* pair_field(int i, int j) const;        // U[j->i] on the flow grid
   float* pair_grad(int i, int j) const;
   float* pair_img(int i, int j) const;          // U[j->i] on the image grid
+  RigidState* rigid(int j) const { return m_rigid.as<RigidState>() + (j - 1); }  // j >= 1
   float* pair_grad_img(int i, int j) const;
   float* pp(int dir, int k) const { return field(m_pp.as<float>(), (size_t)dir * 2 + k); }
   bool staged() const { return p.K >= 2; }
@@ -193,7 +196,7 @@ void load_tune_cache(Ctx* ctx);
 // A launch plan: one iteration (or a forward pass) of a set of jobs.
 enum StageKind {
   ST_EXP_FWD, ST_COMPOSE_FWD, ST_SIM_STATS, ST_SIM_GRAD, ST_COMPOSE_BWD, ST_EXP_BWD, ST_ADAM,
-  ST_FINISH, ST_SMOOTH, ST_UPSAMPLE, ST_UPSAMPLE_ADJ
+  ST_FINISH, ST_SMOOTH, ST_UPSAMPLE, ST_UPSAMPLE_ADJ, ST_RIGID_GRAD, ST_RIGID_STEP
 };
 
 struct Stage {

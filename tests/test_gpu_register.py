@@ -270,3 +270,71 @@ def test_registration_on_a_coarse_flow_grid(ctx):
     # least its direction agrees with the flow on the image grid
     f01 = pairs[0].cpu().numpy().ravel()
     assert float(np.dot(f01, svf[0].cpu().numpy().ravel())) > 0
+
+
+def test_solver_steps_with_rigid_adjustment_match_oracle(ctx):
+    """Three Adam steps with the rigid adjustment on (the last rate is 0): the
+    losses L(0) and L(step 2), the rigid parameters and phi_2 follow the
+    oracle's updates."""
+    from paper_2412_14671_amd import MusterParams, synth
+    s = synth.phantom_series((20, 24, 28), 3, seed=17)
+    imgs = [x.numpy() for x in s.images]
+    params = MusterParams(iters=[3], K=5, window=5, metric="silncc", alpha_ss=0.5, lr=0.05,
+                          rigid=True, use_graph=False)
+    svf, _, rep = ctx.register(s.images.to(DEV), s.times, params)
+    p = O.Params(K=5, window=5, metric=O.SILNCC, alpha_ss=0.5, rigid=True)
+    phi = [np.zeros((3, 20, 24, 28)) for _ in range(2)]
+    rig = [np.zeros(6) for _ in range(2)]
+    m = [np.zeros_like(x) for x in phi]
+    v = [np.zeros_like(x) for x in phi]
+    rm = [np.zeros(6) for _ in range(2)]
+    rv = [np.zeros(6) for _ in range(2)]
+    rlr = O.rigid_lr(1.0, (20, 24, 28))
+    losses, gs = [], []
+    for t in (1, 2, 3):
+        L, g, aux = O.loss_and_grad(phi, imgs, p, rigid=rig)
+        losses.append(L)
+        gs.append(np.stack(g))
+        lr = O.lr_schedule(t, 3, 0.05)
+        for k in range(2):
+            phi[k], m[k], v[k] = O.adam_step(phi[k], g[k], m[k], v[k], t, lr)
+            gr = aux["rigid_grad"][k]
+            rm[k] = 0.9 * rm[k] + 0.1 * gr
+            rv[k] = 0.999 * rv[k] + 0.001 * gr * gr
+            rig[k] = rig[k] - lr * rlr * (rm[k] / (1 - 0.9 ** t)) / (np.sqrt(rv[k] / (1 - 0.999 ** t)) + 1e-8)
+    log(f"rigid: gpu {rep['rigid'].cpu().numpy()} oracle {np.stack(rig)}")
+    assert abs(rep["loss_first"] - losses[0]) < 1e-3 * abs(losses[0])
+    assert abs(rep["loss_last"] - losses[2]) < 1e-3 * abs(losses[2])
+    got = rep["rigid"].cpu().numpy().astype(np.float64)
+    want = np.stack(rig)
+    # Adam steps of about lr per parameter: compare against that scale
+    assert np.abs(got - want).max() < 0.02 * 0.05 * np.maximum(1.0, np.abs(want) / 0.05).max()
+    g0, g1 = gs[0], gs[1]
+    big = (np.abs(g0) > 1e-2 * np.abs(g0).max()) & (np.abs(g1) > 1e-2 * np.abs(g1).max())
+    assert np.abs(svf.cpu().numpy()[big] - np.stack(phi)[big]).max() < 2e-3 * 0.1
+
+
+def test_rigid_adjustment_recovers_a_translation(ctx):
+    """Session 1 is session 0 read (0.8, -0.6, 1.1) voxels away; with the flows
+    held near zero by a strong L_L2 term, the rigid translation of session 1
+    converges to the displacement that maps it back, minus that offset
+    (sampling I_1 at p - offset gives I_0 at p)."""
+    import math
+    from paper_2412_14671_amd import MusterParams, synth
+    shape = (40, 44, 48)
+    rng_ = np.random.Generator(np.random.PCG64(23))
+    P = synth.Phantom(shape, rng_)
+    g = torch.stack(torch.meshgrid(*[torch.arange(n, dtype=torch.float64) for n in shape],
+                                   indexing="ij"))
+    off = torch.tensor([0.8, -0.6, 1.1], dtype=torch.float64)[:, None, None, None]
+    imgs = torch.stack([P(g), P(g + off)]).float()
+    params = MusterParams(iters=[60, 60], K=5, window=5, metric="silncc", alpha_ss=1.0,
+                          alpha_l2=1e4, lr=0.2, rigid=True)
+    _, pairs, rep = ctx.register(imgs.to(DEV), [0.0, 1.0], params, pairs=True)
+    r = rep["rigid"].cpu().numpy()[0]
+    log(f"recovered rigid {r}, loss {rep['loss_first']:.5f} -> {rep['loss_last']:.5f}")
+    assert np.abs(r[3:] + np.array([0.8, -0.6, 1.1])).max() < 0.15
+    assert np.abs(r[:3]).max() < 0.02
+    # the returned pair field (0, 1) is the total deformation: about -offset
+    tot = pairs[0].cpu().numpy().reshape(3, -1).mean(axis=1)
+    assert np.abs(tot + np.array([0.8, -0.6, 1.1])).max() < 0.15
