@@ -943,12 +943,14 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
 // Windowed statistics (Sec. 2.6): warp + LNCC/SiLNCC per window, loss and
 // the per-window adjoint coefficients.
 //
-// A block owns ST_Y x ST_X window centres in (y, x) and marches through a
-// chunk of z.  For every input slice it warps the source image on the
-// (ST_Y + 2r) x (ST_X + 2r) patch into an LDS ring of w slices; for every
-// centre slice it sums the five products over z from the ring, then over x
-// and y through LDS.  Values are shifted by one per-block constant before the
-// products, which keeps the variance differences well conditioned.
+// A block owns TY x TX window centres in (y, x) and marches through a chunk
+// of z.  Every thread owns a few columns of the (TY + 2r) x (TX + 2r) patch
+// around them.  For each input slice it warps the source image at its columns
+// and keeps the last w slices of its per-column values in registers with
+// their running sums over z.  For every centre slice the z-sums go to LDS and
+// are summed over x, then over y (box_x, box_y).  Values are shifted by one
+// per-block constant before the products, which keeps the variance
+// differences well conditioned.
 // ---------------------------------------------------------------------------
 struct STile {
   int z0, z1, y0, x0;
@@ -967,27 +969,82 @@ __device__ __forceinline__ STile stat_tile(int local, int D, int H, int W, int z
   return t;
 }
 
-// A block of TY x TX threads owns TY x TX window centres; its patch of
-// columns is (TY + 2R) x (TX + 2R), and a thread owns the patch columns
-// threadIdx.x + k * NT.
-template <int R, int TY, int TX>
-struct Patch {
-  static constexpr int NT = TY * TX;
+// Geometry of the window sums of Q quantities.  A block of TY x TX threads;
+// thread t owns the patch columns t + k * NT.  LDS holds, per quantity, the
+// z-sums of the patch (rows of PXS floats), their x-sums (PY rows of TXS
+// floats) and the finished sums of the centres (TY x TX).  The row strides
+// are odd, so the rows a wave walks along fall in distinct banks.  The x and
+// y passes give each thread a segment of 8 outputs: it reads the 8 + 2r
+// inputs once and forms the 8 sums from registers.
+template <int R, int TY, int TX, int Q>
+struct Box {
+  static constexpr int NT = TY * TX, RW = R, TXO = TX;
   static constexpr int WN = 2 * R + 1;
   static constexpr int PY = TY + 2 * R, PX = TX + 2 * R, P1 = PY * PX;
   static constexpr int NS = (P1 + NT - 1) / NT;
+  static constexpr int PXS = PX | 1, TXS = TX + 1;
+  static constexpr int SX = 8, SY = 8, NXS = TX / SX, NYS = TY / SY;
+  static constexpr int ZQ = PY * PXS, XQ = PY * TXS, YQ = TY * TX;
+  static constexpr int LDS = Q * (ZQ + XQ + YQ);
+  static_assert(TX % SX == 0 && TY % SY == 0, "tile not a multiple of the segments");
 };
+
+// x-sums of the window: xs[q][row][c] = sum_k zs[q][row][c + k].
+template <class B>
+__device__ __forceinline__ void box_x(const float* __restrict__ zs, float* __restrict__ xs, int Q) {
+  constexpr int R = B::RW, WN = B::WN, SX = B::SX, PY = B::PY, NXS = B::NXS;
+  const int n = Q * PY * NXS;
+  for (int e = threadIdx.x; e < n; e += B::NT) {
+    const int q = e / (PY * NXS), r = e - q * (PY * NXS);
+    const int seg = r / PY, row = r - seg * PY;
+    const float* s = zs + q * B::ZQ + row * B::PXS + seg * SX;
+    float* d = xs + q * B::XQ + row * B::TXS + seg * SX;
+    float v[SX + 2 * R];
+#pragma unroll
+    for (int k = 0; k < SX + 2 * R; ++k) v[k] = s[k];
+#pragma unroll
+    for (int i = 0; i < SX; ++i) {
+      float acc = v[i];
+#pragma unroll
+      for (int k = 1; k < WN; ++k) acc += v[i + k];
+      d[i] = acc;
+    }
+  }
+}
+
+// y-sums of the x-sums: ys[q][y][c] = sum_k xs[q][y + k][c].
+template <class B>
+__device__ __forceinline__ void box_y(const float* __restrict__ xs, float* __restrict__ ys, int Q) {
+  constexpr int R = B::RW, WN = B::WN, SY = B::SY, TX = B::TXO, NYS = B::NYS, TXS = B::TXS;
+  const int n = Q * TX * NYS;
+  for (int e = threadIdx.x; e < n; e += B::NT) {
+    const int q = e / (TX * NYS), r = e - q * (TX * NYS);
+    const int seg = r / TX, x = r - seg * TX;
+    const float* s = xs + q * B::XQ + seg * SY * TXS + x;
+    float* d = ys + q * B::YQ + seg * SY * TX + x;
+    float v[SY + 2 * R];
+#pragma unroll
+    for (int k = 0; k < SY + 2 * R; ++k) v[k] = s[k * TXS];
+#pragma unroll
+    for (int i = 0; i < SY; ++i) {
+      float acc = v[i];
+#pragma unroll
+      for (int k = 1; k < WN; ++k) acc += v[i + k];
+      d[i * TX] = acc;
+    }
+  }
+}
 
 template <int R, int TY, int TX>
 __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict__ items, int n_items,
                                                        int n_tiles, int metric) {
-  using P = Patch<R, TY, TX>;
-  constexpr int WN = P::WN, PY = P::PY, PX = P::PX, P1 = P::P1, NS = P::NS, NT = P::NT;
-  __shared__ float rF[WN][P1];
-  __shared__ float rM[WN][P1];
-  __shared__ float zs[5][P1];
-  __shared__ float xs[5][PY * TX];
+  using B = Box<R, TY, TX, 5>;
+  constexpr int WN = B::WN, PX = B::PX, P1 = B::P1, NS = B::NS, NT = B::NT;
+  __shared__ float lds[B::LDS];
   __shared__ double red[NT / 64];
+  float* zs = lds;
+  float* xs = lds + 5 * B::ZQ;
+  float* ys = xs + 5 * B::XQ;
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const SimItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
@@ -1004,15 +1061,17 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
   const int y = tc.y0 + ty, x = tc.x0 + tx;
   const bool yx_in = (y < H) && (x < W);
   const bool yx_valid = yx_in && y >= R && y <= H - 1 - R && x >= R && x <= W - 1 - R;
-  // owned patch columns
-  int cyy[NS], cxx[NS];
+  // owned patch columns and their place in the z-sum rows
+  int cyy[NS], cxx[NS], zofs[NS];
   bool cin[NS], cval[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int col = threadIdx.x + k * NT;
+    const int row = col / PX, cx = col % PX;
     cval[k] = col < P1;
-    cyy[k] = tc.y0 - R + col / PX;
-    cxx[k] = tc.x0 - R + col % PX;
+    cyy[k] = tc.y0 - R + row;
+    cxx[k] = tc.x0 - R + cx;
+    zofs[k] = row * B::PXS + cx;
     cin[k] = cval[k] && cyy[k] >= 0 && cyy[k] < H && cxx[k] >= 0 && cxx[k] < W;
   }
   // software pipeline: U of slice zi+1 and the warped values of slice zi are
@@ -1076,68 +1135,83 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
     finish(tc.z0 - R, fr, v, az, ay, ax, fv0, mv0);
     load_u(tc.z0 - R + 1, u1);
   }
+  // the last WN slices of each owned column (oldest first) and their sums
+  // of f, m, f^2, m^2 and f m over z; the sums are formed anew from the
+  // ring every WN slices, so rounding does not build up along the chunk
+  float rf[NS][WN], rm[NS][WN], S[NS][5];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+#pragma unroll
+    for (int j = 0; j < WN; ++j) rf[k][j] = rm[k][j] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) S[k][q] = 0.f;
+  }
+  int phase = 0;
   double lsum = 0.0;
   for (int zi = tc.z0 - R; zi < tc.z1 + R; ++zi) {
-    const int slot = (zi + WN * 4096) % WN;
+    const bool exact = ++phase == WN;
+    if (exact) phase = 0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      if (!cval[k]) continue;
-      const int col = threadIdx.x + k * NT;
-      rF[slot][col] = fv0[k];
-      rM[slot][col] = mv0[k];
+      const float fo = rf[k][0], mo = rm[k][0];
+#pragma unroll
+      for (int j = 0; j + 1 < WN; ++j) {
+        rf[k][j] = rf[k][j + 1];
+        rm[k][j] = rm[k][j + 1];
+      }
+      const float f = fv0[k], m = mv0[k];
+      rf[k][WN - 1] = f;
+      rm[k][WN - 1] = m;
+      if (exact) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          s0 += rf[k][j];
+          s1 += rm[k][j];
+          s2 = fmaf(rf[k][j], rf[k][j], s2);
+          s3 = fmaf(rm[k][j], rm[k][j], s3);
+          s4 = fmaf(rf[k][j], rm[k][j], s4);
+        }
+        S[k][0] = s0; S[k][1] = s1; S[k][2] = s2; S[k][3] = s3; S[k][4] = s4;
+      } else {
+        S[k][0] += f - fo;
+        S[k][1] += m - mo;
+        S[k][2] += fmaf(f, f, -fo * fo);
+        S[k][3] += fmaf(m, m, -mo * mo);
+        S[k][4] += fmaf(f, m, -fo * mo);
+      }
     }
     float u2[NS][3], fr[NS], v[NS][8];
     Ax az[NS], ay[NS], ax[NS];
     load_u(zi + 2, u2);
     issue(zi + 1, u1, fr, v, az, ay, ax);
-    __syncthreads();
     const int zcen = zi - R;
     if (zcen >= tc.z0) {
       const bool zvalid = zcen >= R && zcen <= D - 1 - R;
       if (zvalid) {
-        for (int col = threadIdx.x; col < P1; col += NT) {
-          float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
-          for (int k = 0; k < WN; ++k) {
-            const float f = rF[k][col], m = rM[k][col];
-            s0 += f;
-            s1 += m;
-            s2 = fmaf(f, f, s2);
-            s3 = fmaf(m, m, s3);
-            s4 = fmaf(f, m, s4);
-          }
-          zs[0][col] = s0; zs[1][col] = s1; zs[2][col] = s2; zs[3][col] = s3; zs[4][col] = s4;
+        for (int k = 0; k < NS; ++k) {
+          if (!cval[k]) continue;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) zs[q * B::ZQ + zofs[k]] = S[k][q];
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < PY * TX; e += NT) {
-          const int row = e / TX, c = e % TX;
-          const int b = row * PX + c;
-#pragma unroll
-          for (int q = 0; q < 5; ++q) {
-            float acc = 0.f;
-#pragma unroll
-            for (int k = 0; k < WN; ++k) acc += zs[q][b + k];
-            xs[q][e] = acc;
-          }
-        }
+        box_x<B>(zs, xs, 5);
+        __syncthreads();
+        box_y<B>(xs, ys, 5);
         __syncthreads();
       }
       if (yx_in) {
         const int p = (zcen * H + y) * W + x;
         float al = 0.f, be = 0.f, ga = 0.f;
         if (zvalid && yx_valid) {
-          float S[5];
+          float Sw[5];
 #pragma unroll
-          for (int q = 0; q < 5; ++q) {
-            float acc = 0.f;
-#pragma unroll
-            for (int k = 0; k < WN; ++k) acc += xs[q][(ty + k) * TX + tx];
-            S[q] = acc;
-          }
-          const float mF = S[0] * inv_n, mM = S[1] * inv_n;
-          const float vFr = S[2] * inv_n - mF * mF;
-          const float vMr = S[3] * inv_n - mM * mM;
-          const float c = S[4] * inv_n - mF * mM;
+          for (int q = 0; q < 5; ++q) Sw[q] = ys[q * B::YQ + threadIdx.x];
+          const float mF = Sw[0] * inv_n, mM = Sw[1] * inv_n;
+          const float vFr = Sw[2] * inv_n - mF * mF;
+          const float vMr = Sw[3] * inv_n - mM * mM;
+          const float c = Sw[4] * inv_n - mF * mM;
           const float vF = fmaxf(vFr, 0.f), vM = fmaxf(vMr, 0.f);
           float l, av, ac;
           if (metric == 0) {
@@ -1173,7 +1247,6 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
         }
       }
     }
-    __syncthreads();
     finish(zi + 1, fr, v, az, ay, ax, fv0, mv0);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -1193,16 +1266,18 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
 // Gradient of Sim with respect to the pair field:
 //   dSim/dM(y) = (Box alpha + 2 M Box beta + F Box gamma)(y) / N_R,
 //   dSim/dU(y) = dSim/dM(y) * grad I_j(y + U(y)).
-// Pipelined like k_sim_stats: coefficients of the next slice and the output
-// voxel's loads are issued before the current slice's sums.
+// The window sums of the coefficients are formed like those of k_sim_stats;
+// the coefficients of the next slice and the output voxel's loads are issued
+// before the current slice's sums.
 template <int R, int TY, int TX>
 __global__ __launch_bounds__(TY * TX) void k_sim_grad(const SimItem* __restrict__ items, int n_items,
                                                       int n_tiles) {
-  using P = Patch<R, TY, TX>;
-  constexpr int WN = P::WN, PY = P::PY, PX = P::PX, P1 = P::P1, NS = P::NS, NT = P::NT;
-  __shared__ float ring[3][WN][P1];
-  __shared__ float zs[3][P1];
-  __shared__ float xs[3][PY * TX];
+  using B = Box<R, TY, TX, 3>;
+  constexpr int WN = B::WN, PX = B::PX, P1 = B::P1, NS = B::NS, NT = B::NT;
+  __shared__ float lds[B::LDS];
+  float* zs = lds;
+  float* xs = lds + 3 * B::ZQ;
+  float* ys = xs + 3 * B::XQ;
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const SimItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
@@ -1216,14 +1291,16 @@ __global__ __launch_bounds__(TY * TX) void k_sim_grad(const SimItem* __restrict_
   const int ty = threadIdx.x / TX, tx = threadIdx.x % TX;
   const int y = tc.y0 + ty, x = tc.x0 + tx;
   const bool yx_in = y < H && x < W;
-  int cyy[NS], cxx[NS];
+  int cyy[NS], cxx[NS], zofs[NS];
   bool cin[NS], cval[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int col = threadIdx.x + k * NT;
+    const int row = col / PX, cx = col % PX;
     cval[k] = col < P1;
-    cyy[k] = tc.y0 - R + col / PX;
-    cxx[k] = tc.x0 - R + col % PX;
+    cyy[k] = tc.y0 - R + row;
+    cxx[k] = tc.x0 - R + cx;
+    zofs[k] = row * B::PXS + cx;
     cin[k] = cval[k] && cyy[k] >= 0 && cyy[k] < H && cxx[k] >= 0 && cxx[k] < W;
   }
   auto load_coef = [&](int z, float (&c)[NS][3]) {
@@ -1262,16 +1339,38 @@ __global__ __launch_bounds__(TY * TX) void k_sim_grad(const SimItem* __restrict_
   load_coef(tc.z0 - R, c0);
   float uo[3];
   load_uo(tc.z0, uo);
-  for (int zi = tc.z0 - R; zi < tc.z1 + R; ++zi) {
-    const int slot = (zi + WN * 4096) % WN;
+  // the last WN slices of the coefficients of each owned column and their
+  // sums over z (formed anew every WN slices)
+  float rc[NS][3][WN], S[NS][3];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      if (!cval[k]) continue;
-      const int col = threadIdx.x + k * NT;
-      ring[0][slot][col] = c0[k][0];
-      ring[1][slot][col] = c0[k][1];
-      ring[2][slot][col] = c0[k][2];
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      S[k][q] = 0.f;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) rc[k][q][j] = 0.f;
     }
+  int phase = 0;
+  for (int zi = tc.z0 - R; zi < tc.z1 + R; ++zi) {
+    const bool exact = ++phase == WN;
+    if (exact) phase = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const float o = rc[k][q][0];
+#pragma unroll
+        for (int j = 0; j + 1 < WN; ++j) rc[k][q][j] = rc[k][q][j + 1];
+        rc[k][q][WN - 1] = c0[k][q];
+        if (exact) {
+          float s = 0.f;
+#pragma unroll
+          for (int j = 0; j < WN; ++j) s += rc[k][q][j];
+          S[k][q] = s;
+        } else {
+          S[k][q] += c0[k][q] - o;
+        }
+      }
     float c1[NS][3];
     load_coef(zi + 1, c1);
     const int zo = zi - R;
@@ -1290,49 +1389,30 @@ __global__ __launch_bounds__(TY * TX) void k_sim_grad(const SimItem* __restrict_
     }
     float un[3];
     load_uo(out_now ? zo + 1 : tc.z0, un);
-    __syncthreads();
     if (out_now) {
-      for (int col = threadIdx.x; col < P1; col += NT) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          float acc = 0.f;
+      for (int k = 0; k < NS; ++k) {
+        if (!cval[k]) continue;
 #pragma unroll
-          for (int k = 0; k < WN; ++k) acc += ring[q][k][col];
-          zs[q][col] = acc;
-        }
+        for (int q = 0; q < 3; ++q) zs[q * B::ZQ + zofs[k]] = S[k][q];
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < PY * TX; e += NT) {
-        const int row = e / TX, c = e % TX;
-        const int b = row * PX + c;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          float acc = 0.f;
-#pragma unroll
-          for (int k = 0; k < WN; ++k) acc += zs[q][b + k];
-          xs[q][e] = acc;
-        }
-      }
+      box_x<B>(zs, xs, 3);
+      __syncthreads();
+      box_y<B>(xs, ys, 3);
       __syncthreads();
       if (yx_in) {
-        float B[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          float acc = 0.f;
-#pragma unroll
-          for (int k = 0; k < WN; ++k) acc += xs[q][(ty + k) * TX + tx];
-          B[q] = acc;
-        }
+        const float B0 = ys[threadIdx.x], B1 = ys[B::YQ + threadIdx.x],
+                    B2 = ys[2 * B::YQ + threadIdx.x];
         const int p = (zo * H + y) * W + x;
         float dz, dy, dx;
         const float M = tri_grad(vI, az.t, ay.t, ax.t, dz, dy, dx);
-        const float dM = (B[0] + 2.f * M * B[1] + fo * B[2]) * inv_nr;
+        const float dM = (B0 + 2.f * M * B1 + fo * B2) * inv_nr;
         gU[p] = dM * dz * az.live;
         gU[V + p] = dM * dy * ay.live;
         gU[2 * V + p] = dM * dx * ax.live;
       }
     }
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       c0[k][0] = c1[k][0];
