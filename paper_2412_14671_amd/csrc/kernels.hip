@@ -172,49 +172,31 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-__device__ __forceinline__ int wave_min(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
+// Minimum / maximum over a wave: four DPP steps leave each row of 16 lanes
+// holding its row's result (swap neighbours, swap pairs, mirror the half
+// rows, mirror the rows), and the four row results are read from lanes 15,
+// 31, 47 and 63.  The result is wave-uniform.  Every lane must be active.
+__device__ __forceinline__ int dpp_min(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+  return min(min(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             min(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
 }
-__device__ __forceinline__ int wave_max(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
+__device__ __forceinline__ int dpp_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+  return max(max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
 }
 
-// Bounding box of the cells a tile touches, reduced over the block.
+// Bounding box of the cells a tile touches.
 struct BBox {
   int lz, ly, lx, ez, ey, ex, cells;
 };
-
-__device__ __forceinline__ BBox block_bbox(int lo[3], int hi[3], int* sbb) {
-  if (threadIdx.x == 0) {
-    sbb[0] = sbb[1] = sbb[2] = INT_MAX;
-    sbb[3] = sbb[4] = sbb[5] = INT_MIN;
-  }
-  __syncthreads();
-  for (int d = 0; d < 3; ++d) {
-    const int a = wave_min(lo[d]);
-    const int b = wave_max(hi[d]);
-    if ((threadIdx.x & 63) == 0) {
-      atomicMin(&sbb[d], a);
-      atomicMax(&sbb[3 + d], b);
-    }
-  }
-  __syncthreads();
-  BBox bb;
-  bb.lz = sbb[0]; bb.ly = sbb[1]; bb.lx = sbb[2];
-  if (sbb[3] < sbb[0]) {  // no voxel in the tile
-    bb.ez = bb.ey = bb.ex = 0;
-    bb.cells = 0;
-    return bb;
-  }
-  bb.ez = sbb[3] - sbb[0] + 1;
-  bb.ey = sbb[4] - sbb[1] + 1;
-  bb.ex = sbb[5] - sbb[2] + 1;
-  const long long c = (long long)bb.ez * bb.ey * bb.ex;
-  bb.cells = c > (long long)INT_MAX ? INT_MAX : (int)c;
-  return bb;
-}
 
 // Regulariser of Eq. reg_ss at voxel p for one component plane f: forward
 // differences, mean per (component, axis) over its valid set.  Returns the
@@ -389,8 +371,9 @@ __global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __rest
 // term to add at its own position (oz, oy, ox).
 //
 // The bins are 32-bit fixed point: every contribution is scaled by
-// 2^23 / m, where m is the largest magnitude the block spreads, rounded, and
-// added with an integer LDS atomic; integer LDS atomics run several times
+// 2^23 / m, where m is the largest magnitude the block spreads, truncated
+// (an error below 2^-23 m per contribution), and added with an integer LDS
+// atomic; integer LDS atomics run several times
 // faster than float ones on this hardware and make the in-block sum
 // independent of the order of the adds.  A bin can absorb contributions of
 // total weight up to 256 (a 256-fold local compression of the sampling
@@ -415,15 +398,13 @@ struct ScatterBox {
 
 __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], float mx,
                                                   int* sred) {
+  // mx >= 0 (fmaxf drops NaN operands), so its bits order like its values
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = min(lo[d], __shfl_xor(lo[d], o));
-      hi[d] = max(hi[d], __shfl_xor(hi[d], o));
-    }
-    mx = fmaxf(mx, __shfl_xor(mx, o));
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = dpp_min(lo[d]);
+    hi[d] = dpp_max(hi[d]);
   }
+  const int mxb = dpp_max(__float_as_int(mx));
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
@@ -431,11 +412,11 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
       sred[w * 8 + d] = lo[d];
       sred[w * 8 + 3 + d] = hi[d];
     }
-    sred[w * 8 + 6] = __float_as_int(mx);
+    sred[w * 8 + 6] = mxb;
   }
   __syncthreads();
   int l[3] = {INT_MAX, INT_MAX, INT_MAX}, h[3] = {INT_MIN, INT_MIN, INT_MIN};
-  float m = 0.f;
+  int mb = 0;
 #pragma unroll
   for (int i = 0; i < BLOCK / 64; ++i) {
 #pragma unroll
@@ -443,10 +424,10 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
       l[d] = min(l[d], sred[i * 8 + d]);
       h[d] = max(h[d], sred[i * 8 + 3 + d]);
     }
-    m = fmaxf(m, __int_as_float(sred[i * 8 + 6]));
+    mb = max(mb, sred[i * 8 + 6]);
   }
   ScatterBox sb;
-  sb.bmax = m;
+  sb.bmax = __int_as_float(mb);
   sb.bb.lz = l[0]; sb.bb.ly = l[1]; sb.bb.lx = l[2];
   if (h[0] < l[0]) {
     sb.bb.ez = sb.bb.ey = sb.bb.ex = 0;
@@ -538,12 +519,12 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
         if (g == 0.f) continue;
         int* a = acc + c * cells + l;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) atomicAdd(a + off[q], __float2int_rn(w[q] * g));
+        for (int q = 0; q < 8; ++q) atomicAdd(a + off[q], (int)(w[q] * g));
       }
       if (OWN) {
         const int lo2 = ((sv[j].oz - bb.lz) * bb.ey + (sv[j].oy - bb.ly)) * bb.ex + (sv[j].ox - bb.lx);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) atomicAdd(acc + c * cells + lo2, __float2int_rn(sv[j].own[c] * scale));
+        for (int c = 0; c < 3; ++c) atomicAdd(acc + c * cells + lo2, (int)(sv[j].own[c] * scale));
       }
     }
     __syncthreads();
@@ -560,8 +541,7 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
           so.slot[c * STAGE_CAP + i] = (float)v * inv;
         }
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) amax = max(amax, __shfl_xor(amax, o));
+      amax = dpp_max(amax);
       if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = amax;
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -660,7 +640,10 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     // fixed point, scaled so that the sum of the boxes' largest cell
     // magnitudes maps to 2^30: no bin can overflow.  Then the flat overflow,
     // if any block of the previous step used it.
-    __shared__ int nbd[27][12];
+    // per neighbour d: nyx, nx, index in its box of the overlap's first
+    // cell, the box's z and y strides, the tile-local index of that cell,
+    // the neighbour's tile, 1 / nyx and 1 / nx (float bits); [11] = cells
+    __shared__ __align__(16) int nbd[27][12];
     __shared__ int pre[28];
     __shared__ float nbm[27];
     __shared__ float nbmax;
@@ -699,12 +682,18 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
         const int y0 = max(by, tc.y0), y1 = min(by + ey, min(tc.y0 + PT_Y, H));
         const int x0 = max(bx, tc.x0), x1 = min(bx + ex, min(tc.x0 + PT_X, W));
         if (ez > 0 && z1 > z0 && y1 > y0 && x1 > x0) {
-          n = (z1 - z0) * (y1 - y0) * (x1 - x0);
+          const int nyx = (y1 - y0) * (x1 - x0);
+          n = (z1 - z0) * nyx;
           bm = __int_as_float(dsc[6]);
-          e[0] = z0; e[1] = y0; e[2] = x0;
-          e[3] = y1 - y0; e[4] = x1 - x0;
-          e[5] = bz; e[6] = by; e[7] = bx; e[8] = ey; e[9] = ex;
-          e[10] = nb;
+          e[0] = nyx;
+          e[1] = x1 - x0;
+          e[2] = ((z0 - bz) * ey + (y0 - by)) * ex + (x0 - bx);
+          e[3] = ey * ex;
+          e[4] = ex;
+          e[5] = ((z0 - tc.z0) * PT_Y + (y0 - tc.y0)) * PT_X + (x0 - tc.x0);
+          e[6] = nb;
+          e[7] = __float_as_int(1.f / (float)nyx);
+          e[8] = __float_as_int(1.f / (float)(x1 - x0));
         }
       }
       e[11] = n;
@@ -742,23 +731,27 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
             if (d + step < 27 && pre[d + step] <= w) d += step;
           const int* e = nbd[d];
           const int r = w - pre[d];
-          const int nyx = e[3] * e[4];
-          const int iz = r / nyx, rr = r - iz * nyx, iy = rr / e[4], ix = rr - iy * e[4];
-          const int gz = e[0] + iz, gy = e[1] + iy, gx = e[2] + ix;
-          const int idx = ((gz - e[5]) * e[8] + (gy - e[6])) * e[9] + (gx - e[7]);
-          const cgfloat* __restrict__ sl = st + (size_t)e[10] * 3 * STAGE_CAP;
+          // (iz, iy, ix) of cell r of the overlap; the float quotients are
+          // exact here (r < 1024, the overlap lies in one tile)
+          const int nyx = e[0], nx = e[1];
+          const int iz = (int)(((float)r + 0.5f) * __int_as_float(e[7]));
+          const int rr = r - iz * nyx;
+          const int iy = (int)(((float)rr + 0.5f) * __int_as_float(e[8]));
+          const int ix = rr - iy * nx;
+          const int idx = e[2] + iz * e[3] + iy * e[4] + ix;
+          const cgfloat* __restrict__ sl = st + (size_t)e[6] * 3 * STAGE_CAP;
           v0[u] = sl[idx];
           v1[u] = sl[STAGE_CAP + idx];
           v2[u] = sl[2 * STAGE_CAP + idx];
-          loc[u] = ((gz - tc.z0) * PT_Y + (gy - tc.y0)) * PT_X + (gx - tc.x0);
+          loc[u] = e[5] + (iz * PT_Y + iy) * PT_X + ix;
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (loc[u] < 0) continue;
-        atomicAdd(&gacc[loc[u]], __float2int_rn(v0[u] * qscale));
-        atomicAdd(&gacc[PT_VOX + loc[u]], __float2int_rn(v1[u] * qscale));
-        atomicAdd(&gacc[2 * PT_VOX + loc[u]], __float2int_rn(v2[u] * qscale));
+        atomicAdd(&gacc[loc[u]], (int)(v0[u] * qscale));
+        atomicAdd(&gacc[PT_VOX + loc[u]], (int)(v1[u] * qscale));
+        atomicAdd(&gacc[2 * PT_VOX + loc[u]], (int)(v2[u] * qscale));
       }
     }
     __syncthreads();
@@ -806,24 +799,21 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
     const int base = (az.i0 * H + ay.i0) * W + ax.i0;
     const float g0 = gv[j][0], g1 = gv[j][1], g2 = gv[j][2];
-    float own0 = g0, own1 = g1, own2 = g2;
-    float v[8], dz, dy, dx;
-    // row c of the Jacobian of a*src at q, times g_c, added to column terms
-    load8(s, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    own0 = fmaf(a * dz * az.live, g0, own0);
-    own1 = fmaf(a * dy * ay.live, g0, own1);
-    own2 = fmaf(a * dx * ax.live, g0, own2);
-    load8(s + V, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    own0 = fmaf(a * dz * az.live, g1, own0);
-    own1 = fmaf(a * dy * ay.live, g1, own1);
-    own2 = fmaf(a * dx * ax.live, g1, own2);
-    load8(s + 2 * V, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    own0 = fmaf(a * dz * az.live, g2, own0);
-    own1 = fmaf(a * dy * ay.live, g2, own1);
-    own2 = fmaf(a * dx * ax.live, g2, own2);
+    // (J^T g) of the Jacobian J of src at q: rows c, each times g_c; the
+    // factor a and the clamped axes apply per column
+    float v0[8], v1[8], v2[8], dz, dy, dx;
+    load8(s, base, W, HW, v0);
+    load8(s + V, base, W, HW, v1);
+    load8(s + 2 * V, base, W, HW, v2);
+    tri_grad(v0, az.t, ay.t, ax.t, dz, dy, dx);
+    float jz = dz * g0, jy = dy * g0, jx = dx * g0;
+    tri_grad(v1, az.t, ay.t, ax.t, dz, dy, dx);
+    jz = fmaf(dz, g1, jz); jy = fmaf(dy, g1, jy); jx = fmaf(dx, g1, jx);
+    tri_grad(v2, az.t, ay.t, ax.t, dz, dy, dx);
+    jz = fmaf(dz, g2, jz); jy = fmaf(dy, g2, jy); jx = fmaf(dx, g2, jx);
+    float own0 = fmaf(a * az.live, jz, g0);
+    float own1 = fmaf(a * ay.live, jy, g1);
+    float own2 = fmaf(a * ax.live, jx, g2);
     if (it.reg_w != 0.f) {
       own0 = fmaf(it.reg_w, reg_point(s, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own0);
       own1 = fmaf(it.reg_w, reg_point(s + V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own1);
@@ -905,23 +895,19 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
     const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
     const int base = (az.i0 * H + ay.i0) * W + ax.i0;
     const float g0 = G[p], g1 = G[V + p], g2 = G[2 * V + p];
-    float o0 = g0, o1 = g1, o2 = g2;
-    float v[8], dz, dy, dx;
-    load8(C, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    o0 = fmaf(dz * az.live, g0, o0);
-    o1 = fmaf(dy * ay.live, g0, o1);
-    o2 = fmaf(dx * ax.live, g0, o2);
-    load8(C + V, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    o0 = fmaf(dz * az.live, g1, o0);
-    o1 = fmaf(dy * ay.live, g1, o1);
-    o2 = fmaf(dx * ax.live, g1, o2);
-    load8(C + 2 * V, base, W, HW, v);
-    tri_grad(v, az.t, ay.t, ax.t, dz, dy, dx);
-    o0 = fmaf(dz * az.live, g2, o0);
-    o1 = fmaf(dy * ay.live, g2, o1);
-    o2 = fmaf(dx * ax.live, g2, o2);
+    float v0[8], v1[8], v2[8], dz, dy, dx;
+    load8(C, base, W, HW, v0);
+    load8(C + V, base, W, HW, v1);
+    load8(C + 2 * V, base, W, HW, v2);
+    tri_grad(v0, az.t, ay.t, ax.t, dz, dy, dx);
+    float jz = dz * g0, jy = dy * g0, jx = dx * g0;
+    tri_grad(v1, az.t, ay.t, ax.t, dz, dy, dx);
+    jz = fmaf(dz, g1, jz); jy = fmaf(dy, g1, jy); jx = fmaf(dx, g1, jx);
+    tri_grad(v2, az.t, ay.t, ax.t, dz, dy, dx);
+    jz = fmaf(dz, g2, jz); jy = fmaf(dy, g2, jy); jx = fmaf(dx, g2, jx);
+    const float o0 = fmaf(az.live, jz, g0);
+    const float o1 = fmaf(ay.live, jy, g1);
+    const float o2 = fmaf(ax.live, jx, g2);
     if (it.prev_atomic) {
       gadd(gpv + p, o0);
       gadd(gpv + V + p, o1);
