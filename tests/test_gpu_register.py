@@ -166,9 +166,16 @@ def test_invalid_arguments_are_rejected(ctx):
 
 def test_server_results_match_alone(ctx):
     """Jobs submitted together are admitted, batched with each other and
-    retired between ticks; each result equals the job run alone."""
+    retired between ticks; each result equals the job run alone.  Both
+    contexts use one fixed tiling of the window sums: the autotuner of each
+    context may pick another tiling for a level, and a different summation
+    order changes gradients at rounding level, which the first Adam step of a
+    level turns into steps of either sign at voxels whose gradient is at that
+    level."""
     from paper_2412_14671_amd import Context, MusterParams, Server, synth
     c2 = Context(0)
+    c2.set_tiling("fixed", 0, 32)
+    ctx.set_tiling("fixed", 0, 32)
     srv = Server(c2)
     subjects = [synth.phantom_series((24, 24, 24), 3, seed=41),
                 synth.phantom_series((32, 24, 16), 4, seed=42),
@@ -188,6 +195,7 @@ def test_server_results_match_alone(ctx):
         assert r["iterations"] == sum(p.iters)
     st = srv.stats()
     assert st["resident"] == 0 and st["queued"] == 0
+    ctx.set_tiling("autotune")
     c2.close()
 
 
