@@ -218,6 +218,43 @@ __device__ __forceinline__ float reg_point(const cgfloat* __restrict__ f, int z,
   return g;
 }
 
+// The same regulariser read from a halo tile in LDS: the field over a point
+// tile and one voxel around it (coordinates clamped to the grid; a clamped
+// neighbour is never used), three component planes of RH_N values.
+constexpr int RH_Z = PT_Z + 2, RH_Y = PT_Y + 2, RH_X = PT_X + 2, RH_N = RH_Z * RH_Y * RH_X;
+static_assert(RH_N <= SCATTER_CELLS, "the halo tile must fit the scatter bins");
+
+__device__ __forceinline__ void reg_tile_load(const cgfloat* __restrict__ f, int V, int z0, int y0,
+                                              int x0, int D, int H, int W, float* __restrict__ t) {
+  for (int i = threadIdx.x; i < 3 * RH_N; i += BLOCK) {
+    const int c = i / RH_N, r = i - c * RH_N;
+    const int hz = r / (RH_Y * RH_X), r2 = r - hz * (RH_Y * RH_X);
+    const int hy = r2 / RH_X, hx = r2 - hy * RH_X;
+    const int z = min(max(z0 - 1 + hz, 0), D - 1);
+    const int y = min(max(y0 - 1 + hy, 0), H - 1);
+    const int x = min(max(x0 - 1 + hx, 0), W - 1);
+    t[i] = f[c * V + (z * H + y) * W + x];
+  }
+}
+
+__device__ __forceinline__ float reg_tile_point(const float* __restrict__ t, int lz, int ly, int lx,
+                                                int z, int y, int x, int D, int H, int W,
+                                                float inv_mz, float inv_my, float inv_mx,
+                                                float* val) {
+  constexpr int SZ = RH_Y * RH_X, SY = RH_X;
+  const int q = ((lz + 1) * RH_Y + ly + 1) * RH_X + lx + 1;
+  const float c = t[q];
+  float g = 0.f, e = 0.f;
+  if (z + 1 < D) { const float d = t[q + SZ] - c; g -= 2.f * d * inv_mz; e = fmaf(d * d, inv_mz, e); }
+  if (z > 0)     { const float d = c - t[q - SZ]; g += 2.f * d * inv_mz; }
+  if (y + 1 < H) { const float d = t[q + SY] - c; g -= 2.f * d * inv_my; e = fmaf(d * d, inv_my, e); }
+  if (y > 0)     { const float d = c - t[q - SY]; g += 2.f * d * inv_my; }
+  if (x + 1 < W) { const float d = t[q + 1] - c;  g -= 2.f * d * inv_mx; e = fmaf(d * d, inv_mx, e); }
+  if (x > 0)     { const float d = c - t[q - 1];  g += 2.f * d * inv_mx; }
+  *val += e;
+  return g;
+}
+
 // ---------------------------------------------------------------------------
 // Point tiles.  A thread owns VPT voxels of an 8x8x16 tile.  Their loads are
 // issued together, component by component across the voxels, so each round
@@ -788,6 +825,15 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
       }
     }
   }
+  // the regulariser's stencil reads a halo tile of src staged in acc, which
+  // the scatter below reuses once every thread has formed its own terms
+  float* rt = reinterpret_cast<float*>(acc);
+  float rvf = 0.f;
+  if (it.reg_w != 0.f) {
+    __syncthreads();  // the staged pull above is done with acc
+    reg_tile_load(s, V, tc.z0, tc.y0, tc.x0, D, H, W, rt);
+    __syncthreads();
+  }
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
@@ -815,10 +861,13 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     float own1 = fmaf(a * ay.live, jy, g1);
     float own2 = fmaf(a * ax.live, jx, g2);
     if (it.reg_w != 0.f) {
-      own0 = fmaf(it.reg_w, reg_point(s, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own0);
-      own1 = fmaf(it.reg_w, reg_point(s + V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval), own1);
-      own2 = fmaf(it.reg_w, reg_point(s + 2 * V, z, y, x, D, H, W, inv_mz, inv_my, inv_mx, &rval),
-                  own2);
+      const int lz = z - tc.z0, ly = y - tc.y0, lx = x - tc.x0;
+      own0 = fmaf(it.reg_w, reg_tile_point(rt, lz, ly, lx, z, y, x, D, H, W, inv_mz, inv_my,
+                                           inv_mx, &rvf), own0);
+      own1 = fmaf(it.reg_w, reg_tile_point(rt + RH_N, lz, ly, lx, z, y, x, D, H, W, inv_mz,
+                                           inv_my, inv_mx, &rvf), own1);
+      own2 = fmaf(it.reg_w, reg_tile_point(rt + 2 * RH_N, lz, ly, lx, z, y, x, D, H, W, inv_mz,
+                                           inv_my, inv_mx, &rvf), own2);
     }
     if (it.ext) {
       // L_L2 and L_ts (Sec. 2.4): linear in the flows of this interval and its neighbours
@@ -862,6 +911,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   } else {
     scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred);
   }
+  rval = (double)rvf;
   if (reg) {
     const double tot = block_sum(rval * (double)it.reg_loss_w + rext, red);
     if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot);
