@@ -979,14 +979,15 @@ __global__ __launch_bounds__(BLOCK) void k_compose_bwd(const ComposeBwdItem* __r
 // Windowed statistics (Sec. 2.6): warp + LNCC/SiLNCC per window, loss and
 // the per-window adjoint coefficients.
 //
-// A block owns TY x TX window centres in (y, x) and marches through a chunk
-// of z.  Every thread owns a few columns of the (TY + 2r) x (TX + 2r) patch
-// around them.  For each input slice it warps the source image at its columns
-// and keeps the last w slices of its per-column values in registers with
-// their running sums over z.  For every centre slice the z-sums go to LDS and
-// are summed over x, then over y (box_x, box_y).  Values are shifted by one
-// per-block constant before the products, which keeps the variance
-// differences well conditioned.
+// The source image is first warped by the pair field once per voxel
+// (k_warp).  A block of the statistics owns TY x TX window centres in (y, x)
+// and marches through a chunk of z.  Every thread owns a few columns of the
+// (TY + 2r) x (TX + 2r) patch around them.  For each input slice it reads the
+// fixed and the warped image at its columns and keeps the last w slices of
+// its per-column values in registers with their running sums over z.  For
+// every centre slice the z-sums go to LDS and are summed over x, then over y
+// (box_x, box_y).  Values are shifted by one per-block constant before the
+// products, which keeps the variance differences well conditioned.
 // ---------------------------------------------------------------------------
 struct STile {
   int z0, z1, y0, x0;
@@ -1011,7 +1012,7 @@ __device__ __forceinline__ STile stat_tile(int local, int D, int H, int W, int z
 // floats) and the finished sums of the centres (TY x TX).  The row strides
 // are odd, so the rows a wave walks along fall in distinct banks.  The x and
 // y passes give each thread a segment of 8 outputs: it reads the 8 + 2r
-// inputs once and forms the 8 sums from registers.
+// inputs once and forms the 8 sums from registers as a sliding sum.
 template <int R, int TY, int TX, int Q>
 struct Box {
   static constexpr int NT = TY * TX, RW = R, TXO = TX;
@@ -1038,11 +1039,13 @@ __device__ __forceinline__ void box_x(const float* __restrict__ zs, float* __res
     float v[SX + 2 * R];
 #pragma unroll
     for (int k = 0; k < SX + 2 * R; ++k) v[k] = s[k];
+    float acc = v[0];
 #pragma unroll
-    for (int i = 0; i < SX; ++i) {
-      float acc = v[i];
+    for (int k = 1; k < WN; ++k) acc += v[k];
+    d[0] = acc;
 #pragma unroll
-      for (int k = 1; k < WN; ++k) acc += v[i + k];
+    for (int i = 1; i < SX; ++i) {
+      acc += v[i + 2 * R] - v[i - 1];
       d[i] = acc;
     }
   }
@@ -1061,14 +1064,64 @@ __device__ __forceinline__ void box_y(const float* __restrict__ xs, float* __res
     float v[SY + 2 * R];
 #pragma unroll
     for (int k = 0; k < SY + 2 * R; ++k) v[k] = s[k * TXS];
+    float acc = v[0];
 #pragma unroll
-    for (int i = 0; i < SY; ++i) {
-      float acc = v[i];
+    for (int k = 1; k < WN; ++k) acc += v[k];
+    d[0] = acc;
 #pragma unroll
-      for (int k = 1; k < WN; ++k) acc += v[i + k];
+    for (int i = 1; i < SY; ++i) {
+      acc += v[i + 2 * R] - v[i - 1];
       d[i * TX] = acc;
     }
   }
+}
+
+// Warp of the source image by the pair field (Sec. 2.1): M(p) = I(p + U(p)),
+// with the rigid adjustment of the source session added to U (Sec. 2.5).
+__global__ __launch_bounds__(BLOCK) void k_warp(const SimItem* __restrict__ items, int n_items,
+                                                int n_tiles) {
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const SimItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
+  const PTile tc = point_tile(tile - it.tile0, H, W);
+  const cgfloat* __restrict__ I = gp(it.I);
+  const cgfloat* __restrict__ U = gp(it.U);
+  gfloat* __restrict__ M = gp(it.M);
+  VoxSet vs;
+  vox_set(tc, D, H, W, vs);
+  float u[VPT][3];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    u[j][0] = U[vs.p[j]];
+    u[j][1] = U[V + vs.p[j]];
+    u[j][2] = U[2 * V + vs.p[j]];
+  }
+  if (it.rigid) {
+    float rA[9], rO[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) rA[k] = it.rigid->A[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rO[k] = it.rigid->off[k];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const float fz = (float)vs.z[j], fy = (float)vs.y[j], fx = (float)vs.x[j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        u[j][c] += fmaf(rA[3 * c], fz, fmaf(rA[3 * c + 1], fy, fmaf(rA[3 * c + 2], fx, rO[c])));
+    }
+  }
+  float v[VPT][8];
+  Ax az[VPT], ay[VPT], ax[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    az[j] = axis_disp(vs.z[j], u[j][0], D);
+    ay[j] = axis_disp(vs.y[j], u[j][1], H);
+    ax[j] = axis_disp(vs.x[j], u[j][2], W);
+    load8(I, (az[j].i0 * H + ay[j].i0) * W + ax[j].i0, W, HW, v[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < VPT; ++j)
+    if (vs.ok[j]) M[vs.p[j]] = tri_val(v[j], az[j].t, ay[j].t, ax[j].t);
 }
 
 template <int R, int TY, int TX>
@@ -1086,91 +1139,40 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const STile tc = stat_tile<TY, TX>(tile - it.tile0, D, H, W, it.zc);
   const cgfloat* __restrict__ F = gp(it.F);
-  const cgfloat* __restrict__ I = gp(it.I);
-  const cgfloat* __restrict__ U = gp(it.U);
+  const cgfloat* __restrict__ M = gp(it.M);
   gfloat* __restrict__ coef = gp(it.coef);
   const int pm = (min((tc.z0 + tc.z1) / 2, D - 1) * H + min(tc.y0 + TY / 2, H - 1)) * W +
                  min(tc.x0 + TX / 2, W - 1);
-  const float sF = F[pm], sM = I[pm];
+  const float sF = F[pm], sM = M[pm];
   const float inv_n = 1.f / (float)(WN * WN * WN);
   const int ty = threadIdx.x / TX, tx = threadIdx.x % TX;
   const int y = tc.y0 + ty, x = tc.x0 + tx;
   const bool yx_in = (y < H) && (x < W);
   const bool yx_valid = yx_in && y >= R && y <= H - 1 - R && x >= R && x <= W - 1 - R;
-  // owned patch columns and their place in the z-sum rows
-  int cyy[NS], cxx[NS], zofs[NS];
-  bool cin[NS], cval[NS];
+  // owned patch columns: offset in a slice (-1 outside the volume) and place
+  // in the z-sum rows
+  int cofs[NS], zofs[NS];
+  bool cval[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int col = threadIdx.x + k * NT;
     const int row = col / PX, cx = col % PX;
+    const int yy = tc.y0 - R + row, xx = tc.x0 - R + cx;
     cval[k] = col < P1;
-    cyy[k] = tc.y0 - R + row;
-    cxx[k] = tc.x0 - R + cx;
+    cofs[k] = (cval[k] && yy >= 0 && yy < H && xx >= 0 && xx < W) ? yy * W + xx : -1;
     zofs[k] = row * B::PXS + cx;
-    cin[k] = cval[k] && cyy[k] >= 0 && cyy[k] < H && cxx[k] >= 0 && cxx[k] < W;
   }
-  // software pipeline: U of slice zi+1 and the warped values of slice zi are
-  // in registers when iteration zi starts; the loads for the next slices are
-  // issued before this slice's sums so their latency overlaps the sums.
-  float u1[NS][3];
-  float fv0[NS], mv0[NS];
-  // the rigid adjustment of the source session adds A p + off (Sec. 2.5)
-  float rA[9], rO[3];
-  const bool rigid = it.rigid != nullptr;
-  if (rigid) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) rA[k] = it.rigid->A[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) rO[k] = it.rigid->off[k];
-  }
-  auto load_u = [&](int z, float (&u)[NS][3]) {
+  // shifted values of slice z at the owned columns (0 outside the volume)
+  auto load = [&](int z, float (&f)[NS], float (&m)[NS]) {
+    const bool zin = z >= 0 && z < D;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const bool in = cin[k] && z >= 0 && z < D;
-      const int p = in ? (z * H + cyy[k]) * W + cxx[k] : 0;
-      u[k][0] = in ? U[p] : 0.f;
-      u[k][1] = in ? U[V + p] : 0.f;
-      u[k][2] = in ? U[2 * V + p] : 0.f;
-      if (rigid && in) {
-        const float fz = (float)z, fy = (float)cyy[k], fx = (float)cxx[k];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          u[k][c] += fmaf(rA[3 * c], fz, fmaf(rA[3 * c + 1], fy, fmaf(rA[3 * c + 2], fx, rO[c])));
-      }
+      const bool in = zin && cofs[k] >= 0;
+      const int p = in ? z * HW + cofs[k] : 0;
+      f[k] = in ? F[p] - sF : 0.f;
+      m[k] = in ? M[p] - sM : 0.f;
     }
   };
-  // issue the loads of slice z (F and the 8 corners of I at the warped position)
-  auto issue = [&](int z, const float (&u)[NS][3], float (&fr)[NS], float (&v)[NS][8],
-                   Ax (&az)[NS], Ax (&ay)[NS], Ax (&ax)[NS]) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const bool in = cin[k] && z >= 0 && z < D;
-      const int zz = in ? z : 0, yy = in ? cyy[k] : 0, xx = in ? cxx[k] : 0;
-      az[k] = axis_disp(zz, u[k][0], D);
-      ay[k] = axis_disp(yy, u[k][1], H);
-      ax[k] = axis_disp(xx, u[k][2], W);
-      load8(I, (az[k].i0 * H + ay[k].i0) * W + ax[k].i0, W, HW, v[k]);
-      fr[k] = F[(zz * H + yy) * W + xx];
-    }
-  };
-  auto finish = [&](int z, const float (&fr)[NS], const float (&v)[NS][8], const Ax (&az)[NS],
-                    const Ax (&ay)[NS], const Ax (&ax)[NS], float (&fo)[NS], float (&mo)[NS]) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const bool in = cin[k] && z >= 0 && z < D;
-      mo[k] = in ? tri_val(v[k], az[k].t, ay[k].t, ax[k].t) - sM : 0.f;
-      fo[k] = in ? fr[k] - sF : 0.f;
-    }
-  };
-  {
-    float u0[NS][3], fr[NS], v[NS][8];
-    Ax az[NS], ay[NS], ax[NS];
-    load_u(tc.z0 - R, u0);
-    issue(tc.z0 - R, u0, fr, v, az, ay, ax);
-    finish(tc.z0 - R, fr, v, az, ay, ax, fv0, mv0);
-    load_u(tc.z0 - R + 1, u1);
-  }
   // the last WN slices of each owned column (oldest first) and their sums
   // of f, m, f^2, m^2 and f m over z; the sums are formed anew from the
   // ring every WN slices, so rounding does not build up along the chunk
@@ -1182,11 +1184,21 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
 #pragma unroll
     for (int q = 0; q < 5; ++q) S[k][q] = 0.f;
   }
+  // values of slice zi are loaded one iteration ahead
+  float fn[NS], mn[NS];
+  load(tc.z0 - R, fn, mn);
   int phase = 0;
   double lsum = 0.0;
   for (int zi = tc.z0 - R; zi < tc.z1 + R; ++zi) {
     const bool exact = ++phase == WN;
     if (exact) phase = 0;
+    float fv[NS], mv[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      fv[k] = fn[k];
+      mv[k] = mn[k];
+    }
+    load(zi + 1, fn, mn);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const float fo = rf[k][0], mo = rm[k][0];
@@ -1195,7 +1207,7 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
         rf[k][j] = rf[k][j + 1];
         rm[k][j] = rm[k][j + 1];
       }
-      const float f = fv0[k], m = mv0[k];
+      const float f = fv[k], m = mv[k];
       rf[k][WN - 1] = f;
       rm[k][WN - 1] = m;
       if (exact) {
@@ -1217,10 +1229,6 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
         S[k][4] += fmaf(f, m, -fo * mo);
       }
     }
-    float u2[NS][3], fr[NS], v[NS][8];
-    Ax az[NS], ay[NS], ax[NS];
-    load_u(zi + 2, u2);
-    issue(zi + 1, u1, fr, v, az, ay, ax);
     const int zcen = zi - R;
     if (zcen >= tc.z0) {
       const bool zvalid = zcen >= R && zcen <= D - 1 - R;
@@ -1282,13 +1290,6 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
           coef[2 * V + p] = ga;
         }
       }
-    }
-    finish(zi + 1, fr, v, az, ay, ax, fv0, mv0);
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      u1[k][0] = u2[k][0];
-      u1[k][1] = u2[k][1];
-      u1[k][2] = u2[k][2];
     }
   }
   const double tot = block_sum<NT>(lsum, red);
@@ -1894,6 +1895,12 @@ static hipError_t sim_window(bool grad, const SimItem* items, int n_items, int n
     case 7: return sim_shape<3>(grad, items, n_items, n_tiles, metric, shape, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_warp(const SimItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_warp, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
 }
 
 hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,

@@ -170,6 +170,8 @@ struct SimItem {
   const float* F;
   const float* I;
   const float* U;
+  float* M;      // [V]: I warped by U (and the rigid adjustment), written by k_warp and read
+                 // by k_sim_stats; may be the first plane of gU, which k_sim_grad overwrites
   float* coef;   // [3][V]: alpha, beta, gamma per window centre (may be null in sim_stats)
   float* gU;     // [3][V]: dSim/dU, written by sim_grad
   double inv_nr; // 1 / number of windows
@@ -288,6 +290,8 @@ hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int
                           hipStream_t s);
 hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
                               hipStream_t s);
+// M = I o (Omega + U) of each item, over point tiles of its grid.
+hipError_t launch_warp(const SimItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,
                             int shape, hipStream_t s);
 hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int window, int shape,

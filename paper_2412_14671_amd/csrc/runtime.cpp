@@ -539,7 +539,7 @@ namespace {
 
 // Algorithmic bytes per voxel (the unique bytes each step must move).
 constexpr double B_EXP_FWD = 24, B_COMPOSE_FWD = 36, B_SIM_STATS = 20, B_SIM_GRAD = 32,
-                 B_COMPOSE_BWD = 84, B_EXP_BWD = 60, B_ADAM = 96, B_SMOOTH = 24;
+                 B_COMPOSE_BWD = 84, B_EXP_BWD = 60, B_ADAM = 96, B_SMOOTH = 24, B_WARP = 20;
 
 struct Builder {
   Plan* plan;
@@ -799,6 +799,7 @@ std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int shape, int& ti
         it.U = J->pair_img(i, j);
         it.coef = J->coef(i, j);
         it.gU = J->pair_grad_img(i, j);
+        it.M = it.gU;  // free until k_sim_grad writes gU
         it.inv_nr = 1.0 / nr;
         it.js = J->js;
         it.sim_out = nullptr;
@@ -811,9 +812,26 @@ std::vector<SimItem> sim_items(const std::vector<Job*>& jobs, int shape, int& ti
   return items;
 }
 
-// One window-statistics stage per tile shape in use.
+// One window-statistics stage per tile shape in use; the statistics are
+// preceded by the warp of every pair's source image.
 void add_sim_stages(Builder& b, const std::vector<Job*>& jobs, StageKind kind) {
   const int window = jobs[0]->p.window, metric = jobs[0]->p.metric;
+  if (kind == ST_SIM_STATS) {
+    std::vector<SimItem> items;
+    int tiles = 0;
+    double vox = 0;
+    for (int shape = 0; shape < SIM_SHAPES; ++shape) {
+      int t;
+      double v;
+      for (SimItem it : sim_items(jobs, shape, t, v)) {
+        it.tile0 = tiles;
+        tiles += point_tiles(it.D, it.H, it.W);
+        vox += (double)it.D * it.H * it.W;
+        items.push_back(it);
+      }
+    }
+    b.add(ST_WARP, items, tiles, B_WARP * vox);
+  }
   for (int shape = 0; shape < SIM_SHAPES; ++shape) {
     int tiles;
     double vox;
@@ -1076,6 +1094,7 @@ static int kclass(StageKind k) {
     case ST_UPSAMPLE_ADJ: return MUSTER_K_UPSAMPLE_ADJ;
     case ST_RIGID_GRAD: return MUSTER_K_RIGID;
     case ST_RIGID_STEP: return MUSTER_K_RIGID;
+    case ST_WARP: return MUSTER_K_WARP;
   }
   return MUSTER_K_FINISH;
 }
@@ -1102,6 +1121,7 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_RIGID_GRAD:
       return launch_rigid_grad((const RigidGradItem*)p, st.n_items, st.n_tiles, s);
     case ST_RIGID_STEP: return launch_rigid_step((const RigidStepItem*)p, st.n_items, s);
+    case ST_WARP: return launch_warp((const SimItem*)p, st.n_items, st.n_tiles, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1461,9 +1481,18 @@ SimTile tune_sim_tile(Ctx* ctx, const int dims[3], int window, int metric, hipSt
     it.U = base;
     it.coef = base + 3 * V;
     it.gU = base + 6 * V;
+    it.M = it.gU;
     it.inv_nr = 1.0 / ((double)(dims[0] - 2 * r) * (dims[1] - 2 * r) * (dims[2] - 2 * r));
     it.js = nullptr;
     it.sim_out = acc.as<double>();
+  }
+  // the warp does not depend on the tiling: once, before the timed stages
+  {
+    const int pt = point_tiles(dims[0], dims[1], dims[2]);
+    for (int k = 0; k < P; ++k) its[k].tile0 = k * pt;
+    MUSTER_HIP(hipMemcpyAsync(item.p, its.data(), (size_t)P * sizeof(SimItem),
+                              hipMemcpyHostToDevice, s));
+    MUSTER_HIP(launch_warp(item.as<SimItem>(), P, P * pt, s));
   }
   std::vector<int> zcs;
   for (int z : {16, 32, 64}) {
@@ -2087,8 +2116,9 @@ muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int win
     std::lock_guard<std::mutex> lk(ctx->mu);
     StepCall sc{ctx, (hipStream_t)stream, {}};
     const size_t V = (size_t)dims[0] * dims[1] * dims[2];
-    DevMem coef;
+    DevMem coef, warped;
     if (grad_U) coef.alloc(ctx, 3 * V * sizeof(float));
+    warped.alloc(ctx, V * sizeof(float));
     const int r = (window - 1) / 2;
     const SimTile tl = choose_sim_tile(ctx, dims, window, metric, sc.s);
     SimItem it{};
@@ -2097,6 +2127,7 @@ muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int win
     it.F = F;
     it.I = I;
     it.U = U;
+    it.M = warped.as<float>();
     it.coef = grad_U ? coef.as<float>() : nullptr;
     it.gU = grad_U;
     it.inv_nr = 1.0 / ((double)(dims[0] - 2 * r) * (dims[1] - 2 * r) * (dims[2] - 2 * r));
@@ -2105,6 +2136,8 @@ muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int win
     const size_t off = sc.add(it);
     sc.upload();
     MUSTER_HIP(hipMemsetAsync(ctx->step_acc, 0, sizeof(double), sc.s));
+    MUSTER_HIP(launch_warp((const SimItem*)(sc.dev() + off), 1,
+                           point_tiles(dims[0], dims[1], dims[2]), sc.s));
     const int tiles = stat_tiles(dims[0], dims[1], dims[2], tl.zc, tl.shape);
     MUSTER_HIP(launch_sim_stats((const SimItem*)(sc.dev() + off), 1, tiles, window, metric,
                                 tl.shape, sc.s));
@@ -2378,7 +2411,7 @@ const char* muster_kernel_name(int k) {
   static const char* names[MUSTER_K_COUNT] = {"exp_fwd", "compose_fwd", "sim_stats", "sim_grad",
                                               "compose_bwd", "exp_bwd", "adam", "finish",
                                               "pool2", "upsample2", "smooth", "upsample2_adj",
-                                              "rigid"};
+                                              "rigid", "warp"};
   if (k < 0 || k >= MUSTER_K_COUNT) return "";
   return names[k];
 }
