@@ -339,7 +339,7 @@ enum {
   MUSTER_K_EXP_FWD = 0, MUSTER_K_COMPOSE_FWD, MUSTER_K_SIM_STATS, MUSTER_K_SIM_GRAD,
   MUSTER_K_COMPOSE_BWD, MUSTER_K_EXP_BWD, MUSTER_K_ADAM, MUSTER_K_FINISH,
   MUSTER_K_POOL, MUSTER_K_UPSAMPLE, MUSTER_K_SMOOTH, MUSTER_K_UPSAMPLE_ADJ, MUSTER_K_RIGID,
-  MUSTER_K_WARP, MUSTER_K_COUNT
+  MUSTER_K_WARP, MUSTER_K_UNSTAGE, MUSTER_K_COUNT
 };
 /* When enabled, eager launches (graphs off) of each kernel class are
  * bracketed by HIP events on the stream they run on. */

@@ -24,7 +24,7 @@ TILES_DEFAULT, TILES_AUTOTUNE, TILES_FIXED = 0, 1, 2
 SIM_SHAPES = [(8, 32), (16, 32), (8, 64)]
 EXP_STORE, EXP_RECOMPUTE = 0, 1
 KERNELS = ["exp_fwd", "compose_fwd", "sim_stats", "sim_grad", "compose_bwd", "exp_bwd", "adam",
-           "finish", "pool2", "upsample2", "smooth", "upsample2_adj", "rigid", "warp"]
+           "finish", "pool2", "upsample2", "smooth", "upsample2_adj", "rigid", "warp", "unstage"]
 
 
 class MusterLibraryMissing(ImportError):

@@ -630,12 +630,161 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[VPT], gfloat
   }
 }
 
+// G over a point tile from the staged boxes of a scatter step.  The tile's
+// own box (which holds every owned voxel) is read straight into registers.
+// The parts of the 26 neighbours' boxes that reach into the tile form one
+// list of cells, which the block reads with all its loads in flight and adds
+// into LDS bins (neighbouring boxes overlap) in 32-bit fixed point, scaled so
+// that the sum of the boxes' largest cell magnitudes maps to 2^30: no bin can
+// overflow.  Then the flat overflow gin, if any block of that step used it
+// (*flag_in); gin is cleared where read.  gv must hold zeros on entry.  acc:
+// LDS of at least 3 * PT_VOX ints.  Every thread of the block must call this.
+__device__ __forceinline__ void pull_staged(const float* stage_in, const int* desc_in,
+                                            const int* flag_in, gfloat* __restrict__ gin, int local,
+                                            const PTile& tc, int D, int H, int W,
+                                            const int (&vz)[VPT], const int (&vy)[VPT],
+                                            const int (&vx)[VPT], const bool (&vok)[VPT],
+                                            float (&gv)[VPT][3], int* acc) {
+  const int V = D * H * W;
+  __shared__ __align__(16) int nbd[27][12];
+  __shared__ int pre[28];
+  __shared__ float nbm[27];
+  __shared__ float nbmax;
+  int* gacc = acc;  // [3][PT_VOX]
+  const int ntz = (D + PT_Z - 1) / PT_Z, nty = (H + PT_Y - 1) / PT_Y, ntx = (W + PT_X - 1) / PT_X;
+  const int tz = tc.z0 / PT_Z, ty = tc.y0 / PT_Y, tx = tc.x0 / PT_X;
+  const cgfloat* __restrict__ st = gp(stage_in);
+  // own box, straight into registers
+  {
+    const int* dsc = desc_in + local * 8;
+    const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
+    if (ez > 0) {
+      const cgfloat* __restrict__ sl = st + (size_t)local * 3 * STAGE_CAP;
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        if (!vok[j]) continue;
+        const int idx = ((vz[j] - bz) * ey + (vy[j] - by)) * ex + (vx[j] - bx);
+        gv[j][0] = sl[idx];
+        gv[j][1] = sl[STAGE_CAP + idx];
+        gv[j][2] = sl[2 * STAGE_CAP + idx];
+      }
+    }
+  }
+  if (threadIdx.x < 27) {
+    const int d = threadIdx.x;
+    const int nz = tz + d / 9 - 1, ny = ty + (d / 3) % 3 - 1, nx = tx + d % 3 - 1;
+    int n = 0;
+    float bm = 0.f;
+    int* e = nbd[d];
+    if (d != 13 && nz >= 0 && nz < ntz && ny >= 0 && ny < nty && nx >= 0 && nx < ntx) {
+      const int nb = (nz * nty + ny) * ntx + nx;
+      const int* dsc = desc_in + nb * 8;
+      const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
+      // intersection with this tile, in global coordinates
+      const int z0 = max(bz, tc.z0), z1 = min(bz + ez, min(tc.z0 + PT_Z, D));
+      const int y0 = max(by, tc.y0), y1 = min(by + ey, min(tc.y0 + PT_Y, H));
+      const int x0 = max(bx, tc.x0), x1 = min(bx + ex, min(tc.x0 + PT_X, W));
+      if (ez > 0 && z1 > z0 && y1 > y0 && x1 > x0) {
+        const int nyx = (y1 - y0) * (x1 - x0);
+        n = (z1 - z0) * nyx;
+        bm = __int_as_float(dsc[6]);
+        e[0] = nyx;
+        e[1] = x1 - x0;
+        e[2] = ((z0 - bz) * ey + (y0 - by)) * ex + (x0 - bx);
+        e[3] = ey * ex;
+        e[4] = ex;
+        e[5] = ((z0 - tc.z0) * PT_Y + (y0 - tc.y0)) * PT_X + (x0 - tc.x0);
+        e[6] = nb;
+        e[7] = __float_as_int(1.f / (float)nyx);
+        e[8] = __float_as_int(1.f / (float)(x1 - x0));
+      }
+    }
+    e[11] = n;
+    nbm[d] = bm;
+  }
+  for (int i = threadIdx.x; i < 3 * PT_VOX; i += BLOCK) gacc[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    float m = 0.f;
+    for (int d = 0; d < 27; ++d) {
+      pre[d] = t;
+      t += nbd[d][11];
+      m += nbm[d];
+    }
+    pre[27] = t;
+    nbmax = m;
+  }
+  __syncthreads();
+  const int total = pre[27];
+  const float qscale = nbmax > 0.f ? 1073741824.0f / nbmax : 0.f;  // 2^30 / sum of maxima
+  const float qinv = nbmax / 1073741824.0f;
+  constexpr int U = 4;
+  for (int w0 = threadIdx.x; w0 < total; w0 += BLOCK * U) {
+    float v0[U], v1[U], v2[U];
+    int loc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int w = w0 + u * BLOCK;
+      loc[u] = -1;
+      if (w < total) {
+        int d = 0;  // the last d with pre[d] <= w: the non-empty entry holding w
+#pragma unroll
+        for (int step = 16; step > 0; step >>= 1)
+          if (d + step < 27 && pre[d + step] <= w) d += step;
+        const int* e = nbd[d];
+        const int r = w - pre[d];
+        // (iz, iy, ix) of cell r of the overlap; the float quotients are
+        // exact here (r < 1024, the overlap lies in one tile)
+        const int nyx = e[0], nx = e[1];
+        const int iz = (int)(((float)r + 0.5f) * __int_as_float(e[7]));
+        const int rr = r - iz * nyx;
+        const int iy = (int)(((float)rr + 0.5f) * __int_as_float(e[8]));
+        const int ix = rr - iy * nx;
+        const int idx = e[2] + iz * e[3] + iy * e[4] + ix;
+        const cgfloat* __restrict__ sl = st + (size_t)e[6] * 3 * STAGE_CAP;
+        v0[u] = sl[idx];
+        v1[u] = sl[STAGE_CAP + idx];
+        v2[u] = sl[2 * STAGE_CAP + idx];
+        loc[u] = e[5] + (iz * PT_Y + iy) * PT_X + ix;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (loc[u] < 0) continue;
+      atomicAdd(&gacc[loc[u]], (int)(v0[u] * qscale));
+      atomicAdd(&gacc[PT_VOX + loc[u]], (int)(v1[u] * qscale));
+      atomicAdd(&gacc[2 * PT_VOX + loc[u]], (int)(v2[u] * qscale));
+    }
+  }
+  __syncthreads();
+  const bool flat = *flag_in != 0;
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vok[j]) continue;
+    const int k = threadIdx.x + j * BLOCK;
+    gv[j][0] += (float)gacc[k] * qinv;
+    gv[j][1] += (float)gacc[PT_VOX + k] * qinv;
+    gv[j][2] += (float)gacc[2 * PT_VOX + k] * qinv;
+    if (flat) {
+      const int p = (vz[j] * H + vy[j]) * W + vx[j];
+      gv[j][0] += gin[p];
+      gv[j][1] += gin[V + p];
+      gv[j][2] += gin[2 * V + p];
+      gin[p] = 0.f;
+      gin[V + p] = 0.f;
+      gin[2 * V + p] = 0.f;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Exp backward: one squaring, dL/du_s from dL/du_{s+1}
 //   G_s(p) = G(p) + J_u(q)^T G(p) + sum_{p': corners of q(p') contain p} w G(p')
 // ---------------------------------------------------------------------------
 // MODE: 0 flat G_{s+1} in, flat G_s out; 1 flat in, staged out; 2 staged
-// in, staged out; 3 staged in, flat out (see ExpBwdItem).
+// in, staged out; 3 staged in, flat out (see ExpBwdItem).  A staged G_0 is
+// turned into a flat field by k_unstage.
 template <int MODE>
 __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict__ items,
                                                    int n_items, int n_tiles) {
@@ -669,147 +818,9 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     gv[j][0] = gv[j][1] = gv[j][2] = 0.f;
   }
   if (IN_ST) {
-    // G_{s+1} over this tile from the staged boxes of the previous step.  The
-    // tile's own box (which holds every owned voxel) is read straight into
-    // registers.  The parts of the 26 neighbours' boxes that reach into the
-    // tile form one list of cells, which the block reads with all its loads in
-    // flight and adds into LDS bins (neighbouring boxes overlap) in 32-bit
-    // fixed point, scaled so that the sum of the boxes' largest cell
-    // magnitudes maps to 2^30: no bin can overflow.  Then the flat overflow,
-    // if any block of the previous step used it.
-    // per neighbour d: nyx, nx, index in its box of the overlap's first
-    // cell, the box's z and y strides, the tile-local index of that cell,
-    // the neighbour's tile, 1 / nyx and 1 / nx (float bits); [11] = cells
-    __shared__ __align__(16) int nbd[27][12];
-    __shared__ int pre[28];
-    __shared__ float nbm[27];
-    __shared__ float nbmax;
-    int* gacc = acc;  // [3][PT_VOX], before the scatter reuses acc
-    const int ntz = (D + PT_Z - 1) / PT_Z, nty = (H + PT_Y - 1) / PT_Y, ntx = (W + PT_X - 1) / PT_X;
-    const int tz = tc.z0 / PT_Z, ty = tc.y0 / PT_Y, tx = tc.x0 / PT_X;
-    const cgfloat* __restrict__ st = gp(it.stage_in);
-    // own box, straight into registers
-    {
-      const int* dsc = it.desc_in + local * 8;
-      const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
-      if (ez > 0) {
-        const cgfloat* __restrict__ sl = st + (size_t)local * 3 * STAGE_CAP;
-#pragma unroll
-        for (int j = 0; j < VPT; ++j) {
-          if (!vok[j]) continue;
-          const int idx = ((vz[j] - bz) * ey + (vy[j] - by)) * ex + (vx[j] - bx);
-          gv[j][0] = sl[idx];
-          gv[j][1] = sl[STAGE_CAP + idx];
-          gv[j][2] = sl[2 * STAGE_CAP + idx];
-        }
-      }
-    }
-    if (threadIdx.x < 27) {
-      const int d = threadIdx.x;
-      const int nz = tz + d / 9 - 1, ny = ty + (d / 3) % 3 - 1, nx = tx + d % 3 - 1;
-      int n = 0;
-      float bm = 0.f;
-      int* e = nbd[d];
-      if (d != 13 && nz >= 0 && nz < ntz && ny >= 0 && ny < nty && nx >= 0 && nx < ntx) {
-        const int nb = (nz * nty + ny) * ntx + nx;
-        const int* dsc = it.desc_in + nb * 8;
-        const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
-        // intersection with this tile, in global coordinates
-        const int z0 = max(bz, tc.z0), z1 = min(bz + ez, min(tc.z0 + PT_Z, D));
-        const int y0 = max(by, tc.y0), y1 = min(by + ey, min(tc.y0 + PT_Y, H));
-        const int x0 = max(bx, tc.x0), x1 = min(bx + ex, min(tc.x0 + PT_X, W));
-        if (ez > 0 && z1 > z0 && y1 > y0 && x1 > x0) {
-          const int nyx = (y1 - y0) * (x1 - x0);
-          n = (z1 - z0) * nyx;
-          bm = __int_as_float(dsc[6]);
-          e[0] = nyx;
-          e[1] = x1 - x0;
-          e[2] = ((z0 - bz) * ey + (y0 - by)) * ex + (x0 - bx);
-          e[3] = ey * ex;
-          e[4] = ex;
-          e[5] = ((z0 - tc.z0) * PT_Y + (y0 - tc.y0)) * PT_X + (x0 - tc.x0);
-          e[6] = nb;
-          e[7] = __float_as_int(1.f / (float)nyx);
-          e[8] = __float_as_int(1.f / (float)(x1 - x0));
-        }
-      }
-      e[11] = n;
-      nbm[d] = bm;
-    }
-    for (int i = threadIdx.x; i < 3 * PT_VOX; i += BLOCK) gacc[i] = 0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int t = 0;
-      float m = 0.f;
-      for (int d = 0; d < 27; ++d) {
-        pre[d] = t;
-        t += nbd[d][11];
-        m += nbm[d];
-      }
-      pre[27] = t;
-      nbmax = m;
-    }
-    __syncthreads();
-    const int total = pre[27];
-    const float qscale = nbmax > 0.f ? 1073741824.0f / nbmax : 0.f;  // 2^30 / sum of maxima
-    const float qinv = nbmax / 1073741824.0f;
-    constexpr int U = 4;
-    for (int w0 = threadIdx.x; w0 < total; w0 += BLOCK * U) {
-      float v0[U], v1[U], v2[U];
-      int loc[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int w = w0 + u * BLOCK;
-        loc[u] = -1;
-        if (w < total) {
-          int d = 0;  // the last d with pre[d] <= w: the non-empty entry holding w
-#pragma unroll
-          for (int step = 16; step > 0; step >>= 1)
-            if (d + step < 27 && pre[d + step] <= w) d += step;
-          const int* e = nbd[d];
-          const int r = w - pre[d];
-          // (iz, iy, ix) of cell r of the overlap; the float quotients are
-          // exact here (r < 1024, the overlap lies in one tile)
-          const int nyx = e[0], nx = e[1];
-          const int iz = (int)(((float)r + 0.5f) * __int_as_float(e[7]));
-          const int rr = r - iz * nyx;
-          const int iy = (int)(((float)rr + 0.5f) * __int_as_float(e[8]));
-          const int ix = rr - iy * nx;
-          const int idx = e[2] + iz * e[3] + iy * e[4] + ix;
-          const cgfloat* __restrict__ sl = st + (size_t)e[6] * 3 * STAGE_CAP;
-          v0[u] = sl[idx];
-          v1[u] = sl[STAGE_CAP + idx];
-          v2[u] = sl[2 * STAGE_CAP + idx];
-          loc[u] = e[5] + (iz * PT_Y + iy) * PT_X + ix;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (loc[u] < 0) continue;
-        atomicAdd(&gacc[loc[u]], (int)(v0[u] * qscale));
-        atomicAdd(&gacc[PT_VOX + loc[u]], (int)(v1[u] * qscale));
-        atomicAdd(&gacc[2 * PT_VOX + loc[u]], (int)(v2[u] * qscale));
-      }
-    }
-    __syncthreads();
-    const bool flat = *it.flag_in != 0;
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      if (!vok[j]) continue;
-      const int k = threadIdx.x + j * BLOCK;
-      gv[j][0] += (float)gacc[k] * qinv;
-      gv[j][1] += (float)gacc[PT_VOX + k] * qinv;
-      gv[j][2] += (float)gacc[2 * PT_VOX + k] * qinv;
-      if (flat) {
-        const int p = (vz[j] * H + vy[j]) * W + vx[j];
-        gv[j][0] += gin[p];
-        gv[j][1] += gin[V + p];
-        gv[j][2] += gin[2 * V + p];
-        gin[p] = 0.f;
-        gin[V + p] = 0.f;
-        gin[2 * V + p] = 0.f;
-      }
-    }
+    // G_{s+1} over this tile from the staged boxes of the previous step
+    pull_staged(it.stage_in, it.desc_in, it.flag_in, gin, local, tc, D, H, W, vz, vy, vx, vok, gv,
+                acc);
   } else {
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
@@ -915,6 +926,81 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   if (reg) {
     const double tot = block_sum(rval * (double)it.reg_loss_w + rext, red);
     if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Staged G_0 of the last backward squaring to the flat field gout: each
+// voxel gets the boxes that hold it plus the flat overflow, which is read
+// from gout itself before it is overwritten.  Plain stores, no atomics.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_unstage(const ExpBwdItem* __restrict__ items,
+                                                   int n_items, int n_tiles) {
+  __shared__ __align__(16) int acc[3 * PT_VOX];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const ExpBwdItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
+  const int local = tile - it.tile0;
+  const PTile tc = point_tile(local, H, W);
+  gfloat* __restrict__ g = gp(it.gout);
+  float gv[VPT][3];
+  int vz[VPT], vy[VPT], vx[VPT];
+  bool vok[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int k = threadIdx.x + j * BLOCK;
+    vx[j] = tc.x0 + (k % PT_X);
+    vy[j] = tc.y0 + (k / PT_X) % PT_Y;
+    vz[j] = tc.z0 + k / (PT_X * PT_Y);
+    vok[j] = vx[j] < W && vy[j] < H && vz[j] < D;
+    gv[j][0] = gv[j][1] = gv[j][2] = 0.f;
+  }
+  pull_staged(it.stage_in, it.desc_in, it.flag_in, g, local, tc, D, H, W, vz, vy, vx, vok, gv, acc);
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vok[j]) continue;
+    const int p = (vz[j] * H + vy[j]) * W + vx[j];
+    g[p] = gv[j][0];
+    g[V + p] = gv[j][1];
+    g[2 * V + p] = gv[j][2];
+  }
+}
+
+// The gradient of each SVF from the staged G_0 of its forward and backward
+// directions (PullItem), without a flat G_0 in between.
+__global__ __launch_bounds__(BLOCK) void k_pull_combine(const PullItem* __restrict__ items,
+                                                        int n_items, int n_tiles) {
+  __shared__ __align__(16) int acc[3 * PT_VOX];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const PullItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
+  const int local = tile - it.tile0;
+  const PTile tc = point_tile(local, H, W);
+  float gf[VPT][3], gb[VPT][3];
+  int vz[VPT], vy[VPT], vx[VPT];
+  bool vok[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int k = threadIdx.x + j * BLOCK;
+    vx[j] = tc.x0 + (k % PT_X);
+    vy[j] = tc.y0 + (k / PT_X) % PT_Y;
+    vz[j] = tc.z0 + k / (PT_X * PT_Y);
+    vok[j] = vx[j] < W && vy[j] < H && vz[j] < D;
+    gf[j][0] = gf[j][1] = gf[j][2] = 0.f;
+    gb[j][0] = gb[j][1] = gb[j][2] = 0.f;
+  }
+  pull_staged(it.stage[0], it.desc[0], it.flag[0], gp(it.gflat[0]), local, tc, D, H, W, vz, vy,
+              vx, vok, gf, acc);
+  __syncthreads();  // the first pull is done with acc
+  pull_staged(it.stage[1], it.desc[1], it.flag[1], gp(it.gflat[1]), local, tc, D, H, W, vz, vy,
+              vx, vok, gb, acc);
+  gfloat* __restrict__ out = gp(it.out);
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vok[j]) continue;
+    const int p = (vz[j] * H + vy[j]) * W + vx[j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * V + p] = it.scale * (gf[j][c] - gb[j][c]);
   }
 }
 
@@ -1853,6 +1939,18 @@ hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int
     case 3: hipLaunchKernelGGL(k_exp_bwd<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_unstage(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unstage, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_pull_combine(const PullItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pull_combine, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 

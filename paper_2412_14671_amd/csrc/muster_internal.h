@@ -217,6 +217,22 @@ struct AdamItem {
   JobState* js;
 };
 
+// The gradient of an SVF from the staged G_0 of its two directions:
+// out = scale * (G_0 forward - G_0 backward), over point tiles.  Each
+// direction's stage / desc / flag are those of its last backward squaring and
+// gflat its flat overflow (cleared where read).
+struct PullItem {
+  int tile0;
+  int D, H, W;
+  const float* stage[2];
+  const int* desc[2];
+  const int* flag[2];
+  float* gflat[2];
+  float* out;
+  float scale;
+  int pad;
+};
+
 // One separable pass of the circular Gaussian smoothing along one axis, for
 // one field of three components.  A tile holds whole lines of one component
 // in LDS: `lines` adjacent x columns of lines along z or y, or `lines`
@@ -288,6 +304,9 @@ hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles
 // 3 staged in / flat out
 hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int staged,
                           hipStream_t s);
+// A staged G_0 (stage_in, desc_in, flag_in of each item) to the flat gout.
+hipError_t launch_unstage(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_pull_combine(const PullItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
                               hipStream_t s);
 // M = I o (Omega + U) of each item, over point tiles of its grid.

@@ -539,7 +539,8 @@ namespace {
 
 // Algorithmic bytes per voxel (the unique bytes each step must move).
 constexpr double B_EXP_FWD = 24, B_COMPOSE_FWD = 36, B_SIM_STATS = 20, B_SIM_GRAD = 32,
-                 B_COMPOSE_BWD = 84, B_EXP_BWD = 60, B_ADAM = 96, B_SMOOTH = 24, B_WARP = 20;
+                 B_COMPOSE_BWD = 84, B_EXP_BWD = 60, B_ADAM = 96, B_SMOOTH = 24, B_WARP = 20,
+                 B_UNSTAGE = 24;
 
 struct Builder {
   Plan* plan;
@@ -940,7 +941,8 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
       if (s >= K) continue;
       const int* d = J->ldims[J->level];
       const float scale = std::ldexp(1.f, -K);
-      const bool in_st = J->staged() && s < K - 1, out_st = J->staged() && s > 0;
+      // a staged G_0 is read by k_pull_combine or k_unstage
+      const bool in_st = J->staged() && s < K - 1, out_st = J->staged();
       const int mode = in_st ? (out_st ? 2 : 3) : (out_st ? 1 : 0);
       for (int dir = 0; dir < 2 * (J->N - 1); ++dir) {
         const int i = dir / 2;
@@ -988,12 +990,61 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
     }
   }
   {
-    // gradients of smoothing jobs: combine into t1, then smooth t1 -> t2 -> t1 -> t2
+    // staged G_0: straight into the combined gradient t1 of smoothing jobs,
+    // else to the flat G_0 of each direction
+    std::vector<PullItem> pitems;
+    std::vector<ExpBwdItem> uitems;
+    int ptiles = 0, utiles = 0;
+    double pbytes = 0, ubytes = 0;
+    for (Job* J : jobs) {
+      if (!J->staged()) continue;
+      const int* d = J->ldims[J->level];
+      const int pt = point_tiles(d[0], d[1], d[2]);
+      for (int i = 0; i < J->N - 1; ++i) {
+        if (J->smoothing()) {
+          PullItem it{};
+          it.tile0 = ptiles;
+          it.D = d[0]; it.H = d[1]; it.W = d[2];
+          for (int k = 0; k < 2; ++k) {
+            const int dir = 2 * i + k;
+            it.stage[k] = J->stage(dir, 0);
+            it.desc[k] = J->desc(dir, 0);
+            it.flag[k] = J->flag(dir, 0);
+            it.gflat[k] = J->pp(dir, 0);
+          }
+          it.out = J->field(J->m_t1.as<float>(), i);
+          it.scale = std::ldexp(1.f, -J->K());
+          pitems.push_back(it);
+          ptiles += pt;
+          pbytes += 2 * B_UNSTAGE * J->Vc();
+        } else {
+          for (int k = 0; k < 2; ++k) {
+            const int dir = 2 * i + k;
+            ExpBwdItem it{};
+            it.tile0 = utiles;
+            it.D = d[0]; it.H = d[1]; it.W = d[2];
+            it.gout = J->pp(dir, 0);
+            it.stage_in = J->stage(dir, 0);
+            it.desc_in = J->desc(dir, 0);
+            it.flag_in = J->flag(dir, 0);
+            uitems.push_back(it);
+            utiles += pt;
+            ubytes += B_UNSTAGE * J->Vc();
+          }
+        }
+      }
+    }
+    b.add(ST_PULL_COMBINE, pitems, ptiles, pbytes);
+    b.add(ST_UNSTAGE, uitems, utiles, ubytes);
+  }
+  {
+    // gradients of smoothing jobs: combine into t1 (staged jobs did above),
+    // then smooth t1 -> t2 -> t1 -> t2
     std::vector<AdamItem> items;
     int tiles = 0;
     double bytes = 0;
     for (Job* J : jobs) {
-      if (!J->smoothing()) continue;
+      if (!J->smoothing() || J->staged()) continue;
       const size_t V = J->Vc();
       for (int i = 0; i < J->N - 1; ++i) {
         AdamItem it{};
@@ -1095,6 +1146,8 @@ static int kclass(StageKind k) {
     case ST_RIGID_GRAD: return MUSTER_K_RIGID;
     case ST_RIGID_STEP: return MUSTER_K_RIGID;
     case ST_WARP: return MUSTER_K_WARP;
+    case ST_UNSTAGE: return MUSTER_K_UNSTAGE;
+    case ST_PULL_COMBINE: return MUSTER_K_UNSTAGE;
   }
   return MUSTER_K_FINISH;
 }
@@ -1122,6 +1175,9 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
       return launch_rigid_grad((const RigidGradItem*)p, st.n_items, st.n_tiles, s);
     case ST_RIGID_STEP: return launch_rigid_step((const RigidStepItem*)p, st.n_items, s);
     case ST_WARP: return launch_warp((const SimItem*)p, st.n_items, st.n_tiles, s);
+    case ST_UNSTAGE: return launch_unstage((const ExpBwdItem*)p, st.n_items, st.n_tiles, s);
+    case ST_PULL_COMBINE:
+      return launch_pull_combine((const PullItem*)p, st.n_items, st.n_tiles, s);
   }
   return hipErrorInvalidValue;
 }
@@ -2411,7 +2467,7 @@ const char* muster_kernel_name(int k) {
   static const char* names[MUSTER_K_COUNT] = {"exp_fwd", "compose_fwd", "sim_stats", "sim_grad",
                                               "compose_bwd", "exp_bwd", "adam", "finish",
                                               "pool2", "upsample2", "smooth", "upsample2_adj",
-                                              "rigid", "warp"};
+                                              "rigid", "warp", "unstage"};
   if (k < 0 || k >= MUSTER_K_COUNT) return "";
   return names[k];
 }

@@ -196,7 +196,8 @@ void load_tune_cache(Ctx* ctx);
 // A launch plan: one iteration (or a forward pass) of a set of jobs.
 enum StageKind {
   ST_EXP_FWD, ST_COMPOSE_FWD, ST_SIM_STATS, ST_SIM_GRAD, ST_COMPOSE_BWD, ST_EXP_BWD, ST_ADAM,
-  ST_FINISH, ST_SMOOTH, ST_UPSAMPLE, ST_UPSAMPLE_ADJ, ST_RIGID_GRAD, ST_RIGID_STEP, ST_WARP
+  ST_FINISH, ST_SMOOTH, ST_UPSAMPLE, ST_UPSAMPLE_ADJ, ST_RIGID_GRAD, ST_RIGID_STEP, ST_WARP,
+  ST_UNSTAGE, ST_PULL_COMBINE
 };
 
 struct Stage {
