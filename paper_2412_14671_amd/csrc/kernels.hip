@@ -856,18 +856,16 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
     const int base = (az.i0 * H + ay.i0) * W + ax.i0;
     const float g0 = gv[j][0], g1 = gv[j][1], g2 = gv[j][2];
-    // (J^T g) of the Jacobian J of src at q: rows c, each times g_c; the
-    // factor a and the clamped axes apply per column
-    float v0[8], v1[8], v2[8], dz, dy, dx;
+    // (J^T g) of the Jacobian J of src at q is the gradient of the
+    // interpolant of sum_c g_c src_c: combine the corners first, then one
+    // gradient; the factor a and the clamped axes apply per column
+    float v0[8], v1[8], v2[8], jz, jy, jx;
     load8(s, base, W, HW, v0);
     load8(s + V, base, W, HW, v1);
     load8(s + 2 * V, base, W, HW, v2);
-    tri_grad(v0, az.t, ay.t, ax.t, dz, dy, dx);
-    float jz = dz * g0, jy = dy * g0, jx = dx * g0;
-    tri_grad(v1, az.t, ay.t, ax.t, dz, dy, dx);
-    jz = fmaf(dz, g1, jz); jy = fmaf(dy, g1, jy); jx = fmaf(dx, g1, jx);
-    tri_grad(v2, az.t, ay.t, ax.t, dz, dy, dx);
-    jz = fmaf(dz, g2, jz); jy = fmaf(dy, g2, jy); jx = fmaf(dx, g2, jx);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v0[k] = fmaf(g2, v2[k], fmaf(g1, v1[k], g0 * v0[k]));
+    tri_grad(v0, az.t, ay.t, ax.t, jz, jy, jx);
     float own0 = fmaf(a * az.live, jz, g0);
     float own1 = fmaf(a * ay.live, jy, g1);
     float own2 = fmaf(a * ax.live, jx, g2);
