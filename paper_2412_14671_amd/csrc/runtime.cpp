@@ -1182,44 +1182,46 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
   return hipErrorInvalidValue;
 }
 
-// Event pairs of timed launches, resolved at the next synchronisation.
-struct TimedLaunch {
-  hipEvent_t a, b;
-  int k;
-  double bytes;
-};
-static std::mutex g_timing_mu;
-static std::vector<TimedLaunch> g_pending;
-
 static void resolve_timing(Ctx* ctx) {
-  std::lock_guard<std::mutex> lk(g_timing_mu);
-  for (auto& t : g_pending) {
+  std::lock_guard<std::mutex> lk(ctx->timing_mu);
+  for (auto& t : ctx->pending) {
     float ms = 0.f;
     if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
       ctx->stats.launches[t.k] += 1;
       ctx->stats.ms[t.k] += ms;
       ctx->stats.bytes[t.k] += t.bytes;
     }
-    (void)hipEventDestroy(t.a);
-    (void)hipEventDestroy(t.b);
+    ctx->event_pool.push_back(t.a);
+    ctx->event_pool.push_back(t.b);
   }
-  g_pending.clear();
+  ctx->pending.clear();
+}
+
+static hipEvent_t pooled_event(Ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  MUSTER_HIP(hipEventCreate(&e));
+  return e;
 }
 
 void Plan::run(Ctx* ctx, hipStream_t s) {
   const unsigned char* base = dev.as<unsigned char>();
   for (const Stage& st : stages) {
     if (ctx->timing) {
+      std::lock_guard<std::mutex> lk(ctx->timing_mu);
       TimedLaunch t{};
       t.k = kclass(st.kind);
       t.bytes = st.bytes;
-      MUSTER_HIP(hipEventCreate(&t.a));
-      MUSTER_HIP(hipEventCreate(&t.b));
+      t.a = pooled_event(ctx);
+      t.b = pooled_event(ctx);
       MUSTER_HIP(hipEventRecord(t.a, s));
       MUSTER_HIP(launch_stage(st, base, s));
       MUSTER_HIP(hipEventRecord(t.b, s));
-      std::lock_guard<std::mutex> lk(g_timing_mu);
-      g_pending.push_back(t);
+      ctx->pending.push_back(t);
     } else {
       MUSTER_HIP(launch_stage(st, base, s));
     }
@@ -1741,6 +1743,11 @@ muster_status muster_ctx_destroy(muster_ctx* h) {
   }
   if (c->step_items) c->arena.release(c->step_items);
   if (c->step_acc) c->arena.release(c->step_acc);
+  for (auto& t : c->pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   delete c;
   delete h;
   return MUSTER_OK;

@@ -70,6 +70,13 @@ struct SimTile {
   int zc = 32;
 };
 
+// Event pair of one timed launch, resolved at the next synchronisation.
+struct TimedLaunch {
+  hipEvent_t a, b;
+  int k;
+  double bytes;
+};
+
 struct Ctx {
   int device = 0;
   Arena arena;
@@ -77,6 +84,11 @@ struct Ctx {
   bool poisoned = false;
   bool timing = false;
   KernelStats stats;
+  // timed launches not yet resolved, and created events kept for reuse (an
+  // event pair per launch would otherwise be created and destroyed each time)
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::mutex timing_mu;
   std::mutex mu;                     // serialises API calls that use ws
   void* step_items = nullptr;        // device buffer for single-step item tables
   size_t step_items_bytes = 0;
