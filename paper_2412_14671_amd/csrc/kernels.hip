@@ -16,6 +16,7 @@
 // block-to-tile map: blocks are dealt round-robin over the 8 XCDs, and the
 // map hands each XCD a contiguous run of tiles so the neighbouring rows that
 // the gathers touch stay in that XCD's L2.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <climits>
 #include <cmath>
@@ -1915,15 +1916,34 @@ __global__ void k_fill(float* p, int64_t n, float v) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// Optional start / stop events of the next launches on this thread (the
+// runtime's kernel timing): recorded by the launch packet itself, so a timed
+// launch costs one API call and the events bracket the kernel alone.
+static thread_local hipEvent_t t_launch_start = nullptr, t_launch_stop = nullptr;
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_launch_start = start;
+  t_launch_stop = stop;
+}
+
+#define MUSTER_LAUNCH(kernel, grid, block, shm, stream, ...)                                  \
+  do {                                                                                         \
+    if (t_launch_start)                                                                        \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, t_launch_start, t_launch_stop, 0, \
+                            __VA_ARGS__);                                                      \
+    else                                                                                       \
+      hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                      \
+  } while (0)
+
 hipError_t launch_exp_fwd(const ExpFwdItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_exp_fwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_exp_fwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compose_fwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_compose_fwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
@@ -1931,10 +1951,10 @@ hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int
                           hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   switch (staged) {
-    case 0: hipLaunchKernelGGL(k_exp_bwd<0>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
-    case 1: hipLaunchKernelGGL(k_exp_bwd<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
-    case 2: hipLaunchKernelGGL(k_exp_bwd<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
-    case 3: hipLaunchKernelGGL(k_exp_bwd<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 0: MUSTER_LAUNCH(k_exp_bwd<0>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 1: MUSTER_LAUNCH(k_exp_bwd<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 2: MUSTER_LAUNCH(k_exp_bwd<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 3: MUSTER_LAUNCH(k_exp_bwd<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1942,20 +1962,20 @@ hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int
 
 hipError_t launch_unstage(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unstage, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_unstage, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_pull_combine(const PullItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pull_combine, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_pull_combine, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
                               hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compose_bwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_compose_bwd, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
@@ -1963,10 +1983,10 @@ template <int R, int TY, int TX>
 static void sim_launch(bool grad, const SimItem* items, int n_items, int n_tiles, int metric,
                        hipStream_t s) {
   if (grad)
-    hipLaunchKernelGGL((k_sim_grad<R, TY, TX>), dim3(n_tiles), dim3(TY * TX), 0, s, items, n_items,
+    MUSTER_LAUNCH((k_sim_grad<R, TY, TX>), dim3(n_tiles), dim3(TY * TX), 0, s, items, n_items,
                        n_tiles);
   else
-    hipLaunchKernelGGL((k_sim_stats<R, TY, TX>), dim3(n_tiles), dim3(TY * TX), 0, s, items,
+    MUSTER_LAUNCH((k_sim_stats<R, TY, TX>), dim3(n_tiles), dim3(TY * TX), 0, s, items,
                        n_items, n_tiles, metric);
 }
 
@@ -1995,7 +2015,7 @@ static hipError_t sim_window(bool grad, const SimItem* items, int n_items, int n
 
 hipError_t launch_warp(const SimItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_warp, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_warp, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
@@ -2011,7 +2031,7 @@ hipError_t launch_sim_grad(const SimItem* items, int n_items, int n_tiles, int w
 
 hipError_t launch_adam(const AdamItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adam, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_adam, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
@@ -2019,7 +2039,7 @@ hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, int 
                          hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   if (lds_floats <= 0 || lds_floats > SMOOTH_LDS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_smooth, dim3(n_tiles), dim3(BLOCK), lds_floats * sizeof(float), s, items,
+  MUSTER_LAUNCH(k_smooth, dim3(n_tiles), dim3(BLOCK), lds_floats * sizeof(float), s, items,
                      n_items, n_tiles);
   return hipGetLastError();
 }
@@ -2039,7 +2059,7 @@ __global__ void k_pattern(float* __restrict__ p, int64_t n, int D, int H, int W,
 hipError_t launch_pattern(float* p, int64_t n, const int dims[3], float off, float amp,
                           float phase, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pattern, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, dims[0],
+  MUSTER_LAUNCH(k_pattern, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, dims[0],
                      dims[1], dims[2], off, amp, phase);
   return hipGetLastError();
 }
@@ -2072,20 +2092,20 @@ hipError_t launch_reg_ext(GridDims d, const float* f, const float* fprev, float 
   const int V = d.D * d.H * d.W;
   if (V <= 0) return hipSuccess;
   const int blocks = ceil_div(V, BLOCK) < 2048 ? ceil_div(V, BLOCK) : 2048;
-  hipLaunchKernelGGL(k_reg_ext, dim3(blocks), dim3(BLOCK), 0, s, d, f, fprev, l2w, tsw, inv_dp,
+  MUSTER_LAUNCH(k_reg_ext, dim3(blocks), dim3(BLOCK), 0, s, d, f, fprev, l2w, tsw, inv_dp,
                      inv_ds, out);
   return hipGetLastError();
 }
 
 hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finish, dim3(ceil_div(n_jobs, 64)), dim3(64), 0, s, states, n_jobs);
+  MUSTER_LAUNCH(k_finish, dim3(ceil_div(n_jobs, 64)), dim3(64), 0, s, states, n_jobs);
   return hipGetLastError();
 }
 
 hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pool2, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_pool2, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
@@ -2170,7 +2190,7 @@ hipError_t launch_jacobian_det(GridDims d, const float* U, float* out, hipStream
   const int V = d.D * d.H * d.W;
   if (V <= 0) return hipSuccess;
   const int blocks = ceil_div(V, BLOCK) < 4096 ? ceil_div(V, BLOCK) : 4096;
-  hipLaunchKernelGGL(k_jacobian_det, dim3(blocks), dim3(BLOCK), 0, s, d, U, out);
+  MUSTER_LAUNCH(k_jacobian_det, dim3(blocks), dim3(BLOCK), 0, s, d, U, out);
   return hipGetLastError();
 }
 
@@ -2178,7 +2198,7 @@ hipError_t launch_field_stats(int V, const float* a, const float* b, const unsig
                               double* out, hipStream_t s) {
   if (V <= 0) return hipSuccess;
   const int blocks = ceil_div(V, BLOCK) < 1024 ? ceil_div(V, BLOCK) : 1024;
-  hipLaunchKernelGGL(k_field_stats, dim3(blocks), dim3(BLOCK), 0, s, V, a, b, roi, out);
+  MUSTER_LAUNCH(k_field_stats, dim3(blocks), dim3(BLOCK), 0, s, V, a, b, roi, out);
   return hipGetLastError();
 }
 
@@ -2294,13 +2314,13 @@ __global__ __launch_bounds__(BLOCK) void k_add_rigid(GridDims d, float* __restri
 
 hipError_t launch_rigid_grad(const RigidGradItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rigid_grad, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_rigid_grad, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_rigid_step(const RigidStepItem* items, int n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rigid_step, dim3(ceil_div(n_items, 64)), dim3(64), 0, s, items, n_items);
+  MUSTER_LAUNCH(k_rigid_step, dim3(ceil_div(n_items, 64)), dim3(64), 0, s, items, n_items);
   return hipGetLastError();
 }
 
@@ -2308,19 +2328,19 @@ hipError_t launch_add_rigid(GridDims d, float* field, const RigidState* rg, hipS
   const int V = d.D * d.H * d.W;
   if (V <= 0) return hipSuccess;
   const int blocks = ceil_div(V, BLOCK) < 2048 ? ceil_div(V, BLOCK) : 2048;
-  hipLaunchKernelGGL(k_add_rigid, dim3(blocks), dim3(BLOCK), 0, s, d, field, rg);
+  MUSTER_LAUNCH(k_add_rigid, dim3(blocks), dim3(BLOCK), 0, s, d, field, rg);
   return hipGetLastError();
 }
 
 hipError_t launch_upsample2_adj(const UpItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_upsample2_adj, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_upsample2_adj, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_upsample2(const UpItem* items, int n_items, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_upsample2, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_upsample2, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 
@@ -2332,14 +2352,14 @@ hipError_t launch_adam_flat(int64_t n, float* x, const float* g, float* m, float
   const float step_size = (float)(lr / bc1);
   const float bc2s = (float)std::sqrt(bc2);
   const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-  hipLaunchKernelGGL(k_adam_flat, dim3((unsigned)blocks), dim3(BLOCK), 0, s, n, x, g, m, v,
+  MUSTER_LAUNCH(k_adam_flat, dim3((unsigned)blocks), dim3(BLOCK), 0, s, n, x, g, m, v,
                      step_size, bc2s, b1, b2, eps);
   return hipGetLastError();
 }
 
 hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hipStream_t s) {
   const int V = d.D * d.H * d.W;
-  hipLaunchKernelGGL(k_reg, dim3(ceil_div(V, BLOCK)), dim3(BLOCK), 0, s, d.D, d.H, d.W, phi, out,
+  MUSTER_LAUNCH(k_reg, dim3(ceil_div(V, BLOCK)), dim3(BLOCK), 0, s, d.D, d.H, d.W, phi, out,
                      grad);
   return hipGetLastError();
 }
@@ -2347,7 +2367,7 @@ hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hi
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(BLOCK), 0, s, p, n, v);
+  MUSTER_LAUNCH(k_fill, dim3((unsigned)blocks), dim3(BLOCK), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -298,6 +298,9 @@ inline int stat_tiles(int D, int H, int W, int zc, int shape) {
 }
 
 // Launchers (kernels.hip).  All return hipError_t of the launch.
+// Start and stop events for every following launch on this thread (null:
+// untimed).  Each plan stage is one launch.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 hipError_t launch_exp_fwd(const ExpFwdItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles, hipStream_t s);
 // staged: 0 flat in / flat out, 1 flat in / staged out, 2 staged in / staged out,

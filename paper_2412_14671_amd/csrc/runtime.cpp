@@ -1218,9 +1218,10 @@ void Plan::run(Ctx* ctx, hipStream_t s) {
       t.bytes = st.bytes;
       t.a = pooled_event(ctx);
       t.b = pooled_event(ctx);
-      MUSTER_HIP(hipEventRecord(t.a, s));
-      MUSTER_HIP(launch_stage(st, base, s));
-      MUSTER_HIP(hipEventRecord(t.b, s));
+      set_launch_events(t.a, t.b);
+      const hipError_t e = launch_stage(st, base, s);
+      set_launch_events(nullptr, nullptr);
+      MUSTER_HIP(e);
       ctx->pending.push_back(t);
     } else {
       MUSTER_HIP(launch_stage(st, base, s));

@@ -346,3 +346,33 @@ def test_rigid_adjustment_recovers_a_translation(ctx):
     # the returned pair field (0, 1) is the total deformation: about -offset
     tot = pairs[0].cpu().numpy().reshape(3, -1).mean(axis=1)
     assert np.abs(tot + np.array([0.8, -0.6, 1.1])).max() < 0.15
+
+
+def test_kernel_timing_counts_every_launch(ctx):
+    """Kernel timing (the events the bench reads its roofline from) sees every
+    launch of the eager path: K Exp-backward launches and one finish per Adam
+    step, positive durations, and a total below the wall time of the run."""
+    import time
+    from paper_2412_14671_amd import MusterParams, synth
+    s = synth.phantom_series((24, 28, 32), 3, seed=5)
+    imgs = s.images.to(DEV)
+    params = MusterParams(iters=[4], K=5, window=3, metric="silncc", use_graph=False)
+    ctx.register(imgs, s.times, params)
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(True)
+    ctx.kernel_stats_reset()
+    try:
+        t0 = time.perf_counter()
+        ctx.register(imgs, s.times, params)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3
+    finally:
+        ctx.set_kernel_timing(False)
+    st = ctx.kernel_stats()
+    log("timed kernels: " + ", ".join(f"{k} {v['launches']}x {v['ms']:.3f} ms"
+                                      for k, v in st.items() if v["launches"]))
+    assert st["exp_bwd"]["launches"] == 4 * 5
+    assert st["finish"]["launches"] == 4
+    assert st["sim_stats"]["launches"] == 4 and st["sim_grad"]["launches"] == 4
+    assert all(v["ms"] > 0 for v in st.values() if v["launches"])
+    assert 0 < sum(v["ms"] for v in st.values()) < wall_ms
