@@ -1784,26 +1784,52 @@ __global__ __launch_bounds__(BLOCK) void k_pool2(const PoolItem* __restrict__ it
   }
 }
 
+// A block stages the coarse cells behind a tile of UF_TZ x UF_TY x UF_TX fine
+// voxels (t/2 + 2 per axis, three components, coordinates clamped to the
+// grid) in LDS; every fine voxel then reads its 8 corners from there.
 __global__ __launch_bounds__(BLOCK) void k_upsample2(const UpItem* __restrict__ items, int n_items,
                                                      int n_tiles) {
-  const int tile = blockIdx.x;
+  constexpr int CZ = UF_TZ / 2 + 2, CY = UF_TY / 2 + 2, CX = UF_TX / 2 + 2, CN = CZ * CY * CX;
+  constexpr int PER = UF_TZ * UF_TY * UF_TX / BLOCK;
+  static_assert(UF_TY * UF_TX == BLOCK, "one fine slice of the tile per thread pass");
+  __shared__ float cs[3 * CN];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
   const UpItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
   const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W;
   const int n = D2 * H2 * W2;
-  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
-  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
-    const int q = q0 + k;
-    if (q >= n) break;
-    const int x = q % W2, y = (q / W2) % H2, z = q / (W2 * H2);
-    const Ax az = axis_pos(((float)z - 0.5f) * 0.5f, D), ay = axis_pos(((float)y - 0.5f) * 0.5f, H),
-             ax = axis_pos(((float)x - 0.5f) * 0.5f, W);
-    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
-    float v[8];
+  const int local = tile - it.tile0;
+  const int ntx = (W2 + UF_TX - 1) / UF_TX, nty = (H2 + UF_TY - 1) / UF_TY;
+  const int fx0 = (local % ntx) * UF_TX, fy0 = ((local / ntx) % nty) * UF_TY,
+            fz0 = (local / ntx / nty) * UF_TZ;
+  // first staged coarse cell per axis: the floor cell of the tile's first
+  // fine sample, (f0 - 0.5) / 2 = f0 / 2 - 0.25
+  const int cz0 = fz0 / 2 - 1, cy0 = fy0 / 2 - 1, cx0 = fx0 / 2 - 1;
+  const cgfloat* __restrict__ src = gp(it.src);
+  for (int i = threadIdx.x; i < 3 * CN; i += BLOCK) {
+    const int c = i / CN, r = i - c * CN;
+    const int lz = r / (CY * CX), r2 = r - lz * (CY * CX), ly = r2 / CX, lx = r2 - ly * CX;
+    const int z = min(max(cz0 + lz, 0), D - 1), y = min(max(cy0 + ly, 0), H - 1),
+              x = min(max(cx0 + lx, 0), W - 1);
+    cs[i] = src[c * V + (z * H + y) * W + x];
+  }
+  __syncthreads();
+  const int fy = fy0 + threadIdx.x / UF_TX, fx = fx0 + threadIdx.x % UF_TX;
+  const Ax ay = axis_pos(((float)fy - 0.5f) * 0.5f, H), ax = axis_pos(((float)fx - 0.5f) * 0.5f, W);
+  gfloat* __restrict__ dst = gp(it.dst);
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int fz = fz0 + j;
+    if (fz >= D2 || fy >= H2 || fx >= W2) continue;
+    const Ax az = axis_pos(((float)fz - 0.5f) * 0.5f, D);
+    const int base = ((az.i0 - cz0) * CY + (ay.i0 - cy0)) * CX + (ax.i0 - cx0);
+    const int q = (fz * H2 + fy) * W2 + fx;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      load8(gp(it.src) + c * V, base, W, HW, v);
-      it.dst[c * n + q] = 2.f * tri_val(v, az.t, ay.t, ax.t);
+      const float* p = cs + c * CN + base;
+      const float v[8] = {p[0], p[1], p[CX], p[CX + 1],
+                          p[CY * CX], p[CY * CX + 1], p[CY * CX + CX], p[CY * CX + CX + 1]};
+      dst[c * n + q] = 2.f * tri_val(v, az.t, ay.t, ax.t);
     }
   }
 }
@@ -1818,53 +1844,93 @@ __device__ __forceinline__ float up_weight(int f, int c, int n) {
   return c == a.i0 ? 1.f - a.t : (c == a.i0 + 1 ? a.t : 0.f);
 }
 
+// The weights are separable, so a block stages the fine region behind a tile
+// of UA_TZ x UA_TY x UA_TX coarse voxels (2t + 2 fine samples per axis) in
+// LDS, one component at a time, and sums along x, then y, then z, with the
+// 4 weights per coarse index of each axis computed once per block: every fine
+// sample is read from HBM once and the 64-tap gather becomes 3 x 4 taps.
 __global__ __launch_bounds__(BLOCK) void k_upsample2_adj(const UpItem* __restrict__ items,
                                                          int n_items, int n_tiles) {
-  const int tile = blockIdx.x;
+  constexpr int FZ = 2 * UA_TZ + 2, FY = 2 * UA_TY + 2, FX = 2 * UA_TX + 2;
+  constexpr int FN = FZ * FY * FX;           // fine region; later the y sums
+  constexpr int S1 = FZ * FY * UA_TX;        // x sums
+  constexpr int S2 = FZ * UA_TY * UA_TX;     // y sums
+  constexpr int TN = UA_TZ * UA_TY * UA_TX;  // outputs
+  static_assert(S2 <= FN, "the y sums reuse the fine region");
+  __shared__ float fine[FN];
+  __shared__ float s1[S1];
+  __shared__ float wz[UA_TZ][4], wy[UA_TY][4], wx[UA_TX][4];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
   const UpItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, V = D * H * W;
-  const int H2 = 2 * H, W2 = 2 * W, n2 = 8 * V;
+  const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W, n2 = 8 * V;
+  const int local = tile - it.tile0;
+  const int ntx = (W + UA_TX - 1) / UA_TX, nty = (H + UA_TY - 1) / UA_TY;
+  const int cx0 = (local % ntx) * UA_TX, cy0 = ((local / ntx) % nty) * UA_TY,
+            cz0 = (local / ntx / nty) * UA_TZ;
+  // fine index of the first staged sample along each axis: 2 c0 - 1
+  const int fz0 = 2 * cz0 - 1, fy0 = 2 * cy0 - 1, fx0 = 2 * cx0 - 1;
+  // w[o][k]: weight of fine 2(c0 + o) - 1 + k for coarse c0 + o (0 off the grid)
+  auto weight = [](int f, int c, int n) { return (f >= 0 && f < 2 * n) ? up_weight(f, c, n) : 0.f; };
+  for (int i = threadIdx.x; i < (UA_TZ + UA_TY + UA_TX) * 4; i += BLOCK) {
+    const int o = i / 4, k = i % 4;
+    if (o < UA_TZ) {
+      wz[o][k] = weight(fz0 + 2 * o + k, cz0 + o, D);
+    } else if (o < UA_TZ + UA_TY) {
+      const int q = o - UA_TZ;
+      wy[q][k] = weight(fy0 + 2 * q + k, cy0 + q, H);
+    } else {
+      const int q = o - UA_TZ - UA_TY;
+      wx[q][k] = weight(fx0 + 2 * q + k, cx0 + q, W);
+    }
+  }
   const cgfloat* __restrict__ g = gp(it.src);
   gfloat* __restrict__ out = gp(it.dst);
-  const int q0 = (tile - it.tile0) * ELEM_PER_BLOCK;
-  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
-    const int q = q0 + k;
-    if (q >= V) break;
-    const int x = q % W, y = (q / W) % H, z = q / (W * H);
-    float wz[4], wy[4], wx[4];
-    int fz[4], fy[4], fx[4];
+  for (int c = 0; c < 3; ++c) {
+    // UL loads in flight per thread before they land in LDS
+    constexpr int UL = 8;
+    for (int i0 = threadIdx.x; i0 < FN; i0 += BLOCK * UL) {
+      float v[UL];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      fz[t] = 2 * z - 1 + t;
-      fy[t] = 2 * y - 1 + t;
-      fx[t] = 2 * x - 1 + t;
-      wz[t] = (fz[t] >= 0 && fz[t] < 2 * D) ? up_weight(fz[t], z, D) : 0.f;
-      wy[t] = (fy[t] >= 0 && fy[t] < H2) ? up_weight(fy[t], y, H) : 0.f;
-      wx[t] = (fx[t] >= 0 && fx[t] < W2) ? up_weight(fx[t], x, W) : 0.f;
-    }
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (wz[i] == 0.f) continue;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (wy[j] == 0.f) continue;
-        const float wzy = wz[i] * wy[j];
-        const int row = (fz[i] * H2 + fy[j]) * W2;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          if (wx[l] == 0.f) continue;
-          const float w = wzy * wx[l];
-          const int p = row + fx[l];
-          a0 = fmaf(w, g[p], a0);
-          a1 = fmaf(w, g[n2 + p], a1);
-          a2 = fmaf(w, g[2 * n2 + p], a2);
-        }
+      for (int u = 0; u < UL; ++u) {
+        const int i = i0 + u * BLOCK;
+        const int lz = i / (FY * FX), r = i - lz * (FY * FX), ly = r / FX, lx = r - ly * FX;
+        const int fz = fz0 + lz, fy = fy0 + ly, fx = fx0 + lx;
+        const bool in = i < FN && fz >= 0 && fz < D2 && fy >= 0 && fy < H2 && fx >= 0 && fx < W2;
+        v[u] = in ? g[c * n2 + (fz * H2 + fy) * W2 + fx] : 0.f;
       }
+#pragma unroll
+      for (int u = 0; u < UL; ++u)
+        if (i0 + u * BLOCK < FN) fine[i0 + u * BLOCK] = v[u];
     }
-    out[q] = 2.f * a0;
-    out[V + q] = 2.f * a1;
-    out[2 * V + q] = 2.f * a2;
+    __syncthreads();
+    for (int i = threadIdx.x; i < S1; i += BLOCK) {
+      const int row = i / UA_TX, ox = i - row * UA_TX;
+      const float* f = fine + row * FX + 2 * ox;
+      s1[i] = fmaf(wx[ox][3], f[3], fmaf(wx[ox][2], f[2], fmaf(wx[ox][1], f[1], wx[ox][0] * f[0])));
+    }
+    __syncthreads();
+    float* s2 = fine;
+    for (int i = threadIdx.x; i < S2; i += BLOCK) {
+      const int lz = i / (UA_TY * UA_TX), r = i - lz * (UA_TY * UA_TX);
+      const int oy = r / UA_TX, ox = r - oy * UA_TX;
+      const float* f = s1 + (lz * FY + 2 * oy) * UA_TX + ox;
+      s2[i] = fmaf(wy[oy][3], f[3 * UA_TX],
+                   fmaf(wy[oy][2], f[2 * UA_TX], fmaf(wy[oy][1], f[UA_TX], wy[oy][0] * f[0])));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TN; i += BLOCK) {
+      const int oz = i / (UA_TY * UA_TX), r = i - oz * (UA_TY * UA_TX);
+      const int oy = r / UA_TX, ox = r - oy * UA_TX;
+      const int z = cz0 + oz, y = cy0 + oy, x = cx0 + ox;
+      if (z >= D || y >= H || x >= W) continue;
+      const float* f = s2 + (2 * oz) * (UA_TY * UA_TX) + oy * UA_TX + ox;
+      constexpr int SZ = UA_TY * UA_TX;
+      const float v = fmaf(wz[oz][3], f[3 * SZ],
+                           fmaf(wz[oz][2], f[2 * SZ], fmaf(wz[oz][1], f[SZ], wz[oz][0] * f[0])));
+      out[c * V + (z * H + y) * W + x] = 2.f * v;
+    }
+    __syncthreads();  // before the next component overwrites the fine region
   }
 }
 

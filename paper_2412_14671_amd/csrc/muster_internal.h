@@ -275,6 +275,20 @@ struct UpItem {
   float* dst;   // [3][2D][2H][2W]
 };
 
+// Tiles of the upsampling: UF_TZ x UF_TY x UF_TX fine voxels (D, H, W
+// coarse).
+constexpr int UF_TZ = 8, UF_TY = 8, UF_TX = 32;
+inline int up_tiles(int D, int H, int W) {
+  return ((2 * D + UF_TZ - 1) / UF_TZ) * ((2 * H + UF_TY - 1) / UF_TY) *
+         ((2 * W + UF_TX - 1) / UF_TX);
+}
+
+// Tiles of the upsampling adjoint: UA_TZ x UA_TY x UA_TX coarse voxels.
+constexpr int UA_TZ = 4, UA_TY = 8, UA_TX = 16;
+inline int up_adj_tiles(int D, int H, int W) {
+  return ((D + UA_TZ - 1) / UA_TZ) * ((H + UA_TY - 1) / UA_TY) * ((W + UA_TX - 1) / UA_TX);
+}
+
 // Tiles of the gather/scatter kernels.
 constexpr int PT_Z = 8, PT_Y = 8, PT_X = 16;   // 1024 voxels, 256 threads
 constexpr int PT_VOX = PT_Z * PT_Y * PT_X;

@@ -434,7 +434,7 @@ void job_begin_level(Job& J, int level, hipStream_t s) {
         it.src = J.phi + i * 3 * Vcoarse;
         it.dst = J.mbuf + i * 3 * V;
         items.push_back(it);
-        tiles += elem_tiles(V);
+        tiles += up_tiles(dc[0], dc[1], dc[2]);
       }
       run_items(ctx, items, tiles, s, launch_upsample2);
       std::swap(J.phi, J.mbuf);
@@ -496,7 +496,7 @@ void job_final_outputs(Job& J, hipStream_t s) {
         it.src = J.flow(i);
         it.dst = J.svf_out + (size_t)i * 3 * VI;
         items.push_back(it);
-        tiles += elem_tiles(VI);
+        tiles += up_tiles(it.D, it.H, it.W);
       }
       run_items(ctx, items, tiles, s, launch_upsample2);
     }
@@ -684,12 +684,12 @@ void add_pair_resampling(Builder& b, const std::vector<Job*>& jobs, bool adjoint
         if (adjoint) {
           it.src = J->pair_grad_img(i, j);
           it.dst = J->pair_grad(i, j);
-          tiles += elem_tiles(J->Vc());
+          tiles += up_adj_tiles(d[0], d[1], d[2]);
           bytes += B_UPSAMPLE_ADJ * J->Vc();
         } else {
           it.src = J->pair_field(i, j);
           it.dst = J->pair_img(i, j);
-          tiles += elem_tiles(J->VIc());
+          tiles += up_tiles(d[0], d[1], d[2]);
           bytes += B_UPSAMPLE * J->Vc();
         }
         items.push_back(it);
@@ -2312,8 +2312,8 @@ muster_status muster_upsample2(muster_ctx* h, void* stream, const int dims[3], c
     it.dst = dst;
     const size_t off = sc.add(it);
     sc.upload();
-    const size_t n = (size_t)dims[0] * dims[1] * dims[2] * 8;
-    MUSTER_HIP(launch_upsample2((const UpItem*)(sc.dev() + off), 1, elem_tiles(n), sc.s));
+    MUSTER_HIP(launch_upsample2((const UpItem*)(sc.dev() + off), 1,
+                                up_tiles(dims[0], dims[1], dims[2]), sc.s));
     MUSTER_HIP(hipStreamSynchronize(sc.s));
   });
 }
@@ -2333,8 +2333,8 @@ muster_status muster_upsample2_adjoint(muster_ctx* h, void* stream, const int di
     it.dst = dst;
     const size_t off = sc.add(it);
     sc.upload();
-    const size_t V = (size_t)dims[0] * dims[1] * dims[2];
-    MUSTER_HIP(launch_upsample2_adj((const UpItem*)(sc.dev() + off), 1, elem_tiles(V), sc.s));
+    MUSTER_HIP(launch_upsample2_adj((const UpItem*)(sc.dev() + off), 1,
+                                    up_adj_tiles(dims[0], dims[1], dims[2]), sc.s));
     MUSTER_HIP(hipStreamSynchronize(sc.s));
   });
 }
