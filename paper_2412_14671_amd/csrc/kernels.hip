@@ -647,8 +647,13 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
                                             const int (&vx)[VPT], const bool (&vok)[VPT],
                                             float (&gv)[VPT][3], int* acc) {
   const int V = D * H * W;
+  // per neighbour d: nyx, nx, (unused), the box's z and y strides, the
+  // tile-local index of the overlap's first cell, the staging element of
+  // that cell (64 bits: [6] low, [10] high), 1 / nyx and 1 / nx (float
+  // bits); [11] = cells.  pre[d]: first list position of d; pre[27] = total,
+  // and the padding above it never compares below a position.
   __shared__ __align__(16) int nbd[27][12];
-  __shared__ int pre[28];
+  __shared__ int pre[32];
   __shared__ float nbm[27];
   __shared__ float nbmax;
   int* gacc = acc;  // [3][PT_VOX]
@@ -689,13 +694,15 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
         const int nyx = (y1 - y0) * (x1 - x0);
         n = (z1 - z0) * nyx;
         bm = __int_as_float(dsc[6]);
+        const long long first = (long long)nb * 3 * STAGE_CAP +
+                                ((z0 - bz) * ey + (y0 - by)) * ex + (x0 - bx);
         e[0] = nyx;
         e[1] = x1 - x0;
-        e[2] = ((z0 - bz) * ey + (y0 - by)) * ex + (x0 - bx);
         e[3] = ey * ex;
         e[4] = ex;
         e[5] = ((z0 - tc.z0) * PT_Y + (y0 - tc.y0)) * PT_X + (x0 - tc.x0);
-        e[6] = nb;
+        e[6] = (int)(unsigned)(first & 0xffffffffLL);
+        e[10] = (int)(first >> 32);
         e[7] = __float_as_int(1.f / (float)nyx);
         e[8] = __float_as_int(1.f / (float)(x1 - x0));
       }
@@ -714,6 +721,7 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
       m += nbm[d];
     }
     pre[27] = t;
+    pre[28] = pre[29] = pre[30] = pre[31] = INT_MAX;
     nbmax = m;
   }
   __syncthreads();
@@ -729,10 +737,12 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
       const int w = w0 + u * BLOCK;
       loc[u] = -1;
       if (w < total) {
-        int d = 0;  // the last d with pre[d] <= w: the non-empty entry holding w
+        // the last d with pre[d] <= w: the non-empty entry holding w (the
+        // search stays below 31, and pre above 27 is never <= w)
+        int d = 0;
 #pragma unroll
         for (int step = 16; step > 0; step >>= 1)
-          if (d + step < 27 && pre[d + step] <= w) d += step;
+          d = pre[d + step] <= w ? d + step : d;
         const int* e = nbd[d];
         const int r = w - pre[d];
         // (iz, iy, ix) of cell r of the overlap; the float quotients are
@@ -742,11 +752,12 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
         const int rr = r - iz * nyx;
         const int iy = (int)(((float)rr + 0.5f) * __int_as_float(e[8]));
         const int ix = rr - iy * nx;
-        const int idx = e[2] + iz * e[3] + iy * e[4] + ix;
-        const cgfloat* __restrict__ sl = st + (size_t)e[6] * 3 * STAGE_CAP;
-        v0[u] = sl[idx];
-        v1[u] = sl[STAGE_CAP + idx];
-        v2[u] = sl[2 * STAGE_CAP + idx];
+        const long long first =
+            ((long long)e[10] << 32) | (long long)(unsigned)e[6];
+        const cgfloat* __restrict__ sl = st + first + (iz * e[3] + iy * e[4] + ix);
+        v0[u] = sl[0];
+        v1[u] = sl[STAGE_CAP];
+        v2[u] = sl[2 * STAGE_CAP];
         loc[u] = e[5] + (iz * PT_Y + iy) * PT_X + ix;
       }
     }
