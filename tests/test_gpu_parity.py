@@ -375,7 +375,7 @@ def test_large_displacements_take_the_overflow_path_and_match_oracle(ctx):
 # Flow grid twice as coarse as the images (Sec. 2.7 stage geometry)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape", [(5, 6, 7), (16, 12, 20), (2, 9, 33)])
+@pytest.mark.parametrize("shape", [(5, 6, 7), (16, 12, 20), (2, 9, 33), (21, 26, 40)])
 def test_upsample2_and_adjoint_match_oracle(ctx, shape):
     f = smooth_field(shape, 1.5, seed=sum(shape), sigma=1.0)
     g = smooth_field(tuple(2 * n for n in shape), 1.0, seed=sum(shape) + 1, sigma=1.0)
