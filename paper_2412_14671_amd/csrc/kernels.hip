@@ -1136,7 +1136,9 @@ __device__ __forceinline__ void box_x(const float* __restrict__ zs, float* __res
   const int n = Q * PY * NXS;
   for (int e = threadIdx.x; e < n; e += B::NT) {
     const int q = e / (PY * NXS), r = e - q * (PY * NXS);
-    const int seg = r / PY, row = r - seg * PY;
+    // segments fastest across lanes: with the odd row stride, the lanes of a
+    // half wave read and write distinct banks
+    const int row = r / NXS, seg = r - row * NXS;
     const float* s = zs + q * B::ZQ + row * B::PXS + seg * SX;
     float* d = xs + q * B::XQ + row * B::TXS + seg * SX;
     float v[SX + 2 * R];
