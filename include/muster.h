@@ -182,6 +182,14 @@ muster_status muster_ctx_set_tiling(muster_ctx* ctx, int mode, int shape, int zc
  * `stream`, if the mode is AUTOTUNE and it is not cached). */
 muster_status muster_ctx_sim_tiling(muster_ctx* ctx, void* stream, const int dims[3], int window,
                                     int metric, int* shape, int* zchunk);
+/* Device bytes the context's arena holds now (*in_use) and the most it has
+ * held (*peak) since the context was created or the mark was last reset;
+ * either pointer may be NULL.  reset_peak != 0 resets the mark to the bytes
+ * in use, after reading it.  Counts workspaces only (the caller's buffers
+ * are not the library's); used to compare the stored and recomputed
+ * squaring steps of the Exp adjoint. */
+muster_status muster_ctx_memory(muster_ctx* ctx, uint64_t* in_use, uint64_t* peak,
+                                int reset_peak);
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* muster_last_error(void);
 /* Library version string. */

@@ -103,6 +103,7 @@ SIGNATURES = {
                                    POINTER(c_double)]),
     "muster_smooth": (_ST, [_P, _P, DIMS, c_float, _P, _P]),
     "muster_ctx_set_tiling": (_ST, [_P, c_int, c_int, c_int]),
+    "muster_ctx_memory": (_ST, [_P, POINTER(c_uint64), POINTER(c_uint64), c_int]),
     "muster_ctx_sim_tiling": (_ST, [_P, _P, DIMS, c_int, c_int, POINTER(c_int), POINTER(c_int)]),
     "muster_set_kernel_timing": (_ST, [_P, c_int]),
     "muster_kernel_stats": (_ST, [_P, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),

@@ -295,6 +295,14 @@ class Context:
     def kernel_stats_reset(self):
         L.check(self.lib.muster_kernel_stats_reset(self.h))
 
+    # -- workspace memory ------------------------------------------------------------
+    def memory(self, reset_peak: bool = False) -> Dict[str, int]:
+        """Device bytes the library's arena holds now and at most since the
+        mark was last reset (then resets the mark if asked)."""
+        u, pk = c_uint64(), c_uint64()
+        L.check(self.lib.muster_ctx_memory(self.h, byref(u), byref(pk), 1 if reset_peak else 0))
+        return {"in_use": u.value, "peak": pk.value}
+
 
 def register(images: torch.Tensor, times=None, pairs=False, ctx: Optional[Context] = None,
              **params):
@@ -302,6 +310,45 @@ def register(images: torch.Tensor, times=None, pairs=False, ctx: Optional[Contex
     c = ctx or Context(images.device.index or 0)
     svf, pr, _ = c.register(images, times, MusterParams(**params), pairs=pairs)
     return svf, pr
+
+
+class _Saved:
+    """Owner of a muster_saved handle: freed by the backward pass, or when the
+    autograd graph holding it is dropped without one."""
+
+    def __init__(self, owner: "Context", handle):
+        self.owner, self.handle = owner, handle
+
+    def free(self):
+        # a context closed first has already let go of the job's memory
+        if self.handle is not None and self.handle.value and self.owner.h:
+            self.owner.lib.muster_saved_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        self.free()
+
+
+def _loss_forward(lib_ctx: "Context", svf_c, img_c, params: MusterParams, times):
+    loss = c_double()
+    saved = c_void_p()
+    p = params.to_c()
+    tarr = None
+    if times is not None:
+        tarr = (c_double * img_c.shape[0])(*[float(t) for t in times])
+    L.check(lib_ctx.lib.muster_loss_forward(lib_ctx.h, _stream(), img_c.shape[0],
+                                            _dims(img_c.shape[1:]), _ptr(img_c), tarr,
+                                            _ptr(svf_c), byref(p), byref(loss), byref(saved)))
+    return loss.value, _Saved(lib_ctx, saved)
+
+
+def loss_value(svf: torch.Tensor, images: torch.Tensor, params: MusterParams, lib_ctx: "Context",
+               times=None) -> float:
+    """L(phi) only (no state kept for a backward pass)."""
+    val, saved = _loss_forward(lib_ctx, svf.detach().contiguous(), images.detach().contiguous(),
+                               params, times)
+    saved.free()
+    return val
 
 
 class MusterLoss(torch.autograd.Function):
@@ -313,31 +360,26 @@ class MusterLoss(torch.autograd.Function):
     def forward(ctx, svf, images, params: MusterParams, lib_ctx: Context, times=None):
         svf_c = svf.detach().contiguous()
         img_c = images.detach().contiguous()
-        loss = c_double()
-        saved = c_void_p()
-        p = params.to_c()
-        tarr = None
-        if times is not None:
-            tarr = (c_double * img_c.shape[0])(*[float(t) for t in times])
-        L.check(lib_ctx.lib.muster_loss_forward(lib_ctx.h, _stream(), img_c.shape[0],
-                                                _dims(img_c.shape[1:]), _ptr(img_c), tarr,
-                                                _ptr(svf_c), byref(p), byref(loss), byref(saved)))
+        val, saved = _loss_forward(lib_ctx, svf_c, img_c, params, times)
+        if not ctx.needs_input_grad[0]:
+            saved.free()
         ctx.lib_ctx = lib_ctx
-        ctx.saved_handle = saved
+        ctx.saved = saved
         ctx.keep = (svf_c, img_c)
-        return torch.tensor(loss.value, dtype=torch.float64, device=svf.device)
+        return torch.tensor(val, dtype=torch.float64, device=svf.device)
 
     @staticmethod
     def backward(ctx, grad_out):
         lib = ctx.lib_ctx.lib
         svf_c, _ = ctx.keep
         g = torch.empty_like(svf_c)
+        if ctx.saved.handle is None:
+            raise RuntimeError("the saved state of this loss was already used or freed")
         try:
-            L.check(lib.muster_loss_backward(ctx.lib_ctx.h, _stream(), ctx.saved_handle,
+            L.check(lib.muster_loss_backward(ctx.lib_ctx.h, _stream(), ctx.saved.handle,
                                              float(grad_out), _ptr(g)))
         finally:
-            lib.muster_saved_free(ctx.saved_handle)
-            ctx.saved_handle = None
+            ctx.saved.free()
         return g, None, None, None, None
 
 

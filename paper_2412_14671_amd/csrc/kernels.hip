@@ -347,62 +347,6 @@ __device__ __forceinline__ void jt_cells(const cgfloat* __restrict__ f, float a,
   }
 }
 
-// ---------------------------------------------------------------------------
-// Exp forward: one squaring u' = u + u o (Omega + u)   (Alg. 1)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_exp_fwd(const ExpFwdItem* __restrict__ items,
-                                                   int n_items, int n_tiles) {
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
-  const ExpFwdItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
-  const PTile tc = point_tile(tile - it.tile0, H, W);
-  const float a = it.a;
-  const cgfloat* __restrict__ s = gp(it.src);
-  gfloat* __restrict__ d = gp(it.dst);
-  VoxSet vs;
-  vox_set(tc, D, H, W, vs);
-  float uu[VPT][3];
-  CellSet cs;
-  load_cells(s, a, D, H, W, vs, uu, cs);
-  float sm[VPT][3];
-  sample_cells(s, V, H, W, cs, sm);
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) {
-    if (!vs.ok[j]) continue;
-    d[vs.p[j]] = uu[j][0] + a * sm[j][0];
-    d[V + vs.p[j]] = uu[j][1] + a * sm[j][1];
-    d[2 * V + vs.p[j]] = uu[j][2] + a * sm[j][2];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Composition forward: out = prev + C o (Omega + prev)   (Eq. cum_deformation)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __restrict__ items,
-                                                       int n_items, int n_tiles) {
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
-  const ComposeItem it = items[find_item(items, n_items, tile)];
-  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
-  const PTile tc = point_tile(tile - it.tile0, H, W);
-  const cgfloat* __restrict__ pr = gp(it.prev);
-  const cgfloat* __restrict__ C = gp(it.C);
-  gfloat* __restrict__ o = gp(it.out);
-  VoxSet vs;
-  vox_set(tc, D, H, W, vs);
-  float uu[VPT][3];
-  CellSet cs;
-  load_cells(pr, 1.f, D, H, W, vs, uu, cs);
-  float sm[VPT][3];
-  sample_cells(C, V, H, W, cs, sm);
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) {
-    if (!vs.ok[j]) continue;
-    o[vs.p[j]] = uu[j][0] + sm[j][0];
-    o[V + vs.p[j]] = uu[j][1] + sm[j][1];
-    o[2 * V + vs.p[j]] = uu[j][2] + sm[j][2];
-  }
-}
-
 // Scatter of per-voxel cell contributions into a field through LDS bins.
 // Each thread holds up to VPT voxels: cell origin (cz, cy, cx), fractions,
 // the 3-vector to spread with the trilinear weights, and optionally an own
@@ -479,6 +423,130 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
   const long long c = (long long)sb.bb.ez * sb.bb.ey * sb.bb.ex;
   sb.bb.cells = c > (long long)INT_MAX ? INT_MAX : (int)c;
   return sb;
+}
+
+// ---------------------------------------------------------------------------
+// Gathers from a box staged in LDS.  The block reduces the bounding box of
+// the cells its voxels sample (the reduction of the scatters), loads that box
+// of the three component planes into LDS with coalesced loads, and reads the
+// 8 corners of each cell there.  A few wide row loads per cell then replace
+// the scattered corner loads of every voxel, which otherwise keep the L1 and
+// texture path saturated.  The values and the arithmetic are those of
+// sample_cells, so the result is bit-identical; a box larger than
+// GATHER_CELLS falls back to sample_cells.  box: LDS of 3 * GATHER_CELLS
+// floats.  Every thread of the block must call this.
+// ---------------------------------------------------------------------------
+constexpr int GATHER_CELLS = SCATTER_CELLS;
+
+__device__ __forceinline__ void sample_cells_lds(const cgfloat* __restrict__ f, int V, int H, int W,
+                                                 const VoxSet& vs, const CellSet& cs,
+                                                 float* __restrict__ box, int* sred,
+                                                 float (&out)[VPT][3]) {
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
+  int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vs.ok[j]) continue;
+    lo[0] = min(lo[0], cs.az[j].i0); hi[0] = max(hi[0], cs.az[j].i0 + 1);
+    lo[1] = min(lo[1], cs.ay[j].i0); hi[1] = max(hi[1], cs.ay[j].i0 + 1);
+    lo[2] = min(lo[2], cs.ax[j].i0); hi[2] = max(hi[2], cs.ax[j].i0 + 1);
+  }
+  const BBox bb = scatter_box<BLOCK>(lo, hi, 0.f, sred).bb;
+  if (bb.cells == 0 || bb.cells > GATHER_CELLS) {  // block-uniform
+    sample_cells(f, V, H, W, cs, out);
+    return;
+  }
+  const int cells = bb.cells;
+  // cell i -> (lz, ly, lx) by float reciprocals: exact here since i < 2^22
+  const float inv_ex = 1.f / (float)bb.ex, inv_ey = 1.f / (float)bb.ey;
+  for (int i = threadIdx.x; i < cells; i += BLOCK) {
+    const int r = (int)(((float)i + 0.5f) * inv_ex);
+    const int lx = i - r * bb.ex;
+    const int lz = (int)(((float)r + 0.5f) * inv_ey);
+    const int ly = r - lz * bb.ey;
+    const int g = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
+    box[i] = f[g];
+    box[cells + i] = f[V + g];
+    box[2 * cells + i] = f[2 * V + g];
+  }
+  __syncthreads();
+  const int sy = bb.ex, sz = bb.ex * bb.ey;
+  int l[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j)
+    l[j] = vs.ok[j] ? ((cs.az[j].i0 - bb.lz) * bb.ey + (cs.ay[j].i0 - bb.ly)) * bb.ex +
+                          (cs.ax[j].i0 - bb.lx)
+                    : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float* __restrict__ b = box + c * cells;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const float* q = b + l[j];
+      const float v[8] = {q[0], q[1], q[sy], q[sy + 1], q[sz], q[sz + 1], q[sz + sy], q[sz + sy + 1]};
+      out[j][c] = tri_val(v, cs.az[j].t, cs.ay[j].t, cs.ax[j].t);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exp forward: one squaring u' = u + u o (Omega + u)   (Alg. 1)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_exp_fwd(const ExpFwdItem* __restrict__ items,
+                                                   int n_items, int n_tiles) {
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const ExpFwdItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
+  const PTile tc = point_tile(tile - it.tile0, H, W);
+  const float a = it.a;
+  const cgfloat* __restrict__ s = gp(it.src);
+  gfloat* __restrict__ d = gp(it.dst);
+  __shared__ float box[3 * GATHER_CELLS];
+  __shared__ int sred[8 * (BLOCK / 64)];
+  VoxSet vs;
+  vox_set(tc, D, H, W, vs);
+  float uu[VPT][3];
+  CellSet cs;
+  load_cells(s, a, D, H, W, vs, uu, cs);
+  float sm[VPT][3];
+  sample_cells_lds(s, V, H, W, vs, cs, box, sred, sm);
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vs.ok[j]) continue;
+    d[vs.p[j]] = uu[j][0] + a * sm[j][0];
+    d[V + vs.p[j]] = uu[j][1] + a * sm[j][1];
+    d[2 * V + vs.p[j]] = uu[j][2] + a * sm[j][2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Composition forward: out = prev + C o (Omega + prev)   (Eq. cum_deformation)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_compose_fwd(const ComposeItem* __restrict__ items,
+                                                       int n_items, int n_tiles) {
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const ComposeItem it = items[find_item(items, n_items, tile)];
+  const int D = it.D, H = it.H, W = it.W, V = D * H * W;
+  const PTile tc = point_tile(tile - it.tile0, H, W);
+  const cgfloat* __restrict__ pr = gp(it.prev);
+  const cgfloat* __restrict__ C = gp(it.C);
+  gfloat* __restrict__ o = gp(it.out);
+  __shared__ float box[3 * GATHER_CELLS];
+  __shared__ int sred[8 * (BLOCK / 64)];
+  VoxSet vs;
+  vox_set(tc, D, H, W, vs);
+  float uu[VPT][3];
+  CellSet cs;
+  load_cells(pr, 1.f, D, H, W, vs, uu, cs);
+  float sm[VPT][3];
+  sample_cells_lds(C, V, H, W, vs, cs, box, sred, sm);
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    if (!vs.ok[j]) continue;
+    o[vs.p[j]] = uu[j][0] + sm[j][0];
+    o[V + vs.p[j]] = uu[j][1] + sm[j][1];
+    o[2 * V + vs.p[j]] = uu[j][2] + sm[j][2];
+  }
 }
 
 // Staged output of a scatter: this tile's slot ([3][STAGE_CAP]) and

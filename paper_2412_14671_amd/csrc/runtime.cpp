@@ -78,6 +78,7 @@ void* Arena::try_alloc(size_t bytes) {
   }
   live_[p] = bytes;
   used_ += bytes;
+  peak_ = std::max(peak_, used_);
   return p;
 }
 
@@ -2437,6 +2438,16 @@ muster_status muster_ctx_sim_tiling(muster_ctx* h, void* stream, const int dims[
     const SimTile t = choose_sim_tile(ctx, dims, window, metric, (hipStream_t)stream);
     *shape = t.shape;
     *zchunk = t.zc;
+  });
+}
+
+muster_status muster_ctx_memory(muster_ctx* h, uint64_t* in_use, uint64_t* peak, int reset_peak) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx, "ctx is NULL");
+    if (in_use) *in_use = ctx->arena.used();
+    if (peak) *peak = ctx->arena.peak();
+    if (reset_peak) ctx->arena.reset_peak();
   });
 }
 

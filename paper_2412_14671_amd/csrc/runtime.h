@@ -46,12 +46,19 @@ class Arena {
   void release(void* p);
   uint64_t used() const { return used_; }
   uint64_t budget() const { return budget_; }
+  // Largest used() since the context was made or the mark was last reset.
+  uint64_t peak() const { return peak_; }
+  void reset_peak() {
+    std::lock_guard<std::mutex> lk(mu_);
+    peak_ = used_;
+  }
   bool fits(uint64_t bytes) const { return budget_ == 0 || used_ + bytes <= budget_; }
 
  private:
   std::mutex mu_;
   uint64_t budget_;
   uint64_t used_ = 0;
+  uint64_t peak_ = 0;
   std::map<void*, size_t> live_;
 };
 
