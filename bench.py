@@ -55,6 +55,9 @@ def parse():
                                                      "exp_bwd_phantom6_160x192x160_traffic.txt"),
                     help="JSON summary of rocprofv3 FETCH_SIZE/WRITE_SIZE passes for the dominant "
                          "kernel (per grid size); used only if it matches the current kernels")
+    ap.add_argument("--l2hit", default=os.path.join(ROOT, "profiles",
+                                                    "l2_hit_phantom6_160x192x160.txt"),
+                    help="committed L2 hit-rate summary (TCC_HIT / TCC_MISS per kernel and grid)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter calibration)")
     ap.add_argument("--shape", default="160,192,160")
@@ -253,6 +256,30 @@ def traffic_per_launch(path, kernel, launch_grids):
     return round(tot / n) if n else None
 
 
+def l2_hit_per_launch(path, kernel, launch_grids):
+    """L2 hit rate of `kernel` from the committed TCC_HIT / TCC_MISS summary,
+    over the timed launch mix ({grid in blocks: launches}); None if the
+    summary is absent or predates the current kernels."""
+    import hashlib
+    if not path or not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2412_14671_amd", "csrc", "kernels.hip")
+    if t.get("kernels_hip_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    per = t.get("kernels", {}).get(kernel)
+    if per is None:
+        return None
+    hit = miss = 0.0
+    for grid, launches in launch_grids.items():
+        e = per.get(str(grid))
+        if e is None:
+            return None
+        hit += launches * e["hit"]
+        miss += launches * e["miss"]
+    return round(hit / (hit + miss), 4) if hit + miss > 0 else None
+
+
 def roofline_from_stats(stats, traffic=None):
     best = max(stats.items(), key=lambda kv: kv[1]["ms"])
     name, st = best
@@ -352,6 +379,8 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
         grids[g] = grids.get(g, 0) + 7 * iters[l] * args.steps
     traffic = {"exp_bwd": traffic_per_launch(args.traffic, "exp_bwd", grids)}
     kname, roof = roofline_from_stats(stats, traffic)
+    if roof is not None:
+        roof["l2_hit_rate"] = l2_hit_per_launch(args.l2hit, "k_" + kname, grids)
     out = {
         "metric": "voxel-iterations/sec (fwd+bwd)",
         "value": round(float(value), 1),

@@ -401,6 +401,56 @@ def test_T13_gradient_matches_finite_differences_sampled(w, K, metric, N, seed):
     assert abs((Lp - Lm) / (2 * hh) - dd) < 1e-5 * abs(dd) + 1e-8
 
 
+# Central differences of the FP64 loss on the 64^3 series.  A difference
+# whose interval [-h, h] crosses a cell face of the trilinear interpolant (a
+# kink of the loss) is off by up to about 0.6 % of max |g| at h = 1e-3; at
+# h = 1e-4 such crossings are rare (none of the 256 LNCC triples, one of the
+# 64 SiLNCC ones) and the other differences agree with the adjoint to 5e-5 of
+# max |g|.  Bounds: at h = 1e-4, every triple but the largest-error 2 % (at
+# least one) within FD4_TOL max |g|; at h = 1e-3, max |g - fd| below 2 % of
+# max |g| and the relative L2 error below 4 %.
+FD4_TOL = 2e-4
+FD3_MAX, FD3_REL = 2e-2, 4e-2
+
+
+def fd_check(an, fd, gmax, h, extra=0.0):
+    """Bounds of the 64^3 differences at step h (a string key of the stored
+    file); extra widens them by a parity tolerance (fractions of max |g|)."""
+    err = np.sort(np.abs(an - fd))
+    if h == "0.0001":
+        keep = len(err) - max(1, len(err) // 50)
+        return bool(err[keep - 1] < (FD4_TOL + extra) * gmax)
+    return bool(err[-1] < (FD3_MAX + extra) * gmax and
+                np.linalg.norm(an - fd) < (FD3_REL + extra) * np.linalg.norm(fd))
+
+
+@pytest.mark.parametrize("metric", ["lncc", "silncc"])
+def test_T13_gradient_at_64cubed_matches_stored_finite_differences(metric):
+    """The oracle's adjoint on the 64^3 gradient-check series (four phantom
+    sessions, K 6, window 7) against central differences of its own FP64 loss
+    at random triples away from the border, stored by
+    tests/golden/make_config3_fd.py."""
+    import json
+    import os
+    from paper_2412_14671_amd import synth
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config3_fd.json")) as f:
+        gold = json.load(f)
+    s = synth.config3()
+    imgs = [x.numpy().astype(np.float64) for x in s.images]
+    phis = [x.astype(np.float64) for x in (0.5 * s.svf_true).numpy().astype(np.float32)]
+    p = O.Params(K=gold["K"], window=gold["window"], alpha_ss=gold["alpha_ss"],
+                 metric=O.LNCC if metric == "lncc" else O.SILNCC)
+    L, grads, _ = O.loss_and_grad(phis, imgs, p)
+    g = np.stack(grads)
+    assert abs(L - gold[metric]["loss"]) <= 1e-12 * abs(L)
+    tr = [tuple(t) for t in gold[metric]["triples"]]
+    an = np.array([g[t] for t in tr])
+    gmax = np.abs(g).max()
+    assert set(gold[metric]["fd"]) == {"0.0001", "0.001"}
+    for h, fd in gold[metric]["fd"].items():
+        assert fd_check(an, np.array(fd), gmax, h), h
+
+
 # --------------------------------------------------------------------------
 # Optimiser (Sec. 2.7)
 # --------------------------------------------------------------------------
