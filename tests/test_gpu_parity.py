@@ -432,3 +432,36 @@ def test_field_metrics_match_oracle(ctx, with_roi):
     assert abs(eu_ - O.euclidean_error(A, B, roi)) < 1e-9
     assert abs(pcc_ - O.pcc(A, B, roi)) < 1e-9
     assert abs(sl_ - O.slope(A, B, roi)) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Ownership of the autograd Function's saved state
+# ---------------------------------------------------------------------------
+
+def test_loss_state_is_freed(ctx):
+    """loss_value keeps no state; an autograd forward whose input needs no
+    gradient frees its saved state at once; a backward frees it after use.
+    The context's arena returns to its size every time."""
+    from paper_2412_14671_amd import MusterLoss, MusterParams, loss_value
+    log("loss state ownership")
+    shape, N = (20, 22, 24), 3
+    imgs = gpu(np.stack([smooth_image(shape, seed=60 + k) for k in range(N)]))
+    phis = gpu(np.stack([smooth_field(shape, 1.0, seed=70 + k) for k in range(N - 1)]))
+    params = MusterParams(K=5, window=5, metric="lncc")
+    # warm-up: tiling and the context's own item buffers
+    svf = phis.clone().requires_grad_(True)
+    MusterLoss.apply(svf, imgs, params, ctx).backward()
+    torch.cuda.synchronize()
+    base = ctx.memory()["in_use"]
+    vals = [loss_value(phis, imgs, params, ctx) for _ in range(4)]
+    assert ctx.memory()["in_use"] == base
+    assert max(vals) - min(vals) <= 1e-12 * abs(vals[0])
+    L = MusterLoss.apply(phis, imgs, params, ctx)  # no gradient needed
+    assert ctx.memory()["in_use"] == base
+    assert abs(float(L) - vals[0]) <= 1e-12 * abs(vals[0])
+    svf = phis.clone().requires_grad_(True)
+    L = MusterLoss.apply(svf, imgs, params, ctx)
+    assert ctx.memory()["in_use"] > base  # the state the backward pass needs
+    L.backward()
+    assert ctx.memory()["in_use"] == base
+    assert ctx.memory()["peak"] >= base
