@@ -235,8 +235,10 @@ muster_status muster_register_batch(muster_ctx* ctx, void* stream, int n_jobs,
  * budget, then advances every resident job by one iteration per tick (one
  * batched launch sequence); jobs join and leave between ticks. */
 muster_status muster_server_start(muster_ctx* ctx, int max_queue);
-/* Submit a job (E_BUSY if the queue is full); the job's buffers must stay
- * valid until it is terminal.  *ticket identifies it. */
+/* Submit a job (E_BUSY if the queue is full, E_NOMEM if its footprint
+ * exceeds the context's whole budget, so that it could never be admitted);
+ * the job's buffers must stay valid until it is terminal.  *ticket
+ * identifies it. */
 muster_status muster_submit(muster_ctx* ctx, const muster_job* job, uint64_t* ticket);
 /* State of a job: 0 queued, 1 running, 2 done, 3 failed, 4 cancelled. */
 muster_status muster_poll(muster_ctx* ctx, uint64_t ticket, int* state);

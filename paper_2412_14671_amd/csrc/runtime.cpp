@@ -1851,8 +1851,9 @@ muster_status muster_submit(muster_ctx* h, const muster_job* job, uint64_t* tick
     validate_problem(job->N, job->dims, job->params, job->times_host);
     NEED(job->images_dev && job->svf_out_dev, "images and svf_out must not be NULL");
     const uint64_t fp = job_footprint(job->N, job->dims, job->params);
-    NEED(ctx->arena.budget() == 0 || fp <= ctx->arena.budget(),
-         "job footprint %llu exceeds the context budget", (unsigned long long)fp);
+    if (ctx->arena.budget() != 0 && fp > ctx->arena.budget())
+      fail(MUSTER_E_NOMEM, "job footprint %llu exceeds the context budget %llu",
+           (unsigned long long)fp, (unsigned long long)ctx->arena.budget());
     Server& sv = *ctx->server;
     std::lock_guard<std::mutex> lk(sv.mu);
     if ((int)sv.queue.size() >= sv.max_queue) fail(MUSTER_E_BUSY, "serving queue is full");

@@ -376,3 +376,55 @@ def test_kernel_timing_counts_every_launch(ctx):
     assert st["sim_stats"]["launches"] == 4 and st["sim_grad"]["launches"] == 4
     assert all(v["ms"] > 0 for v in st.values() if v["launches"])
     assert 0 < sum(v["ms"] for v in st.values()) < wall_ms
+
+
+def test_server_budget_queue_and_cancellation():
+    """Forced failures of the server: a job larger than the context's whole
+    budget is refused (E_NOMEM); with a budget for one job, a second job
+    waits in the queue and a third is refused while the queue is full
+    (E_BUSY); cancelling the queued and the running job ends both with
+    E_CANCELLED; the server then serves a new job normally."""
+    import time
+    from paper_2412_14671_amd import Context, MusterError, MusterParams, Server, synth
+    from paper_2412_14671_amd import _lib as L
+    small = synth.phantom_series((24, 24, 24), 3, seed=51)
+    big = synth.phantom_series((48, 48, 48), 4, seed=52)
+    long_p = MusterParams(iters=[4000], K=5, window=3, metric="silncc")
+    short_p = MusterParams(iters=[3], K=5, window=3, metric="silncc")
+    probe = Context(0)
+    fp = probe.footprint(3, (24, 24, 24), long_p)
+    probe.close()
+    c = Context(0, budget_bytes=int(1.6 * fp))  # room for one such job, not two
+    try:
+        c.set_tiling("default")  # no autotuning scratch inside the small budget
+        srv = Server(c, max_queue=1)
+        with pytest.raises(MusterError) as ei:
+            srv.submit(big.images.to(DEV), big.times, long_p)
+        assert "E_NOMEM" in str(ei.value)
+        img = small.images.to(DEV)
+        ta, _ = srv.submit(img, small.times, long_p)
+        t0 = time.time()
+        while srv.poll(ta) != 1:  # admitted and running
+            assert time.time() - t0 < 60, "job not admitted"
+            time.sleep(0.01)
+        tb, _ = srv.submit(img, small.times, long_p)
+        time.sleep(0.05)
+        assert srv.poll(tb) == 0  # no room for a second job: it waits
+        st = srv.stats()
+        assert st["resident"] == 1 and st["queued"] == 1
+        with pytest.raises(MusterError) as ei:
+            srv.submit(img, small.times, long_p)
+        assert "E_BUSY" in str(ei.value)
+        srv.cancel(tb)
+        srv.cancel(ta)
+        ra, rb = srv.wait(ta), srv.wait(tb)
+        assert ra["status"] == L.E_CANCELLED and rb["status"] == L.E_CANCELLED
+        assert ra["iterations"] < 4000
+        td, out = srv.submit(img, small.times, short_p)
+        rd = srv.wait(td)
+        assert rd["status"] == 0 and rd["iterations"] == 3
+        assert torch.isfinite(out).all()
+        st = srv.stats()
+        assert st["resident"] == 0 and st["queued"] == 0
+    finally:
+        c.close()
