@@ -226,17 +226,17 @@ def phantom_series(shape=(64, 64, 64), N=4, seed=2, sigma_v=6.0, amp=(0.5, 1.5),
 SIZES = ((96, 96, 96), (128, 128, 128), (160, 192, 160))
 
 
-def config1(device="cpu") -> Series:
+def blobs_3x32(device="cpu") -> Series:
     """One subject, three 32^3 sessions of 20 blobs, flowed for t = 1, 2."""
     return blobs_series((32, 32, 32), 3, seed=1, device=device)
 
 
-def config2(device="cpu", shape=(160, 192, 160)) -> Series:
+def phantoms_6x160x192x160(device="cpu", shape=(160, 192, 160)) -> Series:
     """One subject, six 160x192x160 phantom sessions."""
     return phantom_series(shape, 6, seed=2, device=device)
 
 
-def config3(device="cpu") -> Series:
+def phantoms_4x64(device="cpu") -> Series:
     """Four 64^3 phantom sessions (gradient check)."""
     return phantom_series((64, 64, 64), 4, seed=3, device=device)
 

@@ -1,4 +1,4 @@
-"""Writes tests/golden/config1_oracle.json: the FP64 oracle's end-to-end
+"""Writes tests/golden/blobs_3x32_oracle.json: the FP64 oracle's end-to-end
 registration of the 3-session 32^3 blob series (50 Adam steps, K 7, LNCC w5,
 alpha_ss 1, lr 0.1, one level) -- its loss trajectory and final Euclidean
 error against the generator's ground truth.  Calls only the oracle and the
@@ -17,7 +17,7 @@ from paper_2412_14671_amd import synth  # noqa: E402
 
 
 def main():
-    s = synth.config1()
+    s = synth.blobs_3x32()
     imgs = [x.numpy() for x in s.images]
     p = O.Params(K=7, window=5, metric=O.LNCC, alpha_ss=1.0, lr=0.1, iters=(50,))
     phis, U, hist = O.register(imgs, p)
@@ -27,7 +27,7 @@ def main():
     eu0 = float(np.mean([O.euclidean_error(true[k], np.zeros_like(phis[k]), roi) for k in range(2)]))
     out = {"workload": "3 sessions of 32^3 blobs, 50 steps, K7, LNCC w5, alpha_ss 1, lr 0.1",
            "loss": hist, "eu_final": eu, "eu_zero": eu0}
-    with open(os.path.join(HERE, "config1_oracle.json"), "w") as f:
+    with open(os.path.join(HERE, "blobs_3x32_oracle.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({"eu_final": eu, "eu_zero": eu0, "loss0": hist[0], "lossT": hist[-1]}))
 

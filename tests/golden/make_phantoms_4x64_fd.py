@@ -1,4 +1,4 @@
-"""Writes tests/golden/config3_fd.json: central finite differences of the
+"""Writes tests/golden/phantoms_4x64_fd.json: central finite differences of the
 FP64 oracle's loss on the 64^3 gradient-check series (four phantom sessions,
 K 6, window 7, alpha_ss 1), evaluated at half the ground-truth SVFs, at random
 (interval, component, voxel) triples at least r + 2 voxels from the border:
@@ -7,7 +7,7 @@ adds the differences of one step to the file.  Each difference takes two
 whole-volume oracle evaluations, so the triples are spread over a process
 pool.  Calls only the oracle and the seeded input generator.
 
-    python tests/golden/make_config3_fd.py [h] [workers]
+    python tests/golden/make_phantoms_4x64_fd.py [h] [workers]
 """
 import json
 import os
@@ -36,7 +36,7 @@ _imgs = _phis = None
 
 
 def problem():
-    s = synth.config3()
+    s = synth.phantoms_4x64()
     imgs = [x.numpy().astype(np.float64) for x in s.images]
     phis = [x.astype(np.float64) for x in (0.5 * s.svf_true).numpy().astype(np.float32)]
     return imgs, phis
@@ -75,7 +75,7 @@ def main():
     workers = int(sys.argv[2]) if len(sys.argv) > 2 else 8
     _imgs, _phis = problem()
     shape = _imgs[0].shape
-    path = os.path.join(HERE, "config3_fd.json")
+    path = os.path.join(HERE, "phantoms_4x64_fd.json")
     out = {"workload": "four 64^3 phantom sessions (seed 3), K 6, window 7, alpha_ss 1, "
                        "at half the ground-truth SVFs",
            "K": K, "window": W, "alpha_ss": 1.0}

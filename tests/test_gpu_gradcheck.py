@@ -7,8 +7,8 @@ the warp, the compositions, scaling and squaring and the window statistics
 
 * against central finite differences of the FP64 oracle's loss at 256
   random (interval, component, voxel) triples away from the border (64 for
-  SiLNCC), stored in tests/golden/config3_fd.json by
-  tests/golden/make_config3_fd.py, with h = 1e-4 and h = 1e-3, under the
+  SiLNCC), stored in tests/golden/phantoms_4x64_fd.json by
+  tests/golden/make_phantoms_4x64_fd.py, with h = 1e-4 and h = 1e-3, under the
   bounds of the oracle's own pin (a difference that crosses a cell face of
   the trilinear interpolant, a kink of the loss, is off by up to about 0.6 %
   of the largest entry at h = 1e-3; at h = 1e-4 such crossings are rare),
@@ -39,7 +39,7 @@ pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
 K, W = 6, 7
-with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config3_fd.json")) as _f:
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "phantoms_4x64_fd.json")) as _f:
     GOLDEN = json.load(_f)
 
 
@@ -59,7 +59,7 @@ def ctx():
 @pytest.fixture(scope="module")
 def series():
     from paper_2412_14671_amd import synth
-    s = synth.config3()
+    s = synth.phantoms_4x64()
     imgs = s.images.numpy()
     phis = (0.5 * s.svf_true).numpy().astype(np.float32)
     return imgs, phis

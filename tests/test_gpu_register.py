@@ -74,16 +74,16 @@ def test_first_solver_step_matches_oracle(ctx):
     assert np.abs(got[big] - want[big]).max() < 1e-3 * 0.05
 
 
-def test_config1_registration_matches_oracle_error(ctx):
+def test_blob_series_registration_matches_oracle_error(ctx):
     """The 50-step single-level run on the 32^3 blob series reaches the
     oracle's final registration error (trajectories differ by rounding only)."""
     from paper_2412_14671_amd import MusterParams, synth
-    gold = json.load(open(os.path.join(HERE, "golden", "config1_oracle.json")))
-    s = synth.config1()
+    gold = json.load(open(os.path.join(HERE, "golden", "blobs_3x32_oracle.json")))
+    s = synth.blobs_3x32()
     params = MusterParams(iters=[50], K=7, window=5, metric="lncc", alpha_ss=1.0, lr=0.1)
     svf, pairs, rep = ctx.register(s.images.to(DEV), s.times, params, pairs=True)
     e = eu(s.svf_true.numpy(), svf.cpu().numpy(), s.roi.numpy())
-    log(f"config1: Eu {e:.4f} (oracle {gold['eu_final']:.4f}, zero {gold['eu_zero']:.4f})")
+    log(f"3x32^3 blobs: Eu {e:.4f} (oracle {gold['eu_final']:.4f}, zero {gold['eu_zero']:.4f})")
     assert e < 0.8 * gold["eu_zero"]
     assert abs(e - gold["eu_final"]) < 1e-3
     assert abs(rep["loss_first"] - gold["loss"][0]) < 1e-3 * abs(gold["loss"][0])

@@ -429,13 +429,13 @@ def test_T13_gradient_at_64cubed_matches_stored_finite_differences(metric):
     """The oracle's adjoint on the 64^3 gradient-check series (four phantom
     sessions, K 6, window 7) against central differences of its own FP64 loss
     at random triples away from the border, stored by
-    tests/golden/make_config3_fd.py."""
+    tests/golden/make_phantoms_4x64_fd.py."""
     import json
     import os
     from paper_2412_14671_amd import synth
-    with open(os.path.join(os.path.dirname(__file__), "golden", "config3_fd.json")) as f:
+    with open(os.path.join(os.path.dirname(__file__), "golden", "phantoms_4x64_fd.json")) as f:
         gold = json.load(f)
-    s = synth.config3()
+    s = synth.phantoms_4x64()
     imgs = [x.numpy().astype(np.float64) for x in s.images]
     phis = [x.astype(np.float64) for x in (0.5 * s.svf_true).numpy().astype(np.float32)]
     p = O.Params(K=gold["K"], window=gold["window"], alpha_ss=gold["alpha_ss"],

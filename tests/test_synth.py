@@ -9,8 +9,8 @@ from paper_2412_14671_amd import synth
 
 
 def test_generators_are_deterministic_and_shaped():
-    a = synth.config1()
-    b = synth.config1()
+    a = synth.blobs_3x32()
+    b = synth.blobs_3x32()
     assert torch.equal(a.images, b.images)
     assert a.images.shape == (3, 32, 32, 32) and a.images.dtype == torch.float32
     assert a.svf_true.shape == (2, 3, 32, 32, 32)
@@ -23,7 +23,7 @@ def test_generators_are_deterministic_and_shaped():
     assert p.roi.any()
 
 
-@pytest.mark.parametrize("maker,metric,w", [(synth.config1, O.LNCC, 5),
+@pytest.mark.parametrize("maker,metric,w", [(synth.blobs_3x32, O.LNCC, 5),
                                             (lambda: synth.phantom_series((32, 32, 32), 3, seed=5),
                                              O.SILNCC, 5)])
 def test_ground_truth_lowers_the_similarity(maker, metric, w):
