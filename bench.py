@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="register", choices=["register", "batch", "serve"])
+    ap.add_argument("--workload", default="register", choices=["register", "batch", "serve", "blobs"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured graphs in the timed region (no per-kernel timing)")
@@ -311,6 +311,8 @@ def main():
         out = bench_register(args, ctx, dev, torch, synth, MusterParams)
     elif args.workload == "batch":
         out = bench_batch(args, ctx, dev, torch, synth, MusterParams)
+    elif args.workload == "blobs":
+        out = bench_blobs(args, ctx, dev, torch, synth, MusterParams)
     else:
         out = bench_serve(args, ctx, dev, torch, synth, MusterParams)
     if args.copy_calibration:
@@ -526,6 +528,84 @@ def bench_serve(args, ctx, dev, torch, synth, MusterParams):
             "service_mean_s": round(float(np.mean([r["seconds"] - r["queue_seconds"] for r in reps])), 3),
             "failed": int(sum(r["status"] != 0 for r in reps)),
             "failed_status": sorted({int(r["status"]) for r in reps if r["status"] != 0})}
+
+def bench_blobs(args, ctx, dev, torch, synth, MusterParams):
+    """Three 32^3 sessions of 20 Gaussian blobs (the later two flowed for t =
+    1, 2), 50 Adam steps at one level, K 7, LNCC window 5, alpha_ss 1, lr 0.1:
+    about 0.1 GB of traffic per iteration, so launch- and latency-bound.  The
+    median over repetitions of the whole registration, eager with kernel
+    timing (value) and graph-replayed (the library's default); the oracle's
+    full 50-step run beside it."""
+    s = synth.blobs_3x32(device=dev)
+    images = s.images.contiguous()
+    N, V, T = images.shape[0], images[0].numel(), 50
+
+    def params(graph):
+        return MusterParams(iters=[T], K=7, window=5, metric="lncc", alpha_ss=1.0, lr=0.1,
+                            use_graph=graph)
+
+    vox = N * V * T
+    log("warmup")
+    for g in (False, True):
+        ctx.register(images, s.times, params(g))
+    reps = max(args.steps, 5)
+
+    def timed(graph):
+        ts, out = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = ctx.register(images, s.times, params(graph))
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), out
+
+    log(f"timed {reps} eager")
+    ctx.set_kernel_timing(True)
+    ctx.kernel_stats_reset()
+    te, (svf, _, rep) = timed(False)
+    ctx.set_kernel_timing(False)
+    stats = ctx.kernel_stats()
+    log(f"timed {reps} graph")
+    tg, _ = timed(True)
+    _, roof = roofline_from_stats(stats)
+    roi = s.roi.cpu().numpy()
+    true_np = s.svf_true.cpu().numpy()
+    svf_np = svf.cpu().numpy()
+    gold_path = os.path.join(ROOT, "tests", "golden", "blobs_3x32_oracle.json")
+    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else {}
+    out = {
+        "metric": "voxel-iterations/sec (fwd+bwd)",
+        "value": round(vox / te, 1),
+        "unit": "session-voxel-iterations/s",
+        "n_gpus": 1, "steps": reps, "warmup": 2,
+        "ms_per_step": round(te * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "one subject, 3 sessions of 32^3 Gaussian blobs, 50 Adam steps "
+                               "at one level, LNCC w5, K7, alpha_ss 1, lr 0.1 (median of repetitions)",
+                   "sessions": N, "dims": list(images.shape[1:]), "levels": 1, "iters": [T]},
+        "roofline": roof,
+        "cpu_baseline": None,
+        "graph_replay": {"ms_per_step": round(tg * 1e3, 2), "value": round(vox / tg, 1)},
+        "eu_voxels": round(eu(true_np, svf_np, roi), 4),
+        "eu_at_zero": round(eu(true_np, np.zeros_like(svf_np), roi), 4),
+        "eu_oracle": gold.get("eu_final"),
+        "loss_first": rep["loss_first"], "loss_last": rep["loss_last"],
+    }
+    if not args.no_cpu_baseline:
+        from oracle import muster_oracle as O
+        log("cpu baseline (oracle, full run)")
+        imgs = [x.astype(np.float64) for x in images.cpu().numpy()]
+        p = O.Params(K=7, window=5, metric=O.LNCC, alpha_ss=1.0, lr=0.1, iters=(T,))
+        t0 = time.perf_counter()
+        O.register(imgs, p)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": vox / dt, "unit": "session-voxel-iterations/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the whole 50-step registration (NumPy float64, "
+                                         f"single-threaded), {dt:.1f} s"}
+    return out
 
 
 if __name__ == "__main__":
