@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=2.0)
     ap.add_argument("--batch-subjects", type=int, default=16)
     ap.add_argument("--batch-iters", type=int, default=100)
+    ap.add_argument("--batch-sizes", default="",
+                    help="edge lengths of cubic subjects to draw from (e.g. 32,48,64) instead of "
+                         "96^3/128^3/160x192x160")
     return ap.parse_args()
 
 
@@ -425,10 +428,13 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
 
 def bench_batch(args, ctx, dev, torch, synth, MusterParams):
     subjects = []
+    sizes = synth.SIZES
+    if args.batch_sizes:
+        sizes = tuple((int(e),) * 3 for e in args.batch_sizes.split(","))
     for k in range(args.batch_subjects):
-        N, shape = synth.subject_draw(100 + k)
+        N, shape = synth.subject_draw(100 + k, sizes)
         log(f"subject {k}: N={N} {shape}")
-        subjects.append(synth.batch_subject(100 + k, device=dev))
+        subjects.append(synth.batch_subject(100 + k, device=dev, shape=shape, N=N))
     params_b = MusterParams(iters=[args.batch_iters], K=7, window=7, metric="silncc", lr=0.1,
                             alpha_ss=args.alpha, smooth_sigma=args.smooth, use_graph=True)
     params_p = MusterParams(iters=[args.batch_iters], K=7, window=7, metric="silncc", lr=0.1,
@@ -471,8 +477,9 @@ def bench_batch(args, ctx, dev, torch, synth, MusterParams):
             "value": round(vox / tb, 1), "unit": "session-voxel-iterations/s", "n_gpus": 1,
             "steps": 1, "warmup": 0, "ms_per_step": round(tb * 1e3, 1), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": f"{len(subjects)} subjects, N in 3..10, sizes from 96^3/128^3/160x192x160, "
-                                   f"{args.batch_iters} steps at the finest level, SiLNCC w7, K7"},
+            "config": {"workload": f"{len(subjects)} subjects, N in 3..10, sizes from "
+                                   + "/".join("x".join(map(str, z)) for z in sizes)
+                                   + f", {args.batch_iters} steps at the finest level, SiLNCC w7, K7"},
             "plain_loop_value": round(vox / tp, 1), "batched_over_plain": round(tp / tb, 3),
             "torch_eager_loop_value": round(vox / t_eager, 1),
             "batched_over_torch_eager": round(t_eager / tb, 3),

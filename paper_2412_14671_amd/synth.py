@@ -241,12 +241,12 @@ def phantoms_4x64(device="cpu") -> Series:
     return phantom_series((64, 64, 64), 4, seed=3, device=device)
 
 
-def subject_draw(seed: int):
+def subject_draw(seed: int, sizes=SIZES):
     """Session count and volume size of one subject of the batched and served
-    workloads: N uniform on 3..10, size uniform over SIZES."""
+    workloads: N uniform on 3..10, size uniform over `sizes`."""
     rng = _rng(seed)
     N = int(rng.integers(3, 11))
-    shape = SIZES[int(rng.integers(0, len(SIZES)))]
+    shape = tuple(sizes[int(rng.integers(0, len(sizes)))])
     return N, shape
 
 
