@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--sessions", type=int, default=6)
     ap.add_argument("--iters", default="200,100,50")
     ap.add_argument("--alpha", type=float, default=0.1, help="alpha_ss")
+    ap.add_argument("--window", type=int, default=7, help="window edge w (3, 5 or 7)")
+    ap.add_argument("--metric", default="silncc", choices=["silncc", "lncc"])
     ap.add_argument("--smooth", type=float, default=3.0,
                     help="Gaussian smoothing width of the flow, finest-level flow-grid voxels")
     ap.add_argument("--flow-factor", type=int, default=1,
@@ -98,7 +100,8 @@ def cpu_baseline_register(series, params_np, level_shape):
         imgs = [O.pool2(x) for x in imgs]
         f //= 2
     N = len(imgs)
-    phis = [np.zeros((3,) + imgs[0].shape) for _ in range(N - 1)]
+    ff = getattr(params_np, "flow_factor", 1)
+    phis = [np.zeros((3,) + tuple(n // ff for n in imgs[0].shape)) for _ in range(N - 1)]
     m = [np.zeros_like(x) for x in phis]
     v = [np.zeros_like(x) for x in phis]
     t0 = time.perf_counter()
@@ -335,7 +338,7 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
     log(f"generating {N} sessions of {shape}")
     s = synth.phantom_series(shape, N, seed=2, device=dev)
     images = s.images.contiguous()
-    params = MusterParams(iters=iters, K=7, window=7, metric="silncc", alpha_ss=args.alpha, lr=0.1,
+    params = MusterParams(iters=iters, K=7, window=args.window, metric=args.metric, alpha_ss=args.alpha, lr=0.1,
                           smooth_sigma=args.smooth, use_graph=args.graph,
                           flow_factor=args.flow_factor)
     L = len(iters)
@@ -362,7 +365,7 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
     if not args.graph and args.graph_steps > 0:
         # the same registration with each level's iteration captured once and
         # replayed (capture included in the time); per-kernel timing is off
-        gparams = MusterParams(iters=iters, K=7, window=7, metric="silncc", alpha_ss=args.alpha,
+        gparams = MusterParams(iters=iters, K=7, window=args.window, metric=args.metric, alpha_ss=args.alpha,
                                lr=0.1, smooth_sigma=args.smooth, use_graph=True,
                                flow_factor=args.flow_factor)
         log(f"graph replay {args.graph_steps}")
@@ -396,7 +399,8 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"one subject, {N} phantom sessions {shape[0]}x{shape[1]}x{shape[2]}, "
                                 f"{L}-level pyramid {'/'.join(map(str, iters))} steps, "
-                                f"SiLNCC w7, K7, alpha_ss {args.alpha:g}, smoothing sigma {args.smooth:g}"
+                                f"{'SiLNCC' if args.metric == 'silncc' else 'LNCC'} w{args.window}, K7, "
+                                f"alpha_ss {args.alpha:g}, smoothing sigma {args.smooth:g}"
                                 + (f", flows on a grid {args.flow_factor}x coarser"
                                    if args.flow_factor > 1 else "")),
                    "sessions": N, "dims": list(shape), "levels": L, "iters": iters,
@@ -420,8 +424,9 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
         from oracle import muster_oracle as O
         log("cpu baseline (oracle)")
         coarse = tuple(d // 2 ** (L - 1) for d in shape)
-        p = O.Params(K=7, window=7, metric=O.SILNCC, alpha_ss=args.alpha, lr=0.1,
-                     smooth_sigma=args.smooth / 2 ** (L - 1))
+        p = O.Params(K=7, window=args.window, metric=O.SILNCC if args.metric == "silncc" else O.LNCC,
+                     alpha_ss=args.alpha, lr=0.1, smooth_sigma=args.smooth / 2 ** (L - 1),
+                     flow_factor=args.flow_factor)
         out["cpu_baseline"] = cpu_baseline_register(s.images.cpu().numpy(), p, coarse)
     return out
 
