@@ -51,7 +51,7 @@ SILNCC = 1
 
 
 # ---------------------------------------------------------------------------
-# Grid and trilinear sampling (Sec. 2.2: "trilinear interpolation")
+# Grid and trilinear sampling (Sec. 2.2)
 # ---------------------------------------------------------------------------
 
 def identity_grid(shape) -> np.ndarray:
