@@ -98,6 +98,15 @@ def test_blob_series_registration_matches_oracle_error(ctx):
     idx = lambda i, j: i * (N - 1) + (j if j < i else j - 1)  # noqa: E731
     assert torch.allclose(pairs[idx(0, 1)], f0, atol=1e-6)
     assert torch.allclose(pairs[idx(0, 2)], U02, atol=1e-5)
+    # and every pair field equals the oracle's (Sec. 2.2: consecutive fields
+    # Exp(+-phi_i), composed outward from the target) for the returned SVFs
+    phis = svf.cpu().numpy().astype(np.float64)
+    f = [O.exp_fwd(phis[k], 7)[-1] for k in range(N - 1)]
+    b = [O.exp_fwd(-phis[k], 7)[-1] for k in range(N - 1)]
+    U = O.all_pairs(f, b)
+    got = pairs.cpu().numpy().astype(np.float64)
+    for (i, j), want in U.items():
+        assert np.abs(got[idx(i, j)] - want).max() < 1e-4, (i, j)
 
 
 def test_graph_replay_matches_eager(ctx):
