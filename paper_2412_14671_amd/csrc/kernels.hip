@@ -362,6 +362,7 @@ __device__ __forceinline__ void jt_cells(const cgfloat* __restrict__ f, float a,
 // positions) before it could overflow.  Each non-zero bin is then added to the
 // field with one hardware float atomic.
 constexpr float FIX_SCALE = 8388608.0f;  // 2^23
+static_assert(SCATTER_CELLS % 4 == 0, "bin planes are cleared as int4");
 
 struct ScatterVox {
   int cz, cy, cx;      // cell origin; cz < 0 marks an empty slot
@@ -610,10 +611,14 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
     const float scale = FIX_SCALE / bmax;
     const float inv = bmax / FIX_SCALE;
     const int cells = bb.cells;
+    // one plane of SCATTER_CELLS bins per component: the plane offsets are
+    // constants, which the LDS instructions take as immediate offsets
     {
       int4* a4 = reinterpret_cast<int4*>(acc);
-      const int n4 = (3 * cells + 3) >> 2;
-      for (int i = threadIdx.x; i < n4; i += NT) a4[i] = make_int4(0, 0, 0, 0);
+      const int n4 = (cells + 3) >> 2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        for (int i = threadIdx.x; i < n4; i += NT) a4[c * (SCATTER_CELLS / 4) + i] = make_int4(0, 0, 0, 0);
     }
     __syncthreads();
     const int sy = bb.ex, sz = bb.ex * bb.ey;
@@ -629,15 +634,14 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float g = sv[j].g[c] * scale;
-        if (g == 0.f) continue;
-        int* a = acc + c * cells + l;
+        int* a = acc + c * SCATTER_CELLS + l;
 #pragma unroll
         for (int q = 0; q < 8; ++q) atomicAdd(a + off[q], (int)(w[q] * g));
       }
       if (OWN) {
         const int lo2 = ((sv[j].oz - bb.lz) * bb.ey + (sv[j].oy - bb.ly)) * bb.ex + (sv[j].ox - bb.lx);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) atomicAdd(acc + c * cells + lo2, (int)(sv[j].own[c] * scale));
+        for (int c = 0; c < 3; ++c) atomicAdd(acc + c * SCATTER_CELLS + lo2, (int)(sv[j].own[c] * scale));
       }
     }
     __syncthreads();
@@ -649,7 +653,7 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
       for (int i = threadIdx.x; i < cells; i += NT) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const int v = acc[c * cells + i];
+          const int v = acc[c * SCATTER_CELLS + i];
           amax = max(amax, abs(v));
           so.slot[c * STAGE_CAP + i] = (float)v * inv;
         }
@@ -674,7 +678,7 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
       const int gpos = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const int v = acc[c * cells + i];
+        const int v = acc[c * SCATTER_CELLS + i];
         if (v != 0) gadd(out + c * V + gpos, (float)v * inv);
       }
     }
