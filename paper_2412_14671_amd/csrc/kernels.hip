@@ -105,14 +105,30 @@ __device__ __forceinline__ float lerp_(float a, float b, float t) { return fmaf(
 // multi-dword global loads); halves the address work of a gather.
 __device__ __forceinline__ float2a ld2(const cgfloat* p) { return *(const GLOBAL float2a*)p; }
 
+// Loads at element i of a plane whose base is uniform across the wave: the
+// byte offset is formed in 32 bits (i < 2^30 for any volume the library
+// accepts), so the load takes the scalar base plus a 32-bit vector offset
+// instead of a 64-bit vector address.
+__device__ __forceinline__ float2a ld2o(const cgfloat* plane, uint32_t i) {
+  return *(const GLOBAL float2a*)((const GLOBAL char*)plane + (i << 2));
+}
+
+__device__ __forceinline__ float ldo(const cgfloat* plane, uint32_t i) {
+  return *(const GLOBAL float*)((const GLOBAL char*)plane + (i << 2));
+}
+__device__ __forceinline__ void sto(gfloat* plane, uint32_t i, float v) {
+  *(GLOBAL float*)((GLOBAL char*)plane + (i << 2)) = v;
+}
+
 // The 8 corners of a cell.  Corner order: bit 0 = x+1, bit 1 = y+1,
 // bit 2 = z+1; the x pairs are adjacent in memory and come in one load.
 __device__ __forceinline__ void load8(const cgfloat* __restrict__ f, int base, int sy, int sz,
                                       float (&v)[8]) {
-  const float2a a = ld2(f + base);
-  const float2a b = ld2(f + base + sy);
-  const float2a c = ld2(f + base + sz);
-  const float2a d = ld2(f + base + sz + sy);
+  const uint32_t b0 = (uint32_t)base;
+  const float2a a = ld2o(f, b0);
+  const float2a b = ld2o(f, b0 + (uint32_t)sy);
+  const float2a c = ld2o(f, b0 + (uint32_t)sz);
+  const float2a d = ld2o(f, b0 + (uint32_t)(sz + sy));
   v[0] = a.x; v[1] = a.y;
   v[2] = b.x; v[3] = b.y;
   v[4] = c.x; v[5] = c.y;
@@ -297,9 +313,9 @@ __device__ __forceinline__ void load_cells(const cgfloat* __restrict__ u, float 
   const int V = D * H * W;
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
-    uu[j][0] = a * u[vs.p[j]];
-    uu[j][1] = a * u[V + vs.p[j]];
-    uu[j][2] = a * u[2 * V + vs.p[j]];
+    uu[j][0] = a * ldo(u, vs.p[j]);
+    uu[j][1] = a * ldo(u + V, vs.p[j]);
+    uu[j][2] = a * ldo(u + 2 * V, vs.p[j]);
   }
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
@@ -471,9 +487,9 @@ __device__ __forceinline__ void sample_cells_lds(const cgfloat* __restrict__ f, 
     const int lz = (int)(((float)r + 0.5f) * inv_ey);
     const int ly = r - lz * bb.ey;
     const int g = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
-    box[i] = f[g];
-    box[cells + i] = f[V + g];
-    box[2 * cells + i] = f[2 * V + g];
+    box[i] = ldo(f, g);
+    box[cells + i] = ldo(f + V, g);
+    box[2 * cells + i] = ldo(f + 2 * V, g);
   }
   __syncthreads();
   const int sy = bb.ex, sz = bb.ex * bb.ey;
@@ -519,9 +535,9 @@ __global__ __launch_bounds__(BLOCK) GATHER_WAVES void k_exp_fwd(const ExpFwdItem
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     if (!vs.ok[j]) continue;
-    d[vs.p[j]] = uu[j][0] + a * sm[j][0];
-    d[V + vs.p[j]] = uu[j][1] + a * sm[j][1];
-    d[2 * V + vs.p[j]] = uu[j][2] + a * sm[j][2];
+    sto(d, vs.p[j], uu[j][0] + a * sm[j][0]);
+    sto(d + V, vs.p[j], uu[j][1] + a * sm[j][1]);
+    sto(d + 2 * V, vs.p[j], uu[j][2] + a * sm[j][2]);
   }
 }
 
@@ -549,9 +565,9 @@ __global__ __launch_bounds__(BLOCK) GATHER_WAVES void k_compose_fwd(const Compos
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     if (!vs.ok[j]) continue;
-    o[vs.p[j]] = uu[j][0] + sm[j][0];
-    o[V + vs.p[j]] = uu[j][1] + sm[j][1];
-    o[2 * V + vs.p[j]] = uu[j][2] + sm[j][2];
+    sto(o, vs.p[j], uu[j][0] + sm[j][0]);
+    sto(o + V, vs.p[j], uu[j][1] + sm[j][1]);
+    sto(o + 2 * V, vs.p[j], uu[j][2] + sm[j][2]);
   }
 }
 
@@ -655,7 +671,7 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
         for (int c = 0; c < 3; ++c) {
           const int v = acc[c * SCATTER_CELLS + i];
           amax = max(amax, abs(v));
-          so.slot[c * STAGE_CAP + i] = (float)v * inv;
+          sto(so.slot, c * STAGE_CAP + i, (float)v * inv);
         }
       }
       amax = dpp_max(amax);
@@ -749,9 +765,9 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
       for (int j = 0; j < VPT; ++j) {
         if (!vok[j]) continue;
         const int idx = ((vz[j] - bz) * ey + (vy[j] - by)) * ex + (vx[j] - bx);
-        gv[j][0] = sl[idx];
-        gv[j][1] = sl[STAGE_CAP + idx];
-        gv[j][2] = sl[2 * STAGE_CAP + idx];
+        gv[j][0] = ldo(sl, idx);
+        gv[j][1] = ldo(sl + STAGE_CAP, idx);
+        gv[j][2] = ldo(sl + 2 * STAGE_CAP, idx);
       }
     }
   }
@@ -943,7 +959,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     if (!vok[j]) continue;
     const int x = vx[j], y = vy[j], z = vz[j];
     const int p = (z * H + y) * W + x;
-    const float uz = a * s[p], uy = a * s[V + p], ux = a * s[2 * V + p];
+    const float uz = a * ldo(s, p), uy = a * ldo(s + V, p), ux = a * ldo(s + 2 * V, p);
     const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
     const int base = (az.i0 * H + ay.i0) * W + ax.i0;
     const float g0 = gv[j][0], g1 = gv[j][1], g2 = gv[j][2];
@@ -1121,10 +1137,10 @@ __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __r
     const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
     if (x >= W || y >= H || z >= D) continue;
     const int p = (z * H + y) * W + x;
-    const float uz = pr[p], uy = pr[V + p], ux = pr[2 * V + p];
+    const float uz = ldo(pr, p), uy = ldo(pr + V, p), ux = ldo(pr + 2 * V, p);
     const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
     const int base = (az.i0 * H + ay.i0) * W + ax.i0;
-    const float g0 = G[p], g1 = G[V + p], g2 = G[2 * V + p];
+    const float g0 = ldo(G, p), g1 = ldo(G + V, p), g2 = ldo(G + 2 * V, p);
     float v0[8], v1[8], v2[8], dz, dy, dx;
     load8(C, base, W, HW, v0);
     load8(C + V, base, W, HW, v1);
@@ -1274,9 +1290,9 @@ __global__ __launch_bounds__(BLOCK) void k_warp(const SimItem* __restrict__ item
   float u[VPT][3];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
-    u[j][0] = U[vs.p[j]];
-    u[j][1] = U[V + vs.p[j]];
-    u[j][2] = U[2 * V + vs.p[j]];
+    u[j][0] = ldo(U, vs.p[j]);
+    u[j][1] = ldo(U + V, vs.p[j]);
+    u[j][2] = ldo(U + 2 * V, vs.p[j]);
   }
   if (it.rigid) {
     float rA[9], rO[3];
@@ -1303,7 +1319,7 @@ __global__ __launch_bounds__(BLOCK) void k_warp(const SimItem* __restrict__ item
   }
 #pragma unroll
   for (int j = 0; j < VPT; ++j)
-    if (vs.ok[j]) M[vs.p[j]] = tri_val(v[j], az[j].t, ay[j].t, ax[j].t);
+    if (vs.ok[j]) sto(M, vs.p[j], tri_val(v[j], az[j].t, ay[j].t, ax[j].t));
 }
 
 template <int R, int TY, int TX>
@@ -1351,8 +1367,8 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
     for (int k = 0; k < NS; ++k) {
       const bool in = zin && cofs[k] >= 0;
       const int p = in ? z * HW + cofs[k] : 0;
-      f[k] = in ? F[p] - sF : 0.f;
-      m[k] = in ? M[p] - sM : 0.f;
+      f[k] = in ? ldo(F, p) - sF : 0.f;
+      m[k] = in ? ldo(M, p) - sM : 0.f;
     }
   };
   // the last WN slices of each owned column (oldest first) and their sums
@@ -1467,9 +1483,9 @@ __global__ __launch_bounds__(TY * TX) void k_sim_stats(const SimItem* __restrict
           ga = ac * inv_n;
         }
         if (coef) {
-          coef[p] = al;
-          coef[V + p] = be;
-          coef[2 * V + p] = ga;
+          sto(coef, p, al);
+          sto(coef + V, p, be);
+          sto(coef + 2 * V, p, ga);
         }
       }
     }
