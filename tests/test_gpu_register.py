@@ -398,7 +398,7 @@ def test_server_budget_queue_and_cancellation():
     from paper_2412_14671_amd import _lib as L
     small = synth.phantom_series((24, 24, 24), 3, seed=51)
     big = synth.phantom_series((48, 48, 48), 4, seed=52)
-    long_p = MusterParams(iters=[4000], K=5, window=3, metric="silncc")
+    long_p = MusterParams(iters=[20000], K=5, window=3, metric="silncc")
     short_p = MusterParams(iters=[3], K=5, window=3, metric="silncc")
     probe = Context(0)
     fp = probe.footprint(3, (24, 24, 24), long_p)
@@ -428,7 +428,7 @@ def test_server_budget_queue_and_cancellation():
         srv.cancel(ta)
         ra, rb = srv.wait(ta), srv.wait(tb)
         assert ra["status"] == L.E_CANCELLED and rb["status"] == L.E_CANCELLED
-        assert ra["iterations"] < 4000
+        assert ra["iterations"] < 20000
         td, out = srv.submit(img, small.times, short_p)
         rd = srv.wait(td)
         assert rd["status"] == 0 and rd["iterations"] == 3
