@@ -239,6 +239,16 @@ def torch_register(torch, images, iters, lr=0.1, warmup=0.2, timed_iters=None, *
     return [p.detach() for p in phis], per
 
 
+def kernels_sha256():
+    """SHA-256 of the kernel source and the header of its tile and bin
+    constants: the counter summaries hold only while both are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "muster_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2412_14671_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_per_launch(path, kernel, launch_grids):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     weighted like the timed launches ({grid in blocks: launches}); None if the
@@ -247,9 +257,7 @@ def traffic_per_launch(path, kernel, launch_grids):
     if not path or not os.path.exists(path):
         return None
     t = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2412_14671_amd", "csrc", "kernels.hip")
-    if t.get("kernel") != kernel or t.get("kernels_hip_sha256") != hashlib.sha256(
-            open(src, "rb").read()).hexdigest():
+    if t.get("kernel") != kernel or t.get("kernels_sha256") != kernels_sha256():
         return None
     ff, wf = t["calibration"]["fetch_factor"], t["calibration"]["write_factor"]
     tot = n = 0
@@ -270,8 +278,7 @@ def l2_hit_per_launch(path, kernel, launch_grids):
     if not path or not os.path.exists(path):
         return None
     t = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2412_14671_amd", "csrc", "kernels.hip")
-    if t.get("kernels_hip_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if t.get("kernels_sha256") != kernels_sha256():
         return None
     per = t.get("kernels", {}).get(kernel)
     if per is None:

@@ -892,7 +892,7 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
 // MODE: 0 flat G_{s+1} in, flat G_s out; 1 flat in, staged out; 2 staged
 // in, staged out; 3 staged in, flat out (see ExpBwdItem).  A staged G_0 is
 // turned into a flat field by k_unstage.
-template <int MODE>
+template <int MODE, bool REG>
 __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict__ items,
                                                    int n_items, int n_tiles) {
   constexpr bool IN_ST = MODE >= 2, OUT_ST = MODE == 1 || MODE == 2;
@@ -907,7 +907,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   const float a = it.a;
   const cgfloat* __restrict__ s = gp(it.src);
   gfloat* __restrict__ gin = gp(it.gin);
-  const bool reg = it.reg_w != 0.f || it.ext;
+  const bool reg = REG && (it.reg_w != 0.f || it.ext);
   const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
               inv_mx = 1.f / (float)(D * H * (W - 1));
   double rval = 0.0, rext = 0.0;
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   // the scatter below reuses once every thread has formed its own terms
   float* rt = reinterpret_cast<float*>(acc);
   float rvf = 0.f;
-  if (it.reg_w != 0.f) {
+  if ((REG && it.reg_w != 0.f)) {
     __syncthreads();  // the staged pull above is done with acc
     reg_tile_load(s, V, tc.z0, tc.y0, tc.x0, D, H, W, rt);
     __syncthreads();
@@ -976,7 +976,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     float own0 = fmaf(a * az.live, jz, g0);
     float own1 = fmaf(a * ay.live, jy, g1);
     float own2 = fmaf(a * ax.live, jx, g2);
-    if (it.reg_w != 0.f) {
+    if ((REG && it.reg_w != 0.f)) {
       const int lz = z - tc.z0, ly = y - tc.y0, lx = x - tc.x0;
       own0 = fmaf(it.reg_w, reg_tile_point(rt, lz, ly, lx, z, y, x, D, H, W, inv_mz, inv_my,
                                            inv_mx, &rvf), own0);
@@ -985,7 +985,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
       own2 = fmaf(it.reg_w, reg_tile_point(rt + 2 * RH_N, lz, ly, lx, z, y, x, D, H, W, inv_mz,
                                            inv_my, inv_mx, &rvf), own2);
     }
-    if (it.ext) {
+    if (REG && it.ext) {
       // L_L2 and L_ts (Sec. 2.4): linear in the flows of this interval and its neighbours
       const float f0 = s[p], f1 = s[V + p], f2 = s[2 * V + p];
       own0 = fmaf(it.w_self, f0, own0);
@@ -2126,17 +2126,24 @@ hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles
   return hipGetLastError();
 }
 
-hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int staged,
-                          hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
+template <bool REG>
+static hipError_t launch_exp_bwd_(const ExpBwdItem* items, int n_items, int n_tiles, int staged,
+                                  hipStream_t s) {
   switch (staged) {
-    case 0: MUSTER_LAUNCH(k_exp_bwd<0>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
-    case 1: MUSTER_LAUNCH(k_exp_bwd<1>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
-    case 2: MUSTER_LAUNCH(k_exp_bwd<2>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
-    case 3: MUSTER_LAUNCH(k_exp_bwd<3>, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 0: MUSTER_LAUNCH((k_exp_bwd<0, REG>), dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 1: MUSTER_LAUNCH((k_exp_bwd<1, REG>), dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 2: MUSTER_LAUNCH((k_exp_bwd<2, REG>), dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 3: MUSTER_LAUNCH((k_exp_bwd<3, REG>), dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int staged, bool reg,
+                          hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  return reg ? launch_exp_bwd_<true>(items, n_items, n_tiles, staged, s)
+             : launch_exp_bwd_<false>(items, n_items, n_tiles, staged, s);
 }
 
 hipError_t launch_unstage(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s) {

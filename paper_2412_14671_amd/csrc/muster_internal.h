@@ -293,7 +293,7 @@ inline int up_adj_tiles(int D, int H, int W) {
 constexpr int PT_Z = 8, PT_Y = 8, PT_X = 16;   // 1024 voxels, 256 threads
 constexpr int PT_VOX = PT_Z * PT_Y * PT_X;
 constexpr int BLOCK = 256;
-constexpr int SCATTER_CELLS = 3072;          // LDS bins per component
+constexpr int SCATTER_CELLS = 2560;          // LDS bins per component
 constexpr int STAGE_CAP = SCATTER_CELLS;      // cells per component of a staging slot
 // Tiles of the windowed-statistics kernels: TY x TX columns, z chunks.
 // Tile shapes (centres in y x x) of the window-statistics kernels; the block
@@ -319,7 +319,9 @@ hipError_t launch_exp_fwd(const ExpFwdItem* items, int n_items, int n_tiles, hip
 hipError_t launch_compose_fwd(const ComposeItem* items, int n_items, int n_tiles, hipStream_t s);
 // staged: 0 flat in / flat out, 1 flat in / staged out, 2 staged in / staged out,
 // 3 staged in / flat out
-hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int staged,
+// reg: some item adds the regulariser terms (reg_w != 0 or ext); without it
+// a leaner variant of the kernel runs.
+hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int staged, bool reg,
                           hipStream_t s);
 // A staged G_0 (stage_in, desc_in, flag_in of each item) to the flat gout.
 hipError_t launch_unstage(const ExpBwdItem* items, int n_items, int n_tiles, hipStream_t s);

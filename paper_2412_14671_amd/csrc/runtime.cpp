@@ -987,7 +987,10 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
     }
     for (int mode = 0; mode < 4; ++mode) {
       b.add(ST_EXP_BWD, items[mode], tiles[mode], bytes[mode]);
-      if (!items[mode].empty()) b.plan->stages.back().staged = mode;
+      if (items[mode].empty()) continue;
+      b.plan->stages.back().staged = mode;
+      for (const ExpBwdItem& e : items[mode])
+        if (e.reg_w != 0.f || e.ext) b.plan->stages.back().reg = 1;
     }
   }
   {
@@ -1166,7 +1169,7 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_COMPOSE_BWD:
       return launch_compose_bwd((const ComposeBwdItem*)p, st.n_items, st.n_tiles, s);
     case ST_EXP_BWD:
-      return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, st.staged, s);
+      return launch_exp_bwd((const ExpBwdItem*)p, st.n_items, st.n_tiles, st.staged, st.reg != 0, s);
     case ST_ADAM: return launch_adam((const AdamItem*)p, st.n_items, st.n_tiles, s);
     case ST_FINISH: return launch_finish((JobState* const*)p, st.n_items, s);
     case ST_SMOOTH: return launch_smooth((const SmoothItem*)p, st.n_items, st.n_tiles, st.lds, s);
@@ -2118,7 +2121,7 @@ muster_status muster_exp_bwd(muster_ctx* h, void* stream, const int dims[3], int
     for (auto& l : seq) {
       const unsigned char* p = sc.dev() + l.off;
       if (l.kind == 0) MUSTER_HIP(launch_exp_fwd((const ExpFwdItem*)p, 1, tiles, sc.s));
-      if (l.kind == 1) MUSTER_HIP(launch_exp_bwd((const ExpBwdItem*)p, 1, tiles, 0, sc.s));
+      if (l.kind == 1) MUSTER_HIP(launch_exp_bwd((const ExpBwdItem*)p, 1, tiles, 0, true, sc.s));
       if (l.kind == 2) MUSTER_HIP(launch_adam((const AdamItem*)p, 1, elem_tiles(V), sc.s));
     }
     MUSTER_HIP(hipStreamSynchronize(sc.s));

@@ -226,6 +226,7 @@ struct Stage {
   int n_tiles;
   int window = 0, metric = 0, zc = 32;
   int staged = 0;    // Exp-backward staging mode
+  int reg = 0;       // Exp backward: some item adds regulariser terms
   int lds = 0;       // dynamic LDS floats (smoothing)
   int shape = 0;     // window-statistics tile shape
   double bytes = 0;  // algorithmic bytes of the launch
