@@ -1075,7 +1075,10 @@ __global__ __launch_bounds__(BLOCK) void k_unstage(const ExpBwdItem* __restrict_
 // directions (PullItem), without a flat G_0 in between.
 __global__ __launch_bounds__(BLOCK) void k_pull_combine(const PullItem* __restrict__ items,
                                                         int n_items, int n_tiles) {
-  __shared__ __align__(16) int acc[3 * PT_VOX];
+  // the pulls' bins, then the regulariser's halo tile of the flow
+  constexpr int ACC = 3 * PT_VOX > 3 * RH_N ? 3 * PT_VOX : 3 * RH_N;
+  __shared__ __align__(16) int acc[ACC];
+  __shared__ double red[BLOCK / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const PullItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, V = D * H * W;
@@ -1100,6 +1103,30 @@ __global__ __launch_bounds__(BLOCK) void k_pull_combine(const PullItem* __restri
   pull_staged(it.stage[1], it.desc[1], it.flag[1], gp(it.gflat[1]), local, tc, D, H, W, vz, vy,
               vx, vok, gb, acc);
   gfloat* __restrict__ out = gp(it.out);
+  if (it.reg_w != 0.f) {  // block-uniform
+    const float inv_mz = 1.f / (float)((D - 1) * H * W), inv_my = 1.f / (float)(D * (H - 1) * W),
+                inv_mx = 1.f / (float)(D * H * (W - 1));
+    float* rt = reinterpret_cast<float*>(acc);
+    __syncthreads();  // the second pull is done with acc
+    reg_tile_load(gp(it.flow), V, tc.z0, tc.y0, tc.x0, D, H, W, rt);
+    __syncthreads();
+    float rvf = 0.f;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      if (!vok[j]) continue;
+      const int p = (vz[j] * H + vy[j]) * W + vx[j];
+      const int lz = vz[j] - tc.z0, ly = vy[j] - tc.y0, lx = vx[j] - tc.x0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float rg = reg_tile_point(rt + c * RH_N, lz, ly, lx, vz[j], vy[j], vx[j], D, H, W,
+                                        inv_mz, inv_my, inv_mx, &rvf);
+        out[c * V + p] = fmaf(it.reg_w, rg, it.scale * (gf[j][c] - gb[j][c]));
+      }
+    }
+    const double tot = block_sum((double)rvf * (double)it.reg_loss_w, red);
+    if (threadIdx.x == 0 && it.js) unsafeAtomicAdd(&it.js->loss_reg, tot);
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
     if (!vok[j]) continue;

@@ -230,7 +230,13 @@ struct PullItem {
   float* gflat[2];
   float* out;
   float scale;
-  int pad;
+  // Diffusion regulariser of the interval's flow (Eq. reg_ss), when it is
+  // added here rather than in the Exp backward's step 0: out gains
+  // reg_w * dR/dflow, and the job's loss reg_loss_w * R(flow).
+  float reg_w;
+  float reg_loss_w;
+  const float* flow;
+  JobState* js;
 };
 
 // One separable pass of the circular Gaussian smoothing along one axis, for

@@ -974,7 +974,8 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
           it.desc_out = J->desc(dir, s % 2);
           it.flag_out = J->flag(dir, s);
         }
-        if (s == 0 && fwd && J->p.alpha_ss > 0.f) {
+        // L_ss joins here unless k_pull_combine adds it (smoothing jobs)
+        if (s == 0 && fwd && J->p.alpha_ss > 0.f && !(J->staged() && J->smoothing())) {
           it.reg_w = std::ldexp(1.f, K) * J->p.alpha_ss / (float)(J->N - 1);
           it.reg_loss_w = J->p.alpha_ss / (float)(J->N - 1);
         }
@@ -1018,6 +1019,11 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
           }
           it.out = J->field(J->m_t1.as<float>(), i);
           it.scale = std::ldexp(1.f, -J->K());
+          if (J->p.alpha_ss > 0.f) {
+            it.reg_w = it.reg_loss_w = J->p.alpha_ss / (float)(J->N - 1);
+            it.flow = J->flow(i);
+            it.js = J->js;
+          }
           pitems.push_back(it);
           ptiles += pt;
           pbytes += 2 * B_UNSTAGE * J->Vc();
