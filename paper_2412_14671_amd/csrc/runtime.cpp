@@ -1026,7 +1026,9 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
           }
           pitems.push_back(it);
           ptiles += pt;
-          pbytes += 2 * B_UNSTAGE * J->Vc();
+          // the two staged G_0, the gradient written, and the flow the
+          // regulariser reads
+          pbytes += (2 * B_UNSTAGE + (it.reg_w != 0.f ? 12 : 0)) * J->Vc();
         } else {
           for (int k = 0; k < 2; ++k) {
             const int dir = 2 * i + k;
