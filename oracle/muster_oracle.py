@@ -31,9 +31,9 @@ notes of the repository):
   * All arithmetic is float64; inputs are float32 arrays promoted on entry.
 
 Parity status: every function here is pinned by tests against closed forms,
-exact identities, brute force or finite differences, except the end-to-end
-optimisation trajectory (register), whose result is only compared by its
-registration error: "parity unpinned" for the trajectory itself.
+exact identities, brute force, finite differences or library routines.  The
+end-to-end optimisation (register) is pinned by the same loop driven by
+torch's Adam over the pinned loss and gradient, stage by stage.
 """
 from __future__ import annotations
 
