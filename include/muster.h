@@ -354,6 +354,12 @@ enum {
 /* When enabled, eager launches (graphs off) of each kernel class are
  * bracketed by HIP events on the stream they run on. */
 muster_status muster_set_kernel_timing(muster_ctx* ctx, int enable);
+/* The same for the kernel classes whose bits are set in mask (bit k: class
+ * k of the list above; 0 turns timing off).  Only those launches carry
+ * events, so the others run as they do untimed; while any class is timed,
+ * iterations launch eagerly instead of from a graph.  MUSTER_E_INVALID for
+ * a bit at or beyond MUSTER_K_COUNT. */
+muster_status muster_set_kernel_timing_mask(muster_ctx* ctx, uint32_t mask);
 /* Per kernel class: launches, summed milliseconds and summed algorithmic
  * bytes (the unique bytes each launch must move) since the last reset. */
 muster_status muster_kernel_stats(muster_ctx* ctx, int64_t launches[MUSTER_K_COUNT],

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import (POINTER, Structure, c_char_p, c_double, c_float, c_int, c_int64, c_uint64,
+from ctypes import (POINTER, Structure, c_char_p, c_double, c_float, c_int, c_int64, c_uint32, c_uint64,
                     c_void_p)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -106,6 +106,7 @@ SIGNATURES = {
     "muster_ctx_memory": (_ST, [_P, POINTER(c_uint64), POINTER(c_uint64), c_int]),
     "muster_ctx_sim_tiling": (_ST, [_P, _P, DIMS, c_int, c_int, POINTER(c_int), POINTER(c_int)]),
     "muster_set_kernel_timing": (_ST, [_P, c_int]),
+    "muster_set_kernel_timing_mask": (_ST, [_P, c_uint32]),
     "muster_kernel_stats": (_ST, [_P, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
     "muster_kernel_stats_reset": (_ST, [_P]),
     "muster_kernel_name": (c_char_p, [c_int]),

@@ -284,6 +284,14 @@ class Context:
     def set_kernel_timing(self, on: bool):
         L.check(self.lib.muster_set_kernel_timing(self.h, 1 if on else 0))
 
+    def set_kernel_timing_only(self, kernels):
+        """Time the eager launches of the named kernel classes only (names as
+        in kernel_stats); an empty list turns timing off."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << L.KERNELS.index(k)
+        L.check(self.lib.muster_set_kernel_timing_mask(self.h, mask))
+
     def kernel_stats(self) -> Dict[str, dict]:
         n = len(L.KERNELS)
         la = (c_int64 * n)()

@@ -1223,7 +1223,7 @@ static hipEvent_t pooled_event(Ctx* ctx) {
 void Plan::run(Ctx* ctx, hipStream_t s) {
   const unsigned char* base = dev.as<unsigned char>();
   for (const Stage& st : stages) {
-    if (ctx->timing) {
+    if (ctx->timing && ((ctx->timing_mask >> kclass(st.kind)) & 1u)) {
       std::lock_guard<std::mutex> lk(ctx->timing_mu);
       TimedLaunch t{};
       t.k = kclass(st.kind);
@@ -2468,6 +2468,17 @@ muster_status muster_set_kernel_timing(muster_ctx* h, int enable) {
   return guard(ctx, [&] {
     NEED(ctx, "ctx is NULL");
     ctx->timing = enable != 0;
+    ctx->timing_mask = enable != 0 ? (1u << MUSTER_K_COUNT) - 1u : 0u;
+  });
+}
+
+muster_status muster_set_kernel_timing_mask(muster_ctx* h, uint32_t mask) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx, "ctx is NULL");
+    NEED(mask < (1u << MUSTER_K_COUNT), "mask names a kernel class beyond MUSTER_K_COUNT");
+    ctx->timing = mask != 0;
+    ctx->timing_mask = mask;
   });
 }
 

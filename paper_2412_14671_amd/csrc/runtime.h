@@ -90,6 +90,7 @@ struct Ctx {
   hipStream_t ws = nullptr;          // work stream (capturable)
   bool poisoned = false;
   bool timing = false;
+  uint32_t timing_mask = 0;  // kernel classes whose eager launches carry events
   KernelStats stats;
   // timed launches not yet resolved, and created events kept for reuse (an
   // event pair per launch would otherwise be created and destroyed each time)

@@ -134,6 +134,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.muster_register(None, None, 3, L.DIMS(8, 8, 8), None, None, None, None, None,
                                None) == L.E_INVALID
     assert lib.muster_set_kernel_timing(None, 1) == L.E_INVALID
+    assert lib.muster_set_kernel_timing_mask(None, 1) == L.E_INVALID
 
 
 def test_kernel_names(lib):

@@ -385,6 +385,20 @@ def test_kernel_timing_counts_every_launch(ctx):
     assert st["sim_stats"]["launches"] == 4 and st["sim_grad"]["launches"] == 4
     assert all(v["ms"] > 0 for v in st.values() if v["launches"])
     assert 0 < sum(v["ms"] for v in st.values()) < wall_ms
+    # timing one class: only its launches are counted, all of them
+    ctx.set_kernel_timing_only(["exp_bwd"])
+    ctx.kernel_stats_reset()
+    try:
+        ctx.register(imgs, s.times, params)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_kernel_timing(False)
+    only = ctx.kernel_stats()
+    assert only["exp_bwd"]["launches"] == 4 * 5 and only["exp_bwd"]["ms"] > 0
+    assert only["exp_bwd"]["bytes"] == st["exp_bwd"]["bytes"]
+    assert all(v["launches"] == 0 for k, v in only.items() if k != "exp_bwd")
+    from paper_2412_14671_amd import _lib as L
+    assert ctx.lib.muster_set_kernel_timing_mask(ctx.h, 1 << len(L.KERNELS)) == L.E_INVALID
 
 
 def test_server_budget_queue_and_cancellation():
