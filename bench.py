@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured graphs in the timed region (no per-kernel timing)")
+    ap.add_argument("--no-kernel-table", dest="kernel_table", action="store_false",
+                    help="skip the extra registration that times every kernel class")
     ap.add_argument("--graph-steps", type=int, default=1,
                     help="registrations replayed from captured graphs after the timed region")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
@@ -380,7 +382,7 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
     ctx.set_kernel_timing(False)
     stats_timed = ctx.kernel_stats()
     stats = stats_timed
-    if not args.graph:
+    if not args.graph and args.kernel_table:
         log("per-kernel timing, one more registration")
         ctx.set_kernel_timing(True)
         ctx.kernel_stats_reset()
