@@ -1,27 +1,36 @@
 """Benchmark of the MUSTER registration path on one MI355X.
 
-Default workload: one subject of six 160x192x160 phantom sessions registered
-over a three-level pyramid (40x48x40, 80x96x80, 160x192x160; 200/100/50 Adam
-steps), SiLNCC with a 7^3 window, K = 7 squarings, alpha_ss = 0.1 and a
-Gaussian smoothing of the flow with sigma 3 finest-level voxels.  A step is
-one complete registration (every step of the path at every level).  The metric counts
-session-voxel-iterations: sum over levels of N * V_level * steps_level,
-divided by the wall time of a step, with the input series already resident in
-device memory.
+Default workload ("headline"): the batched form of the path against a plain
+per-subject loop, and the serving form's latency.
+  * Sixteen subjects (seeds 100..115), each with a session count drawn from
+    3..10 and a volume size from 96^3 / 128^3 / 160x192x160 (brain-like
+    phantoms with per-session bias, Rician noise and per-interval velocity
+    fields), registered at the finest level from phi = 0: SiLNCC w7, K = 7,
+    alpha_ss = 1, no smoothing, lr 0.1.
+  * A step is one iteration of every subject (forward, adjoint and Adam step
+    of all sixteen, as one batched launch sequence).  W untimed steps, then K
+    timed ones; value = session-voxel-iterations per second over the timed
+    steps (sum of N_s * V_s per step).  The timed steps launch eagerly with
+    HIP events on the dominant kernel's launches (for the roofline).
+  * Then the whole 100-step schedule: batched (one launch sequence for all
+    subjects, each step replayed from a captured hipGraph, autotuned tiles)
+    against the plain loop (the same subjects one after another, the same
+    kernels launched eagerly, default tiles); batched_over_plain and the
+    final registration error Eu of every subject under both.
+  * Serving: Poisson arrivals at 2 requests/s for 30 s into the continuous
+    batching server, each request one of the sixteen subjects on the
+    three-level pyramid 200/100/50; jobs/s and p50/p99 latency.
+  * Extra keys: the single-subject registration of six 160x192x160 sessions
+    (three levels, 200/100/50 steps).
 
-Other workloads (--workload): "batch" (16 subjects of uneven size and session
-count, 100 steps at the finest level, batched graph-replayed loop against two
-per-subject plain loops: this library's kernels launched eagerly, and the same
-loss written op by op in PyTorch eager with autograd) and "serve" (Poisson arrivals into the
-continuous-batching server; p50/p99 latency).
-
+The inputs are resident in device memory before any timed region starts.
 The JSON line carries the roofline of the dominant kernel (algorithmic bytes
-over its HIP-event-timed duration inside the timed region) and the FP64 oracle
-timed on host cores on a bounded sample of the same workload.  The timed
-region launches every kernel eagerly, each bracketed by HIP events;
-"graph_replay" adds the time of the same registration with every level's
-iteration captured once into a HIP graph and replayed (the library's default
-mode), measured after the timed region.
+over its HIP-event-timed duration inside the timed region) and the FP64
+oracle timed on host cores on a bounded sample of the same workload.
+
+Other workloads (--workload): "register" (the single subject alone, a step
+being one whole registration), "batch", "serve" and "blobs" (three 32^3
+sessions; launch-bound).
 """
 from __future__ import annotations
 
@@ -45,7 +54,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="register", choices=["register", "batch", "serve", "blobs"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "register", "batch", "serve", "blobs"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured graphs in the timed region (no per-kernel timing)")
@@ -65,17 +75,23 @@ def parse():
     ap.add_argument("--shape", default="160,192,160")
     ap.add_argument("--sessions", type=int, default=6)
     ap.add_argument("--iters", default="200,100,50")
-    ap.add_argument("--alpha", type=float, default=0.1, help="alpha_ss")
+    ap.add_argument("--alpha", type=float, default=0.1,
+                    help="alpha_ss of the single-subject registration (the headline uses 1)")
     ap.add_argument("--window", type=int, default=7, help="window edge w (3, 5 or 7)")
     ap.add_argument("--metric", default="silncc", choices=["silncc", "lncc"])
     ap.add_argument("--smooth", type=float, default=3.0,
                     help="Gaussian smoothing width of the flow, finest-level flow-grid voxels")
     ap.add_argument("--flow-factor", type=int, default=1,
                     help="2: flows on a grid twice as coarse as the images")
-    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-rate", type=float, default=2.0)
     ap.add_argument("--batch-subjects", type=int, default=16)
     ap.add_argument("--batch-iters", type=int, default=100)
+    ap.add_argument("--no-serve", action="store_true", help="headline: skip the serving run")
+    ap.add_argument("--no-register", action="store_true",
+                    help="headline: skip the single-subject registration (extra keys)")
+    ap.add_argument("--no-full", action="store_true",
+                    help="headline: skip the 100-step batched and plain runs")
     ap.add_argument("--batch-sizes", default="",
                     help="edge lengths of cubic subjects to draw from (e.g. 32,48,64) instead of "
                          "96^3/128^3/160x192x160")
@@ -144,31 +160,18 @@ def _torch_sample(torch, f, q):
 
 
 def _torch_smooth(torch, phi, sigma):
+    """Appendix A's filter through torch's FFT: the spectrum of each component
+    times exp(-sigma^2 |omega|^2 / 2), omega in radians per voxel."""
     if sigma <= 0:
         return phi
-    F = torch.nn.functional
-    r = int(4.0 * sigma + 0.5)
-    k = torch.arange(-r, r + 1, device=phi.device, dtype=torch.float64)
-    w = torch.exp(-0.5 * (k / sigma) ** 2)
-    w = (w / w.sum()).float()
-    x = phi[None]
-    for ax in range(3):
-        shape = [1, 1, 1]
-        shape[ax] = 2 * r + 1
-        pad = [0, 0, 0, 0, 0, 0]
-        pad[2 * (2 - ax)] = pad[2 * (2 - ax) + 1] = r
-        xp = x
-        n = x.shape[2 + ax]
-        while pad[2 * (2 - ax)] > 0:
-            step = min(pad[2 * (2 - ax)], n)
-            pp = [0] * 6
-            pp[2 * (2 - ax)] = pp[2 * (2 - ax) + 1] = step
-            xp = F.pad(xp, pp, mode="circular")
-            pad[2 * (2 - ax)] -= step
-            pad[2 * (2 - ax) + 1] -= step
-            n = xp.shape[2 + ax]
-        x = F.conv3d(xp, w.view(1, 1, *shape).expand(3, 1, *shape).contiguous(), groups=3)
-    return x[0]
+    D, H, W = phi.shape[1:]
+    dev = phi.device
+    om = [2 * math.pi * torch.fft.fftfreq(n, device=dev, dtype=torch.float64) for n in (D, H)]
+    omx = 2 * math.pi * torch.fft.rfftfreq(W, device=dev, dtype=torch.float64)
+    w2 = om[0][:, None, None] ** 2 + om[1][None, :, None] ** 2 + omx[None, None, :] ** 2
+    tf = torch.exp(-0.5 * sigma ** 2 * w2).to(phi.dtype)
+    spec = torch.fft.rfftn(phi, dim=(1, 2, 3))
+    return torch.fft.irfftn(spec * tf, s=(D, H, W), dim=(1, 2, 3))
 
 
 def torch_loss(torch, phis, images, K=7, window=7, metric="silncc", alpha_ss=1.0,
@@ -332,7 +335,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     ctx = Context(0)
-    if args.workload == "register":
+    if args.workload == "headline":
+        out = bench_headline(args, ctx, dev, torch, synth, MusterParams)
+    elif args.workload == "register":
         out = bench_register(args, ctx, dev, torch, synth, MusterParams)
     elif args.workload == "batch":
         out = bench_batch(args, ctx, dev, torch, synth, MusterParams)
@@ -348,6 +353,247 @@ def main():
         torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def host_info():
+    """The host the CPU baseline ran on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "cpus_allowed": aff}
+
+
+def cpu_baseline_steps(images, params_np, pool_times, budget_s=10.0, max_steps=8):
+    """The FP64 oracle, as it stands, on one core (BLAS held to one thread):
+    Adam steps (loss, hand-written gradient, update) of the given sessions
+    pooled pool_times times (2x2x2 means), as many as start within budget_s.
+    Returns (session-voxel-iterations per second, steps, seconds, grid, the
+    seconds of each step)."""
+    from oracle import muster_oracle as O
+    from threadpoolctl import threadpool_limits
+    imgs = [np.asarray(x, np.float64) for x in images]
+    for _ in range(pool_times):
+        imgs = [O.pool2(x) for x in imgs]
+    N = len(imgs)
+    ff = getattr(params_np, "flow_factor", 1)
+    phis = [np.zeros((3,) + tuple(n // ff for n in imgs[0].shape)) for _ in range(N - 1)]
+    m = [np.zeros_like(x) for x in phis]
+    v = [np.zeros_like(x) for x in phis]
+    per = []
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        steps = 0
+        while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < budget_s):
+            ts = time.perf_counter()
+            steps += 1
+            _, grads, _ = O.loss_and_grad(phis, imgs, params_np)
+            for k in range(N - 1):
+                phis[k], m[k], v[k] = O.adam_step(phis[k], grads[k], m[k], v[k], steps,
+                                                  params_np.lr)
+            per.append(round(time.perf_counter() - ts, 3))
+        dt = time.perf_counter() - t0
+    V = int(np.prod(imgs[0].shape))
+    return N * V * steps / dt, steps, dt, tuple(imgs[0].shape), per
+
+
+def bench_headline(args, ctx, dev, torch, synth, MusterParams):
+    from paper_2412_14671_amd import Server
+    W, K, T = args.warmup, args.steps, args.batch_iters
+    subjects = []
+    for k in range(args.batch_subjects):
+        N, shape = synth.subject_draw(100 + k)
+        log(f"subject {k} (seed {100 + k}): N={N} {shape}")
+        subjects.append(synth.batch_subject(100 + k, device=dev))
+    imgs = [s.images.contiguous() for s in subjects]
+    times = [s.times for s in subjects]
+    per_step = sum(int(x.shape[0]) * x[0].numel() for x in imgs)   # sum_s N_s V_s
+
+    def params(iters, graph):
+        return MusterParams(iters=[iters], K=7, window=7, metric="silncc", alpha_ss=1.0, lr=0.1,
+                            use_graph=graph)
+
+    torch.cuda.synchronize()
+    if W > 0:
+        log(f"warmup: {W} batched steps")
+        ctx.register_batch(imgs, times, params(W, False))
+        torch.cuda.synchronize()
+    # timed: K batched steps, eager, events on the dominant kernel's launches
+    ctx.set_kernel_timing_only(["exp_bwd"])
+    ctx.kernel_stats_reset()
+    log(f"timed: {K} batched steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.register_batch(imgs, times, params(K, False))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.set_kernel_timing(False)
+    stats_timed = ctx.kernel_stats()
+    value = per_step * K / dt
+    # exp_bwd launches of one batched step: one per squaring (K = 7), each over
+    # every direction of every subject
+    grid = sum(2 * (s.images.shape[0] - 1) * (-(-s.images.shape[1] // 8)) * (-(-s.images.shape[2] // 8))
+               * (-(-s.images.shape[3] // 16)) for s in subjects)
+    traffic = {"exp_bwd": traffic_per_launch(args.traffic, "exp_bwd", {grid: 7 * K})}
+    _, roof = roofline_from_stats(stats_timed, traffic, stats_timed)
+    if roof is not None:
+        roof["l2_hit_rate"] = l2_hit_per_launch(args.l2hit, "k_exp_bwd", {grid: 7 * K})
+    out = {
+        "metric": "voxel-iterations/sec (fwd+bwd) batched vs plain loop; p50/p99 job latency",
+        "value": round(float(value), 1),
+        "unit": "session-voxel-iterations/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(dt / K * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{len(subjects)} phantom subjects (seeds 100-{99 + len(subjects)}), "
+                                "N in 3..10, sizes 96^3/128^3/160x192x160, one batched step of all "
+                                "subjects at the finest level, SiLNCC w7, K7, alpha_ss 1, lr 0.1"),
+                   "subjects": [[int(s.images.shape[0])] + list(s.images.shape[1:]) for s in subjects],
+                   "session_voxels_per_step": per_step},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_full:
+        # the whole schedule, batched (graph-replayed) against the plain loop
+        log(f"batched: {T} steps, graph-replayed")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs, _ = ctx.register_batch(imgs, times, params(T, True))
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        log(f"plain loop: {T} steps per subject, eager, default tiles")
+        ctx.set_tiling("default")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain = []
+        for im, tm in zip(imgs, times):
+            svf, _, _ = ctx.register(im, tm, params(T, False))
+            plain.append(svf)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        ctx.set_tiling("autotune")
+        eu_b = [eu(s.svf_true.cpu().numpy(), o.cpu().numpy(), s.roi.cpu().numpy())
+                for s, o in zip(subjects, outs)]
+        eu_p = [eu(s.svf_true.cpu().numpy(), o.cpu().numpy(), s.roi.cpu().numpy())
+                for s, o in zip(subjects, plain)]
+        eu_0 = [eu(s.svf_true.cpu().numpy(), np.zeros(tuple(o.shape)), s.roi.cpu().numpy())
+                for s, o in zip(subjects, outs)]
+        del outs, plain
+        out.update({
+            "batched_value": round(per_step * T / tb, 1),
+            "batched_s": round(tb, 3),
+            "plain_loop_value": round(per_step * T / tp, 1),
+            "plain_loop_s": round(tp, 3),
+            "batched_over_plain": round(tp / tb, 3),
+            "eu_batched": [round(x, 4) for x in eu_b],
+            "eu_plain": [round(x, 4) for x in eu_p],
+            "eu_at_zero": [round(x, 4) for x in eu_0],
+            "eu_max_abs_diff": round(max(abs(a - b) for a, b in zip(eu_b, eu_p)), 5),
+        })
+    if not args.no_serve:
+        # continuous batching: Poisson arrivals of the same subjects on the
+        # three-level pyramid
+        rng = np.random.Generator(np.random.PCG64(5))
+        sparams = MusterParams(iters=[200, 100, 50], K=7, window=7, metric="silncc",
+                               alpha_ss=1.0, lr=0.1)
+        from paper_2412_14671_amd import Context
+        sctx = Context(0)
+        srv = Server(sctx)
+        arrivals, t = [], 0.0
+        while True:
+            t += rng.exponential(1.0 / args.serve_rate)
+            if t >= args.serve_seconds:
+                break
+            arrivals.append((t, int(rng.integers(0, len(subjects)))))
+        log(f"serving: {len(arrivals)} arrivals over {args.serve_seconds:g} s")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = []
+        for at, k in arrivals:
+            now = time.perf_counter() - t0
+            if at > now:
+                time.sleep(at - now)
+            tickets.append((srv.submit(imgs[k], times[k], sparams), k))
+        reps = []
+        for n, ((tk, _), k) in enumerate(tickets):
+            reps.append(srv.wait(tk))
+            if (n + 1) % 10 == 0:
+                log(f"serving: {n + 1} of {len(tickets)} done")
+        wall = time.perf_counter() - t0
+        lat = np.array([r["seconds"] for r in reps])
+        eus = [eu(subjects[k].svf_true.cpu().numpy(), o.cpu().numpy(), subjects[k].roi.cpu().numpy())
+               for ((_, o), k), r in zip(tickets, reps) if r["status"] == 0]
+        vox = sum(imgs[k].shape[0] * sum(imgs[k][0].numel() // 8 ** (2 - l) * it
+                                         for l, it in enumerate([200, 100, 50]))
+                  for _, k in tickets)
+        out["serving"] = {
+            "workload": (f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s, "
+                         "each one of the sixteen subjects, pyramid 200/100/50"),
+            "jobs": len(tickets), "wall_s": round(wall, 2),
+            "jobs_per_s": round(len(tickets) / wall, 3),
+            "value": round(vox / wall, 1),
+            "p50_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "queue_p50_s": round(float(np.percentile([r["queue_seconds"] for r in reps], 50)), 3),
+            "failed": int(sum(r["status"] != 0 for r in reps)),
+            "eu_mean": round(float(np.mean(eus)), 4) if eus else None,
+        }
+        del tickets
+        sctx.close()
+    if not args.no_register:
+        log("single subject: six 160x192x160 sessions, 3 levels")
+        reg = bench_register_once(args, ctx, dev, torch, synth, MusterParams)
+        out["single_subject"] = reg
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        kc = min(range(len(subjects)), key=lambda k: imgs[k].numel())
+        from oracle import muster_oracle as O
+        p = O.Params(K=7, window=7, metric=O.SILNCC, alpha_ss=1.0, lr=0.1)
+        rate, n, dt_c, grid_c, per = cpu_baseline_steps(imgs[kc].cpu().numpy(), p, 1)
+        out["cpu_baseline"] = {
+            "value": rate, "unit": "session-voxel-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{n} Adam step{'s' if n > 1 else ''} (loss, adjoint gradient, update) of "
+                       f"subject {kc} ({imgs[kc].shape[0]} sessions) with its images pooled once "
+                       f"to {grid_c[0]}x{grid_c[1]}x{grid_c[2]}, NumPy float64 on one core, "
+                       f"{dt_c:.1f} s"),
+            "step_seconds": per, **host_info()}
+    return out
+
+
+def bench_register_once(args, ctx, dev, torch, synth, MusterParams):
+    """One warm-up and one timed registration of the single six-session
+    160x192x160 subject (three levels, 200/100/50 steps, SiLNCC w7, K7,
+    alpha_ss and smoothing as set), graph-replayed; Eu against the ground
+    truth."""
+    shape = tuple(int(x) for x in args.shape.split(","))
+    iters = [int(x) for x in args.iters.split(",")]
+    N = args.sessions
+    s = synth.phantom_series(shape, N, seed=2, device=dev)
+    params = MusterParams(iters=iters, K=7, window=args.window, metric=args.metric,
+                          alpha_ss=args.alpha, lr=0.1, smooth_sigma=args.smooth,
+                          flow_factor=args.flow_factor)
+    L = len(iters)
+    vox = sum(N * np.prod([d // 2 ** (L - 1 - l) for d in shape]) * iters[l] for l in range(L))
+    ctx.register(s.images, s.times, params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    svf, _, rep = ctx.register(s.images, s.times, params)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    roi = s.roi.cpu().numpy()
+    return {"workload": (f"one subject, {N} phantom sessions {shape[0]}x{shape[1]}x{shape[2]}, "
+                         f"{L}-level pyramid {'/'.join(map(str, iters))} steps, SiLNCC w{args.window}, "
+                         f"K7, alpha_ss {args.alpha:g}, smoothing sigma {args.smooth:g}"),
+            "seconds": round(dt, 3), "value": round(float(vox / dt), 1),
+            "eu_voxels": round(eu(s.svf_true.cpu().numpy(), svf.cpu().numpy(), roi), 4),
+            "eu_at_zero": round(eu(s.svf_true.cpu().numpy(), np.zeros(tuple(svf.shape)), roi), 4),
+            "loss_first": rep["loss_first"], "loss_last": rep["loss_last"]}
 
 
 def bench_register(args, ctx, dev, torch, synth, MusterParams):

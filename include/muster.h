@@ -86,11 +86,15 @@ typedef struct muster_params {
   int use_graph;                   /* 1: replay each level's iteration as a
                                       captured hipGraph; 0: eager launches        */
   float smooth_sigma;              /* Gaussian smoothing of the flow before Exp
-                                      (Sec. 2.4, Appendix A), in voxels of the
+                                      (Sec. 2.4, Appendix A): the transfer
+                                      function exp(-sigma^2 |omega|^2 / 2) on the
+                                      periodic grid, sigma in voxels of the
                                       finest level, halved per coarser level;
-                                      periodic, truncated at 4 sigma; 0 = off;
-                                      at most 15.8; with smoothing on, each
-                                      dimension is at most 4096                   */
+                                      0 = off; at most 22.  Its spatial taps
+                                      must fit a radius of 128 on every line of
+                                      every level (below sigma ~2 they span the
+                                      whole line, so such lines are at most 257
+                                      voxels); each dimension is at most 4096  */
   float alpha_l2;                  /* weight of L_L2 (second form of Eq. reg_ss):
                                       (1/(N-1)) sum_i mean_p |phi_i(p)|^2; 0 = off */
   float alpha_ts;                  /* weight of L_ts (Eq. reg_ts):
@@ -278,7 +282,11 @@ muster_status muster_saved_free(muster_saved* saved);
 muster_status muster_exp(muster_ctx* ctx, void* stream, const int dims[3], int K, int sign,
                          const float* svf_dev, float* disp_dev, float* steps_dev);
 /* grad_svf = d<G, Exp(sign*svf)>/dsvf for G = grad_disp (adjoint of
- * muster_exp), in MUSTER_EXP_STORE or _RECOMPUTE mode. */
+ * muster_exp), in MUSTER_EXP_STORE or _RECOMPUTE mode.  With K >= 2 the
+ * squaring steps hand their scatter boxes to each other through staging
+ * slots, as the registration's backward pass does (the kernels it times);
+ * mode | MUSTER_EXP_FLAT adds every step into a flat field instead. */
+#define MUSTER_EXP_FLAT 4
 muster_status muster_exp_bwd(muster_ctx* ctx, void* stream, const int dims[3], int K,
                              int sign, const float* svf_dev, const float* grad_disp_dev,
                              float* grad_svf_dev, int mode);
@@ -308,10 +316,13 @@ muster_status muster_reg(muster_ctx* ctx, void* stream, const int dims[3],
 muster_status muster_pool2(muster_ctx* ctx, void* stream, const int dims[3],
                            const float* src_dev, float* dst_dev);
 /* Gaussian smoothing of a vector field [3][D][H][W] (Sec. 2.4, Appendix A):
- * separable periodic convolution with the sampled Gaussian of width sigma
- * voxels, normalised and truncated at radius int(4 sigma + 0.5) <= 64.
- * Each dimension is at most 4096 (a whole line is staged on chip).
- * src and dst must not overlap; MUSTER_E_INVALID otherwise. */
+ * the Fourier-domain filter exp(-sigma^2 |omega|^2 / 2) of the periodic grid
+ * (omega in radians per voxel, sigma in voxels, 0 < sigma <= 22), applied as
+ * one circular convolution per axis whose taps are that filter's inverse DFT
+ * along the axis, kept out to where they sum below 2^-26 (the whole line at
+ * small sigma); the radius must be at most 128 on every axis.  Each
+ * dimension is at most 4096 (a whole line is staged on chip).  src and dst
+ * must not overlap; MUSTER_E_INVALID otherwise. */
 muster_status muster_smooth(muster_ctx* ctx, void* stream, const int dims[3], float sigma,
                             const float* src_dev, float* dst_dev);
 /* Displacement field on the 2x finer grid: dst(x) = 2 * src((x - 0.5)/2);

@@ -383,36 +383,35 @@ def reg_ss_grad(phi: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Gaussian smoothing of the flow (Sec. 2.4 and Appendix A: the flow field is
-# smoothed with a Gaussian kernel, applied through FFTs).  Reading: a periodic
-# (circular, as with the FFT) separable convolution with the sampled Gaussian
-# exp(-k^2 / (2 sigma^2)), normalised to unit sum and truncated at radius
-# int(4 sigma + 0.5).  The operator is symmetric, so its adjoint is itself.
+# Gaussian smoothing of the flow (Sec. 2.4 and Appendix A).  Appendix A
+# defines the filter in the Fourier domain: the spectrum of the field is
+# multiplied by exp(-(omega / omega_s)^2 / 2) and transformed back.  With the
+# discrete Fourier transform of the grid, omega is the angular frequency in
+# radians per voxel, omega_k = 2 pi k / n along an axis of n voxels (k taken
+# in -n/2..n/2), and omega_s = 1 / sigma for a width sigma in voxels, so the
+# transfer is exp(-sigma^2 |omega|^2 / 2).  The filter is therefore periodic
+# (the FFT's boundary), real, and even in omega: it maps real fields to real
+# fields and is its own adjoint.
 # ---------------------------------------------------------------------------
 
-def gaussian_taps(sigma: float) -> np.ndarray:
-    """Normalised taps w_{-r..r} of the truncated sampled Gaussian."""
-    r = int(4.0 * sigma + 0.5)
-    k = np.arange(-r, r + 1, dtype=np.float64)
-    w = np.exp(-0.5 * (k / sigma) ** 2)
-    return w / w.sum()
+def gaussian_transfer(shape, sigma: float) -> np.ndarray:
+    """exp(-sigma^2 |omega|^2 / 2) on the DFT frequencies of a grid of the
+    given (D, H, W) shape, omega in radians per voxel."""
+    om = [2.0 * np.pi * np.fft.fftfreq(n) for n in shape]
+    w2 = om[0][:, None, None] ** 2 + om[1][None, :, None] ** 2 + om[2][None, None, :] ** 2
+    return np.exp(-0.5 * sigma ** 2 * w2)
 
 
 def smooth(phi: np.ndarray, sigma: float) -> np.ndarray:
-    """Circular Gaussian smoothing of every component along z, y and x."""
+    """Appendix A's Fourier-domain Gaussian, applied to every component of a
+    (3, D, H, W) field: forward FFT over the three spatial axes, multiply by
+    the transfer function, inverse FFT, real part."""
     phi = np.asarray(phi, np.float64)
     if sigma <= 0.0:
         return phi.copy()
-    w = gaussian_taps(sigma)
-    r = (len(w) - 1) // 2
-    out = phi
-    for ax in (1, 2, 3):
-        acc = np.zeros_like(out)
-        for k in range(-r, r + 1):
-            # acc(x) += w_k * f(x + k), indices taken modulo the axis length
-            acc += w[k + r] * np.roll(out, -k, axis=ax)
-        out = acc
-    return out
+    tf = gaussian_transfer(phi.shape[1:], sigma)
+    spec = np.fft.fftn(phi, axes=(1, 2, 3))
+    return np.real(np.fft.ifftn(spec * tf[None], axes=(1, 2, 3)))
 
 
 # ---------------------------------------------------------------------------

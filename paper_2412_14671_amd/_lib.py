@@ -23,6 +23,7 @@ METRIC_LNCC, METRIC_SILNCC = 0, 1
 TILES_DEFAULT, TILES_AUTOTUNE, TILES_FIXED = 0, 1, 2
 SIM_SHAPES = [(8, 32), (16, 32), (8, 64)]
 EXP_STORE, EXP_RECOMPUTE = 0, 1
+EXP_FLAT = 4  # MUSTER_EXP_FLAT: or-ed into the mode of muster_exp_bwd
 KERNELS = ["exp_fwd", "compose_fwd", "sim_stats", "sim_grad", "compose_bwd", "exp_bwd", "adam",
            "finish", "pool2", "upsample2", "smooth", "upsample2_adj", "rigid", "warp", "unstage"]
 

@@ -109,9 +109,14 @@ class Context:
                                     _ptr(out), _ptr(st)))
         return (out, st) if steps else out
 
-    def exp_bwd(self, svf, grad_disp, K, sign=1, mode="store"):
+    def exp_bwd(self, svf, grad_disp, K, sign=1, mode="store", flat=False):
+        """Adjoint of exp.  flat=False (the default) runs the staged exchange
+        between squaring steps that the registration runs; flat=True the
+        flat path with global atomics."""
         out = torch.empty_like(svf)
         m = {"store": L.EXP_STORE, "recompute": L.EXP_RECOMPUTE}[mode]
+        if flat:
+            m |= L.EXP_FLAT
         L.check(self.lib.muster_exp_bwd(self.h, _stream(), _dims(svf.shape[1:]), K, sign,
                                         _ptr(svf), _ptr(grad_disp), _ptr(out), m))
         return out

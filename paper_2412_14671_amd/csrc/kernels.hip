@@ -210,6 +210,21 @@ __device__ __forceinline__ int dpp_max(int v) {
              max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
 }
 
+// Sum over a wave by the same four DPP steps: after them every lane of a row
+// holds its row's sum, in the same order in every lane, so the result is
+// wave-uniform and does not depend on the lane a value came from.
+__device__ __forceinline__ float dpp_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x141, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x140, 0xF, 0xF, false));
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 15));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 31));
+  const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 47));
+  const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  return (a + b) + (c + d);
+}
+
 // Bounding box of the cells a tile touches.
 struct BBox {
   int lz, ly, lx, ez, ey, ex, cells;
@@ -369,15 +384,18 @@ __device__ __forceinline__ void jt_cells(const cgfloat* __restrict__ f, float a,
 // term to add at its own position (oz, oy, ox).
 //
 // The bins are 32-bit fixed point: every contribution is scaled by
-// 2^23 / m, where m is the largest magnitude the block spreads, truncated
-// (an error below 2^-23 m per contribution), and added with an integer LDS
-// atomic; integer LDS atomics run several times
-// faster than float ones on this hardware and make the in-block sum
-// independent of the order of the adds.  A bin can absorb contributions of
-// total weight up to 256 (a 256-fold local compression of the sampling
-// positions) before it could overflow.  Each non-zero bin is then added to the
-// field with one hardware float atomic.
-constexpr float FIX_SCALE = 8388608.0f;  // 2^23
+// min(2^23 / m, 2^30 / S), where m is the largest magnitude the block
+// spreads and S the sum over its voxels of their largest magnitudes,
+// truncated, and added with an integer LDS atomic; integer LDS atomics run
+// several times faster than float ones on this hardware and make the in-block
+// sum independent of the order of the adds.  A bin holds at most the weighted
+// values of the block's voxels, so its magnitude stays below 2^30 however
+// strongly the sampling positions crowd into one cell: no bin can overflow.
+// The error per contribution is below one quantum, 2^-23 m for spread-out
+// boxes and 2^-30 S where many voxels share cells.  Each non-zero bin is then
+// added to the field with one hardware float atomic.
+constexpr float FIX_SCALE = 8388608.0f;   // 2^23
+constexpr float FIX_TOTAL = 1073741824.0f; // 2^30
 static_assert(SCATTER_CELLS % 4 == 0, "bin planes are cleared as int4");
 
 struct ScatterVox {
@@ -388,15 +406,16 @@ struct ScatterVox {
   float own[3];        // value added at the own voxel
 };
 
-// Bounding box (lo/hi per axis) and largest magnitude over the block in one
-// reduction: wave shuffles, one LDS exchange, one barrier.
+// Bounding box (lo/hi per axis), largest magnitude and sum of magnitudes over
+// the block in one reduction: wave DPP steps, one LDS exchange, one barrier.
 struct ScatterBox {
   BBox bb;
   float bmax;
+  float bsum;
 };
 
 template <int NT>
-__device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], float mx,
+__device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], float mx, float sm,
                                                   int* sred) {
   // mx >= 0 (fmaxf drops NaN operands), so its bits order like its values
 #pragma unroll
@@ -405,6 +424,7 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
     hi[d] = dpp_max(hi[d]);
   }
   const int mxb = dpp_max(__float_as_int(mx));
+  const float smw = dpp_sum(sm);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
@@ -413,10 +433,12 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
       sred[w * 8 + 3 + d] = hi[d];
     }
     sred[w * 8 + 6] = mxb;
+    sred[w * 8 + 7] = __float_as_int(smw);
   }
   __syncthreads();
   int l[3] = {INT_MAX, INT_MAX, INT_MAX}, h[3] = {INT_MIN, INT_MIN, INT_MIN};
   int mb = 0;
+  float sb_sum = 0.f;
 #pragma unroll
   for (int i = 0; i < NT / 64; ++i) {
 #pragma unroll
@@ -425,9 +447,11 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
       h[d] = max(h[d], sred[i * 8 + 3 + d]);
     }
     mb = max(mb, sred[i * 8 + 6]);
+    sb_sum += __int_as_float(sred[i * 8 + 7]);
   }
   ScatterBox sb;
   sb.bmax = __int_as_float(mb);
+  sb.bsum = sb_sum;
   sb.bb.lz = l[0]; sb.bb.ly = l[1]; sb.bb.lx = l[2];
   if (h[0] < l[0]) {
     sb.bb.ez = sb.bb.ey = sb.bb.ex = 0;
@@ -473,7 +497,7 @@ __device__ __forceinline__ void sample_cells_lds(const cgfloat* __restrict__ f, 
     lo[1] = min(lo[1], cs.ay[j].i0); hi[1] = max(hi[1], cs.ay[j].i0 + 1);
     lo[2] = min(lo[2], cs.ax[j].i0); hi[2] = max(hi[2], cs.ax[j].i0 + 1);
   }
-  const BBox bb = scatter_box<BLOCK>(lo, hi, 0.f, sred).bb;
+  const BBox bb = scatter_box<BLOCK>(lo, hi, 0.f, 0.f, sred).bb;
   if (bb.cells == 0 || bb.cells > GATHER_CELLS) {  // block-uniform
     sample_cells(f, V, H, W, cs, out);
     return;
@@ -588,29 +612,35 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
   const int HW = H * W, V = D * HW;
   int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
   int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-  float mx = 0.f;
+  float mx = 0.f, sm = 0.f;
 #pragma unroll
   for (int j = 0; j < VP; ++j) {
     if (sv[j].cz < 0) continue;
     lo[0] = min(lo[0], sv[j].cz); hi[0] = max(hi[0], sv[j].cz + 1);
     lo[1] = min(lo[1], sv[j].cy); hi[1] = max(hi[1], sv[j].cy + 1);
     lo[2] = min(lo[2], sv[j].cx); hi[2] = max(hi[2], sv[j].cx + 1);
-    mx = fmaxf(mx, fmaxf(fabsf(sv[j].g[0]), fmaxf(fabsf(sv[j].g[1]), fabsf(sv[j].g[2]))));
+    const float gm = fmaxf(fabsf(sv[j].g[0]), fmaxf(fabsf(sv[j].g[1]), fabsf(sv[j].g[2])));
+    mx = fmaxf(mx, gm);
+    sm += gm;
     if (OWN) {
       lo[0] = min(lo[0], sv[j].oz); hi[0] = max(hi[0], sv[j].oz);
       lo[1] = min(lo[1], sv[j].oy); hi[1] = max(hi[1], sv[j].oy);
       lo[2] = min(lo[2], sv[j].ox); hi[2] = max(hi[2], sv[j].ox);
-      mx = fmaxf(mx, fmaxf(fabsf(sv[j].own[0]), fmaxf(fabsf(sv[j].own[1]), fabsf(sv[j].own[2]))));
+      const float om = fmaxf(fabsf(sv[j].own[0]), fmaxf(fabsf(sv[j].own[1]), fabsf(sv[j].own[2])));
+      mx = fmaxf(mx, om);
+      sm += om;
     }
   }
-  const ScatterBox sb = scatter_box<NT>(lo, hi, mx, sred);
+  const ScatterBox sb = scatter_box<NT>(lo, hi, mx, sm, sred);
   const BBox& bb = sb.bb;
   const float bmax = sb.bmax;
+  // the bins take finite values only; bsum bounds every bin's magnitude
+  const bool finite = bmax > 0.f && bmax < 3.0e38f && sb.bsum < 3.0e38f;
   bool staged = false;
   if (STAGE) {
     // the box goes to the staging slot if it fits and reaches no farther than
     // the 26 neighbouring tiles (where the reading step looks for it)
-    staged = bb.cells > 0 && bb.cells <= STAGE_CAP && bmax > 0.f && bmax < 3.0e38f &&
+    staged = bb.cells > 0 && bb.cells <= STAGE_CAP && finite &&
              bb.lz >= so.z0 - PT_Z && bb.lz + bb.ez <= so.z0 + 2 * PT_Z &&
              bb.ly >= so.y0 - PT_Y && bb.ly + bb.ey <= so.y0 + 2 * PT_Y &&
              bb.lx >= so.x0 - PT_X && bb.lx + bb.ex <= so.x0 + 2 * PT_X;
@@ -623,9 +653,9 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
     }
   }
   if (bb.cells == 0) return;
-  if (bb.cells <= SCATTER_CELLS && bmax > 0.f && bmax < 3.0e38f) {
-    const float scale = FIX_SCALE / bmax;
-    const float inv = bmax / FIX_SCALE;
+  if (bb.cells <= SCATTER_CELLS && finite) {
+    const float scale = fminf(FIX_SCALE / bmax, FIX_TOTAL / sb.bsum);
+    const float inv = 1.f / scale;
     const int cells = bb.cells;
     // one plane of SCATTER_CELLS bins per component: the plane offsets are
     // constants, which the LDS instructions take as immediate offsets
@@ -1758,9 +1788,12 @@ __global__ __launch_bounds__(BLOCK) void k_adam(const AdamItem* __restrict__ ite
 
 // ---------------------------------------------------------------------------
 // Gaussian smoothing of the flow (Sec. 2.4, Appendix A): one separable pass of
-// the circular convolution with the sampled, normalised Gaussian truncated at
-// the item's radius, on the three components.  The filter is symmetric, so
-// the same pass is its own adjoint.
+// the periodic filter along one axis, on the three components.  Appendix A
+// applies the Gaussian transfer function in the Fourier domain; its spatial
+// form on a periodic line is a circular convolution whose taps the host
+// computes from that transfer function (out to where they vanish below float
+// rounding, or over the whole line), so one pass per axis applies the whole
+// 3-D filter.  The taps are symmetric, so the same pass is its own adjoint.
 // ---------------------------------------------------------------------------
 // SMOOTH_S consecutive outputs, from p0 on, of the circular convolution of a
 // line of n samples held in LDS at line[pos * ls] with the taps w.  The line
@@ -1782,10 +1815,9 @@ __device__ __forceinline__ void smooth_chunk(const float* line, int ls, int n, i
   }
 }
 
-// One pass of the separable circular Gaussian (Appendix A reading: periodic
-// boundary, truncated sampled kernel of radius int(4 sigma + 0.5)).  A block
+// One pass of the separable periodic Gaussian with the item's taps.  A block
 // stages whole lines of one component in LDS, so every sample is read from
-// HBM once and written once.
+// HBM once and written once; a radius up to half the line wraps round it.
 __global__ __launch_bounds__(BLOCK) void k_smooth(const SmoothItem* __restrict__ items, int n_items,
                                                   int n_tiles) {
   extern __shared__ float lds[];

@@ -239,12 +239,15 @@ struct PullItem {
   JobState* js;
 };
 
-// One separable pass of the circular Gaussian smoothing along one axis, for
+// One separable pass of the periodic Gaussian smoothing along one axis, for
 // one field of three components.  A tile holds whole lines of one component
 // in LDS: `lines` adjacent x columns of lines along z or y, or `lines`
 // consecutive rows along x.  Taps w[SMOOTH_WPAD + k] for k = 0..2*radius are
-// the normalised Gaussian weights; every other entry is zero.
-constexpr int MAX_SMOOTH_RADIUS = 64;
+// the filter's weights at offsets k - radius along the periodic line (the
+// host derives them from the Fourier-domain transfer function); every other
+// entry is zero.
+constexpr int MAX_SMOOTH_RADIUS = 128;
+constexpr float MAX_SMOOTH_SIGMA = 22.0f;      // radius 5.66 sigma fits 128
 constexpr int SMOOTH_S = 8;                    // outputs per thread along a line
 constexpr int SMOOTH_WPAD = SMOOTH_S;
 constexpr int SMOOTH_U = 8;                    // loads in flight per thread when staging
@@ -346,6 +349,8 @@ hipError_t launch_smooth(const SmoothItem* items, int n_items, int n_tiles, int 
 // Fills the geometry and taps of a smoothing item; returns its tile count and
 // raises *lds_floats to the LDS the item needs.
 int smooth_item_setup(SmoothItem& it, const int dims[3], int axis, float sigma, int* lds_floats);
+// Radius of the smoothing taps on a periodic line of n samples.
+int smooth_radius(int n, float sigma);
 hipError_t launch_finish(JobState* const* states, int n_jobs, hipStream_t s);
 hipError_t launch_pool2(const PoolItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_upsample2(const UpItem* items, int n_items, int n_tiles, hipStream_t s);

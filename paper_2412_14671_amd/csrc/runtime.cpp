@@ -124,8 +124,9 @@ void validate_params(const muster_params& p) {
     fail(MUSTER_E_INVALID, "bad Adam constants");
   if (p.exp_mode != MUSTER_EXP_STORE && p.exp_mode != MUSTER_EXP_RECOMPUTE)
     fail(MUSTER_E_INVALID, "unknown exp_mode %d", p.exp_mode);
-  if (!(p.smooth_sigma >= 0.f) || (int)(4.0f * p.smooth_sigma + 0.5f) > MAX_SMOOTH_RADIUS)
-    fail(MUSTER_E_INVALID, "smooth_sigma must be in [0, 15.8] (got %g)", (double)p.smooth_sigma);
+  if (!(p.smooth_sigma >= 0.f) || !(p.smooth_sigma <= MAX_SMOOTH_SIGMA))
+    fail(MUSTER_E_INVALID, "smooth_sigma must be in [0, %g] (got %g)", (double)MAX_SMOOTH_SIGMA,
+         (double)p.smooth_sigma);
   if (p.flow_factor != 0 && p.flow_factor != 1 && p.flow_factor != 2)
     fail(MUSTER_E_INVALID, "flow_factor must be 1 or 2 (got %d)", p.flow_factor);
   if (!(p.alpha_l2 >= 0.f) || !std::isfinite(p.alpha_l2)) fail(MUSTER_E_INVALID, "alpha_l2 must be >= 0");
@@ -157,6 +158,20 @@ void validate_problem(int N, const int dims[3], const muster_params& p, const do
   }
   if (V * 3 >= (uint64_t)INT32_MAX) fail(MUSTER_E_INVALID, "volume too large (%llu voxels)",
                                          (unsigned long long)V);
+  if (p.smooth_sigma > 0.f) {
+    // the filter's taps at every level's flow grid must fit the kernel
+    for (int l = 0; l < p.levels; ++l) {
+      const int lf = 1 << (p.levels - 1 - l);
+      const float sg = p.smooth_sigma / (float)lf;
+      for (int d = 0; d < 3; ++d) {
+        const int n = dims[d] / (lf * ff);
+        const int r = smooth_radius(n, sg);
+        if (r > MAX_SMOOTH_RADIUS)
+          fail(MUSTER_E_INVALID, "smoothing width %g at level %d needs a kernel radius of %d on a "
+               "line of %d flow voxels (at most %d)", (double)sg, l, r, n, MAX_SMOOTH_RADIUS);
+      }
+    }
+  }
   if (times) {
     for (int i = 0; i < N; ++i) {
       if (!std::isfinite(times[i])) fail(MUSTER_E_INVALID, "times[%d] is not finite", i);
@@ -567,17 +582,88 @@ struct Builder {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Taps of the smoothing filter.  Appendix A filters in the Fourier domain with
+// the transfer function exp(-(omega / omega_s)^2 / 2), omega_s = 1 / sigma.
+// On a periodic line of n samples the filter is the circular convolution with
+// h[m] = (1/n) sum_k exp(-sigma^2 omega_k^2 / 2) cos(omega_k m), where
+// omega_k = 2 pi min(k, n - k) / n are the line's DFT frequencies in radians
+// per sample; the 3-D transfer is the product of the three axes', so one
+// pass per axis gives the whole filter.  The taps are kept out to the
+// smallest radius beyond which they sum to less than 2^-26 in magnitude (well
+// under float rounding of a unit-sum filter), or over the whole line when the
+// spectrum is still large at Nyquist and the taps ring all the way round
+// (small sigma).  The whole line of an even n is taken as offsets -n/2..n/2
+// with half of h[n/2] at each end, so that the taps stay symmetric.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SmoothTaps {
+  int radius = 0;
+  std::vector<double> w;  // offsets -radius..radius
+};
+
+const SmoothTaps& smooth_taps(int n, float sigma) {
+  static std::mutex mu;
+  static std::map<std::pair<int, float>, SmoothTaps> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_pair(n, sigma);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const double sg = sigma, two_pi = 2.0 * M_PI;
+  std::vector<double> H(n / 2 + 1);
+  for (int k = 0; k <= n / 2; ++k) {
+    const double om = two_pi * k / n;
+    H[k] = std::exp(-0.5 * sg * sg * om * om);
+  }
+  // h[m] for m = 0..n/2: the k and n-k terms of the sum are equal
+  std::vector<double> h(n / 2 + 1);
+  for (int m = 0; m <= n / 2; ++m) {
+    double acc = H[0];
+    for (int k = 1; 2 * k < n; ++k) acc += 2.0 * H[k] * std::cos(two_pi * (double)k * m / n);
+    if (n % 2 == 0) acc += H[n / 2] * ((m & 1) ? -1.0 : 1.0);
+    h[m] = acc / n;
+  }
+  // distinct offsets of the line: +-1..+-(n-1)/2, and n/2 once when n is even
+  const int half = (n - 1) / 2;
+  const double tol = std::ldexp(1.0, -26);
+  double tail = (n % 2 == 0 && n >= 2) ? std::fabs(h[n / 2]) : 0.0;
+  int r = half;
+  while (r > 0 && tail + 2.0 * std::fabs(h[r]) <= tol) {
+    tail += 2.0 * std::fabs(h[r]);
+    --r;
+  }
+  SmoothTaps t;
+  if (r == half && n % 2 == 0 && n >= 2 && tail > tol) {
+    // the whole line of an even n
+    t.radius = n / 2;
+    t.w.assign(2 * t.radius + 1, 0.0);
+    for (int m = -t.radius; m <= t.radius; ++m) t.w[m + t.radius] = h[std::abs(m)];
+    t.w[0] *= 0.5;
+    t.w[2 * t.radius] *= 0.5;
+  } else {
+    t.radius = r;
+    t.w.assign(2 * r + 1, 0.0);
+    for (int m = -r; m <= r; ++m) t.w[m + r] = h[std::abs(m)];
+  }
+  return cache.emplace(key, std::move(t)).first->second;
+}
+
+}  // namespace
+
+int smooth_radius(int n, float sigma) { return smooth_taps(n, sigma).radius; }
+
 int smooth_item_setup(SmoothItem& it, const int dims[3], int axis, float sigma, int* lds_floats) {
   it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
   it.axis = axis;
-  const double sg = sigma;
-  const int r = (int)(4.0 * sg + 0.5);
+  const SmoothTaps& tp = smooth_taps(dims[axis], sigma);
+  const int r = tp.radius;
+  if (r > MAX_SMOOTH_RADIUS)
+    fail(MUSTER_E_INVALID, "smoothing sigma %g on a line of %d voxels needs a kernel radius of %d "
+         "(at most %d)", (double)sigma, dims[axis], r, MAX_SMOOTH_RADIUS);
   it.radius = r;
   for (int k = 0; k < SMOOTH_WLEN; ++k) it.w[k] = 0.f;
-  double tot = 0.0;
-  for (int k = -r; k <= r; ++k) tot += std::exp(-0.5 * (k / sg) * (k / sg));
-  for (int k = -r; k <= r; ++k)
-    it.w[SMOOTH_WPAD + k + r] = (float)(std::exp(-0.5 * (k / sg) * (k / sg)) / tot);
+  for (int k = 0; k <= 2 * r; ++k) it.w[SMOOTH_WPAD + k] = (float)tp.w[k];
   // LDS floats a tile of L lines needs, and the number of lines on offer
   const int n = dims[axis];
   const int avail = axis == 2 ? dims[0] * dims[1] : dims[2];
@@ -2069,23 +2155,37 @@ muster_status muster_exp_bwd(muster_ctx* h, void* stream, const int dims[3], int
     check_dims(dims, 2);
     NEED(K >= 1 && K <= 20, "K must be in 1..20");
     NEED(sign == 1 || sign == -1, "sign must be +1 or -1");
+    const bool flat_only = (mode & MUSTER_EXP_FLAT) != 0;
+    mode &= ~MUSTER_EXP_FLAT;
     NEED(mode == MUSTER_EXP_STORE || mode == MUSTER_EXP_RECOMPUTE, "bad mode");
     std::lock_guard<std::mutex> lk(ctx->mu);
     StepCall sc{ctx, (hipStream_t)stream, {}};
     const size_t V = (size_t)dims[0] * dims[1] * dims[2];
     const size_t F = 3 * V;
     const int nstore = mode == MUSTER_EXP_STORE ? std::max(K - 1, 0) : 2;
-    DevMem us, pp, zero;
+    const int tiles = point_tiles(dims[0], dims[1], dims[2]);
+    // the squaring steps exchange their scatter boxes through staging slots,
+    // as in the registration, unless the caller asks for the flat path
+    const bool staged = !flat_only && K >= 2;
+    DevMem us, pp, zero, stage, desc, flags;
     us.alloc(ctx, std::max<size_t>(nstore, 1) * F * sizeof(float));
     pp.alloc(ctx, 2 * F * sizeof(float));
     zero.alloc(ctx, F * sizeof(float));
     MUSTER_HIP(launch_fill(pp.as<float>(), (int64_t)(2 * F), 0.f, sc.s));
     MUSTER_HIP(launch_fill(zero.as<float>(), (int64_t)F, 0.f, sc.s));
+    if (staged) {
+      stage.alloc(ctx, (size_t)2 * tiles * 3 * STAGE_CAP * sizeof(float));
+      desc.alloc(ctx, (size_t)2 * tiles * 8 * sizeof(int));
+      flags.alloc(ctx, (size_t)K * sizeof(int));
+      // zero bits: the overflow flags start clear
+      MUSTER_HIP(launch_fill(flags.as<float>(), (int64_t)K, 0.f, sc.s));
+    }
+    auto st_slot = [&](int k) { return stage.as<float>() + (size_t)k * tiles * 3 * STAGE_CAP; };
+    auto de_slot = [&](int k) { return desc.as<int>() + (size_t)k * tiles * 8; };
     const float a0 = (float)sign * std::ldexp(1.f, -K);
     auto ustore = [&](int k) { return us.as<float>() + (size_t)(k - 1) * F; };        // store: u_k
     auto uscr = [&](int k) { return us.as<float>() + (size_t)((k - 1) % 2) * F; };    // recompute
-    const int tiles = point_tiles(dims[0], dims[1], dims[2]);
-    struct L { int kind; size_t off; };
+    struct L { int kind; size_t off; int smode; };
     std::vector<L> seq;
     auto fwd_step = [&](int k, float* src, float* dst) {
       ExpFwdItem it{};
@@ -2093,7 +2193,7 @@ muster_status muster_exp_bwd(muster_ctx* h, void* stream, const int dims[3], int
       it.src = k == 0 ? svf : src;
       it.a = k == 0 ? a0 : 1.f;
       it.dst = dst;
-      seq.push_back({0, sc.add(it)});
+      seq.push_back({0, sc.add(it), 0});
     };
     if (mode == MUSTER_EXP_STORE)
       for (int k = 0; k < K - 1; ++k) fwd_step(k, k == 0 ? nullptr : ustore(k), ustore(k + 1));
@@ -2114,7 +2214,28 @@ muster_status muster_exp_bwd(muster_ctx* h, void* stream, const int dims[3], int
       it.gin = s == K - 1 ? const_cast<float*>(grad_disp) : pp.as<float>() + (size_t)((s + 1) % 2) * F;
       it.gout = pp.as<float>() + (size_t)(s % 2) * F;
       it.zero_in = s < K - 1 ? 1 : 0;
-      seq.push_back({1, sc.add(it)});
+      const bool in_st = staged && s < K - 1;
+      if (in_st) {
+        it.stage_in = st_slot((s + 1) % 2);
+        it.desc_in = de_slot((s + 1) % 2);
+        it.flag_in = flags.as<int>() + s + 1;
+      }
+      if (staged) {
+        it.stage_out = st_slot(s % 2);
+        it.desc_out = de_slot(s % 2);
+        it.flag_out = flags.as<int>() + s;
+      }
+      seq.push_back({1, sc.add(it), in_st ? 2 : (staged ? 1 : 0)});
+    }
+    if (staged) {
+      // the staged G_0 to the flat field, as k_unstage does in the registration
+      ExpBwdItem it{};
+      it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+      it.gout = pp.as<float>();
+      it.stage_in = st_slot(0);
+      it.desc_in = de_slot(0);
+      it.flag_in = flags.as<int>();
+      seq.push_back({3, sc.add(it), 0});
     }
     AdamItem ai{};
     ai.n = (int)V;
@@ -2124,12 +2245,13 @@ muster_status muster_exp_bwd(muster_ctx* h, void* stream, const int dims[3], int
     ai.scale = a0;
     ai.gscale = 1.f;
     ai.mode = 1;
-    seq.push_back({2, sc.add(ai)});
+    seq.push_back({2, sc.add(ai), 0});
     sc.upload();
     for (auto& l : seq) {
       const unsigned char* p = sc.dev() + l.off;
       if (l.kind == 0) MUSTER_HIP(launch_exp_fwd((const ExpFwdItem*)p, 1, tiles, sc.s));
-      if (l.kind == 1) MUSTER_HIP(launch_exp_bwd((const ExpBwdItem*)p, 1, tiles, 0, true, sc.s));
+      if (l.kind == 1) MUSTER_HIP(launch_exp_bwd((const ExpBwdItem*)p, 1, tiles, l.smode, false, sc.s));
+      if (l.kind == 3) MUSTER_HIP(launch_unstage((const ExpBwdItem*)p, 1, tiles, sc.s));
       if (l.kind == 2) MUSTER_HIP(launch_adam((const AdamItem*)p, 1, elem_tiles(V), sc.s));
     }
     MUSTER_HIP(hipStreamSynchronize(sc.s));
@@ -2283,9 +2405,13 @@ muster_status muster_smooth(muster_ctx* h, void* stream, const int dims[3], floa
     NEED(ctx && src && dst, "NULL argument");
     NEED(src != dst, "src and dst must differ");
     check_dims(dims, 1);
-    NEED(sigma > 0.f && (int)(4.0f * sigma + 0.5f) <= MAX_SMOOTH_RADIUS, "sigma must be in (0, 15.8]");
+    NEED(sigma > 0.f && sigma <= MAX_SMOOTH_SIGMA, "sigma must be in (0, 22]");
     NEED(dims[0] <= SMOOTH_MAX_DIM && dims[1] <= SMOOTH_MAX_DIM && dims[2] <= SMOOTH_MAX_DIM,
          "every dimension must be at most 4096");
+    for (int a = 0; a < 3; ++a)
+      NEED(smooth_radius(dims[a], sigma) <= MAX_SMOOTH_RADIUS,
+           "sigma needs a kernel radius above 128 along an axis (whole lines up to 257 voxels "
+           "at small sigma)");
     std::lock_guard<std::mutex> lk(ctx->mu);
     StepCall sc{ctx, (hipStream_t)stream, {}};
     const size_t V = (size_t)dims[0] * dims[1] * dims[2];

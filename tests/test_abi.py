@@ -115,7 +115,8 @@ def test_footprint_counts_fields(lib):
     (3, (32, 32, 32), {"levels": 0}),
     (3, (32, 32, 32), {"warmup": 1.5}),
     (3, (32, 32, 32), {"smooth_sigma": -1.0}),
-    (3, (32, 32, 32), {"smooth_sigma": 20.0}),
+    (3, (32, 32, 32), {"smooth_sigma": 30.0}),   # above the largest width
+    (3, (16, 16, 520), {"smooth_sigma": 0.5}),   # taps span a line longer than 257
     (3, (32, 32, 32), {"alpha_l2": -0.5}),
     (3, (32, 32, 32), {"alpha_ts": float("nan")}),
 ])

@@ -27,7 +27,7 @@ def test_eager_loss_and_gradient_match_oracle(metric, sigma):
                  smooth_sigma=sigma)
     L_ref, g_ref, _ = O.loss_and_grad([x.astype(np.float64) for x in phis],
                                       list(s.images.numpy().astype(np.float64)), p)
-    assert abs(float(L) - L_ref) < 1e-3 * abs(L_ref)
+    assert abs(float(L.detach()) - L_ref) < 1e-3 * abs(L_ref)
     g = np.stack([t.grad.cpu().numpy() for t in tp]).astype(np.float64)
     gr = np.stack(g_ref)
     assert np.linalg.norm(g - gr) / np.linalg.norm(gr) < 1e-2

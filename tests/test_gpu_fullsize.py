@@ -5,10 +5,13 @@ statistics and similarity gradient (SiLNCC, w 7).  Inputs are made like the
 benchmark's: two phantom sessions and their interval's velocity field
 (Gaussian-smoothed, sigma 6 voxels, up to 1.5 voxels), the pair field from
 integrating it, and an upstream gradient smoothed at sigma 3.  The kernels run
-in the configuration the benchmark times (8x8x16-voxel tiles, the autotuned
-window-statistics tiling of this shape).  The oracle takes 2-40 s per step at
-this size.  Tolerances as in the smaller parity tests: 1e-4 voxel per
-integration and composition, 1e-3 relative on values and gradients."""
+in the configuration the benchmark times: 8x8x16-voxel tiles, the autotuned
+window-statistics tiling of this shape, and for the Exp adjoint the staged
+exchange of scatter boxes between squaring steps (flat in / staged out, then
+staged in / staged out, then the staged G_0 unstaged), as well as the flat
+path.  The oracle takes 2-40 s per step at this size.  Tolerances as in the
+smaller parity tests: 1e-4 voxel per integration and composition, 1e-3
+relative on values and gradients."""
 import sys
 
 import numpy as np
@@ -81,10 +84,10 @@ def test_exp_full_size(ctx, data):
 
 
 def test_exp_bwd_full_size(ctx, data):
-    log("full size: exp adjoint K=7, store and recompute")
+    log("full size: exp adjoint K=7, staged (store, recompute) and flat")
     want = 2.0 ** -K * O.exp_bwd(data["us"], data["G"].astype(np.float64))
-    for mode in ("store", "recompute"):
-        got = host(ctx.exp_bwd(gpu(data["phi"]), gpu(data["G"]), K, 1, mode))
+    for mode, flat in (("store", False), ("recompute", False), ("store", True)):
+        got = host(ctx.exp_bwd(gpu(data["phi"]), gpu(data["G"]), K, 1, mode, flat=flat))
         assert_grad_close(got, want)
 
 

@@ -102,14 +102,19 @@ def test_exp_of_zero_field_is_identity(ctx):
     assert np.all(out == 0.0)
 
 
-@pytest.mark.parametrize("shape,K", [((32, 32, 32), 7), ((20, 27, 35), 4), ((24, 40, 52), 6)])
+@pytest.mark.parametrize("shape,K", [((32, 32, 32), 7), ((20, 27, 35), 4), ((24, 40, 52), 6),
+                                     ((21, 26, 45), 1)])
 @pytest.mark.parametrize("mode", ["store", "recompute"])
-def test_exp_bwd_matches_oracle(ctx, shape, K, mode):
-    log(f"exp_bwd {shape} K={K} {mode}")
+@pytest.mark.parametrize("flat", [False, True])
+def test_exp_bwd_matches_oracle(ctx, shape, K, mode, flat):
+    """The adjoint of the integration, through the staged exchange of scatter
+    boxes between squaring steps (the registration's path) and through the
+    flat path, in both modes of keeping the steps."""
+    log(f"exp_bwd {shape} K={K} {mode} flat={flat}")
     phi = smooth_field(shape, 2.0, seed=K + 100)
     G = smooth_field(shape, 1.0, seed=K + 200, sigma=1.0)
     for sign in (1, -1):
-        got = host(ctx.exp_bwd(gpu(phi), gpu(G), K, sign, mode))
+        got = host(ctx.exp_bwd(gpu(phi), gpu(G), K, sign, mode, flat=flat))
         us = O.exp_fwd(sign * phi.astype(np.float64), K)
         want = sign * 2.0 ** -K * O.exp_bwd(us, G.astype(np.float64))
         assert_grad_close(got, want)
@@ -151,6 +156,50 @@ def test_compose_bwd_matches_oracle(ctx, shape):
     wp, wc = O.compose_bwd(U.astype(np.float64), C.astype(np.float64), G.astype(np.float64))
     assert_grad_close(host(gp), wp)
     assert_grad_close(host(gc), wc)
+
+
+def contracting_field(shape, rate):
+    """u(p) = -rate (p - c), c the grid centre: Omega + u pulls every voxel
+    towards c by the factor 1 - rate (affine, so trilinear sampling is exact)."""
+    g = O.identity_grid(shape)
+    c = np.array([(n - 1) / 2.0 for n in shape])[:, None, None, None]
+    return (-rate * (g - c)).astype(np.float32)
+
+
+def test_compose_bwd_survives_strong_contraction(ctx):
+    """The adjoint scatter with every sample position crowded into the few
+    cells around the grid centre (1/20 of the distances, and the centre on a
+    grid point): a block pours about a thousand voxel-weights into one bin,
+    four times what the fixed-point bins held before their scale was bounded
+    by the block's summed magnitudes."""
+    shape = (33, 29, 41)
+    U = contracting_field(shape, 0.95)
+    C = smooth_field(shape, 2.0, seed=41)
+    G = (1.0 + 0.2 * smooth_field(shape, 1.0, seed=42, sigma=1.0)).astype(np.float32)
+    gp = torch.zeros((3,) + shape, device=DEV)
+    gc = torch.zeros((3,) + shape, device=DEV)
+    ctx.compose_bwd(gpu(U), gpu(C), gpu(G), gp, gc)
+    wp, wc = O.compose_bwd(U.astype(np.float64), C.astype(np.float64), G.astype(np.float64))
+    assert np.abs(wc).max() > 1000 * np.abs(G).max()   # the crowding is real
+    assert_grad_close(host(gp), wp)
+    assert_grad_close(host(gc), wc)
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+@pytest.mark.parametrize("flat", [False, True])
+def test_exp_bwd_survives_strong_contraction(ctx, sign, flat):
+    """Exp of -6 (p - c) contracts by e^-3 per axis at the last squaring; of
+    +6 (p - c) it expands, and the border clamp then crowds every position
+    beyond the grid into the border cells.  Both pour hundreds of voxel
+    weights into single bins of the scatter."""
+    shape = (33, 29, 41)
+    K = 7
+    phi = contracting_field(shape, 6.0)
+    G = (1.0 + 0.2 * smooth_field(shape, 1.0, seed=43, sigma=1.0)).astype(np.float32)
+    got = host(ctx.exp_bwd(gpu(phi), gpu(G), K, sign, "store", flat=flat))
+    us = O.exp_fwd(sign * phi.astype(np.float64), K)
+    want = sign * 2.0 ** -K * O.exp_bwd(us, G.astype(np.float64))
+    assert_grad_close(got, want)
 
 
 # ---------------------------------------------------------------------------
@@ -252,11 +301,18 @@ def test_loss_and_gradient_match_oracle(ctx, case, mode):
 # Gaussian smoothing of the flow (Sec. 2.4, Appendix A)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape,sigma", [((20, 27, 35), 0.6), ((32, 32, 32), 1.5),
-                                         ((9, 40, 23), 3.0), ((6, 7, 5), 2.0)])
+@pytest.mark.parametrize("shape,sigma", [((20, 27, 35), 0.375), ((20, 24, 20), 0.375),
+                                         ((40, 48, 40), 0.5), ((40, 48, 40), 0.75),
+                                         ((45, 37, 70), 1.0), ((32, 32, 32), 1.5),
+                                         ((80, 96, 80), 1.5), ((9, 40, 23), 3.0),
+                                         ((6, 7, 5), 2.0), ((33, 70, 129), 3.0)])
 def test_smooth_matches_oracle(ctx, shape, sigma):
+    """The smoothing kernel against Appendix A's Fourier-domain filter (the
+    oracle's FFT), at every width a pyramid of the timed workloads uses (0.75,
+    1.5 and 3; 0.375 with flows on a twice coarser grid) and below, on grids
+    whose lines are odd and even, shorter and longer than the taps."""
     log(f"smooth {shape} sigma={sigma}")
-    f = smooth_field(shape, 1.0, seed=int(10 * sigma), sigma=1.0)
+    f = smooth_field(shape, 1.0, seed=int(10 * sigma) + shape[0], sigma=1.0)
     got = host(ctx.smooth(gpu(f), sigma))
     assert np.abs(got - O.smooth(f.astype(np.float64), sigma)).max() < 1e-6
 

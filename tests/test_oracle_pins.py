@@ -582,26 +582,77 @@ def test_loss_weights_the_regulariser_by_alpha_over_intervals():
 # Gaussian smoothing of the flow (Sec. 2.4, Appendix A)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("sigma", [0.5, 1.0, 1.7, 3.0])
-def test_smoothing_matches_scipy_gaussian_filter_wrap(sigma):
-    import scipy.ndimage as ndi
-    x = rng(100).standard_normal((3, 9, 12, 14))
-    want = np.stack([ndi.gaussian_filter(c, sigma, mode="wrap", truncate=4.0) for c in x])
-    assert np.abs(O.smooth(x, sigma) - want).max() < 1e-13
+SMOOTH_SIGMAS = [0.375, 0.5, 0.75, 1.0, 1.5, 3.0]
+
+
+@pytest.mark.parametrize("sigma", SMOOTH_SIGMAS)
+def test_smoothing_scales_every_fourier_mode_by_the_transfer_of_appendix_a(sigma):
+    """Appendix A: the spectrum is multiplied by exp(-(omega/omega_s)^2 / 2),
+    omega_s = 1/sigma.  A sampled plane wave cos(omega . p + phase) with
+    omega_d = 2 pi k_d / n_d is an eigenfunction of that filter on the
+    periodic grid, with eigenvalue exp(-sigma^2 |omega|^2 / 2).  Waves along
+    each axis alone (Nyquist included) and along all three at once, on a grid
+    with odd and even, unequal sides: a frequency in cycles instead of
+    radians, a missing 1/2, sigma in place of 1/sigma, an axis mix-up or a
+    dropped axis each fail it."""
+    shape = (10, 12, 15)
+    g = O.identity_grid(shape)
+    r = rng(103)
+    cases = [(k, 0, 0) for k in (1, 2, 5)] + [(0, k, 0) for k in (1, 3, 6)] \
+        + [(0, 0, k) for k in (1, 4, 7)] + [(1, 2, 3), (3, 5, 2), (5, 6, 7)]
+    for kz, ky, kx in cases:
+        om = [2 * np.pi * kz / shape[0], 2 * np.pi * ky / shape[1], 2 * np.pi * kx / shape[2]]
+        phase = r.uniform(0, 2 * np.pi)
+        wave = np.cos(om[0] * g[0] + om[1] * g[1] + om[2] * g[2] + phase)
+        x = np.zeros((3,) + shape)
+        c = int(r.integers(0, 3))
+        x[c] = wave
+        gain = math.exp(-0.5 * sigma ** 2 * (om[0] ** 2 + om[1] ** 2 + om[2] ** 2))
+        y = O.smooth(x, sigma)
+        assert np.abs(y[c] - gain * wave).max() < 1e-12, (kz, ky, kx)
+        assert np.abs(np.delete(y, c, axis=0)).max() < 1e-12
+
+
+@pytest.mark.parametrize("s1,s2", [(0.375, 0.5), (0.5, 0.75), (0.75, 1.0), (1.0, 3.0)])
+def test_smoothing_composes_as_a_gaussian_semigroup(s1, s2):
+    """Two Gaussian filters in a row are one of width sqrt(s1^2 + s2^2): the
+    transfer functions multiply.  A sampled, truncated spatial Gaussian does
+    not have this property at these widths."""
+    x = rng(104).standard_normal((3, 9, 12, 14))
+    want = O.smooth(x, math.hypot(s1, s2))
+    assert np.abs(O.smooth(O.smooth(x, s1), s2) - want).max() < 1e-12
 
 
 @pytest.mark.parametrize("sigma", [1.5, 2.0, 3.0])
-def test_smoothing_matches_the_fourier_domain_gaussian_of_appendix_a(sigma):
-    """Appendix A filters with the transfer function exp(-(omega sigma)^2 / 2)
-    (omega_s = 1/sigma) on the periodic grid.  The truncated sampled kernel
-    differs from it only by the tail mass beyond 4 sigma (about 6e-5) and the
-    aliasing of the sampled Gaussian (exp(-pi^2 sigma^2 / 2))."""
-    x = rng(102).standard_normal((3, 16, 20, 24))
-    w = [2 * np.pi * np.fft.fftfreq(n) for n in x.shape[1:]]
-    tf = np.exp(-0.5 * sigma ** 2 * (w[0][:, None, None] ** 2 + w[1][None, :, None] ** 2
-                                      + w[2][None, None, :] ** 2))
-    want = np.real(np.fft.ifftn(np.fft.fftn(x, axes=(1, 2, 3)) * tf, axes=(1, 2, 3)))
-    assert np.abs(O.smooth(x, sigma) - want).max() < 3e-4 * np.abs(x).max()
+def test_wide_smoothing_matches_the_continuous_gaussian_convolution(sigma):
+    """For a kernel several voxels wide, the Fourier-domain filter and the
+    circular convolution with the sampled continuous Gaussian (scipy, wrap
+    mode, truncated far out) differ only by the aliasing of the sampled
+    Gaussian's spectrum, whose size is exp(-pi^2 sigma^2 / 2) at Nyquist."""
+    import scipy.ndimage as ndi
+    x = rng(100).standard_normal((3, 16, 20, 24))
+    want = np.stack([ndi.gaussian_filter(c, sigma, mode="wrap", truncate=10.0) for c in x])
+    bound = 3.0 * math.exp(-0.5 * math.pi ** 2 * sigma ** 2) * np.abs(x).max() + 1e-12
+    assert np.abs(O.smooth(x, sigma) - want).max() < bound
+
+
+def test_narrow_smoothing_rings_like_the_band_limited_gaussian():
+    """At sigma = 0.375 the transfer is still 0.5 at Nyquist, so the impulse
+    response is not a sampled Gaussian: along one line it is the inverse DFT
+    (1/n) sum_k exp(-sigma^2 omega_k^2 / 2) cos(omega_k m) with the
+    frequencies of the DFT taken in -pi..pi (omega_k = 2 pi min(k, n-k) / n),
+    summed here term by term, and it takes negative values (a sampled
+    Gaussian never does)."""
+    n, sigma = 16, 0.375
+    x = np.zeros((3, 1, 1, n))
+    x[0, 0, 0, 0] = 1.0
+    h = O.smooth(x, sigma)[0, 0, 0]
+    for m in range(n):
+        want = sum(math.exp(-0.5 * sigma ** 2 * (2 * math.pi * min(k, n - k) / n) ** 2)
+                   * math.cos(2 * math.pi * k * m / n) for k in range(n)) / n
+        assert abs(h[m] - want) < 1e-14
+    assert h.min() < -1e-3
+    assert abs(h.sum() - 1.0) < 1e-14
 
 
 def test_smoothing_is_self_adjoint_and_keeps_constants():
@@ -795,6 +846,54 @@ def test_pcc_and_slope_closed_forms():
 # Rigid adjustment (Sec. 2.5)
 # --------------------------------------------------------------------------
 
+def test_euclidean_error_closed_forms():
+    """Eu (Sec. 2.8) is the mean over the region of interest of the length of
+    the difference vector: a constant offset c gives |c|; offsets of +c on
+    half the region and -c on the other half still give |c| (a mean of
+    lengths, not the length of a mean); differences outside the region do not
+    count, and inside it they count by their share of the region."""
+    shape = (6, 7, 8)
+    r = rng(130)
+    ref = r.standard_normal((3,) + shape)
+    c = np.array([0.3, -1.2, 0.4])                       # |c| = 1.3
+    assert abs(O.euclidean_error(ref, ref + c[:, None, None, None]) - 1.3) < 1e-12
+    sign = np.where(r.uniform(size=shape) < 0.5, 1.0, -1.0)
+    assert abs(O.euclidean_error(ref, ref + sign * c[:, None, None, None]) - 1.3) < 1e-12
+    roi = np.zeros(shape, bool)
+    roi[1:5, 2:6, 1:7] = True
+    est = ref.copy()
+    est[:, ~roi] += 7.0                                  # outside the region: ignored
+    assert O.euclidean_error(ref, est, roi) == 0.0
+    inside = np.argwhere(roi)
+    hit = inside[r.choice(len(inside), size=10, replace=False)]
+    for z, y, x in hit:
+        est[:, z, y, x] += np.array([0.0, 3.0, 4.0])      # length 5 at 10 voxels
+    assert abs(O.euclidean_error(ref, est, roi) - 5.0 * 10 / roi.sum()) < 1e-12
+    assert O.euclidean_error(ref, est) > O.euclidean_error(ref, est, roi)
+
+
+def test_level_sigma_halves_per_coarser_level_and_keeps_the_physical_width():
+    """The smoothing width is given in voxels of the finest grid; a level
+    2^m times coarser holds the same physical width in 2^m times fewer of its
+    voxels.  So the widths of a three-level pyramid with sigma 3 are 0.75,
+    1.5 and 3; and a wave of k periods over the grid is damped alike on every
+    level when each level smooths with its own width."""
+    p = O.Params(smooth_sigma=3.0, iters=(200, 100, 50))
+    assert [O.level_sigma(p, lv) for lv in range(3)] == [0.75, 1.5, 3.0]
+    assert O.level_sigma(O.Params(smooth_sigma=1.25, iters=(10,)), 0) == 1.25
+    assert O.level_sigma(O.Params(smooth_sigma=2.0, iters=(5, 5, 5, 5)), 0) == 0.25
+    fine = (32, 24, 16)
+    gains = []
+    for lv in range(3):
+        shape = tuple(n >> (2 - lv) for n in fine)
+        g = O.identity_grid(shape)
+        wave = np.cos(2 * np.pi * 2 * g[2] / shape[2])   # two periods across x
+        x = np.stack([wave, 0 * wave, 0 * wave])
+        gains.append(O.smooth(x, O.level_sigma(p, lv))[0].max() / wave.max())
+    assert max(gains) - min(gains) < 0.02 * max(gains)
+    assert gains[0] < 0.9
+
+
 def test_rigid_matrix_is_a_rotation_and_its_derivatives_are_exact():
     th = np.array([0.3, -0.2, 0.45])
     R = O.rigid_matrix(th)
@@ -880,7 +979,9 @@ def _torch_adam_registration(images, p):
         if p.rigid:
             groups += [{"params": at, "scale": 1.0 / r}, {"params": tt, "scale": 1.0}]
         opt = torch.optim.Adam(groups, lr=p.lr, betas=p.betas, eps=p.eps)
-        pl = O.Params(**{**p.__dict__, "smooth_sigma": O.level_sigma(p, lv)})
+        # the smoothing width is given on the finest grid: a level that is
+        # 2^m times coarser sees it as 2^m times fewer of its voxels
+        pl = O.Params(**{**p.__dict__, "smooth_sigma": p.smooth_sigma / 2 ** (n_lv - 1 - lv)})
         for t in range(1, T + 1):
             rig = [np.concatenate([a.detach().numpy(), b.detach().numpy()]) for a, b in zip(at, tt)]
             L, grads, aux = O.loss_and_grad([x.detach().numpy() for x in xs], imgs, pl,
@@ -898,7 +999,7 @@ def _torch_adam_registration(images, p):
         phis = [x.detach().numpy().copy() for x in xs]
         ang = [a.detach().numpy().copy() for a in at]
         tra = [b.detach().numpy().copy() for b in tt]
-    sm = [O.smooth(x, O.level_sigma(p, n_lv - 1)) for x in phis]
+    sm = [O.smooth(x, p.smooth_sigma) for x in phis]
     return sm, hist, [np.concatenate([a, b]) for a, b in zip(ang, tra)]
 
 
