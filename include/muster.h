@@ -122,6 +122,19 @@ typedef struct muster_params {
                                       is added to every pair field that samples
                                       that session (Sec. 2.5).  Registration
                                       entry points only (not the autograd ones) */
+  int deterministic;               /* 1: results that do not depend on the order
+                                      of atomic adds, so a job gives bit-identical
+                                      flows alone, batched or served: the adjoint
+                                      scatters that add into shared fields with
+                                      atomics add 64-bit fixed point at a scale
+                                      set per job and launch (one more reduce-only
+                                      pass of those kernels and a fold; about 12 %
+                                      slower; 6(N-1) more int64 fields of the
+                                      flow grid), and the window statistics use
+                                      the default tiling instead of the
+                                      autotuner's.  Registration entry points
+                                      only.  The rigid adjustment's sums remain
+                                      FP64 atomics.  0 = off                     */
 } muster_params;
 
 /* Per-job result summary. */

@@ -44,7 +44,8 @@ class Params(Structure):
                 ("metric", c_int), ("alpha_ss", c_float), ("lr", c_float), ("warmup", c_float),
                 ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("exp_mode", c_int),
                 ("use_graph", c_int), ("smooth_sigma", c_float), ("alpha_l2", c_float),
-                ("alpha_ts", c_float), ("flow_factor", c_int), ("rigid", c_int)]
+                ("alpha_ts", c_float), ("flow_factor", c_int), ("rigid", c_int),
+                ("deterministic", c_int)]
 
 
 class Report(Structure):

@@ -35,6 +35,7 @@ class MusterParams:
     alpha_ts: float = 0.0             # weight of L_ts (temporal smoothness; needs times)
     flow_factor: int = 1              # 2: flows on a grid twice as coarse as the images
     rigid: bool = False               # rigid adjustment of every session but the first
+    deterministic: bool = False       # results independent of the order of atomic adds
 
     def to_c(self) -> L.Params:
         p = L.Params()
@@ -58,6 +59,7 @@ class MusterParams:
         p.alpha_ts = float(self.alpha_ts)
         p.flow_factor = int(self.flow_factor)
         p.rigid = 1 if self.rigid else 0
+        p.deterministic = 1 if self.deterministic else 0
         return p
 
 

@@ -604,12 +604,36 @@ struct StageOut {
   int z0, y0, x0;
 };
 
-template <bool OWN, bool STAGE = false, int NT = BLOCK>
-__device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT], gfloat* __restrict__ out,
-                                             int D, int H, int W, int* acc, int* sred,
-                                             const StageOut& so = StageOut{}) {
+// Deterministic accumulation: a block that would add into the float field
+// with global atomics adds round(value * scale) into out64 instead (64-bit
+// integer atomics, whose sum does not depend on their order).
+struct DetOut {
+  long long* out64 = nullptr;
+  double scale = 0.0;
+};
+
+__device__ __forceinline__ void det_add(long long* p, float v, double scale) {
+  const long long q = __double2ll_rn((double)v * scale);
+  if (q != 0) atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)q);
+}
+
+// Scale of a job's deterministic slot over `blocks` blocks: 2^(61 - e) with
+// 2^e >= blocks * m (m the slot's largest summed block magnitude), so that
+// no cell of the 64-bit field can exceed 2^61; 0 when nothing finite was
+// recorded.
+__device__ __forceinline__ double det_scale(const JobState* js, int slot, int blocks) {
+  const float m = __int_as_float((int)js->det_max[slot]);
+  if (!(m > 0.f) || !(m < 3.0e38f)) return 0.0;
+  int e;
+  frexp((double)m * (double)blocks, &e);
+  return ldexp(1.0, 61 - e);
+}
+
+// Bounding box, largest magnitude and summed magnitudes of a block's
+// scatter (every thread must call it).
+template <bool OWN, int NT>
+__device__ __forceinline__ ScatterBox scatter_bound(const ScatterVox (&sv)[PT_VOX / NT], int* sred) {
   constexpr int VP = PT_VOX / NT;
-  const int HW = H * W, V = D * HW;
   int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
   int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
   float mx = 0.f, sm = 0.f;
@@ -631,19 +655,48 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
       sm += om;
     }
   }
-  const ScatterBox sb = scatter_box<NT>(lo, hi, mx, sm, sred);
+  return scatter_box<NT>(lo, hi, mx, sm, sred);
+}
+
+// Whether a block's box goes to its staging slot: it fits the slot and
+// reaches no farther than the 26 neighbouring tiles (where the reading step
+// looks for it).
+__device__ __forceinline__ bool stage_fits(const ScatterBox& sb, const StageOut& so) {
+  const BBox& bb = sb.bb;
+  const bool finite = sb.bmax > 0.f && sb.bmax < 3.0e38f && sb.bsum < 3.0e38f;
+  return bb.cells > 0 && bb.cells <= STAGE_CAP && finite &&
+         bb.lz >= so.z0 - PT_Z && bb.lz + bb.ez <= so.z0 + 2 * PT_Z &&
+         bb.ly >= so.y0 - PT_Y && bb.ly + bb.ey <= so.y0 + 2 * PT_Y &&
+         bb.lx >= so.x0 - PT_X && bb.lx + bb.ex <= so.x0 + 2 * PT_X;
+}
+
+// Deterministic mode, reduce-only pass: a block that will add into the flat
+// field (every block unless it stages its box) raises the job's slot to its
+// summed magnitude.
+template <bool OWN, bool STAGE, int NT>
+__device__ __forceinline__ void det_bound(const ScatterVox (&sv)[PT_VOX / NT], int* sred,
+                                          const StageOut& so, JobState* js, int slot) {
+  const ScatterBox sb = scatter_bound<OWN, NT>(sv, sred);
+  if (sb.bb.cells == 0 || !(sb.bmax > 0.f)) return;
+  if (STAGE && stage_fits(sb, so)) return;
+  if (threadIdx.x == 0) atomicMax(&js->det_max[slot], (unsigned int)__float_as_int(sb.bsum));
+}
+
+template <bool OWN, bool STAGE = false, int NT = BLOCK>
+__device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT], gfloat* __restrict__ out,
+                                             int D, int H, int W, int* acc, int* sred,
+                                             const StageOut& so = StageOut{},
+                                             const DetOut& det = DetOut{}) {
+  constexpr int VP = PT_VOX / NT;
+  const int HW = H * W, V = D * HW;
+  const ScatterBox sb = scatter_bound<OWN, NT>(sv, sred);
   const BBox& bb = sb.bb;
   const float bmax = sb.bmax;
   // the bins take finite values only; bsum bounds every bin's magnitude
   const bool finite = bmax > 0.f && bmax < 3.0e38f && sb.bsum < 3.0e38f;
   bool staged = false;
   if (STAGE) {
-    // the box goes to the staging slot if it fits and reaches no farther than
-    // the 26 neighbouring tiles (where the reading step looks for it)
-    staged = bb.cells > 0 && bb.cells <= STAGE_CAP && finite &&
-             bb.lz >= so.z0 - PT_Z && bb.lz + bb.ez <= so.z0 + 2 * PT_Z &&
-             bb.ly >= so.y0 - PT_Y && bb.ly + bb.ey <= so.y0 + 2 * PT_Y &&
-             bb.lx >= so.x0 - PT_X && bb.lx + bb.ex <= so.x0 + 2 * PT_X;
+    staged = stage_fits(sb, so);
     if (threadIdx.x == 0) {
       so.desc[0] = bb.lz; so.desc[1] = bb.ly; so.desc[2] = bb.lx;
       so.desc[3] = staged ? bb.ez : 0;
@@ -725,7 +778,11 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int v = acc[c * SCATTER_CELLS + i];
-        if (v != 0) gadd(out + c * V + gpos, (float)v * inv);
+        if (v == 0) continue;
+        if (det.out64)
+          det_add(det.out64 + c * V + gpos, (float)v * inv, det.scale);
+        else
+          gadd(out + c * V + gpos, (float)v * inv);
       }
     }
   } else {
@@ -745,12 +802,22 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
         const float g = sv[j].g[c];
         if (g == 0.f) continue;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) gadd(out + c * V + base + off[q], w[q] * g);
+        for (int q = 0; q < 8; ++q) {
+          if (det.out64)
+            det_add(det.out64 + c * V + base + off[q], w[q] * g, det.scale);
+          else
+            gadd(out + c * V + base + off[q], w[q] * g);
+        }
       }
       if (OWN) {
         const int po = (sv[j].oz * H + sv[j].oy) * W + sv[j].ox;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) gadd(out + c * V + po, sv[j].own[c]);
+        for (int c = 0; c < 3; ++c) {
+          if (det.out64)
+            det_add(det.out64 + c * V + po, sv[j].own[c], det.scale);
+          else
+            gadd(out + c * V + po, sv[j].own[c]);
+        }
       }
     }
   }
@@ -770,7 +837,7 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
                                             const PTile& tc, int D, int H, int W,
                                             const int (&vz)[VPT], const int (&vy)[VPT],
                                             const int (&vx)[VPT], const bool (&vok)[VPT],
-                                            float (&gv)[VPT][3], int* acc) {
+                                            float (&gv)[VPT][3], int* acc, bool clear = true) {
   const int V = D * H * W;
   // per neighbour d: nyx, nx, (unused), the box's z and y strides, the
   // tile-local index of the overlap's first cell, the staging element of
@@ -908,9 +975,11 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
       gv[j][0] += gin[p];
       gv[j][1] += gin[V + p];
       gv[j][2] += gin[2 * V + p];
-      gin[p] = 0.f;
-      gin[V + p] = 0.f;
-      gin[2 * V + p] = 0.f;
+      if (clear) {
+        gin[p] = 0.f;
+        gin[V + p] = 0.f;
+        gin[2 * V + p] = 0.f;
+      }
     }
   }
 }
@@ -921,8 +990,9 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
 // ---------------------------------------------------------------------------
 // MODE: 0 flat G_{s+1} in, flat G_s out; 1 flat in, staged out; 2 staged
 // in, staged out; 3 staged in, flat out (see ExpBwdItem).  A staged G_0 is
-// turned into a flat field by k_unstage.
-template <int MODE, bool REG>
+// turned into a flat field by k_unstage.  DETMAX: the deterministic mode's
+// reduce-only pass (no writes but the job's slot).
+template <int MODE, bool REG, bool DETMAX = false>
 __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict__ items,
                                                    int n_items, int n_tiles) {
   constexpr bool IN_ST = MODE >= 2, OUT_ST = MODE == 1 || MODE == 2;
@@ -957,7 +1027,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   if (IN_ST) {
     // G_{s+1} over this tile from the staged boxes of the previous step
     pull_staged(it.stage_in, it.desc_in, it.flag_in, gin, local, tc, D, H, W, vz, vy, vx, vok, gv,
-                acc);
+                acc, !DETMAX);
   } else {
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
@@ -966,7 +1036,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
       gv[j][0] = gin[p];
       gv[j][1] = gin[V + p];
       gv[j][2] = gin[2 * V + p];
-      if (it.zero_in) {
+      if (it.zero_in && !DETMAX) {
         gin[p] = 0.f;
         gin[V + p] = 0.f;
         gin[2 * V + p] = 0.f;
@@ -1047,16 +1117,26 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
     sv[j].own[0] = own0; sv[j].own[1] = own1; sv[j].own[2] = own2;
   }
+  StageOut so{};
   if (OUT_ST) {
-    StageOut so;
     so.slot = gp(it.stage_out) + (size_t)local * 3 * STAGE_CAP;
     so.desc = it.desc_out + local * 8;
     so.flag = it.flag_out;
     so.z0 = tc.z0; so.y0 = tc.y0; so.x0 = tc.x0;
-    scatter_tile<true, true>(sv, gp(it.gout), D, H, W, acc, sred, so);
-  } else {
-    scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred);
   }
+  if (DETMAX) {
+    det_bound<true, OUT_ST, BLOCK>(sv, sred, so, it.js, it.det_slot);
+    return;
+  }
+  DetOut det;
+  if (it.gout64) {
+    det.out64 = it.gout64;
+    det.scale = det_scale(it.js, it.det_slot, it.det_blocks);
+  }
+  if (OUT_ST)
+    scatter_tile<true, true>(sv, gp(it.gout), D, H, W, acc, sred, so, det);
+  else
+    scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred, StageOut{}, det);
   rval = (double)rvf;
   if (reg) {
     const double tot = block_sum(rval * (double)it.reg_loss_w + rext, red);
@@ -1174,6 +1254,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_combine(const PullItem* __restri
 // occupancy than it loses in loads in flight per thread (measured: 11 %).
 constexpr int CB_NT = 2 * BLOCK, CB_VP = PT_VOX / CB_NT;
 
+template <bool DETMAX>
 __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __restrict__ items,
                                                        int n_items, int n_tiles) {
   __shared__ __align__(16) int acc[3 * SCATTER_CELLS];
@@ -1211,7 +1292,9 @@ __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __r
     const float o0 = fmaf(az.live, jz, g0);
     const float o1 = fmaf(ay.live, jy, g1);
     const float o2 = fmaf(ax.live, jx, g2);
-    if (it.prev_atomic) {
+    if (DETMAX) {
+      // reduce-only pass: no writes
+    } else if (it.prev_atomic && !it.gc64) {
       gadd(gpv + p, o0);
       gadd(gpv + V + p, o1);
       gadd(gpv + 2 * V + p, o2);
@@ -1225,7 +1308,45 @@ __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __r
     sv[j].tz = az.t; sv[j].ty = ay.t; sv[j].tx = ax.t;
     sv[j].g[0] = g0; sv[j].g[1] = g1; sv[j].g[2] = g2;
   }
-  scatter_tile<false, false, CB_NT>(sv, gp(it.gc), D, H, W, acc, sred);
+  if (DETMAX) {
+    det_bound<false, false, CB_NT>(sv, sred, StageOut{}, it.js, it.det_slot);
+    return;
+  }
+  DetOut det;
+  if (it.gc64) {
+    det.out64 = it.gc64;
+    det.scale = det_scale(it.js, it.det_slot, it.det_blocks);
+  }
+  scatter_tile<false, false, CB_NT>(sv, gp(it.gc), D, H, W, acc, sred, StageOut{}, det);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic mode: fold of a 64-bit fixed-point field into its float
+// field (one pass over the elements, in no particular order: each element
+// is independent), and the clearing of the jobs' slots.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_det_fold(const DetFoldItem* __restrict__ items,
+                                                    int n_items, int n_tiles) {
+  const int tile = blockIdx.x;
+  const DetFoldItem it = items[find_item(items, n_items, tile)];
+  if (it.flag && *it.flag == 0) return;
+  const double sc = det_scale(it.js, it.det_slot, it.det_blocks);
+  const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+  const int e0 = (tile - it.tile0) * ELEM_PER_BLOCK;
+  for (int k = threadIdx.x; k < ELEM_PER_BLOCK; k += BLOCK) {
+    const int e = e0 + k;
+    if (e >= it.n) break;
+    const long long q = it.q[e];
+    if (q == 0) continue;
+    it.f[e] += (float)((double)q * inv);
+    it.q[e] = 0;
+  }
+}
+
+__global__ void k_det_clear(JobState* const* __restrict__ states, int n_jobs) {
+  const int j = blockIdx.x;
+  if (j >= n_jobs) return;
+  for (int k = threadIdx.x; k < DET_SLOTS; k += blockDim.x) states[j]->det_max[k] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -2198,6 +2319,31 @@ static hipError_t launch_exp_bwd_(const ExpBwdItem* items, int n_items, int n_ti
   return hipGetLastError();
 }
 
+hipError_t launch_exp_bwd_detmax(const ExpBwdItem* items, int n_items, int n_tiles, int staged,
+                                 hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (staged) {
+    case 0: MUSTER_LAUNCH((k_exp_bwd<0, true, true>), dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 1: MUSTER_LAUNCH((k_exp_bwd<1, true, true>), dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 2: MUSTER_LAUNCH((k_exp_bwd<2, true, true>), dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    case 3: MUSTER_LAUNCH((k_exp_bwd<3, true, true>), dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_det_fold(const DetFoldItem* items, int n_items, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  MUSTER_LAUNCH(k_det_fold, dim3(n_tiles), dim3(BLOCK), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_det_clear(JobState* const* states, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  MUSTER_LAUNCH(k_det_clear, dim3(n_jobs), dim3(64), 0, s, states, n_jobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_exp_bwd(const ExpBwdItem* items, int n_items, int n_tiles, int staged, bool reg,
                           hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
@@ -2220,7 +2366,14 @@ hipError_t launch_pull_combine(const PullItem* items, int n_items, int n_tiles, 
 hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
                               hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  MUSTER_LAUNCH(k_compose_bwd, dim3(n_tiles), dim3(CB_NT), 0, s, items, n_items, n_tiles);
+  MUSTER_LAUNCH(k_compose_bwd<false>, dim3(n_tiles), dim3(CB_NT), 0, s, items, n_items, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_bwd_detmax(const ComposeBwdItem* items, int n_items, int n_tiles,
+                                     hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  MUSTER_LAUNCH(k_compose_bwd<true>, dim3(n_tiles), dim3(CB_NT), 0, s, items, n_items, n_tiles);
   return hipGetLastError();
 }
 

@@ -13,6 +13,16 @@
 
 namespace muster {
 
+// Deterministic accumulation (a job's params.deterministic): every scatter
+// that would add into a float field with global atomics adds 64-bit fixed
+// point instead, at a scale shared by all blocks of the job in that launch:
+// 2^(61 - e) with 2^e >= blocks * m, m the largest summed magnitude any of
+// the job's blocks spreads (found by a pass of the same kernel that only
+// reduces it), so no cell can overflow and integer adds make the sum
+// independent of their order.  A fold then adds the fixed-point field into
+// the float one.  One slot per such launch of an iteration.
+constexpr int DET_SLOTS = 96;
+
 // Per-job device state: optimiser step counter and schedule, loss
 // accumulators and the loss history.  Lives in device memory so that a
 // captured iteration can be replayed without host involvement.
@@ -30,6 +40,7 @@ struct JobState {
   int* flags;       // overflow flags of the staged Exp backward, cleared per iteration
   int n_flags;
   int hist_base;    // index of this level's first step in history
+  unsigned int det_max[DET_SLOTS];  // deterministic mode: largest block magnitude (float bits)
 };
 
 struct GridDims {
@@ -94,6 +105,13 @@ struct ExpBwdItem {
   float* stage_out;
   int* desc_out;
   int* flag_out;
+  // Deterministic accumulation: where a block adds into gout with atomics it
+  // adds into gout64 ([3][V] 64-bit fixed point) instead, at the scale of
+  // the job's slot det_slot over det_blocks blocks (see DET_SLOTS); null
+  // otherwise.
+  long long* gout64;
+  int det_slot;
+  int det_blocks;
 };
 
 // Backward of one composition out = prev + C o (Omega + prev): given
@@ -109,6 +127,28 @@ struct ComposeBwdItem {
   float* gc;
   int prev_atomic;
   int pad;
+  // Deterministic accumulation: the scatter into gc goes to gc64 ([3][V]
+  // 64-bit fixed point) at the scale of the job's slot (see DET_SLOTS), and
+  // gprev, whose only float writer in the launch is then this item, is
+  // updated with plain stores; null otherwise.
+  long long* gc64;
+  JobState* js;
+  int det_slot;
+  int det_blocks;
+};
+
+// Fold of a 64-bit fixed-point field into its float field: f += q / scale,
+// q = 0, over n = 3V elements, for the scale of the job's slot; skipped when
+// flag is set and *flag is 0 (no block of the launch added into q).
+struct DetFoldItem {
+  int tile0;
+  int n;
+  float* f;
+  long long* q;
+  const JobState* js;
+  const int* flag;
+  int det_slot;
+  int det_blocks;
 };
 
 // One session pair (target F = I_i, source I_j, field U = U[j->i]).
@@ -337,6 +377,15 @@ hipError_t launch_unstage(const ExpBwdItem* items, int n_items, int n_tiles, hip
 hipError_t launch_pull_combine(const PullItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_compose_bwd(const ComposeBwdItem* items, int n_items, int n_tiles,
                               hipStream_t s);
+// Deterministic mode: the passes of the composition and Exp adjoints that
+// only reduce each job's largest block magnitude into its slot (no other
+// writes), the fold of the fixed-point fields, and the clearing of the slots.
+hipError_t launch_compose_bwd_detmax(const ComposeBwdItem* items, int n_items, int n_tiles,
+                                     hipStream_t s);
+hipError_t launch_exp_bwd_detmax(const ExpBwdItem* items, int n_items, int n_tiles, int staged,
+                                 hipStream_t s);
+hipError_t launch_det_fold(const DetFoldItem* items, int n_items, int n_tiles, hipStream_t s);
+hipError_t launch_det_clear(JobState* const* states, int n_jobs, hipStream_t s);
 // M = I o (Omega + U) of each item, over point tiles of its grid.
 hipError_t launch_warp(const SimItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_sim_stats(const SimItem* items, int n_items, int n_tiles, int window, int metric,

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <tuple>
 
 namespace muster {
 
@@ -131,6 +132,8 @@ void validate_params(const muster_params& p) {
     fail(MUSTER_E_INVALID, "flow_factor must be 1 or 2 (got %d)", p.flow_factor);
   if (!(p.alpha_l2 >= 0.f) || !std::isfinite(p.alpha_l2)) fail(MUSTER_E_INVALID, "alpha_l2 must be >= 0");
   if (!(p.alpha_ts >= 0.f) || !std::isfinite(p.alpha_ts)) fail(MUSTER_E_INVALID, "alpha_ts must be >= 0");
+  if (p.deterministic != 0 && p.deterministic != 1)
+    fail(MUSTER_E_INVALID, "deterministic must be 0 or 1 (got %d)", p.deterministic);
 }
 
 void validate_problem(int N, const int dims[3], const muster_params& p, const double* times) {
@@ -202,6 +205,9 @@ uint64_t job_footprint(int N, const int dims[3], const muster_params& p) {
   bytes += P * FI;
   if (ff > 1) bytes += 2 * P * FI;
   if (p.rigid) bytes += n1 * sizeof(RigidState) + 256;
+  // deterministic mode: 64-bit fixed-point twins of the consecutive-field
+  // gradients and of the Exp-backward ping-pong
+  if (p.deterministic) bytes += 6 * n1 * 3 * V * sizeof(long long);
   if (p.K >= 2) {
     // staging slots and descriptors of the Exp backward, per direction, two steps
     const uint64_t tiles = (uint64_t)point_tiles(fd[0], fd[1], fd[2]);
@@ -322,6 +328,12 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
     std::memset(z.data(), 0, n1 * sizeof(RigidState));
     MUSTER_HIP(hipMemcpy(J.m_rigid.p, z.data(), n1 * sizeof(RigidState), hipMemcpyHostToDevice));
   }
+  if (J.p.deterministic) {
+    J.m_det64.alloc(ctx, 6 * n1 * 3 * V0 * sizeof(long long));
+    // zero bits: the fixed-point fields start (and are left by every fold) at 0
+    MUSTER_HIP(launch_fill(J.m_det64.as<float>(), (int64_t)(12 * n1 * 3 * V0), 0.f, nullptr));
+    MUSTER_HIP(hipStreamSynchronize(nullptr));
+  }
   if (J.staged()) {
     J.m_stage.alloc(ctx, 2 * 2 * n1 * (size_t)J.tiles_fine * 3 * STAGE_CAP * sizeof(float));
     J.m_desc.alloc(ctx, 2 * 2 * n1 * (size_t)J.tiles_fine * 8 * sizeof(int));
@@ -352,7 +364,7 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
                 J.m_gpair.bytes + J.m_pp.bytes + J.m_coef.bytes + J.m_img.bytes +
                 J.m_state.bytes + J.m_hist.bytes + J.m_phis.bytes + J.m_t1.bytes + J.m_t2.bytes +
                 J.m_stage.bytes + J.m_desc.bytes + J.m_flags.bytes + J.m_pimg.bytes +
-                J.m_gimg.bytes + J.m_rigid.bytes;
+                J.m_gimg.bytes + J.m_rigid.bytes + J.m_det64.bytes;
   return job;
 }
 
@@ -481,7 +493,14 @@ void job_begin_level(Job& J, int level, hipStream_t s) {
   st.hist_base = base;
   *J.host_state = st;
   MUSTER_HIP(hipMemcpyAsync(J.js, J.host_state, sizeof(JobState), hipMemcpyHostToDevice, s));
-  J.sim_tile[level] = choose_sim_tile(ctx, J.idims[level], J.p.window, J.p.metric, s);
+  // a deterministic job's result must not depend on timing: it takes the
+  // context's fixed tiling if one is set, else the default one
+  if (J.det() && ctx->tile_mode == MUSTER_TILES_AUTOTUNE) {
+    J.sim_tile[level].shape = 0;
+    J.sim_tile[level].zc = std::min(32, J.idims[level][0]);
+  } else {
+    J.sim_tile[level] = choose_sim_tile(ctx, J.idims[level], J.p.window, J.p.metric, s);
+  }
   MUSTER_HIP(hipStreamSynchronize(s));
 }
 
@@ -971,17 +990,74 @@ void set_reg_ext(ExpBwdItem& it, const Job& J, int i) {
   it.w_next = (float)(k2 * w_next);
 }
 
+// Deterministic jobs' part of a scatter launch: the job's tiles in it (the
+// blocks that share its scale) and a slot of its own, the reduce-only pass
+// before the launch and the fold of the fixed-point fields after it.
+struct DetLaunch {
+  std::map<Job*, int> tiles;   // per deterministic job, its tiles in the launch
+  std::map<Job*, int> slot;
+};
+
+template <class Item>
+void det_assign(DetLaunch& dl, std::vector<Item>& items, const std::vector<Job*>& owner,
+                std::map<Job*, int>& next_slot) {
+  for (size_t k = 0; k < items.size(); ++k) {
+    Job* J = owner[k];
+    if (!J->det()) continue;
+    const int* d = J->ldims[J->level];
+    dl.tiles[J] += point_tiles(d[0], d[1], d[2]);
+  }
+  for (auto& kv : dl.tiles) {
+    if (next_slot[kv.first] >= DET_SLOTS) fail(MUSTER_E_INTERNAL, "deterministic slots exhausted");
+    dl.slot[kv.first] = next_slot[kv.first]++;
+  }
+}
+
+template <class Item>
+void add_det_stages(Builder& b, StageKind kind, const std::vector<Item>& items,
+                    const std::vector<Job*>& owner, int staged,
+                    const std::vector<DetFoldItem>& folds) {
+  std::vector<Item> dmax;
+  int tiles = 0;
+  for (size_t k = 0; k < items.size(); ++k) {
+    if (!owner[k]->det()) continue;
+    Item it = items[k];
+    it.tile0 = tiles;
+    const int* d = owner[k]->ldims[owner[k]->level];
+    tiles += point_tiles(d[0], d[1], d[2]);
+    dmax.push_back(it);
+  }
+  b.add(kind, dmax, tiles, 0.0);
+  if (!dmax.empty()) b.plan->stages.back().staged = staged;
+  (void)folds;
+}
+
+void add_det_folds(Builder& b, std::vector<DetFoldItem>& folds) {
+  int tiles = 0;
+  for (DetFoldItem& f : folds) {
+    f.tile0 = tiles;
+    tiles += (f.n + ELEM_PER_BLOCK - 1) / ELEM_PER_BLOCK;
+  }
+  b.add(ST_DET_FOLD, folds, tiles, 0.0);
+}
+
 void add_backward(Builder& b, const std::vector<Job*>& jobs) {
   int maxK = 0, maxN = 0;
+  std::vector<JobState*> det_states;
+  std::map<Job*, int> next_slot;
   for (Job* J : jobs) {
     maxK = std::max(maxK, J->K());
     maxN = std::max(maxN, J->N);
+    if (J->det()) det_states.push_back(J->js);
   }
+  b.add(ST_DET_CLEAR, det_states, (int)det_states.size(), 0.0);
   add_sim_stages(b, jobs, ST_SIM_GRAD);
   add_rigid_stages(b, jobs);
   add_pair_resampling(b, jobs, true);
   for (int d = maxN - 1; d >= 2; --d) {
     std::vector<ComposeBwdItem> items;
+    std::vector<Job*> owner;
+    std::vector<int> gc_dir;
     int tiles = 0;
     double bytes = 0;
     for (Job* J : jobs) {
@@ -1008,12 +1084,36 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
           }
           it.prev_atomic = (d == 2) ? 1 : 0;
           items.push_back(it);
+          owner.push_back(J);
+          gc_dir.push_back(j > i ? 2 * (j - 1) : 2 * j + 1);
           tiles += point_tiles(dd[0], dd[1], dd[2]);
           bytes += B_COMPOSE_BWD * J->Vc();
         }
       }
     }
+    DetLaunch dl;
+    det_assign(dl, items, owner, next_slot);
+    std::vector<DetFoldItem> folds;
+    for (size_t k = 0; k < items.size(); ++k) {
+      Job* J = owner[k];
+      if (!J->det()) continue;
+      ComposeBwdItem& it = items[k];
+      it.gc64 = J->det64_pair(gc_dir[k]);
+      it.js = J->js;
+      it.det_slot = dl.slot[J];
+      it.det_blocks = dl.tiles[J];
+      DetFoldItem f{};
+      f.n = (int)(3 * J->Vc());
+      f.f = it.gc;
+      f.q = it.gc64;
+      f.js = J->js;
+      f.det_slot = it.det_slot;
+      f.det_blocks = it.det_blocks;
+      folds.push_back(f);
+    }
+    add_det_stages(b, ST_COMPOSE_BWD_DETMAX, items, owner, 0, folds);
     b.add(ST_COMPOSE_BWD, items, tiles, bytes);
+    add_det_folds(b, folds);
   }
   for (int s = maxK - 1; s >= 0; --s) {
     // recompute u_s where needed
@@ -1021,6 +1121,7 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
       for (int k = 0; k < s; ++k) add_exp_fwd_step(b, jobs, k, true, s);
     // one launch per staging mode in use (jobs with different K differ)
     std::vector<ExpBwdItem> items[4];
+    std::vector<Job*> owner[4];
     int tiles[4] = {0, 0, 0, 0};
     double bytes[4] = {0, 0, 0, 0};
     for (Job* J : jobs) {
@@ -1067,17 +1168,47 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
         }
         if (s == 0 && fwd) set_reg_ext(it, *J, i);
         it.js = J->js;
+        if (J->det()) it.gout64 = J->det64_pp(dir, s % 2);
         items[mode].push_back(it);
+        owner[mode].push_back(J);
         tiles[mode] += point_tiles(d[0], d[1], d[2]);
         bytes[mode] += B_EXP_BWD * J->Vc();
       }
     }
     for (int mode = 0; mode < 4; ++mode) {
+      DetLaunch dl;
+      det_assign(dl, items[mode], owner[mode], next_slot);
+      std::vector<DetFoldItem> folds;
+      bool any_det = false;
+      for (size_t k = 0; k < items[mode].size(); ++k) {
+        Job* J = owner[mode][k];
+        if (!J->det()) continue;
+        any_det = true;
+        ExpBwdItem& it = items[mode][k];
+        it.det_slot = dl.slot[J];
+        it.det_blocks = dl.tiles[J];
+        DetFoldItem f{};
+        f.n = (int)(3 * J->Vc());
+        f.f = it.gout;
+        f.q = it.gout64;
+        f.js = J->js;
+        // staged out: only blocks that did not stage added into the flat field,
+        // and each of them raised the flag
+        f.flag = (mode == 1 || mode == 2) ? it.flag_out : nullptr;
+        f.det_slot = it.det_slot;
+        f.det_blocks = it.det_blocks;
+        folds.push_back(f);
+      }
+      add_det_stages(b, ST_EXP_BWD_DETMAX, items[mode], owner[mode], mode, folds);
       b.add(ST_EXP_BWD, items[mode], tiles[mode], bytes[mode]);
       if (items[mode].empty()) continue;
       b.plan->stages.back().staged = mode;
+      // deterministic jobs always run the general variant, so that their
+      // arithmetic does not depend on the other jobs of the launch
+      if (any_det) b.plan->stages.back().reg = 1;
       for (const ExpBwdItem& e : items[mode])
         if (e.reg_w != 0.f || e.ext) b.plan->stages.back().reg = 1;
+      add_det_folds(b, folds);
     }
   }
   {
@@ -1246,6 +1377,10 @@ static int kclass(StageKind k) {
     case ST_WARP: return MUSTER_K_WARP;
     case ST_UNSTAGE: return MUSTER_K_UNSTAGE;
     case ST_PULL_COMBINE: return MUSTER_K_UNSTAGE;
+    case ST_COMPOSE_BWD_DETMAX: return MUSTER_K_COMPOSE_BWD;
+    case ST_EXP_BWD_DETMAX: return MUSTER_K_EXP_BWD;
+    case ST_DET_FOLD: return MUSTER_K_FINISH;
+    case ST_DET_CLEAR: return MUSTER_K_FINISH;
   }
   return MUSTER_K_FINISH;
 }
@@ -1276,6 +1411,12 @@ static hipError_t launch_stage(const Stage& st, const unsigned char* base, hipSt
     case ST_UNSTAGE: return launch_unstage((const ExpBwdItem*)p, st.n_items, st.n_tiles, s);
     case ST_PULL_COMBINE:
       return launch_pull_combine((const PullItem*)p, st.n_items, st.n_tiles, s);
+    case ST_COMPOSE_BWD_DETMAX:
+      return launch_compose_bwd_detmax((const ComposeBwdItem*)p, st.n_items, st.n_tiles, s);
+    case ST_EXP_BWD_DETMAX:
+      return launch_exp_bwd_detmax((const ExpBwdItem*)p, st.n_items, st.n_tiles, st.staged, s);
+    case ST_DET_FOLD: return launch_det_fold((const DetFoldItem*)p, st.n_items, st.n_tiles, s);
+    case ST_DET_CLEAR: return launch_det_clear((JobState* const*)p, st.n_items, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1415,8 +1556,11 @@ void Server::loop() {
     stop = true;
     return;
   }
-  std::unique_ptr<Plan> plan;
-  std::vector<std::pair<uint64_t, int>> sig;
+  // one plan per group of resident jobs that can share launches (window,
+  // metric and K), rebuilt when the group's members or levels change
+  using GroupKey = std::tuple<int, int, int>;
+  std::map<GroupKey, std::unique_ptr<Plan>> plans;
+  std::map<GroupKey, std::vector<std::pair<uint64_t, int>>> sigs;
   auto finish = [&](std::shared_ptr<Ticket>& t, int state, muster_status st, const std::string& err) {
     if (t->rt) {
       t->report.footprint_bytes = t->rt->footprint;
@@ -1454,19 +1598,14 @@ void Server::loop() {
           ++it;
         }
       }
-      // admission by footprint, first come first served
+      // admission by footprint, first come first served; jobs that cannot
+      // share launches with the residents (another window, metric or K) run
+      // in a group of their own in the same ticks
       uint64_t pending = 0;
       while (!queue.empty()) {
         auto& t = queue.front();
         const uint64_t fp = job_footprint(t->job.N, t->job.dims, t->job.params);
         if (!ctx->arena.fits(pending + fp)) break;
-        if (!resident.empty() || !admit.empty()) {
-          // jobs batched together must share window and metric
-          const muster_params& a = resident.empty() ? admit[0]->job.params : resident[0]->job.params;
-          if (a.window != t->job.params.window || a.metric != t->job.params.metric ||
-              a.K != t->job.params.K)
-            break;
-        }
         pending += fp;
         admit.push_back(t);
         queue.pop_front();
@@ -1495,22 +1634,28 @@ void Server::loop() {
     }
     if (res.empty()) continue;
     try {
-      // skip jobs whose current level has no steps
-      std::vector<Job*> jobs;
-      std::vector<std::pair<uint64_t, int>> nsig;
+      // one iteration of every resident job whose current level has steps (a
+      // level of 0 steps is passed over below without touching the job)
+      std::map<GroupKey, std::vector<Job*>> groups;
+      std::map<GroupKey, std::vector<std::pair<uint64_t, int>>> nsigs;
       for (auto& t : res) {
-        jobs.push_back(t->rt.get());
-        nsig.push_back({t->id, t->rt->level});
+        Job* J = t->rt.get();
+        if (t->job.params.iters[J->level] <= 0) continue;
+        const GroupKey k{J->p.window, J->p.metric, J->p.K};
+        groups[k].push_back(J);
+        nsigs[k].push_back({t->id, J->level});
       }
-      if (nsig != sig || !plan) {
-        plan = build_plan(jobs, PLAN_ITERATION);
-        plan->upload(ctx, s);
-        sig = nsig;
+      for (auto it = plans.begin(); it != plans.end();)
+        it = groups.count(it->first) ? std::next(it) : plans.erase(it);
+      for (auto& g : groups) {
+        std::unique_ptr<Plan>& plan = plans[g.first];
+        if (!plan || sigs[g.first] != nsigs[g.first]) {
+          plan = build_plan(g.second, PLAN_ITERATION);
+          plan->upload(ctx, s);
+          sigs[g.first] = nsigs[g.first];
+        }
+        plan->run(ctx, s);
       }
-      bool any_steps = false;
-      for (auto& t : res)
-        if (t->job.params.iters[t->rt->level] > 0) any_steps = true;
-      if (any_steps) plan->run(ctx, s);
       for (auto& t : res)
         MUSTER_HIP(hipMemcpyAsync(t->rt->host_state, t->rt->js, sizeof(JobState),
                                   hipMemcpyDeviceToHost, s));
@@ -1553,7 +1698,8 @@ void Server::loop() {
       if (e.st == MUSTER_E_DEVICE) ctx->poisoned = true;
       for (auto& t : resident) finish(t, 3, e.st, e.msg);
       resident.clear();
-      plan.reset();
+      plans.clear();
+      sigs.clear();
       done_cv.notify_all();
     }
   }
@@ -1566,7 +1712,7 @@ void Server::loop() {
     resident.clear();
     done_cv.notify_all();
   }
-  plan.reset();
+  plans.clear();
   (void)hipStreamSynchronize(s);
   (void)hipStreamDestroy(s);
 }

@@ -160,6 +160,7 @@ struct Job {
   DevMem m_rigid;                    // RigidState of sessions 1..N-1 (params.rigid)
   float* rigid_out = nullptr;
   DevMem m_stage, m_desc, m_flags;   // staged Exp-backward accumulation (K >= 2)
+  DevMem m_det64;                    // deterministic mode: fixed-point twins (see det64_*)
   float* phi = nullptr;              // may alias the caller's field in grad_mode
   float* mbuf = nullptr;
   float* vbuf = nullptr;
@@ -198,6 +199,17 @@ struct Job {
   }
   int* desc(int dir, int k) const { return m_desc.as<int>() + ((size_t)dir * 2 + k) * tiles_fine * 8; }
   int* flag(int dir, int s) const { return m_flags.as<int>() + (size_t)dir * p.K + s; }
+  bool det() const { return p.deterministic != 0; }
+  // 64-bit fixed-point twins of the gradient of consecutive field dir (the
+  // depth-1 pair gradient, dir = 2i for f_i, 2i+1 for b_i) and of the
+  // Exp-backward ping-pong field pp(dir, k); null unless deterministic
+  long long* det64_pair(int dir) const {
+    return det() ? m_det64.as<long long>() + (size_t)dir * 3 * Vc() : nullptr;
+  }
+  long long* det64_pp(int dir, int k) const {
+    return det() ? m_det64.as<long long>() + ((size_t)2 * (N - 1) + (size_t)dir * 2 + k) * 3 * Vc()
+                 : nullptr;
+  }
   float* coef(int i, int j) const;
   const float* image(int i) const { return level_images[level] + (size_t)i * VIc(); }
 };
@@ -217,7 +229,8 @@ void load_tune_cache(Ctx* ctx);
 enum StageKind {
   ST_EXP_FWD, ST_COMPOSE_FWD, ST_SIM_STATS, ST_SIM_GRAD, ST_COMPOSE_BWD, ST_EXP_BWD, ST_ADAM,
   ST_FINISH, ST_SMOOTH, ST_UPSAMPLE, ST_UPSAMPLE_ADJ, ST_RIGID_GRAD, ST_RIGID_STEP, ST_WARP,
-  ST_UNSTAGE, ST_PULL_COMBINE
+  ST_UNSTAGE, ST_PULL_COMBINE, ST_COMPOSE_BWD_DETMAX, ST_EXP_BWD_DETMAX, ST_DET_FOLD,
+  ST_DET_CLEAR
 };
 
 struct Stage {

@@ -32,11 +32,22 @@ def ctx():
 
 
 def assert_same_run(a, b, what):
-    """Two runs of the same job that differ only in the order of float
-    atomics: equal up to rounding, which Adam's per-voxel normalisation
-    amplifies at the isolated voxels whose gradient is at rounding level (there
-    the step direction follows the rounding).  So: a tiny mean, a tiny 99.9th
-    percentile, and a bound on the few outliers well below the step size."""
+    """Two runs of the same deterministic job (params.deterministic): the
+    flows are bit-identical, whatever else shared the launches."""
+    d = (a - b).abs()
+    log(f"{what}: max |diff| {float(d.max()):.2e}")
+    assert torch.equal(a, b), f"{what}: not bit-identical (max |diff| {float(d.max()):.2e})"
+
+
+def assert_close_up_to_adam_rounding(a, b, what):
+    """Two runs of the same job in the default mode, which differ only in the
+    order of float atomics (about 1e-7 relative per gradient).  Adam divides
+    each voxel's step by the root of its second moment, so where a gradient is
+    at rounding level the step's direction follows the rounding, and over
+    many steps such voxels drift apart by a few step sizes while the rest
+    agree to rounding.  So: a tiny mean, a tiny 99.9th percentile, and a
+    bound on the few outliers of a few steps of lr.  Deterministic mode
+    removes the difference altogether (assert_same_run)."""
     d = (a - b).abs().flatten().double()
     q = float(torch.quantile(d[torch.randperm(d.numel(), device=d.device)[:1 << 20]], 0.999))
     log(f"{what}: max |diff| {float(d.max()):.2e}, 99.9% {q:.2e}, mean {float(d.mean()):.2e}")
@@ -109,31 +120,72 @@ def test_blob_series_registration_matches_oracle_error(ctx):
         assert np.abs(got[idx(i, j)] - want).max() < 1e-4, (i, j)
 
 
-def test_graph_replay_matches_eager(ctx):
+@pytest.mark.parametrize("det", [True, False])
+def test_graph_replay_matches_eager(ctx, det):
     from paper_2412_14671_amd import MusterParams, synth
     s = synth.phantom_series((32, 24, 40), 3, seed=4)
     imgs = s.images.to(DEV)
     a, _, ra = ctx.register(imgs, s.times, MusterParams(iters=[4, 6], K=5, window=3,
-                                                         metric="silncc", use_graph=True))
+                                                         metric="silncc", use_graph=True,
+                                                         deterministic=det))
     b, _, rb = ctx.register(imgs, s.times, MusterParams(iters=[4, 6], K=5, window=3,
-                                                         metric="silncc", use_graph=False))
-    assert_same_run(a, b, "graph vs eager")
-    assert abs(ra["loss_last"] - rb["loss_last"]) < 1e-5 * abs(rb["loss_last"])
+                                                         metric="silncc", use_graph=False,
+                                                         deterministic=det))
+    if det:
+        assert_same_run(a, b, "graph vs eager")
+        assert abs(ra["loss_last"] - rb["loss_last"]) < 1e-12 * abs(rb["loss_last"])
+    else:
+        assert_close_up_to_adam_rounding(a, b, "graph vs eager (default mode)")
+        assert abs(ra["loss_last"] - rb["loss_last"]) < 1e-5 * abs(rb["loss_last"])
 
 
-def test_batch_matches_alone(ctx):
+@pytest.mark.parametrize("K", [5, 1])
+def test_batch_matches_alone(ctx, K):
+    """Deterministic jobs with uneven N and grids in one batched launch
+    sequence give bit-identical flows and pair fields to each job alone (K 1:
+    the flat Exp adjoint, every block's scatter through the fixed point)."""
     from paper_2412_14671_amd import MusterParams, synth
     subjects = [synth.phantom_series((24, 24, 24), 3, seed=31),
                 synth.phantom_series((32, 40, 24), 5, seed=32),
                 synth.phantom_series((16, 24, 32), 2, seed=33)]
-    params = MusterParams(iters=[3, 5], K=5, window=5, metric="silncc", lr=0.1)
+    params = MusterParams(iters=[3, 5], K=K, window=5, metric="silncc", lr=0.1,
+                          smooth_sigma=1.0, deterministic=True)
     outs, reps = ctx.register_batch([s.images.to(DEV) for s in subjects],
                                     [s.times for s in subjects], params)
     for s, o, r in zip(subjects, outs, reps):
         alone, _, ra = ctx.register(s.images.to(DEV), s.times, params)
+        again, _, _ = ctx.register(s.images.to(DEV), s.times, params)
         assert r["status"] == 0
+        assert_same_run(alone, again, "alone vs alone")
         assert_same_run(o, alone, "batched vs alone")
-        assert abs(r["loss_last"] - ra["loss_last"]) < 1e-5 * abs(ra["loss_last"])
+        assert abs(r["loss_last"] - ra["loss_last"]) < 1e-12 * abs(ra["loss_last"])
+
+
+def test_deterministic_mode_agrees_with_the_default_mode():
+    """The fixed-point accumulation changes results only at rounding level.
+    Both runs use the same (default) tiling, so only the accumulation
+    differs.  After three Adam steps the flows agree to rounding except where
+    a gradient is near Adam's eps, where the step lr g / (|g| + eps) follows
+    the rounding: a tiny 99.9th percentile, and a maximum below 0.2 % of a
+    step."""
+    from paper_2412_14671_amd import Context, MusterParams, synth
+    c = Context(0)
+    try:
+        c.set_tiling("default")
+        s = synth.phantom_series((32, 40, 24), 4, seed=35)
+        imgs = s.images.to(DEV)
+        lr = 0.05
+        kw = dict(iters=[3], K=6, window=5, metric="silncc", lr=lr, alpha_ss=0.5, smooth_sigma=1.0)
+        a, _, ra = c.register(imgs, s.times, MusterParams(deterministic=True, **kw))
+        b, _, rb = c.register(imgs, s.times, MusterParams(deterministic=False, **kw))
+        d = (a - b).abs().flatten().double()
+        q = float(torch.quantile(d, 0.999))
+        log(f"deterministic vs default: max |diff| {float(d.max()):.2e}, 99.9% {q:.2e}")
+        assert q < 1e-6
+        assert float(d.max()) < 2e-3 * lr
+        assert abs(ra["loss_last"] - rb["loss_last"]) < 1e-6 * abs(rb["loss_last"])
+    finally:
+        c.close()
 
 
 def test_three_level_pyramid_runs_and_improves(ctx):
@@ -174,26 +226,22 @@ def test_invalid_arguments_are_rejected(ctx):
 
 
 def test_server_results_match_alone(ctx):
-    """Jobs submitted together are admitted, batched with each other and
-    retired between ticks; each result equals the job run alone.  Both
-    contexts use one fixed tiling of the window sums: the autotuner of each
-    context may pick another tiling for a level, and a different summation
-    order changes gradients at rounding level, which the first Adam step of a
-    level turns into steps of either sign at voxels whose gradient is at that
-    level."""
+    """Jobs submitted together are admitted, batched with each other (each
+    tick steps every resident job, whatever its level) and retired between
+    ticks; each result is bit-identical to the job run alone on another
+    context (deterministic mode: fixed-point scatters, and the default tiling
+    of the window sums rather than each context's autotuned one)."""
     from paper_2412_14671_amd import Context, MusterParams, Server, synth
     c2 = Context(0)
-    c2.set_tiling("fixed", 0, 32)
-    ctx.set_tiling("fixed", 0, 32)
     srv = Server(c2)
     subjects = [synth.phantom_series((24, 24, 24), 3, seed=41),
                 synth.phantom_series((32, 24, 16), 4, seed=42),
                 synth.phantom_series((16, 16, 32), 3, seed=43),
                 synth.phantom_series((24, 32, 24), 2, seed=44)]
-    params = [MusterParams(iters=[4, 6], K=5, window=3, metric="silncc"),
-              MusterParams(iters=[2, 3], K=5, window=3, metric="silncc"),
-              MusterParams(iters=[5], K=5, window=3, metric="silncc"),
-              MusterParams(iters=[1, 2, 3], K=5, window=3, metric="silncc")]
+    params = [MusterParams(iters=[4, 6], K=5, window=3, metric="silncc", deterministic=True),
+              MusterParams(iters=[2, 3], K=5, window=3, metric="silncc", deterministic=True),
+              MusterParams(iters=[5], K=5, window=3, metric="silncc", deterministic=True),
+              MusterParams(iters=[1, 2, 3], K=5, window=3, metric="silncc", deterministic=True)]
     imgs = [s.images.to(DEV) for s in subjects]
     tickets = [srv.submit(im, s.times, p) for im, s, p in zip(imgs, subjects, params)]
     reps = [srv.wait(tk) for tk, _ in tickets]
@@ -201,11 +249,42 @@ def test_server_results_match_alone(ctx):
         assert r["status"] == 0, r
         alone, _, ra = ctx.register(im, s.times, p)
         assert_same_run(out, alone, "served vs alone")
+        assert abs(r["loss_last"] - ra["loss_last"]) < 1e-12 * abs(ra["loss_last"])
         assert r["iterations"] == sum(p.iters)
     st = srv.stats()
     assert st["resident"] == 0 and st["queued"] == 0
-    ctx.set_tiling("autotune")
     c2.close()
+
+
+def test_server_mixes_levels_without_steps_and_other_windows(ctx):
+    """A served job whose first level has no steps (iters [0, 5]) shares its
+    ticks with stepping jobs but takes no step until its second level, and
+    jobs with another window, metric or K are admitted behind it without
+    waiting (they run in a launch group of their own in the same ticks):
+    every result is bit-identical to the job alone."""
+    from paper_2412_14671_amd import Context, MusterParams, Server, synth
+    c2 = Context(0)
+    try:
+        srv = Server(c2)
+        subjects = [synth.phantom_series((24, 24, 24), 3, seed=45),
+                    synth.phantom_series((32, 24, 16), 3, seed=46),
+                    synth.phantom_series((16, 24, 32), 4, seed=47),
+                    synth.phantom_series((24, 16, 24), 2, seed=48)]
+        params = [MusterParams(iters=[6, 4], K=5, window=3, metric="silncc", deterministic=True),
+                  MusterParams(iters=[0, 5], K=5, window=3, metric="silncc", deterministic=True),
+                  MusterParams(iters=[5], K=5, window=5, metric="lncc", deterministic=True),
+                  MusterParams(iters=[2, 3], K=4, window=3, metric="silncc", deterministic=True)]
+        imgs = [s.images.to(DEV) for s in subjects]
+        tickets = [srv.submit(im, s.times, p) for im, s, p in zip(imgs, subjects, params)]
+        reps = [srv.wait(tk) for tk, _ in tickets]
+        for (tk, out), im, s, p, r in zip(tickets, imgs, subjects, params, reps):
+            assert r["status"] == 0, r
+            assert r["iterations"] == sum(p.iters)
+            alone, _, ra = ctx.register(im, s.times, p)
+            assert_same_run(out, alone, f"served vs alone, iters {list(p.iters)}")
+            assert abs(r["loss_last"] - ra["loss_last"]) < 1e-12 * abs(ra["loss_last"])
+    finally:
+        c2.close()
 
 
 def test_autotuned_tiling_is_valid_cached_and_reproducible():
@@ -224,7 +303,7 @@ def test_autotuned_tiling_is_valid_cached_and_reproducible():
         a, _, ra = c.register(imgs, s.times, params)
         c.set_tiling("fixed", sh, zc)
         b, _, rb = c.register(imgs, s.times, params)
-        assert_same_run(a, b, "autotuned vs fixed")
+        assert_close_up_to_adam_rounding(a, b, "autotuned vs fixed")
         assert abs(ra["loss_last"] - rb["loss_last"]) <= 1e-6 * abs(ra["loss_last"])
     finally:
         c.close()

@@ -154,16 +154,17 @@ def _check_against_oracle(s, out, rep, lr, sigma):
         assert_grad_close(got, want, tol=2e-2)
 
 
-@pytest.mark.parametrize("sigma", [0.0, 1.0])
-def test_batch_of_ragged_subjects_matches_oracle_steps(ctx, sigma):
+@pytest.mark.parametrize("sigma,det", [(0.0, False), (1.0, False), (1.0, True)])
+def test_batch_of_ragged_subjects_matches_oracle_steps(ctx, sigma, det):
     """Three subjects with 3, 4 and 2 sessions on three different grids, in
     one batched launch sequence replayed from a captured graph: each subject's
-    losses and Adam step equal the oracle's for that subject alone."""
+    losses and Adam step equal the oracle's for that subject alone (also in
+    the deterministic mode's fixed-point accumulation)."""
     from paper_2412_14671_amd import MusterParams
     subjects = _subjects()
     lr = 0.05
     params = MusterParams(iters=[2], K=6, window=5, metric="silncc", alpha_ss=0.5, lr=lr,
-                          smooth_sigma=sigma, use_graph=True)
+                          smooth_sigma=sigma, use_graph=True, deterministic=det)
     outs, reps = ctx.register_batch([s.images.to(DEV) for s in subjects],
                                     [s.times for s in subjects], params)
     for s, o, r in zip(subjects, outs, reps):
