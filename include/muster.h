@@ -316,6 +316,21 @@ muster_status muster_compose_bwd(muster_ctx* ctx, void* stream, const int dims[3
 muster_status muster_sim(muster_ctx* ctx, void* stream, const int dims[3], int window,
                          int metric, const float* F_dev, const float* I_dev,
                          const float* U_dev, double* sim_host, float* grad_U_dev);
+/* muster_sim without allocating device memory, for callers that cannot
+ * call hipMalloc: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid it.  The same kernels and arguments as muster_sim;
+ * the warped image, the window coefficients and the sum live in a scratch
+ * array of 96 MiB + 256 bytes that each GPU the library runs on holds from
+ * the first context created on it until the process ends, so the grid is at
+ * most 6 * 2^20 voxels (MUSTER_E_INVALID beyond).  The window statistics use
+ * the context's fixed tiling, or the tiling it has already tuned for this
+ * shape, else the default one (never a new autotuning run).  Every call on a
+ * GPU shares that GPU's scratch: calls that overlap on one GPU (other
+ * streams, threads or contexts) race and must be serialised by the caller.
+ * Synchronises the stream. */
+muster_status muster_sim_noalloc(muster_ctx* ctx, void* stream, const int dims[3], int window,
+                                 int metric, const float* F_dev, const float* I_dev,
+                                 const float* U_dev, double* sim_host, float* grad_U_dev);
 /* One Adam step (PyTorch semantics, bias-corrected, step number t >= 1) on n
  * floats in place. */
 muster_status muster_adam(muster_ctx* ctx, void* stream, int64_t n, float* x_dev,

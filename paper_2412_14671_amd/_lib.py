@@ -94,6 +94,7 @@ SIGNATURES = {
     "muster_compose": (_ST, [_P, _P, DIMS, _P, _P, _P]),
     "muster_compose_bwd": (_ST, [_P, _P, DIMS, _P, _P, _P, _P, _P]),
     "muster_sim": (_ST, [_P, _P, DIMS, c_int, c_int, _P, _P, _P, POINTER(c_double), _P]),
+    "muster_sim_noalloc": (_ST, [_P, _P, DIMS, c_int, c_int, _P, _P, _P, POINTER(c_double), _P]),
     "muster_adam": (_ST, [_P, _P, c_int64, _P, _P, _P, _P, c_int, c_float, c_float, c_float,
                           c_float]),
     "muster_reg": (_ST, [_P, _P, DIMS, _P, POINTER(c_double), _P]),

@@ -156,6 +156,15 @@ class Context:
                                     _ptr(U), byref(val), _ptr(g)))
         return (val.value, g) if grad else val.value
 
+    def sim_noalloc(self, F, I, U, window, metric="lncc", grad=False):
+        """sim() through the entry point that allocates no device memory."""
+        m = {"lncc": L.METRIC_LNCC, "silncc": L.METRIC_SILNCC}[metric]
+        val = c_double()
+        g = torch.empty_like(U) if grad else None
+        L.check(self.lib.muster_sim_noalloc(self.h, _stream(), _dims(F.shape), window, m, _ptr(F),
+                                            _ptr(I), _ptr(U), byref(val), _ptr(g)))
+        return (val.value, g) if grad else val.value
+
     def adam(self, x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         L.check(self.lib.muster_adam(self.h, _stream(), c_int64(x.numel()), _ptr(x), _ptr(g),
                                      _ptr(m), _ptr(v), t, lr, beta1, beta2, eps))

@@ -16,6 +16,8 @@
 // block-to-tile map: blocks are dealt round-robin over the 8 XCDs, and the
 // map hands each XCD a contiguous run of tiles so the neighbouring rows that
 // the gathers touch stay in that XCD's L2.
+#include <map>
+#include <mutex>
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <climits>
@@ -2760,6 +2762,30 @@ hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hi
   MUSTER_LAUNCH(k_reg, dim3(ceil_div(V, BLOCK)), dim3(BLOCK), 0, s, d.D, d.H, d.W, phi, out,
                      grad);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free similarity entry point (see
+// NOALLOC_SCRATCH_BYTES).  Host code never passes the array's name to a
+// kernel or a copy: only the address hipGetSymbolAddress returns for the
+// current device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch_address(int device, void** ptr) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) {
+    *ptr = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  addr.emplace(device, p);
+  *ptr = p;
+  return hipSuccess;
 }
 
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {

@@ -412,6 +412,17 @@ hipError_t launch_reg(GridDims d, const float* phi, double* out, float* grad, hi
 hipError_t launch_reg_ext(GridDims d, const float* f, const float* fprev, float l2w, float tsw,
                           float inv_dp, float inv_ds, double* out, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+
+// Scratch of the allocation-free similarity entry point: a file-scope device
+// array (each GPU holds its own copy until the process ends) with the pair's
+// sum in its first 256 bytes, then the warped source image and the window
+// coefficients, for grids of up to NOALLOC_MAX_VOXELS voxels.
+constexpr size_t NOALLOC_MAX_VOXELS = (size_t)6 << 20;
+constexpr size_t NOALLOC_SCRATCH_BYTES = 256 + 16 * NOALLOC_MAX_VOXELS;
+// Device address of the scratch array on `device`, which must be current:
+// looked up once per device with hipGetSymbolAddress and kept (the array's
+// name is a host-side stand-in, not a device address).
+hipError_t noalloc_scratch_address(int device, void** ptr);
 hipError_t launch_jacobian_det(GridDims d, const float* U, float* out, hipStream_t s);
 hipError_t launch_rigid_grad(const RigidGradItem* items, int n_items, int n_tiles, hipStream_t s);
 hipError_t launch_rigid_step(const RigidStepItem* items, int n_items, hipStream_t s);

@@ -1959,6 +1959,8 @@ muster_status muster_ctx_create(int device, uint64_t hbm_budget, muster_ctx** ou
     }
     auto c = std::make_unique<Ctx>(hbm_budget);
     c->device = device;
+    // the allocation-free entry point's scratch on this device (current now)
+    MUSTER_HIP(noalloc_scratch_address(device, &c->noalloc_scratch));
     load_tune_cache(c.get());
     MUSTER_HIP(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking));
     c->step_items_bytes = 1 << 20;
@@ -2490,6 +2492,71 @@ muster_status muster_sim(muster_ctx* h, void* stream, const int dims[3], int win
       MUSTER_HIP(launch_sim_grad((const SimItem*)(sc.dev() + off), 1, tiles, window, tl.shape,
                                  sc.s));
     MUSTER_HIP(hipMemcpyAsync(sim_host, ctx->step_acc, sizeof(double), hipMemcpyDeviceToHost, sc.s));
+    MUSTER_HIP(hipStreamSynchronize(sc.s));
+  });
+}
+
+muster_status muster_sim_noalloc(muster_ctx* h, void* stream, const int dims[3], int window,
+                                 int metric, const float* F, const float* I, const float* U,
+                                 double* sim_host, float* grad_U) {
+  Ctx* ctx = C(h);
+  return guard(ctx, [&] {
+    NEED(ctx && F && I && U && sim_host, "NULL argument");
+    NEED(window == 3 || window == 5 || window == 7, "window must be 3, 5 or 7");
+    NEED(metric == MUSTER_METRIC_LNCC || metric == MUSTER_METRIC_SILNCC, "unknown metric");
+    check_dims(dims, window);
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2];
+    // sum | warped image | (coefficients), each part on a 256-byte boundary
+    const size_t m_off = 256;
+    const size_t c_off = m_off + ((V * sizeof(float) + 255) & ~(size_t)255);
+    const size_t need = c_off + (grad_U ? 3 * V * sizeof(float) : 0);
+    NEED(V <= NOALLOC_MAX_VOXELS && need <= NOALLOC_SCRATCH_BYTES,
+         "%zu voxels exceed the %zu of the allocation-free scratch", V,
+         (size_t)NOALLOC_MAX_VOXELS);
+    NEED(ctx->noalloc_scratch, "no scratch on this device");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StepCall sc{ctx, (hipStream_t)stream, {}};
+    unsigned char* base = static_cast<unsigned char*>(ctx->noalloc_scratch);
+    double* sum = reinterpret_cast<double*>(base);
+    // the tiling the context already holds for this shape, never a new
+    // autotuning run (that would allocate its scratch problem)
+    SimTile tl;
+    tl.shape = 0;
+    tl.zc = std::min(32, dims[0]);
+    if (ctx->tile_mode == MUSTER_TILES_FIXED) {
+      tl = ctx->fixed_tile;
+      tl.zc = std::min(tl.zc, dims[0]);
+    } else if (ctx->tile_mode == MUSTER_TILES_AUTOTUNE) {
+      std::lock_guard<std::mutex> tk(ctx->tune_mu);
+      auto f = ctx->tuned.find(tune_key(dims, window, metric));
+      if (f != ctx->tuned.end()) tl = f->second;
+    }
+    const int r = (window - 1) / 2;
+    SimItem it{};
+    it.D = dims[0]; it.H = dims[1]; it.W = dims[2];
+    it.zc = tl.zc;
+    it.F = F;
+    it.I = I;
+    it.U = U;
+    it.M = reinterpret_cast<float*>(base + m_off);
+    it.coef = grad_U ? reinterpret_cast<float*>(base + c_off) : nullptr;
+    it.gU = grad_U;
+    it.inv_nr = 1.0 / ((double)(dims[0] - 2 * r) * (dims[1] - 2 * r) * (dims[2] - 2 * r));
+    it.js = nullptr;
+    it.sim_out = sum;
+    const size_t off = sc.add(it);
+    sc.upload();
+    // the sum starts at zero: a fill kernel (two floats of zero bits)
+    MUSTER_HIP(launch_fill(reinterpret_cast<float*>(sum), 2, 0.f, sc.s));
+    MUSTER_HIP(launch_warp((const SimItem*)(sc.dev() + off), 1,
+                           point_tiles(dims[0], dims[1], dims[2]), sc.s));
+    const int tiles = stat_tiles(dims[0], dims[1], dims[2], tl.zc, tl.shape);
+    MUSTER_HIP(launch_sim_stats((const SimItem*)(sc.dev() + off), 1, tiles, window, metric,
+                                tl.shape, sc.s));
+    if (grad_U)
+      MUSTER_HIP(launch_sim_grad((const SimItem*)(sc.dev() + off), 1, tiles, window, tl.shape,
+                                 sc.s));
+    MUSTER_HIP(hipMemcpyAsync(sim_host, sum, sizeof(double), hipMemcpyDeviceToHost, sc.s));
     MUSTER_HIP(hipStreamSynchronize(sc.s));
   });
 }

@@ -101,6 +101,7 @@ struct Ctx {
   void* step_items = nullptr;        // device buffer for single-step item tables
   size_t step_items_bytes = 0;
   double* step_acc = nullptr;        // device doubles for single-step results
+  void* noalloc_scratch = nullptr;   // this device's scratch array (muster_sim_noalloc)
   std::unique_ptr<Server> server;
   // tiling of the window statistics: MUSTER_TILES_* mode, the fixed choice,
   // and the autotuner's results keyed by (D, H, W, window, metric)
