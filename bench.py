@@ -10,8 +10,11 @@ per-subject loop, and the serving form's latency.
   * A step is one iteration of every subject (forward, adjoint and Adam step
     of all sixteen, as one batched launch sequence).  W untimed steps, then K
     timed ones; value = session-voxel-iterations per second over the timed
-    steps (sum of N_s * V_s per step).  The timed steps launch eagerly with
-    HIP events on the dominant kernel's launches (for the roofline).
+    steps (sum of N_s * V_s per step).  The K steps are timed by the library
+    between the stream synchronisations it places around them (the call that
+    runs them also creates the jobs and writes their outputs: timed_call_s).
+    The timed steps launch eagerly with HIP events on the dominant kernel's
+    launches (for the roofline).
   * Then the whole 100-step schedule: batched (one launch sequence for all
     subjects, each step replayed from a captured hipGraph, autotuned tiles)
     against the plain loop (the same subjects one after another, the same
@@ -63,15 +66,13 @@ def parse():
                     help="skip the extra registration that times every kernel class")
     ap.add_argument("--graph-steps", type=int, default=1,
                     help="registrations replayed from captured graphs after the timed region")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
-                                                     "exp_bwd_phantom6_160x192x160_traffic.txt"),
-                    help="JSON summary of rocprofv3 FETCH_SIZE/WRITE_SIZE passes for the dominant "
-                         "kernel (per grid size); used only if it matches the current kernels")
-    ap.add_argument("--l2hit", default=os.path.join(ROOT, "profiles",
-                                                    "l2_hit_phantom6_160x192x160.txt"),
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "batch16_traffic.txt"),
+                    help="JSON summary of rocprofv3 FETCH_SIZE/WRITE_SIZE passes (per kernel class "
+                         "and grid size); used only if it matches the current kernels")
+    ap.add_argument("--l2hit", default=os.path.join(ROOT, "profiles", "batch16_l2_hit.txt"),
                     help="committed L2 hit-rate summary (TCC_HIT / TCC_MISS per kernel and grid)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 256 MiB device copy (for counter calibration)")
+                    help="also run a kernel that reads and writes 256 MiB once (counter calibration)")
     ap.add_argument("--shape", default="160,192,160")
     ap.add_argument("--sessions", type=int, default=6)
     ap.add_argument("--iters", default="200,100,50")
@@ -262,19 +263,20 @@ def kernels_sha256():
 
 
 def traffic_per_launch(path, kernel, launch_grids):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    weighted like the timed launches ({grid in blocks: launches}); None if the
-    summary is absent, covers another kernel or predates the current kernels."""
-    import hashlib
+    """HBM bytes per launch of `kernel` (e.g. "k_exp_bwd") from the committed
+    counter summary, weighted like the timed launches ({grid in blocks:
+    launches}); None if the summary is absent, lacks that kernel or grid, has
+    no calibration, or predates the current kernels."""
     if not path or not os.path.exists(path):
         return None
     t = json.load(open(path))
-    if t.get("kernel") != kernel or t.get("kernels_sha256") != kernels_sha256():
+    if t.get("kernels_sha256") != kernels_sha256() or not t.get("calibration"):
         return None
+    per = t.get("kernels", {}).get(kernel, {}).get("per_grid", {})
     ff, wf = t["calibration"]["fetch_factor"], t["calibration"]["write_factor"]
     tot = n = 0
     for grid, launches in launch_grids.items():
-        e = t["per_grid"].get(str(grid))
+        e = per.get(str(grid))
         if e is None:
             return None
         tot += launches * (e["fetch_kib"] * ff + e["write_kib"] * wf) * 1024.0
@@ -286,15 +288,12 @@ def l2_hit_per_launch(path, kernel, launch_grids):
     """L2 hit rate of `kernel` from the committed TCC_HIT / TCC_MISS summary,
     over the timed launch mix ({grid in blocks: launches}); None if the
     summary is absent or predates the current kernels."""
-    import hashlib
     if not path or not os.path.exists(path):
         return None
     t = json.load(open(path))
     if t.get("kernels_sha256") != kernels_sha256():
         return None
-    per = t.get("kernels", {}).get(kernel)
-    if per is None:
-        return None
+    per = t.get("kernels", {}).get(kernel, {}).get("per_grid", {})
     hit = miss = 0.0
     for grid, launches in launch_grids.items():
         e = per.get(str(grid))
@@ -346,10 +345,11 @@ def main():
     else:
         out = bench_serve(args, ctx, dev, torch, synth, MusterParams)
     if args.copy_calibration:
-        a = torch.empty(64 * 1024 * 1024, device=dev)
-        b = torch.empty_like(a)
+        # a kernel of known traffic for the counters: 64 Mi int32 read and
+        # written once (256 MiB each way), under a name nothing else launches
+        a = torch.zeros(64 * 1024 * 1024, dtype=torch.int32, device=dev)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.bitwise_not(a)
         torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     ctx.close()
@@ -429,9 +429,13 @@ def bench_headline(args, ctx, dev, torch, synth, MusterParams):
     log(f"timed: {K} batched steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.register_batch(imgs, times, params(K, False))
+    _, treps = ctx.register_batch(imgs, times, params(K, False))
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt_call = time.perf_counter() - t0
+    # the K steps alone, between the stream synchronisations the library
+    # places around them (the call also creates the jobs, moves them to the
+    # level and writes their outputs)
+    dt = treps[0]["step_seconds"]
     ctx.set_kernel_timing(False)
     stats_timed = ctx.kernel_stats()
     value = per_step * K / dt
@@ -439,7 +443,7 @@ def bench_headline(args, ctx, dev, torch, synth, MusterParams):
     # every direction of every subject
     grid = sum(2 * (s.images.shape[0] - 1) * (-(-s.images.shape[1] // 8)) * (-(-s.images.shape[2] // 8))
                * (-(-s.images.shape[3] // 16)) for s in subjects)
-    traffic = {"exp_bwd": traffic_per_launch(args.traffic, "exp_bwd", {grid: 7 * K})}
+    traffic = {"exp_bwd": traffic_per_launch(args.traffic, "k_exp_bwd", {grid: 7 * K})}
     _, roof = roofline_from_stats(stats_timed, traffic, stats_timed)
     if roof is not None:
         roof["l2_hit_rate"] = l2_hit_per_launch(args.l2hit, "k_exp_bwd", {grid: 7 * K})
@@ -458,23 +462,27 @@ def bench_headline(args, ctx, dev, torch, synth, MusterParams):
                    "session_voxels_per_step": per_step},
         "roofline": roof,
         "cpu_baseline": None,
+        "timed_call_s": round(dt_call, 3),
     }
     if not args.no_full:
         # the whole schedule, batched (graph-replayed) against the plain loop
         log(f"batched: {T} steps, graph-replayed")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        outs, _ = ctx.register_batch(imgs, times, params(T, True))
+        outs, breps = ctx.register_batch(imgs, times, params(T, True))
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
+        tb_steps = breps[0]["step_seconds"]
         log(f"plain loop: {T} steps per subject, eager, default tiles")
         ctx.set_tiling("default")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plain = []
+        tp_steps = 0.0
         for im, tm in zip(imgs, times):
-            svf, _, _ = ctx.register(im, tm, params(T, False))
+            svf, _, prep = ctx.register(im, tm, params(T, False))
             plain.append(svf)
+            tp_steps += prep["step_seconds"]
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
         ctx.set_tiling("autotune")
@@ -491,6 +499,9 @@ def bench_headline(args, ctx, dev, torch, synth, MusterParams):
             "plain_loop_value": round(per_step * T / tp, 1),
             "plain_loop_s": round(tp, 3),
             "batched_over_plain": round(tp / tb, 3),
+            "batched_steps_s": round(tb_steps, 3),
+            "plain_loop_steps_s": round(tp_steps, 3),
+            "batched_over_plain_steps_only": round(tp_steps / tb_steps, 3),
             "eu_batched": [round(x, 4) for x in eu_b],
             "eu_plain": [round(x, 4) for x in eu_p],
             "eu_at_zero": [round(x, 4) for x in eu_0],
@@ -662,7 +673,7 @@ def bench_register(args, ctx, dev, torch, synth, MusterParams):
         d = [x // 2 ** (L - 1 - l) for x in shape]
         g = 2 * (N - 1) * (-(-d[0] // 8)) * (-(-d[1] // 8)) * (-(-d[2] // 16))
         grids[g] = grids.get(g, 0) + 7 * iters[l] * args.steps
-    traffic = {"exp_bwd": traffic_per_launch(args.traffic, "exp_bwd", grids)}
+    traffic = {"exp_bwd": traffic_per_launch(args.traffic, "k_exp_bwd", grids)}
     kname, roof = roofline_from_stats(stats, traffic, stats_timed)
     if roof is not None:
         roof["l2_hit_rate"] = l2_hit_per_launch(args.l2hit, "k_" + kname, grids)

@@ -128,9 +128,9 @@ typedef struct muster_params {
                                       scatters that add into shared fields with
                                       atomics add 64-bit fixed point at a scale
                                       set per job and launch (one more reduce-only
-                                      pass of those kernels and a fold; about 12 %
-                                      slower; 6(N-1) more int64 fields of the
-                                      flow grid), and the window statistics use
+                                      pass of those kernels and a fold, and
+                                      6(N-1) more int64 fields of the flow
+                                      grid), and the window statistics use
                                       the default tiling instead of the
                                       autotuner's.  Registration entry points
                                       only.  The rigid adjustment's sums remain
@@ -146,6 +146,12 @@ typedef struct muster_report {
   double seconds;                  /* wall time from start (or submission) to end */
   double queue_seconds;            /* serving only: submission to admission       */
   uint64_t footprint_bytes;        /* device bytes the job held                   */
+  double step_seconds;             /* wall time of the optimisation steps alone:
+                                      every level's iterations, each level's run
+                                      bracketed by stream synchronisations (job
+                                      set-up, pyramid and level changes and the
+                                      final outputs excluded); shared by all jobs
+                                      of a batch; 0 for served jobs              */
 } muster_report;
 
 /* One registration job for the batched and serving entry points. */

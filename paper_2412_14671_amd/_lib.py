@@ -13,7 +13,9 @@ from ctypes import (POINTER, Structure, c_char_p, c_double, c_float, c_int, c_in
                     c_void_p)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmuster.so")
+# MUSTER_LIB names another build of the library (the host-sanitizer build of
+# the CPU-side tests); by default the in-tree libmuster.so
+LIB_PATH = os.environ.get("MUSTER_LIB") or os.path.join(HERE, "libmuster.so")
 MAX_LEVELS = 6
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_BUSY, E_NONFINITE, E_CANCELLED, E_INTERNAL = range(8)
@@ -51,7 +53,7 @@ class Params(Structure):
 class Report(Structure):
     _fields_ = [("status", c_int), ("iterations", c_int), ("loss_first", c_double),
                 ("loss_last", c_double), ("seconds", c_double), ("queue_seconds", c_double),
-                ("footprint_bytes", c_uint64)]
+                ("footprint_bytes", c_uint64), ("step_seconds", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1026,6 +1026,16 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     vok[j] = vx[j] < W && vy[j] < H && vz[j] < D;
     gv[j][0] = gv[j][1] = gv[j][2] = 0.f;
   }
+  // u_s at the owned voxels, loaded before G_{s+1} is gathered so that the
+  // loads are in flight while the pull waits on its own
+  float uo[VPT][3];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int p = vok[j] ? (vz[j] * H + vy[j]) * W + vx[j] : 0;
+    uo[j][0] = a * ldo(s, p);
+    uo[j][1] = a * ldo(s + V, p);
+    uo[j][2] = a * ldo(s + 2 * V, p);
+  }
   if (IN_ST) {
     // G_{s+1} over this tile from the staged boxes of the previous step
     pull_staged(it.stage_in, it.desc_in, it.flag_in, gin, local, tc, D, H, W, vz, vy, vx, vok, gv,
@@ -1061,8 +1071,8 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     if (!vok[j]) continue;
     const int x = vx[j], y = vy[j], z = vz[j];
     const int p = (z * H + y) * W + x;
-    const float uz = a * ldo(s, p), uy = a * ldo(s + V, p), ux = a * ldo(s + 2 * V, p);
-    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
+    const Ax az = axis_disp(z, uo[j][0], D), ay = axis_disp(y, uo[j][1], H),
+             ax = axis_disp(x, uo[j][2], W);
     const int base = (az.i0 * H + ay.i0) * W + ax.i0;
     const float g0 = gv[j][0], g1 = gv[j][1], g2 = gv[j][2];
     // (J^T g) of the Jacobian J of src at q is the gradient of the

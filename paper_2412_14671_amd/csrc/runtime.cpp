@@ -4,6 +4,8 @@
 // continuous-batching server, and the C ABI of include/muster.h.
 #include "runtime.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -37,6 +39,23 @@ void fail(muster_status st, const char* fmt, ...) {
   va_end(ap);
   throw Error{st, std::string(buf)};
 }
+
+// A named range on the profiler's marker timeline (rocprofv3
+// --marker-trace): pyramid levels, the final forward pass, server ticks and
+// admissions.  Without a profiler attached the calls return at once.
+struct Range {
+  explicit Range(const char* fmt, ...) {
+    char buf[160];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    roctxRangePushA(buf);
+  }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 double now_seconds() {
   using namespace std::chrono;
@@ -199,6 +218,7 @@ uint64_t job_footprint(int N, const int dims[3], const muster_params& p) {
   // flow grid: phi, m, v, Exp steps, composed pairs, pair gradients, ping-pong
   uint64_t fields = 3 * n1 + 2 * n1 * per_dir_fields(p) + std::max<uint64_t>(Pd, 1) + P + 4 * n1;
   if (p.smooth_sigma > 0.f) fields += 3 * n1;
+  else if (p.K >= 2) fields += n1;  // combined gradient of the staged Exp adjoint
   uint64_t bytes = fields * F;
   // image grid: window coefficients, and with a coarser flow grid the pair
   // fields and their gradients
@@ -319,6 +339,8 @@ std::unique_ptr<Job> make_job(Ctx* ctx, const muster_job& jd) {
     J.m_phis.alloc(ctx, n1 * F);
     J.m_t1.alloc(ctx, n1 * F);
     J.m_t2.alloc(ctx, n1 * F);
+  } else if (J.staged()) {
+    J.m_t1.alloc(ctx, n1 * F);  // the combined SVF gradient Adam reads
   }
   J.tiles_fine = point_tiles(J.ldims[L - 1][0], J.ldims[L - 1][1], J.ldims[L - 1][2]);
   J.rigid_out = jd.rigid_out_dev;
@@ -510,6 +532,7 @@ static void read_state(Job& J, hipStream_t s) {
 }
 
 void job_final_outputs(Job& J, hipStream_t s) {
+  Range range("muster final outputs: N %d", J.N);
   Ctx* ctx = J.ctx;
   std::vector<Job*> one{&J};
   auto plan = build_plan(one, PLAN_FORWARD);
@@ -1161,8 +1184,8 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
           it.desc_out = J->desc(dir, s % 2);
           it.flag_out = J->flag(dir, s);
         }
-        // L_ss joins here unless k_pull_combine adds it (smoothing jobs)
-        if (s == 0 && fwd && J->p.alpha_ss > 0.f && !(J->staged() && J->smoothing())) {
+        // L_ss joins here unless k_pull_combine adds it (staged jobs)
+        if (s == 0 && fwd && J->p.alpha_ss > 0.f && !J->staged()) {
           it.reg_w = std::ldexp(1.f, K) * J->p.alpha_ss / (float)(J->N - 1);
           it.reg_loss_w = J->p.alpha_ss / (float)(J->N - 1);
         }
@@ -1212,8 +1235,9 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
     }
   }
   {
-    // staged G_0: straight into the combined gradient t1 of smoothing jobs,
-    // else to the flat G_0 of each direction
+    // staged G_0 of both directions straight into the combined gradient t1,
+    // with the diffusion regulariser (which the Exp adjoint's step 0 then
+    // need not carry); Adam, or the smoothing of the gradient, reads t1
     std::vector<PullItem> pitems;
     std::vector<ExpBwdItem> uitems;
     int ptiles = 0, utiles = 0;
@@ -1223,7 +1247,7 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
       const int* d = J->ldims[J->level];
       const int pt = point_tiles(d[0], d[1], d[2]);
       for (int i = 0; i < J->N - 1; ++i) {
-        if (J->smoothing()) {
+        if (J->staged()) {
           PullItem it{};
           it.tile0 = ptiles;
           it.D = d[0]; it.H = d[1]; it.W = d[2];
@@ -1309,7 +1333,9 @@ void add_backward(Builder& b, const std::vector<Job*>& jobs) {
         it.phi = J->field(J->phi, i);
         it.g0f = J->pp(2 * i, 0);
         it.g0b = J->pp(2 * i + 1, 0);
-        it.gsrc = J->smoothing() ? J->field(J->m_t2.as<float>(), i) : nullptr;
+        it.gsrc = J->smoothing() ? J->field(J->m_t2.as<float>(), i)
+                  : J->staged()  ? J->field(J->m_t1.as<float>(), i)
+                                 : nullptr;
         it.m = J->field(J->mbuf, i);
         it.v = J->field(J->vbuf, i);
         it.scale = std::ldexp(1.f, -J->K());
@@ -1491,11 +1517,15 @@ void Plan::replay(hipStream_t s) { MUSTER_HIP(hipGraphLaunch(exec, s)); }
 // batched registration engine (one or many jobs in lockstep)
 // ---------------------------------------------------------------------------
 static void run_level(Ctx* ctx, std::vector<Job*>& jobs, int level, hipStream_t s, bool use_graph) {
-  for (Job* J : jobs) job_begin_level(*J, level, s);
   const int T = jobs[0]->p.iters[level];
+  Range range("muster level %d: %zu jobs, %d steps, %dx%dx%d", level, jobs.size(), T,
+              jobs[0]->idims[level][0], jobs[0]->idims[level][1], jobs[0]->idims[level][2]);
+  for (Job* J : jobs) job_begin_level(*J, level, s);
   if (T <= 0) return;
   auto plan = build_plan(jobs, PLAN_ITERATION);
   plan->upload(ctx, s);
+  MUSTER_HIP(hipStreamSynchronize(s));
+  const double t0 = now_seconds();
   if (use_graph && !ctx->timing) {
     plan->capture(ctx, s);
     for (int t = 0; t < T; ++t) plan->replay(s);
@@ -1503,6 +1533,8 @@ static void run_level(Ctx* ctx, std::vector<Job*>& jobs, int level, hipStream_t 
     for (int t = 0; t < T; ++t) plan->run(ctx, s);
   }
   MUSTER_HIP(hipStreamSynchronize(s));
+  const double dt = now_seconds() - t0;
+  for (Job* J : jobs) J->step_seconds += dt;
   if (ctx->timing) resolve_timing(ctx);
   for (Job* J : jobs) read_state(*J, s);
 }
@@ -1521,6 +1553,7 @@ static void fill_report(Job& J, double t0, muster_report* rep, hipStream_t s) {
   rep->seconds = now_seconds() - t0;
   rep->queue_seconds = 0.0;
   rep->footprint_bytes = J.footprint;
+  rep->step_seconds = J.step_seconds;
 }
 
 static void register_jobs(Ctx* ctx, hipStream_t caller, std::vector<std::unique_ptr<Job>>& owned,
@@ -1548,173 +1581,101 @@ static void register_jobs(Ctx* ctx, hipStream_t caller, std::vector<std::unique_
 // ---------------------------------------------------------------------------
 // serving
 // ---------------------------------------------------------------------------
-void Server::loop() {
+// The server's executor: jobs, launch plans (one per group of residents that
+// share window, metric and K, rebuilt when its members or levels change) and
+// kernels on the serving thread's own stream.
+namespace {
+struct HipJob : JobHandle {
+  std::unique_ptr<Job> job;
+};
+
+Job& job_of(JobHandle& h) { return *static_cast<HipJob&>(h).job; }
+
+struct HipExecutor : Executor {
+  Ctx* ctx;
   hipStream_t s = nullptr;
-  if (hipSetDevice(ctx->device) != hipSuccess ||
-      hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-    std::lock_guard<std::mutex> lk(mu);
-    stop = true;
-    return;
-  }
-  // one plan per group of resident jobs that can share launches (window,
-  // metric and K), rebuilt when the group's members or levels change
-  using GroupKey = std::tuple<int, int, int>;
   std::map<GroupKey, std::unique_ptr<Plan>> plans;
   std::map<GroupKey, std::vector<std::pair<uint64_t, int>>> sigs;
-  auto finish = [&](std::shared_ptr<Ticket>& t, int state, muster_status st, const std::string& err) {
-    if (t->rt) {
-      t->report.footprint_bytes = t->rt->footprint;
-      t->rt.reset();
+  explicit HipExecutor(Ctx* c) : ctx(c) {}
+  uint64_t footprint(const muster_job& j) override {
+    return job_footprint(j.N, j.dims, j.params);
+  }
+  uint64_t budget() override { return ctx->arena.budget(); }
+  bool fits(uint64_t bytes) override { return ctx->arena.fits(bytes); }
+  std::unique_ptr<JobHandle> admit(const muster_job& j) override {
+    Range range("muster admit job: N %d", j.N);
+    auto h = std::make_unique<HipJob>();
+    h->job = make_job(ctx, j);
+    job_begin_level(*h->job, 0, s);
+    return h;
+  }
+  void step(const GroupKey& key, const std::vector<JobHandle*>& group,
+            const std::vector<std::pair<uint64_t, int>>& sig) override {
+    std::unique_ptr<Plan>& plan = plans[key];
+    if (!plan || sigs[key] != sig) {
+      std::vector<Job*> jobs;
+      for (JobHandle* h : group) jobs.push_back(&job_of(*h));
+      plan = build_plan(jobs, PLAN_ITERATION);
+      plan->upload(ctx, s);
+      sigs[key] = sig;
     }
-    t->state = state;
-    t->status = st;
-    t->err = err;
-    t->t_done = now_seconds();
-    t->report.status = st;
-    t->report.seconds = t->t_done - t->t_submit;
-    t->report.queue_seconds = (t->t_admit > 0 ? t->t_admit : t->t_done) - t->t_submit;
-    t->report.iterations = t->total_iter;
-  };
-  for (;;) {
-    std::vector<std::shared_ptr<Ticket>> admit;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop || !queue.empty() || !resident.empty(); });
-      if (stop) break;
-      // cancellations
-      for (auto it = queue.begin(); it != queue.end();) {
-        if ((*it)->cancel) {
-          finish(*it, 4, MUSTER_E_CANCELLED, "cancelled");
-          it = queue.erase(it);
-        } else {
-          ++it;
-        }
+    plan->run(ctx, s);
+  }
+  void forget_groups_except(const std::vector<GroupKey>& live) override {
+    for (auto it = plans.begin(); it != plans.end();) {
+      if (std::find(live.begin(), live.end(), it->first) == live.end()) {
+        sigs.erase(it->first);
+        it = plans.erase(it);
+      } else {
+        ++it;
       }
-      for (auto it = resident.begin(); it != resident.end();) {
-        if ((*it)->cancel) {
-          finish(*it, 4, MUSTER_E_CANCELLED, "cancelled");
-          it = resident.erase(it);
-        } else {
-          ++it;
-        }
-      }
-      // admission by footprint, first come first served; jobs that cannot
-      // share launches with the residents (another window, metric or K) run
-      // in a group of their own in the same ticks
-      uint64_t pending = 0;
-      while (!queue.empty()) {
-        auto& t = queue.front();
-        const uint64_t fp = job_footprint(t->job.N, t->job.dims, t->job.params);
-        if (!ctx->arena.fits(pending + fp)) break;
-        pending += fp;
-        admit.push_back(t);
-        queue.pop_front();
-      }
-      done_cv.notify_all();
-    }
-    for (auto& t : admit) {
-      try {
-        t->rt = make_job(ctx, t->job);
-        job_begin_level(*t->rt, 0, s);
-        t->t_admit = now_seconds();
-        std::lock_guard<std::mutex> lk(mu);
-        t->state = 1;
-        resident.push_back(t);
-      } catch (const Error& e) {
-        std::lock_guard<std::mutex> lk(mu);
-        finish(t, 3, e.st, e.msg);
-        if (e.st == MUSTER_E_DEVICE) ctx->poisoned = true;
-        done_cv.notify_all();
-      }
-    }
-    std::vector<std::shared_ptr<Ticket>> res;
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      res = resident;
-    }
-    if (res.empty()) continue;
-    try {
-      // one iteration of every resident job whose current level has steps (a
-      // level of 0 steps is passed over below without touching the job)
-      std::map<GroupKey, std::vector<Job*>> groups;
-      std::map<GroupKey, std::vector<std::pair<uint64_t, int>>> nsigs;
-      for (auto& t : res) {
-        Job* J = t->rt.get();
-        if (t->job.params.iters[J->level] <= 0) continue;
-        const GroupKey k{J->p.window, J->p.metric, J->p.K};
-        groups[k].push_back(J);
-        nsigs[k].push_back({t->id, J->level});
-      }
-      for (auto it = plans.begin(); it != plans.end();)
-        it = groups.count(it->first) ? std::next(it) : plans.erase(it);
-      for (auto& g : groups) {
-        std::unique_ptr<Plan>& plan = plans[g.first];
-        if (!plan || sigs[g.first] != nsigs[g.first]) {
-          plan = build_plan(g.second, PLAN_ITERATION);
-          plan->upload(ctx, s);
-          sigs[g.first] = nsigs[g.first];
-        }
-        plan->run(ctx, s);
-      }
-      for (auto& t : res)
-        MUSTER_HIP(hipMemcpyAsync(t->rt->host_state, t->rt->js, sizeof(JobState),
-                                  hipMemcpyDeviceToHost, s));
-      MUSTER_HIP(hipStreamSynchronize(s));
-      std::vector<std::shared_ptr<Ticket>> done;
-      for (auto& t : res) {
-        Job& J = *t->rt;
-        const int T = t->job.params.iters[J.level];
-        if (T > 0) {
-          t->level_iter++;
-          t->total_iter++;
-        }
-        if (J.host_state->nonfinite) {
-          done.push_back(t);
-          continue;
-        }
-        if (t->level_iter >= T) {
-          if (J.level + 1 < J.p.levels) {
-            job_begin_level(J, J.level + 1, s);
-            t->level_iter = 0;
-          } else {
-            job_final_outputs(J, s);
-            fill_report(J, t->t_submit, &t->report, s);
-            done.push_back(t);
-          }
-        }
-      }
-      if (!done.empty()) {
-        std::lock_guard<std::mutex> lk(mu);
-        for (auto& t : done) {
-          const bool nf = t->rt && t->rt->host_state->nonfinite;
-          finish(t, nf ? 3 : 2, nf ? MUSTER_E_NONFINITE : MUSTER_OK,
-                 nf ? "the loss became non-finite" : "");
-          resident.erase(std::remove(resident.begin(), resident.end(), t), resident.end());
-        }
-        done_cv.notify_all();
-      }
-    } catch (const Error& e) {
-      std::lock_guard<std::mutex> lk(mu);
-      if (e.st == MUSTER_E_DEVICE) ctx->poisoned = true;
-      for (auto& t : resident) finish(t, 3, e.st, e.msg);
-      resident.clear();
-      plans.clear();
-      sigs.clear();
-      done_cv.notify_all();
     }
   }
-  // shut down: fail what is left
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    for (auto& t : queue) finish(t, 4, MUSTER_E_CANCELLED, "server stopped");
-    for (auto& t : resident) finish(t, 4, MUSTER_E_CANCELLED, "server stopped");
-    queue.clear();
-    resident.clear();
-    done_cv.notify_all();
+  void sync(const std::vector<JobHandle*>& resident) override {
+    Range range("muster server tick: %zu resident", resident.size());
+    for (JobHandle* h : resident) {
+      Job& J = job_of(*h);
+      MUSTER_HIP(hipMemcpyAsync(J.host_state, J.js, sizeof(JobState), hipMemcpyDeviceToHost, s));
+    }
+    MUSTER_HIP(hipStreamSynchronize(s));
   }
-  plans.clear();
-  (void)hipStreamSynchronize(s);
-  (void)hipStreamDestroy(s);
+  int level(JobHandle& h) override { return job_of(h).level; }
+  bool nonfinite(JobHandle& h) override { return job_of(h).host_state->nonfinite != 0; }
+  void begin_level(JobHandle& h, int level) override { job_begin_level(job_of(h), level, s); }
+  void finish(JobHandle& h, double t_submit, muster_report* rep) override {
+    job_final_outputs(job_of(h), s);
+    fill_report(job_of(h), t_submit, rep, s);
+  }
+  uint64_t held_bytes(JobHandle& h) override { return job_of(h).footprint; }
+  void on_device_error() override { ctx->poisoned = true; }
+};
+}  // namespace
+
+Server::Server(Ctx* c, int max_queue) : ctx(c) {
+  ex = std::make_unique<HipExecutor>(c);
+  sched = std::make_unique<Scheduler>(*ex, max_queue, now_seconds);
+}
+
+Server::~Server() {
+  sched->stop();
+  if (th.joinable()) th.join();
+}
+
+void Server::loop() {
+  auto* hx = static_cast<HipExecutor*>(ex.get());
+  if (hipSetDevice(ctx->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&hx->s, hipStreamNonBlocking) != hipSuccess) {
+    sched->stop();
+    sched->shutdown();
+    return;
+  }
+  while (sched->wait_for_work()) sched->tick();
+  sched->shutdown();
+  hx->plans.clear();
+  hx->sigs.clear();
+  (void)hipStreamSynchronize(hx->s);
+  (void)hipStreamDestroy(hx->s);
+  hx->s = nullptr;
 }
 
 
@@ -1974,15 +1935,7 @@ muster_status muster_ctx_create(int device, uint64_t hbm_budget, muster_ctx** ou
 muster_status muster_ctx_destroy(muster_ctx* h) {
   if (!h) return MUSTER_OK;
   Ctx* c = h->c;
-  if (c->server) {
-    {
-      std::lock_guard<std::mutex> lk(c->server->mu);
-      c->server->stop = true;
-    }
-    c->server->cv.notify_all();
-    if (c->server->th.joinable()) c->server->th.join();
-    c->server.reset();
-  }
+  if (c->server) c->server.reset();  // stops the serving thread and fails what is left
   (void)hipSetDevice(c->device);
   if (c->ws) {
     (void)hipStreamSynchronize(c->ws);
@@ -2095,21 +2048,7 @@ muster_status muster_submit(muster_ctx* h, const muster_job* job, uint64_t* tick
     NEED(ctx->server, "server not started");
     validate_problem(job->N, job->dims, job->params, job->times_host);
     NEED(job->images_dev && job->svf_out_dev, "images and svf_out must not be NULL");
-    const uint64_t fp = job_footprint(job->N, job->dims, job->params);
-    if (ctx->arena.budget() != 0 && fp > ctx->arena.budget())
-      fail(MUSTER_E_NOMEM, "job footprint %llu exceeds the context budget %llu",
-           (unsigned long long)fp, (unsigned long long)ctx->arena.budget());
-    Server& sv = *ctx->server;
-    std::lock_guard<std::mutex> lk(sv.mu);
-    if ((int)sv.queue.size() >= sv.max_queue) fail(MUSTER_E_BUSY, "serving queue is full");
-    auto t = std::make_shared<Ticket>();
-    t->id = sv.next_id++;
-    t->job = *job;
-    t->t_submit = now_seconds();
-    sv.queue.push_back(t);
-    sv.all[t->id] = t;
-    *ticket = t->id;
-    sv.cv.notify_all();
+    *ticket = ctx->server->sched->submit(*job);
   });
 }
 
@@ -2117,49 +2056,29 @@ muster_status muster_poll(muster_ctx* h, uint64_t ticket, int* state) {
   Ctx* ctx = C(h);
   return guard(nullptr, [&] {
     NEED(ctx && ctx->server && state, "bad arguments");
-    Server& sv = *ctx->server;
-    std::lock_guard<std::mutex> lk(sv.mu);
-    auto it = sv.all.find(ticket);
-    NEED(it != sv.all.end(), "unknown ticket %llu", (unsigned long long)ticket);
-    *state = it->second->state;
+    *state = ctx->server->sched->poll(ticket);
   });
 }
 
 muster_status muster_wait(muster_ctx* h, uint64_t ticket, muster_report* report) {
   Ctx* ctx = C(h);
   muster_status st = MUSTER_OK;
+  std::string err;
   const muster_status g = guard(nullptr, [&] {
     NEED(ctx && ctx->server, "server not started");
-    Server& sv = *ctx->server;
-    std::unique_lock<std::mutex> lk(sv.mu);
-    auto it = sv.all.find(ticket);
-    NEED(it != sv.all.end(), "unknown ticket %llu", (unsigned long long)ticket);
-    auto t = it->second;
-    sv.done_cv.wait(lk, [&] { return t->state >= 2 || sv.stop; });
-    if (t->state < 2) fail(MUSTER_E_CANCELLED, "server stopped");
-    if (report) *report = t->report;
-    st = t->status;
-    if (st != MUSTER_OK) set_error("%s", t->err.c_str());
-    sv.all.erase(it);
+    st = ctx->server->sched->wait(ticket, report, &err);
   });
   if (g != MUSTER_OK) return g;
-  if (st != MUSTER_OK) {
-    // keep the job's error text for the caller
-    return st;
-  }
-  return MUSTER_OK;
+  // keep the job's error text for the caller
+  if (st != MUSTER_OK) set_error("%s", err.c_str());
+  return st;
 }
 
 muster_status muster_cancel(muster_ctx* h, uint64_t ticket) {
   Ctx* ctx = C(h);
   return guard(nullptr, [&] {
     NEED(ctx && ctx->server, "server not started");
-    Server& sv = *ctx->server;
-    std::lock_guard<std::mutex> lk(sv.mu);
-    auto it = sv.all.find(ticket);
-    NEED(it != sv.all.end(), "unknown ticket %llu", (unsigned long long)ticket);
-    it->second->cancel = true;
-    sv.cv.notify_all();
+    ctx->server->sched->cancel(ticket);
   });
 }
 
@@ -2167,10 +2086,7 @@ muster_status muster_server_stats(muster_ctx* h, int* resident, int* queued, uin
   Ctx* ctx = C(h);
   return guard(nullptr, [&] {
     NEED(ctx && ctx->server, "server not started");
-    Server& sv = *ctx->server;
-    std::lock_guard<std::mutex> lk(sv.mu);
-    if (resident) *resident = (int)sv.resident.size();
-    if (queued) *queued = (int)sv.queue.size();
+    ctx->server->sched->stats(resident, queued);
     if (bytes) *bytes = ctx->arena.used();
   });
 }

@@ -18,16 +18,14 @@
 
 #include "../../include/muster.h"
 #include "muster_internal.h"
+#include "scheduler.h"
 
 namespace muster {
 
 void set_error(const char* fmt, ...);
 
-// Thrown inside the library only; converted to a status at the ABI.
-struct Error {
-  muster_status st;
-  std::string msg;
-};
+// Thrown inside the library only (Error, scheduler.h); converted to a status
+// at the ABI.
 [[noreturn]] void fail(muster_status st, const char* fmt, ...);
 
 #define MUSTER_HIP(expr)                                                              \
@@ -168,6 +166,7 @@ struct Job {
   JobState* js = nullptr;
   double* hist = nullptr;
   int hist_len = 0;
+  double step_seconds = 0.0;         // wall time of the iterations run so far (see muster_report)
   std::vector<float*> level_images;  // per level: [N][V_l]
   JobState* host_state = nullptr;    // pinned
   uint64_t footprint = 0;
@@ -263,33 +262,16 @@ struct Plan {
 enum PlanScope { PLAN_ITERATION, PLAN_FORWARD, PLAN_LOSS_FWD, PLAN_LOSS_BWD };
 std::unique_ptr<Plan> build_plan(const std::vector<Job*>& jobs, PlanScope scope);
 
-// Serving: continuous batching over the context's work stream.
-struct Ticket {
-  uint64_t id;
-  muster_job job;
-  std::unique_ptr<Job> rt;
-  int state = 0;                      // 0 queued, 1 running, 2 done, 3 failed, 4 cancelled
-  muster_status status = MUSTER_OK;
-  std::string err;
-  double t_submit = 0, t_admit = 0, t_done = 0;
-  int level_iter = 0;                 // steps done at the current level
-  int total_iter = 0;
-  bool cancel = false;
-  muster_report report{};
-};
-
+// Serving: continuous batching over the context's work stream.  The
+// scheduling (queue, admission, ticks, retirement) is the Scheduler's; the
+// server owns its thread and the executor that runs the jobs with HIP.
 struct Server {
   Ctx* ctx;
-  int max_queue;
+  std::unique_ptr<Executor> ex;
+  std::unique_ptr<Scheduler> sched;
   std::thread th;
-  std::mutex mu;
-  std::condition_variable cv, done_cv;
-  bool stop = false;
-  uint64_t next_id = 1;
-  std::deque<std::shared_ptr<Ticket>> queue;
-  std::vector<std::shared_ptr<Ticket>> resident;
-  std::map<uint64_t, std::shared_ptr<Ticket>> all;
-  Server(Ctx* c, int mq) : ctx(c), max_queue(mq) {}
+  Server(Ctx* c, int max_queue);
+  ~Server();
   void loop();
 };
 

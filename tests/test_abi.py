@@ -90,7 +90,8 @@ def test_footprint_counts_fields(lib):
     assert st == L.OK
     F = 3 * 32 ** 3 * 4
     # phi, m, v (2 each) + 4 dirs x 7 steps + 2 deep + 6 pair grads + 8 ping-pong + 6 coef
-    fields = 3 * 2 + 4 * 7 + 2 + 6 + 8 + 6
+    # + 2 combined SVF gradients of the staged Exp adjoint
+    fields = 3 * 2 + 4 * 7 + 2 + 6 + 8 + 6 + 2
     # Exp-backward staging: 2 steps x 4 directions x 32 tiles of 8x8x16, each a
     # slot of 3 x 2560 floats and an 8-int descriptor
     staging = 2 * 4 * 32 * (3 * 2560 * 4 + 8 * 4)
@@ -100,7 +101,8 @@ def test_footprint_counts_fields(lib):
     st3, b3 = _fp(lib, 10, (160, 192, 160))
     assert st3 == L.OK and 20e9 < b3 < 40e9
     st4, b4 = _fp(lib, 3, (32, 32, 32), smooth_sigma=1.5)
-    assert st4 == L.OK and b4 == b + 3 * 2 * F
+    # smoothing: the smoothed flow and a second gradient buffer (t1 is there already)
+    assert st4 == L.OK and b4 == b + 2 * 2 * F
 
 
 @pytest.mark.parametrize("N,dims,kw", [
