@@ -848,7 +848,6 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
   // and the padding above it never compares below a position.
   __shared__ __align__(16) int nbd[27][12];
   __shared__ int pre[32];
-  __shared__ float nbm[27];
   __shared__ float nbmax;
   int* gacc = acc;  // [3][PT_VOX]
   const int ntz = (D + PT_Z - 1) / PT_Z, nty = (H + PT_Y - 1) / PT_Y, ntx = (W + PT_X - 1) / PT_X;
@@ -870,13 +869,14 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
       }
     }
   }
-  if (threadIdx.x < 27) {
+  if (threadIdx.x < 32) {
+    // one lane per neighbour (lanes 27..31 and absent neighbours count 0)
     const int d = threadIdx.x;
     const int nz = tz + d / 9 - 1, ny = ty + (d / 3) % 3 - 1, nx = tx + d % 3 - 1;
     int n = 0;
     float bm = 0.f;
-    int* e = nbd[d];
-    if (d != 13 && nz >= 0 && nz < ntz && ny >= 0 && ny < nty && nx >= 0 && nx < ntx) {
+    int* e = nbd[d < 27 ? d : 26];
+    if (d < 27 && d != 13 && nz >= 0 && nz < ntz && ny >= 0 && ny < nty && nx >= 0 && nx < ntx) {
       const int nb = (nz * nty + ny) * ntx + nx;
       const int* dsc = desc_in + nb * 8;
       const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
@@ -901,23 +901,23 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
         e[8] = __float_as_int(1.f / (float)(x1 - x0));
       }
     }
-    e[11] = n;
-    nbm[d] = bm;
+    if (d < 27) e[11] = n;
+    // exclusive prefix of the counts and sum of the largest magnitudes over
+    // the 32 lanes by shuffles (the same order in every block)
+    int incl = n;
+    float msum = bm;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const int t = __shfl_up(incl, o, 32);
+      if (d >= o) incl += t;
+      msum += __shfl_xor(msum, o, 32);
+    }
+    if (d < 27) pre[d] = incl - n;
+    if (d == 26) pre[27] = incl;
+    if (d >= 28) pre[d] = INT_MAX;
+    if (d == 0) nbmax = msum;
   }
   for (int i = threadIdx.x; i < 3 * PT_VOX; i += BLOCK) gacc[i] = 0;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int t = 0;
-    float m = 0.f;
-    for (int d = 0; d < 27; ++d) {
-      pre[d] = t;
-      t += nbd[d][11];
-      m += nbm[d];
-    }
-    pre[27] = t;
-    pre[28] = pre[29] = pre[30] = pre[31] = INT_MAX;
-    nbmax = m;
-  }
   __syncthreads();
   const int total = pre[27];
   const float qscale = nbmax > 0.f ? 1073741824.0f / nbmax : 0.f;  // 2^30 / sum of maxima
