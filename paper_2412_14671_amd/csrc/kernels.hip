@@ -660,6 +660,48 @@ __device__ __forceinline__ ScatterBox scatter_bound(const ScatterVox (&sv)[PT_VO
   return scatter_box<NT>(lo, hi, mx, sm, sred);
 }
 
+// Largest magnitude and summed magnitudes of a block's scatter whose
+// bounding box is already known; the same per-thread order and reductions as
+// scatter_bound, so the scale is the same (every thread must call it).
+template <bool OWN, int NT>
+__device__ __forceinline__ ScatterBox scatter_mag(const ScatterVox (&sv)[PT_VOX / NT], int* sred,
+                                                  const BBox& bb) {
+  constexpr int VP = PT_VOX / NT;
+  float mx = 0.f, sm = 0.f;
+#pragma unroll
+  for (int j = 0; j < VP; ++j) {
+    if (sv[j].cz < 0) continue;
+    const float gm = fmaxf(fabsf(sv[j].g[0]), fmaxf(fabsf(sv[j].g[1]), fabsf(sv[j].g[2])));
+    mx = fmaxf(mx, gm);
+    sm += gm;
+    if (OWN) {
+      const float om = fmaxf(fabsf(sv[j].own[0]), fmaxf(fabsf(sv[j].own[1]), fabsf(sv[j].own[2])));
+      mx = fmaxf(mx, om);
+      sm += om;
+    }
+  }
+  const int mxb = dpp_max(__float_as_int(mx));
+  const float smw = dpp_sum(sm);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sred[w * 8 + 6] = mxb;
+    sred[w * 8 + 7] = __float_as_int(smw);
+  }
+  __syncthreads();
+  int mb = 0;
+  float sb_sum = 0.f;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    mb = max(mb, sred[i * 8 + 6]);
+    sb_sum += __int_as_float(sred[i * 8 + 7]);
+  }
+  ScatterBox sb;
+  sb.bb = bb;
+  sb.bmax = __int_as_float(mb);
+  sb.bsum = sb_sum;
+  return sb;
+}
+
 // Whether a block's box goes to its staging slot: it fits the slot and
 // reaches no farther than the 26 neighbouring tiles (where the reading step
 // looks for it).
@@ -688,10 +730,12 @@ template <bool OWN, bool STAGE = false, int NT = BLOCK>
 __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT], gfloat* __restrict__ out,
                                              int D, int H, int W, int* acc, int* sred,
                                              const StageOut& so = StageOut{},
-                                             const DetOut& det = DetOut{}) {
+                                             const DetOut& det = DetOut{},
+                                             const BBox* known = nullptr) {
   constexpr int VP = PT_VOX / NT;
   const int HW = H * W, V = D * HW;
-  const ScatterBox sb = scatter_bound<OWN, NT>(sv, sred);
+  const ScatterBox sb =
+      known ? scatter_mag<OWN, NT>(sv, sred, *known) : scatter_bound<OWN, NT>(sv, sred);
   const BBox& bb = sb.bb;
   const float bmax = sb.bmax;
   // the bins take finite values only; bsum bounds every bin's magnitude
@@ -832,76 +876,90 @@ __device__ __forceinline__ void scatter_tile(const ScatterVox (&sv)[PT_VOX / NT]
 // into LDS bins (neighbouring boxes overlap) in 32-bit fixed point, scaled so
 // that the sum of the boxes' largest cell magnitudes maps to 2^30: no bin can
 // overflow.  Then the flat overflow gin, if any block of that step used it
-// (*flag_in); gin is cleared where read.  gv must hold zeros on entry.  acc:
-// LDS of at least 3 * PT_VOX ints.  Every thread of the block must call this.
-__device__ __forceinline__ void pull_staged(const float* stage_in, const int* desc_in,
-                                            const int* flag_in, gfloat* __restrict__ gin, int local,
-                                            const PTile& tc, int D, int H, int W,
-                                            const int (&vz)[VPT], const int (&vy)[VPT],
-                                            const int (&vx)[VPT], const bool (&vok)[VPT],
-                                            float (&gv)[VPT][3], int* acc, bool clear = true) {
-  const int V = D * H * W;
-  // per neighbour d: nyx, nx, (unused), the box's z and y strides, the
-  // tile-local index of the overlap's first cell, the staging element of
-  // that cell (64 bits: [6] low, [10] high), 1 / nyx and 1 / nx (float
-  // bits); [11] = cells.  pre[d]: first list position of d; pre[27] = total,
-  // and the padding above it never compares below a position.
-  __shared__ __align__(16) int nbd[27][12];
-  __shared__ int pre[32];
-  __shared__ float nbmax;
-  int* gacc = acc;  // [3][PT_VOX]
-  const int ntz = (D + PT_Z - 1) / PT_Z, nty = (H + PT_Y - 1) / PT_Y, ntx = (W + PT_X - 1) / PT_X;
-  const int tz = tc.z0 / PT_Z, ty = tc.y0 / PT_Y, tx = tc.x0 / PT_X;
-  const cgfloat* __restrict__ st = gp(stage_in);
-  // own box, straight into registers
+// (*flag_in); gin is cleared where read.
+//
+// Three parts, so that a kernel can put its own loads between them: the
+// descriptor loads (pull_desc), the neighbour list (pull_setup, which ends
+// with a barrier) and the reads and sums (pull_finish).  pull_staged runs
+// the three in a row.
+
+// Per neighbour d: nyx, nx, the box's z and y strides, the tile-local index
+// of the overlap's first cell, 1 / nyx and 1 / nx (float bits), [7] = cells,
+// and [8..9] the address of that cell's first component.  pre[d]: first list
+// position of d; pre[27] = total, and the padding above it never compares
+// below a position.
+struct PullList {
+  int nbd[27][12];
+  int pre[32];
+  float nbmax;
+};
+
+// The descriptors a thread needs: the tile's own box (every thread) and, in
+// lane d < 27 of the first wave, neighbour d's box (n[3] = 0: none).
+struct PullDesc {
+  int own[6];
+  int n[7];
+  int nb;
+};
+
+__device__ __forceinline__ PullDesc pull_desc(const int* desc_in, int local, const PTile& tc, int D,
+                                              int H, int W) {
+  PullDesc pd;
   {
     const int* dsc = desc_in + local * 8;
-    const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
-    if (ez > 0) {
-      const cgfloat* __restrict__ sl = st + (size_t)local * 3 * STAGE_CAP;
 #pragma unroll
-      for (int j = 0; j < VPT; ++j) {
-        if (!vok[j]) continue;
-        const int idx = ((vz[j] - bz) * ey + (vy[j] - by)) * ex + (vx[j] - bx);
-        gv[j][0] = ldo(sl, idx);
-        gv[j][1] = ldo(sl + STAGE_CAP, idx);
-        gv[j][2] = ldo(sl + 2 * STAGE_CAP, idx);
-      }
+    for (int k = 0; k < 6; ++k) pd.own[k] = dsc[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) pd.n[k] = 0;
+  pd.nb = 0;
+  if (threadIdx.x < 32) {
+    const int ntz = (D + PT_Z - 1) / PT_Z, nty = (H + PT_Y - 1) / PT_Y, ntx = (W + PT_X - 1) / PT_X;
+    const int tz = tc.z0 / PT_Z, ty = tc.y0 / PT_Y, tx = tc.x0 / PT_X;
+    const int d = threadIdx.x;
+    const int nz = tz + d / 9 - 1, ny = ty + (d / 3) % 3 - 1, nx = tx + d % 3 - 1;
+    if (d < 27 && d != 13 && nz >= 0 && nz < ntz && ny >= 0 && ny < nty && nx >= 0 && nx < ntx) {
+      pd.nb = (nz * nty + ny) * ntx + nx;
+      const int* dsc = desc_in + pd.nb * 8;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) pd.n[k] = dsc[k];
     }
   }
+  return pd;
+}
+
+// The neighbour list and the cleared bins; acc: LDS of at least 3 * PT_VOX
+// ints.  Every thread of the block must call this.
+__device__ __forceinline__ void pull_setup(const PullDesc& pd, const float* stage_in,
+                                           const PTile& tc, int D, int H, int W, int* acc,
+                                           PullList& pl) {
   if (threadIdx.x < 32) {
     // one lane per neighbour (lanes 27..31 and absent neighbours count 0)
     const int d = threadIdx.x;
-    const int nz = tz + d / 9 - 1, ny = ty + (d / 3) % 3 - 1, nx = tx + d % 3 - 1;
     int n = 0;
     float bm = 0.f;
-    int* e = nbd[d < 27 ? d : 26];
-    if (d < 27 && d != 13 && nz >= 0 && nz < ntz && ny >= 0 && ny < nty && nx >= 0 && nx < ntx) {
-      const int nb = (nz * nty + ny) * ntx + nx;
-      const int* dsc = desc_in + nb * 8;
-      const int bz = dsc[0], by = dsc[1], bx = dsc[2], ez = dsc[3], ey = dsc[4], ex = dsc[5];
-      // intersection with this tile, in global coordinates
-      const int z0 = max(bz, tc.z0), z1 = min(bz + ez, min(tc.z0 + PT_Z, D));
-      const int y0 = max(by, tc.y0), y1 = min(by + ey, min(tc.y0 + PT_Y, H));
-      const int x0 = max(bx, tc.x0), x1 = min(bx + ex, min(tc.x0 + PT_X, W));
-      if (ez > 0 && z1 > z0 && y1 > y0 && x1 > x0) {
-        const int nyx = (y1 - y0) * (x1 - x0);
-        n = (z1 - z0) * nyx;
-        bm = __int_as_float(dsc[6]);
-        const long long first = (long long)nb * 3 * STAGE_CAP +
-                                ((z0 - bz) * ey + (y0 - by)) * ex + (x0 - bx);
-        e[0] = nyx;
-        e[1] = x1 - x0;
-        e[3] = ey * ex;
-        e[4] = ex;
-        e[5] = ((z0 - tc.z0) * PT_Y + (y0 - tc.y0)) * PT_X + (x0 - tc.x0);
-        e[6] = (int)(unsigned)(first & 0xffffffffLL);
-        e[10] = (int)(first >> 32);
-        e[7] = __float_as_int(1.f / (float)nyx);
-        e[8] = __float_as_int(1.f / (float)(x1 - x0));
-      }
+    int* e = pl.nbd[d < 27 ? d : 26];
+    const int bz = pd.n[0], by = pd.n[1], bx = pd.n[2], ez = pd.n[3], ey = pd.n[4], ex = pd.n[5];
+    // intersection with this tile, in global coordinates
+    const int z0 = max(bz, tc.z0), z1 = min(bz + ez, min(tc.z0 + PT_Z, D));
+    const int y0 = max(by, tc.y0), y1 = min(by + ey, min(tc.y0 + PT_Y, H));
+    const int x0 = max(bx, tc.x0), x1 = min(bx + ex, min(tc.x0 + PT_X, W));
+    if (ez > 0 && z1 > z0 && y1 > y0 && x1 > x0) {
+      const int nyx = (y1 - y0) * (x1 - x0);
+      n = (z1 - z0) * nyx;
+      bm = __int_as_float(pd.n[6]);
+      const cgfloat* first = gp(stage_in) + (size_t)pd.nb * 3 * STAGE_CAP +
+                             (((z0 - bz) * ey + (y0 - by)) * ex + (x0 - bx));
+      e[0] = nyx;
+      e[1] = x1 - x0;
+      e[2] = ey * ex;
+      e[3] = ex;
+      e[4] = ((z0 - tc.z0) * PT_Y + (y0 - tc.y0)) * PT_X + (x0 - tc.x0);
+      e[5] = __float_as_int(1.f / (float)nyx);
+      e[6] = __float_as_int(1.f / (float)(x1 - x0));
+      *reinterpret_cast<const cgfloat**>(e + 8) = first;
     }
-    if (d < 27) e[11] = n;
+    if (d < 27) e[7] = n;
     // exclusive prefix of the counts and sum of the largest magnitudes over
     // the 32 lanes by shuffles (the same order in every block)
     int incl = n;
@@ -912,48 +970,85 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
       if (d >= o) incl += t;
       msum += __shfl_xor(msum, o, 32);
     }
-    if (d < 27) pre[d] = incl - n;
-    if (d == 26) pre[27] = incl;
-    if (d >= 28) pre[d] = INT_MAX;
-    if (d == 0) nbmax = msum;
+    if (d < 27) pl.pre[d] = incl - n;
+    if (d == 26) pl.pre[27] = incl;
+    if (d >= 28) pl.pre[d] = INT_MAX;
+    if (d == 0) pl.nbmax = msum;
   }
-  for (int i = threadIdx.x; i < 3 * PT_VOX; i += BLOCK) gacc[i] = 0;
+  {
+    int4* g4 = reinterpret_cast<int4*>(acc);
+    for (int i = threadIdx.x; i < 3 * PT_VOX / 4; i += BLOCK) g4[i] = make_int4(0, 0, 0, 0);
+  }
   __syncthreads();
+}
+
+// G at the owned voxels: the own box, the neighbour list summed in the
+// bins, and the flat overflow.  gv must hold zeros on entry.  Every thread
+// of the block must call this.
+__device__ __forceinline__ void pull_finish(const PullDesc& pd, const float* stage_in,
+                                            const int* flag_in, gfloat* __restrict__ gin, int local,
+                                            int D, int H, int W, const int (&vz)[VPT],
+                                            const int (&vy)[VPT], const int (&vx)[VPT],
+                                            const bool (&vok)[VPT], float (&gv)[VPT][3], int* acc,
+                                            const PullList& pl, bool clear) {
+  const int V = D * H * W;
+  int* gacc = acc;  // [3][PT_VOX]
+  const int* pre = pl.pre;
+  // own box, straight into registers
+  {
+    const int bz = pd.own[0], by = pd.own[1], bx = pd.own[2], ez = pd.own[3], ey = pd.own[4],
+              ex = pd.own[5];
+    if (ez > 0) {
+      const cgfloat* __restrict__ sl = gp(stage_in) + (size_t)local * 3 * STAGE_CAP;
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        if (!vok[j]) continue;
+        const int idx = ((vz[j] - bz) * ey + (vy[j] - by)) * ex + (vx[j] - bx);
+        gv[j][0] = ldo(sl, idx);
+        gv[j][1] = ldo(sl + STAGE_CAP, idx);
+        gv[j][2] = ldo(sl + 2 * STAGE_CAP, idx);
+      }
+    }
+  }
   const int total = pre[27];
+  const float nbmax = pl.nbmax;
   const float qscale = nbmax > 0.f ? 1073741824.0f / nbmax : 0.f;  // 2^30 / sum of maxima
   const float qinv = nbmax / 1073741824.0f;
   constexpr int U = 4;
   for (int w0 = threadIdx.x; w0 < total; w0 += BLOCK * U) {
+    // positions past the end repeat the last cell (a valid load) and add
+    // nothing; with no branch per position the U searches run side by side
+    int w[U], d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      w[u] = min(w0 + u * BLOCK, total - 1);
+      d[u] = 0;
+    }
+    // the last d with pre[d] <= w: the non-empty entry holding w (the search
+    // stays below 32, and pre above 27 is never <= w)
+#pragma unroll
+    for (int step = 16; step > 0; step >>= 1)
+#pragma unroll
+      for (int u = 0; u < U; ++u) d[u] = pre[d[u] + step] <= w[u] ? d[u] + step : d[u];
     float v0[U], v1[U], v2[U];
     int loc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int w = w0 + u * BLOCK;
-      loc[u] = -1;
-      if (w < total) {
-        // the last d with pre[d] <= w: the non-empty entry holding w (the
-        // search stays below 31, and pre above 27 is never <= w)
-        int d = 0;
-#pragma unroll
-        for (int step = 16; step > 0; step >>= 1)
-          d = pre[d + step] <= w ? d + step : d;
-        const int* e = nbd[d];
-        const int r = w - pre[d];
-        // (iz, iy, ix) of cell r of the overlap; the float quotients are
-        // exact here (r < 1024, the overlap lies in one tile)
-        const int nyx = e[0], nx = e[1];
-        const int iz = (int)(((float)r + 0.5f) * __int_as_float(e[7]));
-        const int rr = r - iz * nyx;
-        const int iy = (int)(((float)rr + 0.5f) * __int_as_float(e[8]));
-        const int ix = rr - iy * nx;
-        const long long first =
-            ((long long)e[10] << 32) | (long long)(unsigned)e[6];
-        const cgfloat* __restrict__ sl = st + first + (iz * e[3] + iy * e[4] + ix);
-        v0[u] = sl[0];
-        v1[u] = sl[STAGE_CAP];
-        v2[u] = sl[2 * STAGE_CAP];
-        loc[u] = e[5] + (iz * PT_Y + iy) * PT_X + ix;
-      }
+      const int* e = pl.nbd[d[u]];
+      const int r = w[u] - pre[d[u]];
+      // (iz, iy, ix) of cell r of the overlap; the float quotients are
+      // exact here (r < 1024, the overlap lies in one tile)
+      const int nyx = e[0], nx = e[1];
+      const int iz = (int)(((float)r + 0.5f) * __int_as_float(e[5]));
+      const int rr = r - iz * nyx;
+      const int iy = (int)(((float)rr + 0.5f) * __int_as_float(e[6]));
+      const int ix = rr - iy * nx;
+      const cgfloat* __restrict__ sl =
+          *reinterpret_cast<const cgfloat* const*>(e + 8) + (uint32_t)(iz * e[2] + iy * e[3] + ix);
+      v0[u] = sl[0];
+      v1[u] = sl[STAGE_CAP];
+      v2[u] = sl[2 * STAGE_CAP];
+      loc[u] = w0 + u * BLOCK < total ? e[4] + (iz * PT_Y + iy) * PT_X + ix : -1;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -986,6 +1081,19 @@ __device__ __forceinline__ void pull_staged(const float* stage_in, const int* de
   }
 }
 
+// The three parts in a row; acc: LDS of at least 3 * PT_VOX ints.
+__device__ __forceinline__ void pull_staged(const float* stage_in, const int* desc_in,
+                                            const int* flag_in, gfloat* __restrict__ gin, int local,
+                                            const PTile& tc, int D, int H, int W,
+                                            const int (&vz)[VPT], const int (&vy)[VPT],
+                                            const int (&vx)[VPT], const bool (&vok)[VPT],
+                                            float (&gv)[VPT][3], int* acc, bool clear = true) {
+  __shared__ PullList pl;
+  const PullDesc pd = pull_desc(desc_in, local, tc, D, H, W);
+  pull_setup(pd, stage_in, tc, D, H, W, acc, pl);
+  pull_finish(pd, stage_in, flag_in, gin, local, D, H, W, vz, vy, vx, vok, gv, acc, pl, clear);
+}
+
 // ---------------------------------------------------------------------------
 // Exp backward: one squaring, dL/du_s from dL/du_{s+1}
 //   G_s(p) = G(p) + J_u(q)^T G(p) + sum_{p': corners of q(p') contain p} w G(p')
@@ -998,8 +1106,9 @@ template <int MODE, bool REG, bool DETMAX = false>
 __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict__ items,
                                                    int n_items, int n_tiles) {
   constexpr bool IN_ST = MODE >= 2, OUT_ST = MODE == 1 || MODE == 2;
+  static_assert(GATHER_CELLS <= SCATTER_CELLS, "the gather box shares the bins' LDS");
   __shared__ __align__(16) int acc[3 * SCATTER_CELLS];
-  __shared__ int sred[8 * (BLOCK / 64)];
+  __shared__ int sred[16 * (BLOCK / 64)];
   __shared__ double red[BLOCK / 64];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ExpBwdItem it = items[find_item(items, n_items, tile)];
@@ -1026,8 +1135,12 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     vok[j] = vx[j] < W && vy[j] < H && vz[j] < D;
     gv[j][0] = gv[j][1] = gv[j][2] = 0.f;
   }
-  // u_s at the owned voxels, loaded before G_{s+1} is gathered so that the
-  // loads are in flight while the pull waits on its own
+  // G_{s+1} over this tile from the staged boxes of the previous step: the
+  // box descriptors are read first and u_s at the owned voxels next, so that
+  // those loads are in flight while the neighbour list is formed
+  __shared__ PullList pl;
+  PullDesc pd;
+  if (IN_ST) pd = pull_desc(it.desc_in, local, tc, D, H, W);
   float uo[VPT][3];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
@@ -1037,9 +1150,9 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     uo[j][2] = a * ldo(s + 2 * V, p);
   }
   if (IN_ST) {
-    // G_{s+1} over this tile from the staged boxes of the previous step
-    pull_staged(it.stage_in, it.desc_in, it.flag_in, gin, local, tc, D, H, W, vz, vy, vx, vok, gv,
-                acc, !DETMAX);
+    pull_setup(pd, it.stage_in, tc, D, H, W, acc, pl);
+    pull_finish(pd, it.stage_in, it.flag_in, gin, local, D, H, W, vz, vy, vx, vok, gv, acc, pl,
+                !DETMAX);
   } else {
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
@@ -1064,6 +1177,52 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     reg_tile_load(s, V, tc.z0, tc.y0, tc.x0, D, H, W, rt);
     __syncthreads();
   }
+  // the cells the owned voxels sample
+  Ax cz[VPT], cy[VPT], cx[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    cz[j] = axis_disp(vz[j], uo[j][0], D);
+    cy[j] = axis_disp(vy[j], uo[j][1], H);
+    cx[j] = axis_disp(vx[j], uo[j][2], W);
+  }
+  // Without the regulariser's tile (which holds acc until the scatter), the
+  // corners come from a box of src staged in acc: the bounding box of the
+  // cells and the owned voxels, which is also the scatter's box.  The values
+  // and the arithmetic are those of the direct loads, so the result is the
+  // same; a box larger than GATHER_CELLS reads the corners directly.
+  BBox gb{};
+  bool lds_box = false;
+  if (!REG) {
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
+    int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      if (!vok[j]) continue;
+      lo[0] = min(lo[0], min(cz[j].i0, vz[j])); hi[0] = max(hi[0], max(cz[j].i0 + 1, vz[j]));
+      lo[1] = min(lo[1], min(cy[j].i0, vy[j])); hi[1] = max(hi[1], max(cy[j].i0 + 1, vy[j]));
+      lo[2] = min(lo[2], min(cx[j].i0, vx[j])); hi[2] = max(hi[2], max(cx[j].i0 + 1, vx[j]));
+    }
+    // the second half of sred: the scatter's own reduction uses the first
+    gb = scatter_box<BLOCK>(lo, hi, 0.f, 0.f, sred + 8 * (BLOCK / 64)).bb;
+    lds_box = gb.cells > 0 && gb.cells <= GATHER_CELLS;  // block-uniform
+    if (lds_box) {
+      float* box = reinterpret_cast<float*>(acc);
+      const int cells = gb.cells;
+      // cell i -> (lz, ly, lx) by float reciprocals: exact here since i < 2^22
+      const float inv_ex = 1.f / (float)gb.ex, inv_ey = 1.f / (float)gb.ey;
+      for (int i = threadIdx.x; i < cells; i += BLOCK) {
+        const int r = (int)(((float)i + 0.5f) * inv_ex);
+        const int lx = i - r * gb.ex;
+        const int lz = (int)(((float)r + 0.5f) * inv_ey);
+        const int ly = r - lz * gb.ey;
+        const int g = ((gb.lz + lz) * H + (gb.ly + ly)) * W + (gb.lx + lx);
+        box[i] = ldo(s, g);
+        box[cells + i] = ldo(s + V, g);
+        box[2 * cells + i] = ldo(s + 2 * V, g);
+      }
+      __syncthreads();
+    }
+  }
   ScatterVox sv[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
@@ -1071,17 +1230,29 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     if (!vok[j]) continue;
     const int x = vx[j], y = vy[j], z = vz[j];
     const int p = (z * H + y) * W + x;
-    const Ax az = axis_disp(z, uo[j][0], D), ay = axis_disp(y, uo[j][1], H),
-             ax = axis_disp(x, uo[j][2], W);
-    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+    const Ax az = cz[j], ay = cy[j], ax = cx[j];
     const float g0 = gv[j][0], g1 = gv[j][1], g2 = gv[j][2];
     // (J^T g) of the Jacobian J of src at q is the gradient of the
     // interpolant of sum_c g_c src_c: combine the corners first, then one
     // gradient; the factor a and the clamped axes apply per column
     float v0[8], v1[8], v2[8], jz, jy, jx;
-    load8(s, base, W, HW, v0);
-    load8(s + V, base, W, HW, v1);
-    load8(s + 2 * V, base, W, HW, v2);
+    if (lds_box) {
+      const float* box = reinterpret_cast<const float*>(acc);
+      const int cells = gb.cells, sy = gb.ex, sz = gb.ex * gb.ey;
+      const int l = ((az.i0 - gb.lz) * gb.ey + (ay.i0 - gb.ly)) * gb.ex + (ax.i0 - gb.lx);
+      const int off[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        v0[k] = box[l + off[k]];
+        v1[k] = box[cells + l + off[k]];
+        v2[k] = box[2 * cells + l + off[k]];
+      }
+    } else {
+      const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+      load8(s, base, W, HW, v0);
+      load8(s + V, base, W, HW, v1);
+      load8(s + 2 * V, base, W, HW, v2);
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) v0[k] = fmaf(g2, v2[k], fmaf(g1, v1[k], g0 * v0[k]));
     tri_grad(v0, az.t, ay.t, ax.t, jz, jy, jx);
@@ -1145,10 +1316,13 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     det.out64 = it.gout64;
     det.scale = det_scale(it.js, it.det_slot, it.det_blocks);
   }
+  // with the box known, the scatter reduces only the magnitudes; the gathers
+  // from acc end before its barrier, after which the bins are cleared
+  const BBox* known = REG ? nullptr : &gb;
   if (OUT_ST)
-    scatter_tile<true, true>(sv, gp(it.gout), D, H, W, acc, sred, so, det);
+    scatter_tile<true, true>(sv, gp(it.gout), D, H, W, acc, sred, so, det, known);
   else
-    scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred, StageOut{}, det);
+    scatter_tile<true>(sv, gp(it.gout), D, H, W, acc, sred, StageOut{}, det, known);
   rval = (double)rvf;
   if (reg) {
     const double tot = block_sum(rval * (double)it.reg_loss_w + rext, red);
@@ -1269,8 +1443,9 @@ constexpr int CB_NT = 2 * BLOCK, CB_VP = PT_VOX / CB_NT;
 template <bool DETMAX>
 __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __restrict__ items,
                                                        int n_items, int n_tiles) {
+  static_assert(GATHER_CELLS <= SCATTER_CELLS, "the gather box shares the bins' LDS");
   __shared__ __align__(16) int acc[3 * SCATTER_CELLS];
-  __shared__ int sred[8 * (CB_NT / 64)];
+  __shared__ int sred[16 * (CB_NT / 64)];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const ComposeBwdItem it = items[find_item(items, n_items, tile)];
   const int D = it.D, H = it.H, W = it.W, HW = H * W, V = D * HW;
@@ -1279,22 +1454,93 @@ __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __r
   const cgfloat* __restrict__ pr = gp(it.prev);
   const cgfloat* __restrict__ G = gp(it.g);
   gfloat* __restrict__ gpv = gp(it.gprev);
+  // the owned voxels, the cells they sample and G there
+  int vp[CB_VP], vz[CB_VP], vy[CB_VP], vx[CB_VP];
+  bool vok[CB_VP];
+  Ax cz[CB_VP], cy[CB_VP], cx[CB_VP];
+  float gv[CB_VP][3];
+#pragma unroll
+  for (int j = 0; j < CB_VP; ++j) {
+    const int k = threadIdx.x + j * CB_NT;
+    vx[j] = tc.x0 + (k % PT_X);
+    vy[j] = tc.y0 + (k / PT_X) % PT_Y;
+    vz[j] = tc.z0 + k / (PT_X * PT_Y);
+    vok[j] = vx[j] < W && vy[j] < H && vz[j] < D;
+    vp[j] = vok[j] ? (vz[j] * H + vy[j]) * W + vx[j] : 0;
+    const float uz = ldo(pr, vp[j]), uy = ldo(pr + V, vp[j]), ux = ldo(pr + 2 * V, vp[j]);
+    cz[j] = axis_disp(vz[j], uz, D);
+    cy[j] = axis_disp(vy[j], uy, H);
+    cx[j] = axis_disp(vx[j], ux, W);
+    gv[j][0] = ldo(G, vp[j]);
+    gv[j][1] = ldo(G + V, vp[j]);
+    gv[j][2] = ldo(G + 2 * V, vp[j]);
+  }
+  // the corners come from a box of C staged in acc (the bounding box of the
+  // cells, which is also the scatter's box; the values are those of the
+  // direct loads), or directly when the box is larger than GATHER_CELLS; the
+  // reduce-only pass needs no corners
+  BBox gb{};
+  bool lds_box = false;
+  if (!DETMAX) {
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
+    int hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+    for (int j = 0; j < CB_VP; ++j) {
+      if (!vok[j]) continue;
+      lo[0] = min(lo[0], cz[j].i0); hi[0] = max(hi[0], cz[j].i0 + 1);
+      lo[1] = min(lo[1], cy[j].i0); hi[1] = max(hi[1], cy[j].i0 + 1);
+      lo[2] = min(lo[2], cx[j].i0); hi[2] = max(hi[2], cx[j].i0 + 1);
+    }
+    // the second half of sred: the scatter's own reduction uses the first
+    gb = scatter_box<CB_NT>(lo, hi, 0.f, 0.f, sred + 8 * (CB_NT / 64)).bb;
+    lds_box = gb.cells > 0 && gb.cells <= GATHER_CELLS;  // block-uniform
+    if (lds_box) {
+      float* box = reinterpret_cast<float*>(acc);
+      const int cells = gb.cells;
+      // cell i -> (lz, ly, lx) by float reciprocals: exact here since i < 2^22
+      const float inv_ex = 1.f / (float)gb.ex, inv_ey = 1.f / (float)gb.ey;
+      for (int i = threadIdx.x; i < cells; i += CB_NT) {
+        const int r = (int)(((float)i + 0.5f) * inv_ex);
+        const int lx = i - r * gb.ex;
+        const int lz = (int)(((float)r + 0.5f) * inv_ey);
+        const int ly = r - lz * gb.ey;
+        const int g = ((gb.lz + lz) * H + (gb.ly + ly)) * W + (gb.lx + lx);
+        box[i] = ldo(C, g);
+        box[cells + i] = ldo(C + V, g);
+        box[2 * cells + i] = ldo(C + 2 * V, g);
+      }
+      __syncthreads();
+    }
+  }
   ScatterVox sv[CB_VP];
 #pragma unroll
   for (int j = 0; j < CB_VP; ++j) {
     sv[j].cz = -1;
-    const int k = threadIdx.x + j * CB_NT;
-    const int x = tc.x0 + (k % PT_X), y = tc.y0 + (k / PT_X) % PT_Y, z = tc.z0 + k / (PT_X * PT_Y);
-    if (x >= W || y >= H || z >= D) continue;
-    const int p = (z * H + y) * W + x;
-    const float uz = ldo(pr, p), uy = ldo(pr + V, p), ux = ldo(pr + 2 * V, p);
-    const Ax az = axis_disp(z, uz, D), ay = axis_disp(y, uy, H), ax = axis_disp(x, ux, W);
-    const int base = (az.i0 * H + ay.i0) * W + ax.i0;
-    const float g0 = ldo(G, p), g1 = ldo(G + V, p), g2 = ldo(G + 2 * V, p);
+    if (!vok[j]) continue;
+    const int x = vx[j], y = vy[j], z = vz[j], p = vp[j];
+    const Ax az = cz[j], ay = cy[j], ax = cx[j];
+    const float g0 = gv[j][0], g1 = gv[j][1], g2 = gv[j][2];
     float v0[8], v1[8], v2[8], dz, dy, dx;
-    load8(C, base, W, HW, v0);
-    load8(C + V, base, W, HW, v1);
-    load8(C + 2 * V, base, W, HW, v2);
+    if (lds_box) {
+      const float* box = reinterpret_cast<const float*>(acc);
+      const int cells = gb.cells, sy = gb.ex, sz = gb.ex * gb.ey;
+      const int l = ((az.i0 - gb.lz) * gb.ey + (ay.i0 - gb.ly)) * gb.ex + (ax.i0 - gb.lx);
+      const int off[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        v0[k] = box[l + off[k]];
+        v1[k] = box[cells + l + off[k]];
+        v2[k] = box[2 * cells + l + off[k]];
+      }
+    } else if (!DETMAX) {
+      const int base = (az.i0 * H + ay.i0) * W + ax.i0;
+      load8(C, base, W, HW, v0);
+      load8(C + V, base, W, HW, v1);
+      load8(C + 2 * V, base, W, HW, v2);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v0[k] = v1[k] = v2[k] = 0.f;
+    }
     tri_grad(v0, az.t, ay.t, ax.t, dz, dy, dx);
     float jz = dz * g0, jy = dy * g0, jx = dx * g0;
     tri_grad(v1, az.t, ay.t, ax.t, dz, dy, dx);
@@ -1329,7 +1575,9 @@ __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __r
     det.out64 = it.gc64;
     det.scale = det_scale(it.js, it.det_slot, it.det_blocks);
   }
-  scatter_tile<false, false, CB_NT>(sv, gp(it.gc), D, H, W, acc, sred, StageOut{}, det);
+  // with the box known, the scatter reduces only the magnitudes; the gathers
+  // from acc end before its barrier, after which the bins are cleared
+  scatter_tile<false, false, CB_NT>(sv, gp(it.gc), D, H, W, acc, sred, StageOut{}, det, &gb);
 }
 
 // ---------------------------------------------------------------------------
