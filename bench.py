@@ -514,6 +514,7 @@ def bench_headline(args, ctx, dev, torch, synth, MusterParams):
         sparams = MusterParams(iters=[200, 100, 50], K=7, window=7, metric="silncc",
                                alpha_ss=1.0, lr=0.1)
         from paper_2412_14671_amd import Context
+        ctx.trim()  # the batched workspaces go back before the server's context takes its budget
         sctx = Context(0)
         srv = Server(sctx)
         arrivals, t = [], 0.0

@@ -210,9 +210,22 @@ muster_status muster_ctx_sim_tiling(muster_ctx* ctx, void* stream, const int dim
  * either pointer may be NULL.  reset_peak != 0 resets the mark to the bytes
  * in use, after reading it.  Counts workspaces only (the caller's buffers
  * are not the library's); used to compare the stored and recomputed
- * squaring steps of the Exp adjoint. */
+ * squaring steps of the Exp adjoint.  Workspaces that finished jobs release
+ * are not counted here: the arena keeps them for later requests of the
+ * same size (see muster_ctx_trim). */
 muster_status muster_ctx_memory(muster_ctx* ctx, uint64_t* in_use, uint64_t* peak,
                                 int reset_peak);
+/* Return to the device the workspaces the context keeps for reuse.  The
+ * arena keeps what finished jobs release, by size, so that repeated
+ * registrations of similar jobs allocate nothing (a device allocation of
+ * tens of GB takes seconds); the kept bytes count against hbm_budget, and
+ * an allocation that fails first takes back what every context of the
+ * process keeps, then tries once more.  Call this to give the memory to
+ * other users of the device.  *released (may be NULL): bytes returned.
+ * Workspaces released while work that uses them may still be in flight are
+ * handed out again only after a device synchronisation, and returned with
+ * the device free, which waits for that work. */
+muster_status muster_ctx_trim(muster_ctx* ctx, uint64_t* released);
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* muster_last_error(void);
 /* Library version string. */

@@ -109,6 +109,7 @@ SIGNATURES = {
     "muster_smooth": (_ST, [_P, _P, DIMS, c_float, _P, _P]),
     "muster_ctx_set_tiling": (_ST, [_P, c_int, c_int, c_int]),
     "muster_ctx_memory": (_ST, [_P, POINTER(c_uint64), POINTER(c_uint64), c_int]),
+    "muster_ctx_trim": (_ST, [_P, POINTER(c_uint64)]),
     "muster_ctx_sim_tiling": (_ST, [_P, _P, DIMS, c_int, c_int, POINTER(c_int), POINTER(c_int)]),
     "muster_set_kernel_timing": (_ST, [_P, c_int]),
     "muster_set_kernel_timing_mask": (_ST, [_P, c_uint32]),

@@ -327,6 +327,13 @@ class Context:
         L.check(self.lib.muster_ctx_memory(self.h, byref(u), byref(pk), 1 if reset_peak else 0))
         return {"in_use": u.value, "peak": pk.value}
 
+    def trim(self) -> int:
+        """Return the workspaces the context keeps for reuse to the device;
+        the bytes returned."""
+        b = c_uint64()
+        L.check(self.lib.muster_ctx_trim(self.h, byref(b)))
+        return b.value
+
 
 def register(images: torch.Tensor, times=None, pairs=False, ctx: Optional[Context] = None,
              **params):

@@ -36,13 +36,30 @@ void set_error(const char* fmt, ...);
                      hipGetErrorString(e_), __FILE__, __LINE__);                      \
   } while (0)
 
+// Device memory of a context.  Blocks that jobs release are kept, by size,
+// and handed out again to requests of that size (or up to 1/8 smaller):
+// repeated registrations of similar jobs then make no device allocation,
+// whose cost grows with the size of the request (seconds for the tens of GB
+// of a large batch).  A released block may still be in use by work in
+// flight (a device free would have waited for it), so released blocks wait
+// in a pending list until the next request that would reuse one, which
+// first synchronises the device.  Cached blocks count against the budget:
+// they are returned to the device before a new allocation would exceed it,
+// when an allocation fails (every context's cache, then one retry), by
+// trim() and when the context is destroyed.
 class Arena {
  public:
-  explicit Arena(uint64_t budget) : budget_(budget) {}
+  Arena(uint64_t budget, int device);
+  ~Arena();
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
   // Returns nullptr (no throw) when the budget or the device is full.
   void* try_alloc(size_t bytes);
   void release(void* p);
+  // Returns the cached blocks to the device; the bytes returned.
+  uint64_t trim();
   uint64_t used() const { return used_; }
+  uint64_t cached() const { return cached_; }
   uint64_t budget() const { return budget_; }
   // Largest used() since the context was made or the mark was last reset.
   uint64_t peak() const { return peak_; }
@@ -53,11 +70,17 @@ class Arena {
   bool fits(uint64_t bytes) const { return budget_ == 0 || used_ + bytes <= budget_; }
 
  private:
+  void* take_cached(size_t bytes);        // under mu_
+  uint64_t free_cached(uint64_t target);  // under mu_: frees until cached_ <= target
   std::mutex mu_;
   uint64_t budget_;
+  int device_;
   uint64_t used_ = 0;
+  uint64_t cached_ = 0;   // pending_ and free_
   uint64_t peak_ = 0;
   std::map<void*, size_t> live_;
+  std::vector<std::pair<size_t, void*>> pending_;  // released since the last device sync
+  std::multimap<size_t, void*> free_;              // safe to hand out
 };
 
 struct KernelStats {
@@ -108,7 +131,7 @@ struct Ctx {
   std::map<std::vector<int>, SimTile> tuned;
   std::string tune_path;             // optional on-disk cache (MUSTER_TUNE_CACHE)
   std::mutex tune_mu;
-  explicit Ctx(uint64_t budget) : arena(budget) {}
+  Ctx(uint64_t budget, int device) : arena(budget, device) {}
 };
 
 // Device allocation owned through the context's arena.

@@ -161,6 +161,33 @@ def test_batch_matches_alone(ctx, K):
         assert abs(r["loss_last"] - ra["loss_last"]) < 1e-12 * abs(ra["loss_last"])
 
 
+def test_released_workspaces_are_reused_and_trimmed():
+    """The arena keeps the workspaces finished jobs release and hands them to
+    later jobs of the same sizes.  A deterministic job run again on kept
+    workspaces, which another job has used in between, gives the flow it gave
+    on a fresh context; trim returns the kept bytes, after which nothing is
+    kept and the bytes in use are unchanged."""
+    from paper_2412_14671_amd import Context, MusterParams, synth
+    s = synth.phantom_series((24, 32, 40), 4, seed=37)
+    other = synth.phantom_series((24, 32, 40), 4, seed=38)
+    p = MusterParams(iters=[2, 4], K=5, window=5, metric="silncc", smooth_sigma=1.0,
+                     deterministic=True)
+    c = Context(0)
+    try:
+        a, _, _ = c.register(s.images.to(DEV), s.times, p)
+        mem = c.memory()
+        c.register(other.images.to(DEV), other.times, p)
+        b, _, _ = c.register(s.images.to(DEV), s.times, p)
+        assert_same_run(a, b, "fresh vs kept workspaces")
+        kept = c.trim()
+        log(f"in use {mem['in_use']}, peak {mem['peak']}, kept {kept}")
+        assert kept >= mem["peak"] - mem["in_use"] > 0
+        assert c.trim() == 0
+        assert c.memory()["in_use"] == mem["in_use"]
+    finally:
+        c.close()
+
+
 def test_deterministic_mode_agrees_with_the_default_mode():
     """The fixed-point accumulation changes results only at rounding level.
     Both runs use the same (default) tiling, so only the accumulation
