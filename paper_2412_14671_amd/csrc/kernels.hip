@@ -484,6 +484,8 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
 // 3-7 % faster than 3072 cells at four waves; 2048 cells overflowed too often.
 // ---------------------------------------------------------------------------
 constexpr int GATHER_CELLS = 2560;
+// The adjoints read their corners from a box in the scatter bins' LDS.
+constexpr int ADJ_BOX_CELLS = GATHER_CELLS < SCATTER_CELLS ? GATHER_CELLS : SCATTER_CELLS;
 #define GATHER_WAVES __attribute__((amdgpu_waves_per_eu(5)))
 
 __device__ __forceinline__ void sample_cells_lds(const cgfloat* __restrict__ f, int V, int H, int W,
@@ -1106,7 +1108,6 @@ template <int MODE, bool REG, bool DETMAX = false>
 __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict__ items,
                                                    int n_items, int n_tiles) {
   constexpr bool IN_ST = MODE >= 2, OUT_ST = MODE == 1 || MODE == 2;
-  static_assert(GATHER_CELLS <= SCATTER_CELLS, "the gather box shares the bins' LDS");
   __shared__ __align__(16) int acc[3 * SCATTER_CELLS];
   __shared__ int sred[16 * (BLOCK / 64)];
   __shared__ double red[BLOCK / 64];
@@ -1189,7 +1190,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
   // corners come from a box of src staged in acc: the bounding box of the
   // cells and the owned voxels, which is also the scatter's box.  The values
   // and the arithmetic are those of the direct loads, so the result is the
-  // same; a box larger than GATHER_CELLS reads the corners directly.
+  // same; a box larger than ADJ_BOX_CELLS reads the corners directly.
   BBox gb{};
   bool lds_box = false;
   if (!REG) {
@@ -1204,7 +1205,7 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
     }
     // the second half of sred: the scatter's own reduction uses the first
     gb = scatter_box<BLOCK>(lo, hi, 0.f, 0.f, sred + 8 * (BLOCK / 64)).bb;
-    lds_box = gb.cells > 0 && gb.cells <= GATHER_CELLS;  // block-uniform
+    lds_box = gb.cells > 0 && gb.cells <= ADJ_BOX_CELLS;  // block-uniform
     if (lds_box) {
       float* box = reinterpret_cast<float*>(acc);
       const int cells = gb.cells;
@@ -1443,7 +1444,6 @@ constexpr int CB_NT = 2 * BLOCK, CB_VP = PT_VOX / CB_NT;
 template <bool DETMAX>
 __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __restrict__ items,
                                                        int n_items, int n_tiles) {
-  static_assert(GATHER_CELLS <= SCATTER_CELLS, "the gather box shares the bins' LDS");
   __shared__ __align__(16) int acc[3 * SCATTER_CELLS];
   __shared__ int sred[16 * (CB_NT / 64)];
   const int tile = xcd_remap(blockIdx.x, n_tiles);
@@ -1477,7 +1477,7 @@ __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __r
   }
   // the corners come from a box of C staged in acc (the bounding box of the
   // cells, which is also the scatter's box; the values are those of the
-  // direct loads), or directly when the box is larger than GATHER_CELLS; the
+  // direct loads), or directly when the box is larger than ADJ_BOX_CELLS; the
   // reduce-only pass needs no corners
   BBox gb{};
   bool lds_box = false;
@@ -1493,7 +1493,7 @@ __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __r
     }
     // the second half of sred: the scatter's own reduction uses the first
     gb = scatter_box<CB_NT>(lo, hi, 0.f, 0.f, sred + 8 * (CB_NT / 64)).bb;
-    lds_box = gb.cells > 0 && gb.cells <= GATHER_CELLS;  // block-uniform
+    lds_box = gb.cells > 0 && gb.cells <= ADJ_BOX_CELLS;  // block-uniform
     if (lds_box) {
       float* box = reinterpret_cast<float*>(acc);
       const int cells = gb.cells;

@@ -342,7 +342,7 @@ inline int up_adj_tiles(int D, int H, int W) {
 constexpr int PT_Z = 8, PT_Y = 8, PT_X = 16;   // 1024 voxels, 256 threads
 constexpr int PT_VOX = PT_Z * PT_Y * PT_X;
 constexpr int BLOCK = 256;
-constexpr int SCATTER_CELLS = 2560;          // LDS bins per component
+constexpr int SCATTER_CELLS = 2048;          // LDS bins per component
 constexpr int STAGE_CAP = SCATTER_CELLS;      // cells per component of a staging slot
 // Tiles of the windowed-statistics kernels: TY x TX columns, z chunks.
 // Tile shapes (centres in y x x) of the window-statistics kernels; the block

@@ -93,8 +93,8 @@ def test_footprint_counts_fields(lib):
     # + 2 combined SVF gradients of the staged Exp adjoint
     fields = 3 * 2 + 4 * 7 + 2 + 6 + 8 + 6 + 2
     # Exp-backward staging: 2 steps x 4 directions x 32 tiles of 8x8x16, each a
-    # slot of 3 x 2560 floats and an 8-int descriptor
-    staging = 2 * 4 * 32 * (3 * 2560 * 4 + 8 * 4)
+    # slot of 3 x 2048 floats and an 8-int descriptor
+    staging = 2 * 4 * 32 * (3 * 2048 * 4 + 8 * 4)
     assert fields * F + staging <= b <= fields * F + staging + 200_000
     st2, b2 = _fp(lib, 3, (32, 32, 32), exp_mode=L.EXP_RECOMPUTE)
     assert st2 == L.OK and b2 == b - 4 * (7 - 3) * F
