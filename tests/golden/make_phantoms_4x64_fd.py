@@ -2,12 +2,14 @@
 FP64 oracle's loss on the 64^3 gradient-check series (four phantom sessions,
 K 6, window 7, alpha_ss 1), evaluated at half the ground-truth SVFs, at random
 (interval, component, voxel) triples at least r + 2 voxels from the border:
-256 triples for LNCC, 64 for SiLNCC.  Steps h = 1e-3 and h = 1e-4; a run
-adds the differences of one step to the file.  Each difference takes two
-whole-volume oracle evaluations, so the triples are spread over a process
-pool.  Calls only the oracle and the seeded input generator.
+256 triples per metric.  Steps h = 1e-3, 1e-4 and 1e-6 (the last resolves
+the rare triples whose interval at 1e-4 crosses a cell face of the
+trilinear interpolant, a kink of the loss); a run adds the differences of
+one step to the file, for both metrics or the ones named.  Each difference
+takes two whole-volume oracle evaluations, so the triples are spread over a
+process pool.  Calls only the oracle and the seeded input generator.
 
-    python tests/golden/make_phantoms_4x64_fd.py [h] [workers]
+    python tests/golden/make_phantoms_4x64_fd.py [h] [workers] [lncc] [silncc]
 """
 import json
 import os
@@ -29,7 +31,7 @@ from paper_2412_14671_amd import synth  # noqa: E402
 
 K, W = 6, 7
 H = 1e-3
-COUNTS = {"lncc": 256, "silncc": 64}
+COUNTS = {"lncc": 256, "silncc": 256}
 SEEDS = {"lncc": 3, "silncc": 4}
 
 _imgs = _phis = None
@@ -73,6 +75,7 @@ def main():
     global _imgs, _phis
     h = float(sys.argv[1]) if len(sys.argv) > 1 else H
     workers = int(sys.argv[2]) if len(sys.argv) > 2 else 8
+    metrics = sys.argv[3:] or ["lncc", "silncc"]
     _imgs, _phis = problem()
     shape = _imgs[0].shape
     path = os.path.join(HERE, "phantoms_4x64_fd.json")
@@ -84,11 +87,13 @@ def main():
             out.update(json.load(f))
     t0 = time.time()
     with mp.get_context("fork").Pool(workers) as pool:
-        for metric in ("lncc", "silncc"):
+        for metric in metrics:
             tr = triples(metric, shape, len(_phis))
             fd = pool.map(_fd, [(metric, h, t) for t in tr], chunksize=1)
             e = out.setdefault(metric, {})
             e["loss"] = O.forward(_phis, _imgs, params(metric))
+            if e.get("triples") != [list(t) for t in tr]:
+                e["fd"] = {}  # differences at other triples no longer apply
             e["triples"] = [list(t) for t in tr]
             e.setdefault("fd", {})[repr(h)] = fd
             print(f"{metric} h={h}: {len(tr)} differences, {time.time() - t0:.0f} s", flush=True)

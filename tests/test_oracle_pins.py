@@ -401,27 +401,32 @@ def test_T13_gradient_matches_finite_differences_sampled(w, K, metric, N, seed):
     assert abs((Lp - Lm) / (2 * hh) - dd) < 1e-5 * abs(dd) + 1e-8
 
 
-# Central differences of the FP64 loss on the 64^3 series.  A difference
-# whose interval [-h, h] crosses a cell face of the trilinear interpolant (a
-# kink of the loss) is off by up to about 0.6 % of max |g| at h = 1e-3; at
-# h = 1e-4 such crossings are rare (none of the 256 LNCC triples, one of the
-# 64 SiLNCC ones) and the other differences agree with the adjoint to 5e-5 of
-# max |g|.  Bounds: at h = 1e-4, every triple but the largest-error 2 % (at
-# least one) within FD4_TOL max |g|; at h = 1e-3, max |g - fd| below 2 % of
-# max |g| and the relative L2 error below 4 %.
-FD4_TOL = 2e-4
+# Central differences of the FP64 loss on the 64^3 series, 256 triples per
+# metric.  A difference whose interval [-h, h] crosses a cell face of the
+# trilinear interpolant (a kink of the loss) is off by up to about 0.6 % of
+# max |g| at h = 1e-3 (5 LNCC and 11 SiLNCC triples beyond 1e-4).  At
+# h = 1e-4 such crossings are rare (one triple per metric), and at h = 1e-6
+# there are none: every triple of both metrics agrees with the adjoint to
+# 5.2e-6 of max |g|.  Bounds: at h = 1e-6, every triple within FD6_TOL
+# max |g|; at h = 1e-4, every triple within FD4_TOL max |g| but at most 2 %
+# (at least one); at h = 1e-3, max |g - fd| below 2 % of max |g| and the
+# relative L2 error below 4 %.
+FD6_TOL = 2e-5
+FD4_TOL = 1e-4
 FD3_MAX, FD3_REL = 2e-2, 4e-2
+FD_STEPS = {"0.001", "0.0001", "1e-06"}
 
 
-def fd_check(an, fd, gmax, h, extra=0.0):
-    """Bounds of the 64^3 differences at step h (a string key of the stored
-    file); extra widens them by a parity tolerance (fractions of max |g|)."""
-    err = np.sort(np.abs(an - fd))
-    if h == "0.0001":
-        keep = len(err) - max(1, len(err) // 50)
-        return bool(err[keep - 1] < (FD4_TOL + extra) * gmax)
-    return bool(err[-1] < (FD3_MAX + extra) * gmax and
-                np.linalg.norm(an - fd) < (FD3_REL + extra) * np.linalg.norm(fd))
+def fd_check(an, fds, gmax, extra=0.0):
+    """Bounds of the 64^3 differences (fds: step -> differences, keys as in
+    the stored file); extra widens them by a parity tolerance (fractions of
+    max |g|)."""
+    f3, f4, f6 = (np.asarray(fds[h]) for h in ("0.001", "0.0001", "1e-06"))
+    crossings = int((np.abs(an - f4) >= (FD4_TOL + extra) * gmax).sum())
+    return bool(np.all(np.abs(an - f6) < (FD6_TOL + extra) * gmax) and
+                crossings <= max(1, len(an) // 50) and
+                np.abs(an - f3).max() < (FD3_MAX + extra) * gmax and
+                np.linalg.norm(an - f3) < (FD3_REL + extra) * np.linalg.norm(f3))
 
 
 @pytest.mark.parametrize("metric", ["lncc", "silncc"])
@@ -446,9 +451,9 @@ def test_T13_gradient_at_64cubed_matches_stored_finite_differences(metric):
     tr = [tuple(t) for t in gold[metric]["triples"]]
     an = np.array([g[t] for t in tr])
     gmax = np.abs(g).max()
-    assert set(gold[metric]["fd"]) == {"0.0001", "0.001"}
-    for h, fd in gold[metric]["fd"].items():
-        assert fd_check(an, np.array(fd), gmax, h), h
+    assert set(gold[metric]["fd"]) == FD_STEPS
+    assert len(tr) == 256
+    assert fd_check(an, gold[metric]["fd"], gmax)
 
 
 # --------------------------------------------------------------------------
