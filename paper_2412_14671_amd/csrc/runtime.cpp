@@ -87,124 +87,6 @@ static muster_status guard(Ctx* ctx, F&& f) {
 // ---------------------------------------------------------------------------
 // arena
 // ---------------------------------------------------------------------------
-namespace {
-// every arena of the process, so that an allocation that fails can first
-// take back what the others keep cached
-std::mutex g_arenas_mu;
-std::set<Arena*> g_arenas;
-
-void trim_other_arenas(Arena* self) {
-  std::vector<Arena*> all;
-  {
-    std::lock_guard<std::mutex> lk(g_arenas_mu);
-    all.assign(g_arenas.begin(), g_arenas.end());
-  }
-  // one arena lock at a time (never two), after the registry lock is dropped
-  for (Arena* a : all)
-    if (a != self) a->trim();
-}
-}  // namespace
-
-Arena::Arena(uint64_t budget, int device) : budget_(budget), device_(device) {
-  std::lock_guard<std::mutex> lk(g_arenas_mu);
-  g_arenas.insert(this);
-}
-
-Arena::~Arena() {
-  {
-    std::lock_guard<std::mutex> lk(g_arenas_mu);
-    g_arenas.erase(this);
-  }
-  trim();
-}
-
-void* Arena::take_cached(size_t bytes) {
-  auto it = free_.lower_bound(bytes);
-  const bool fit = it != free_.end() && it->first <= bytes + bytes / 8;
-  if (!fit && !pending_.empty()) {
-    // the released blocks become reusable once the device has finished the
-    // work that may still read or write them
-    int cur = -1;
-    (void)hipGetDevice(&cur);
-    if (cur != device_) (void)hipSetDevice(device_);
-    (void)hipDeviceSynchronize();
-    if (cur >= 0 && cur != device_) (void)hipSetDevice(cur);
-    for (const auto& e : pending_) free_.emplace(e.first, e.second);
-    pending_.clear();
-    it = free_.lower_bound(bytes);
-  }
-  if (it == free_.end() || it->first > bytes + bytes / 8) return nullptr;
-  if (budget_ && used_ + it->first > budget_) return nullptr;
-  void* p = it->second;
-  const size_t sz = it->first;
-  free_.erase(it);
-  cached_ -= sz;
-  live_[p] = sz;
-  used_ += sz;
-  peak_ = std::max(peak_, used_);
-  return p;
-}
-
-uint64_t Arena::free_cached(uint64_t target) {
-  // a device free waits for the work in flight, so pending blocks may go too
-  uint64_t freed = 0;
-  while (cached_ > target && !pending_.empty()) {
-    (void)hipFree(pending_.back().second);
-    cached_ -= pending_.back().first;
-    freed += pending_.back().first;
-    pending_.pop_back();
-  }
-  while (cached_ > target && !free_.empty()) {
-    auto it = std::prev(free_.end());
-    (void)hipFree(it->second);
-    cached_ -= it->first;
-    freed += it->first;
-    free_.erase(it);
-  }
-  return freed;
-}
-
-uint64_t Arena::trim() {
-  std::lock_guard<std::mutex> lk(mu_);
-  return free_cached(0);
-}
-
-void* Arena::try_alloc(size_t bytes) {
-  if (bytes == 0) bytes = 256;
-  bytes = (bytes + 255) & ~(size_t)255;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      if (budget_ && used_ + bytes > budget_) return nullptr;
-      if (void* p = take_cached(bytes)) return p;
-      // cached blocks count against the budget
-      if (budget_ && used_ + cached_ + bytes > budget_) free_cached(budget_ - used_ - bytes);
-      void* p = nullptr;
-      if (hipMalloc(&p, bytes) == hipSuccess && p) {
-        live_[p] = bytes;
-        used_ += bytes;
-        peak_ = std::max(peak_, used_);
-        return p;
-      }
-      (void)hipGetLastError();
-      if (attempt == 1) return nullptr;
-      free_cached(0);
-    }
-    trim_other_arenas(this);
-  }
-  return nullptr;
-}
-
-void Arena::release(void* p) {
-  std::lock_guard<std::mutex> lk(mu_);
-  auto it = live_.find(p);
-  if (it == live_.end()) return;
-  used_ -= it->second;
-  pending_.emplace_back(it->second, p);
-  cached_ += it->second;
-  live_.erase(it);
-}
-
 void DevMem::alloc(Ctx* c, size_t n) {
   reset();
   ctx = c;

@@ -18,6 +18,7 @@
 
 #include "../../include/muster.h"
 #include "muster_internal.h"
+#include "arena.h"
 #include "scheduler.h"
 
 namespace muster {
@@ -36,52 +37,25 @@ void set_error(const char* fmt, ...);
                      hipGetErrorString(e_), __FILE__, __LINE__);                      \
   } while (0)
 
-// Device memory of a context.  Blocks that jobs release are kept, by size,
-// and handed out again to requests of that size (or up to 1/8 smaller):
-// repeated registrations of similar jobs then make no device allocation,
-// whose cost grows with the size of the request (seconds for the tens of GB
-// of a large batch).  A released block may still be in use by work in
-// flight (a device free would have waited for it), so released blocks wait
-// in a pending list until the next request that would reuse one, which
-// first synchronises the device.  Cached blocks count against the budget:
-// they are returned to the device before a new allocation would exceed it,
-// when an allocation fails (every context's cache, then one retry), by
-// trim() and when the context is destroyed.
-class Arena {
- public:
-  Arena(uint64_t budget, int device);
-  ~Arena();
-  Arena(const Arena&) = delete;
-  Arena& operator=(const Arena&) = delete;
-  // Returns nullptr (no throw) when the budget or the device is full.
-  void* try_alloc(size_t bytes);
-  void release(void* p);
-  // Returns the cached blocks to the device; the bytes returned.
-  uint64_t trim();
-  uint64_t used() const { return used_; }
-  uint64_t cached() const { return cached_; }
-  uint64_t budget() const { return budget_; }
-  // Largest used() since the context was made or the mark was last reset.
-  uint64_t peak() const { return peak_; }
-  void reset_peak() {
-    std::lock_guard<std::mutex> lk(mu_);
-    peak_ = used_;
+// The context's device memory: the arena's bookkeeping (arena.h) over HIP's
+// allocator.  hipMalloc allocates on the current device, which every entry
+// point sets to the context's.
+struct HipDev {
+  static bool alloc(size_t bytes, void** p) {
+    if (hipMalloc(p, bytes) == hipSuccess && *p) return true;
+    (void)hipGetLastError();
+    return false;
   }
-  bool fits(uint64_t bytes) const { return budget_ == 0 || used_ + bytes <= budget_; }
-
- private:
-  void* take_cached(size_t bytes);        // under mu_
-  uint64_t free_cached(uint64_t target);  // under mu_: frees until cached_ <= target
-  std::mutex mu_;
-  uint64_t budget_;
-  int device_;
-  uint64_t used_ = 0;
-  uint64_t cached_ = 0;   // pending_ and free_
-  uint64_t peak_ = 0;
-  std::map<void*, size_t> live_;
-  std::vector<std::pair<size_t, void*>> pending_;  // released since the last device sync
-  std::multimap<size_t, void*> free_;              // safe to hand out
+  static void free(void* p) { (void)hipFree(p); }
+  static void sync(int device) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != device) (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+  }
 };
+using Arena = BasicArena<HipDev>;
 
 struct KernelStats {
   int64_t launches[MUSTER_K_COUNT] = {};
