@@ -118,6 +118,15 @@ __device__ __forceinline__ float2a ld2o(const cgfloat* plane, uint32_t i) {
 __device__ __forceinline__ float ldo(const cgfloat* plane, uint32_t i) {
   return *(const GLOBAL float*)((const GLOBAL char*)plane + (i << 2));
 }
+// One float per lane from global memory straight into LDS: lane l of the
+// wave writes lds_wave[l], where lds_wave is the same for the whole wave (the
+// first element of its run).  No register holds the value, and the barrier
+// that follows waits for the load like for any other.
+__device__ __forceinline__ void ld_to_lds(const cgfloat* src, float* lds_wave) {
+  __builtin_amdgcn_global_load_lds((const GLOBAL void*)src,
+                                   (__attribute__((address_space(3))) void*)lds_wave, 4, 0, 0);
+}
+
 __device__ __forceinline__ void sto(gfloat* plane, uint32_t i, float v) {
   *(GLOBAL float*)((GLOBAL char*)plane + (i << 2)) = v;
 }
@@ -515,9 +524,10 @@ __device__ __forceinline__ void sample_cells_lds(const cgfloat* __restrict__ f, 
     const int lz = (int)(((float)r + 0.5f) * inv_ey);
     const int ly = r - lz * bb.ey;
     const int g = ((bb.lz + lz) * H + (bb.ly + ly)) * W + (bb.lx + lx);
-    box[i] = ldo(f, g);
-    box[cells + i] = ldo(f + V, g);
-    box[2 * cells + i] = ldo(f + 2 * V, g);
+    const int w0 = i & ~63;  // the wave's first cell: i = threadIdx.x + k * block
+    ld_to_lds(f + g, box + w0);
+    ld_to_lds(f + V + g, box + cells + w0);
+    ld_to_lds(f + 2 * V + g, box + 2 * cells + w0);
   }
   __syncthreads();
   const int sy = bb.ex, sz = bb.ex * bb.ey;
@@ -1217,9 +1227,10 @@ __global__ __launch_bounds__(BLOCK) void k_exp_bwd(const ExpBwdItem* __restrict_
         const int lz = (int)(((float)r + 0.5f) * inv_ey);
         const int ly = r - lz * gb.ey;
         const int g = ((gb.lz + lz) * H + (gb.ly + ly)) * W + (gb.lx + lx);
-        box[i] = ldo(s, g);
-        box[cells + i] = ldo(s + V, g);
-        box[2 * cells + i] = ldo(s + 2 * V, g);
+        const int w0 = i & ~63;  // the wave's first cell: i = threadIdx.x + k * block
+        ld_to_lds(s + g, box + w0);
+        ld_to_lds(s + V + g, box + cells + w0);
+        ld_to_lds(s + 2 * V + g, box + 2 * cells + w0);
       }
       __syncthreads();
     }
@@ -1505,9 +1516,10 @@ __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __r
         const int lz = (int)(((float)r + 0.5f) * inv_ey);
         const int ly = r - lz * gb.ey;
         const int g = ((gb.lz + lz) * H + (gb.ly + ly)) * W + (gb.lx + lx);
-        box[i] = ldo(C, g);
-        box[cells + i] = ldo(C + V, g);
-        box[2 * cells + i] = ldo(C + 2 * V, g);
+        const int w0 = i & ~63;  // the wave's first cell: i = threadIdx.x + k * block
+        ld_to_lds(C + g, box + w0);
+        ld_to_lds(C + V + g, box + cells + w0);
+        ld_to_lds(C + 2 * V + g, box + 2 * cells + w0);
       }
       __syncthreads();
     }
