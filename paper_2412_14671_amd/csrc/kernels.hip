@@ -276,7 +276,7 @@ __device__ __forceinline__ void reg_tile_load(const cgfloat* __restrict__ f, int
     const int z = min(max(z0 - 1 + hz, 0), D - 1);
     const int y = min(max(y0 - 1 + hy, 0), H - 1);
     const int x = min(max(x0 - 1 + hx, 0), W - 1);
-    t[i] = f[c * V + (z * H + y) * W + x];
+    ld_to_lds(f + c * V + (z * H + y) * W + x, t + (i & ~63));  // i = threadIdx.x + k * BLOCK
   }
 }
 
