@@ -121,7 +121,10 @@ __device__ __forceinline__ float ldo(const cgfloat* plane, uint32_t i) {
 // One float per lane from global memory straight into LDS: lane l of the
 // wave writes lds_wave[l], where lds_wave is the same for the whole wave (the
 // first element of its run).  No register holds the value, and the barrier
-// that follows waits for the load like for any other.
+// that follows waits for the load like for any other.  The callers walk
+// element i = threadIdx.x + k * (block size), with block sizes multiples of
+// 64, so a wave's run starts at i & ~63; lanes past the end stay inactive
+// and write nothing.
 __device__ __forceinline__ void ld_to_lds(const cgfloat* src, float* lds_wave) {
   __builtin_amdgcn_global_load_lds((const GLOBAL void*)src,
                                    (__attribute__((address_space(3))) void*)lds_wave, 4, 0, 0);
@@ -1451,6 +1454,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_combine(const PullItem* __restri
 // with its extra streams (G, U_prev, G_prev) it gains more from the higher
 // occupancy than it loses in loads in flight per thread (measured: 11 %).
 constexpr int CB_NT = 2 * BLOCK, CB_VP = PT_VOX / CB_NT;
+static_assert(BLOCK % 64 == 0 && CB_NT % 64 == 0, "blocks of whole waves (ld_to_lds)");
 
 template <bool DETMAX>
 __global__ __launch_bounds__(CB_NT) void k_compose_bwd(const ComposeBwdItem* __restrict__ items,
