@@ -234,6 +234,61 @@ def test_sim_of_identical_images_is_zero(ctx):
 
 
 # ---------------------------------------------------------------------------
+# Degenerate grids: the smallest edges the entry points accept (2 for the
+# fields, the window for the similarity), grids smaller than one tile, and
+# one-cell-thick slabs across several tiles
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(2, 2, 2), (2, 3, 70), (3, 5, 7), (9, 2, 17)])
+def test_field_kernels_on_minimal_grids_match_oracle(ctx, shape):
+    """Exp, its adjoint (staged and flat), the composition and its adjoint
+    where every sample position is within a cell of the border and most are
+    clamped."""
+    log(f"minimal grid fields {shape}")
+    K = 3
+    phi = smooth_field(shape, 1.5, seed=sum(shape))
+    G = smooth_field(shape, 1.0, seed=sum(shape) + 1, sigma=1.0)
+    for sign in (1, -1):
+        _, steps = ctx.exp(gpu(phi), K, sign, steps=True)
+        us = O.exp_fwd(sign * phi.astype(np.float64), K)
+        st = host(steps)
+        for s in range(1, K + 1):
+            assert np.abs(st[s - 1] - us[s]).max() < 1e-4, f"sign {sign} step {s}"
+        want = sign * 2.0 ** -K * O.exp_bwd(us, G.astype(np.float64))
+        for flat in (False, True):
+            got = host(ctx.exp_bwd(gpu(phi), gpu(G), K, sign, "store", flat=flat))
+            assert_grad_close(got, want)
+    U = smooth_field(shape, 2.0, seed=sum(shape) + 2)
+    C = smooth_field(shape, 1.5, seed=sum(shape) + 3)
+    got = host(ctx.compose(gpu(U), gpu(C)))
+    assert np.abs(got - O.compose(U.astype(np.float64), C.astype(np.float64))).max() < 1e-4
+    gp = torch.zeros((3,) + shape, device=DEV)
+    gc = torch.zeros((3,) + shape, device=DEV)
+    ctx.compose_bwd(gpu(U), gpu(C), gpu(G), gp, gc)
+    wp, wc = O.compose_bwd(U.astype(np.float64), C.astype(np.float64), G.astype(np.float64))
+    assert_grad_close(host(gp), wp)
+    assert_grad_close(host(gc), wc)
+
+
+@pytest.mark.parametrize("shape,w", [((7, 7, 7), 7), ((5, 9, 12), 5), ((3, 3, 50), 3),
+                                     ((7, 40, 9), 7)])
+@pytest.mark.parametrize("metric", ["lncc", "silncc"])
+def test_sim_on_minimal_grids_matches_oracle(ctx, shape, w, metric):
+    """The similarity and its gradient on grids of one window edge: (7, 7, 7)
+    has a single window centre, the others one row or one plane of them."""
+    log(f"minimal grid sim {shape} w={w} {metric}")
+    F = smooth_image(shape, seed=w + 11)
+    I = smooth_image(shape, seed=w + 12)
+    U = smooth_field(shape, 1.0, seed=w + 13)
+    val, g = ctx.sim(gpu(F), gpu(I), gpu(U), w, metric, grad=True)
+    m = O.LNCC if metric == "lncc" else O.SILNCC
+    s_ref, g_ref = O.pair_sim_grad([F.astype(np.float64), I.astype(np.float64)],
+                                   U.astype(np.float64), 0, 1, O.Params(window=w, metric=m))
+    assert abs(val - s_ref) < 1e-3 * abs(s_ref)
+    assert_grad_close(host(g), g_ref)
+
+
+# ---------------------------------------------------------------------------
 # Regulariser, Adam, pyramid
 # ---------------------------------------------------------------------------
 
