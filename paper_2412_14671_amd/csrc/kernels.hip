@@ -483,8 +483,8 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
 // ---------------------------------------------------------------------------
 // Gathers from a box staged in LDS.  The block reduces the bounding box of
 // the cells its voxels sample (the reduction of the scatters), loads that box
-// of the three component planes into LDS with coalesced loads, and reads the
-// 8 corners of each cell there.  A few wide row loads per cell then replace
+// of the three component planes straight into LDS (coalesced loads that do
+// not pass through registers), and reads the 8 corners of each cell there.  A few wide row loads per cell then replace
 // the scattered corner loads of every voxel, which otherwise keep the L1 and
 // texture path saturated.  The values and the arithmetic are those of
 // sample_cells, so the result is bit-identical; a box larger than
@@ -493,7 +493,8 @@ __device__ __forceinline__ ScatterBox scatter_box(int (&lo)[3], int (&hi)[3], fl
 //
 // 2560 cells (30 KB of LDS) let five blocks share a CU, and the kernels that
 // stage a box are held to five waves per SIMD (at most 102 VGPRs, no spill):
-// 3-7 % faster than 3072 cells at four waves; 2048 cells overflowed too often.
+// 3-7 % faster than 3072 cells at four waves.  2048 cells at six waves per
+// SIMD (80 VGPRs, a few bytes of spill) ran no faster.
 // ---------------------------------------------------------------------------
 constexpr int GATHER_CELLS = 2560;
 // The adjoints read their corners from a box in the scatter bins' LDS.
