@@ -107,6 +107,9 @@ def test_footprint_counts_fields(lib):
 
 @pytest.mark.parametrize("N,dims,kw", [
     (1, (32, 32, 32), {}),                       # one session
+    (65, (32, 32, 32), {}),                      # more sessions than a job holds
+    (3, (1024, 1024, 1024), {}),                 # 3 V beyond 32-bit offsets
+    (3, (896, 896, 892), {}),                    # the first volume past that limit
     (3, (32, 32, 4), {}),                        # smaller than the window
     (3, (32, 32, 30), {"levels": 3, "iters": (1, 1, 1)}),  # not divisible by 4
     (3, (32, 32, 32), {"window": 4}),            # even window
@@ -126,6 +129,16 @@ def test_footprint_rejects_invalid_problems(lib, N, dims, kw):
     st, _ = _fp(lib, N, dims, **kw)
     assert st == L.E_INVALID
     assert lib.muster_last_error()
+
+
+def test_largest_accepted_problem(lib):
+    """The limits at their edge: 64 sessions, and the largest volume whose
+    three component planes stay within 32-bit offsets (3 V < 2^31 - 1)."""
+    st, b = _fp(lib, 64, (32, 32, 32))
+    assert st == L.OK and b > 0
+    assert 3 * 896 * 896 * 890 < 2 ** 31 - 1 <= 3 * 896 * 896 * 892
+    st, b = _fp(lib, 2, (896, 896, 890))
+    assert st == L.OK and b > 3 * 896 * 896 * 890 * 4
 
 
 def test_null_arguments_are_rejected(lib):

@@ -250,6 +250,18 @@ def test_invalid_arguments_are_rejected(ctx):
         ctx.register(imgs, None, MusterParams(iters=[1, 1, 1, 1, 1], window=3))
     with pytest.raises(MusterError, match="E_INVALID"):
         ctx.register(imgs[:1], None, MusterParams(iters=[1], window=3))
+    # an empty batch, and a batch whose jobs differ in their schedule
+    with pytest.raises(MusterError, match="E_INVALID"):
+        ctx.register_batch([], None, MusterParams(iters=[1], window=3))
+    from paper_2412_14671_amd import _lib as L
+    from paper_2412_14671_amd.api import _stream
+    keep = []
+    outs = [torch.empty((2, 3, 16, 16, 16), device=DEV) for _ in range(2)]
+    jobs = (L.Job * 2)()
+    for k, n in enumerate((1, 2)):
+        jobs[k] = ctx._job(imgs, None, MusterParams(iters=[n], window=3), outs[k], None, keep=keep)
+    reps = (L.Report * 2)()
+    assert ctx.lib.muster_register_batch(ctx.h, _stream(), 2, jobs, reps) == L.E_INVALID
 
 
 def test_server_results_match_alone(ctx):
