@@ -157,6 +157,49 @@ def test_T4_composition_of_affine_fields_is_the_matrix_product():
     assert np.max(np.abs(out[:, s, s, s] - want[:, s, s, s])) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(20, 18, 14), (24, 21, 30)])
+def test_adjoints_of_a_contraction_have_closed_forms(shape):
+    """With u(p) = -r (p - c) towards the grid centre every sample position
+    stays inside, and the adjoints of the squaring step and the composition
+    (Alg. 1, Eq. cum_deformation) reduce to closed forms:
+    * composition of -r_U (p - c) and -r_C (p - c) under a constant gradient
+      g: G_prev = (1 - r_C) g; with r_U = 1/2 the sample positions form a
+      lattice of spacing 1/2, on which the linear hat functions sum to 2 per
+      axis, so G_C = 8 g wherever each hat's support is covered and 0 farther
+      than one voxel from the positions;
+    * Exp adjoint: one squaring of u_s = -a_s (p - c) multiplies the sum of
+      the gradient by 2 - a_s (own term 1, Jacobian term -a_s, scatter
+      weights summing to 1)."""
+    g = O.identity_grid(shape)
+    c = np.array([(n - 1) / 2.0 for n in shape])[:, None, None, None]
+    gv = np.array([1.0, -2.0, 0.5])[:, None, None, None] * np.ones((3,) + shape)
+    rU, rC = 0.5, 0.25
+    wp, wc = O.compose_bwd(-rU * (g - c), -rC * (g - c), gv)
+    assert np.abs(wp - (1 - rC) * gv).max() < 1e-14
+    inner, outer = [], []
+    for n in shape:
+        lo, hi = (n - 1) / 4.0, 3.0 * (n - 1) / 4.0
+        inner.append(slice(int(np.ceil(lo + 1.0)), int(np.floor(hi - 1.0)) + 1))
+        outer.append((int(np.floor(lo - 1.0)), int(np.ceil(hi + 1.0))))
+    for a in range(3):
+        assert np.abs(wc[a][tuple(inner)] - 8 * gv[a, 0, 0, 0]).max() < 1e-12
+        for ax in range(3):
+            lo_end, hi_start = outer[ax]
+            for sl in (slice(0, lo_end + 1), slice(hi_start, shape[ax])):
+                idx = [slice(None)] * 3
+                idx[ax] = sl
+                assert np.all(wc[a][tuple(idx)] == 0.0)
+    # the mass is conserved: every weight lands somewhere
+    assert np.allclose(wc.sum(axis=(1, 2, 3)), gv.sum(axis=(1, 2, 3)), rtol=1e-12)
+    r, K = 0.5, 2
+    us = O.exp_fwd(-r * (g - c), K)
+    G0 = O.exp_bwd(us, gv)
+    factor = 1.0
+    for s in range(K):
+        factor *= 2.0 - (1.0 - (1.0 - r / 2 ** K) ** (2 ** s))
+    assert np.allclose(G0.sum(axis=(1, 2, 3)), factor * gv.sum(axis=(1, 2, 3)), rtol=1e-12)
+
+
 @pytest.mark.parametrize("K", [4, 7])
 def test_T5_self_composition_equals_one_more_squaring(K):
     v = smooth_field((12, 13, 14), 1.2, seed=K)
