@@ -182,3 +182,34 @@ def test_exp_adjoint_sums_on_the_largest_grid(ctx):
         assert torch.isfinite(grad[a]).all()
     del grad
     release(ctx)
+
+
+@pytest.mark.parametrize("metric", ["lncc", "silncc"])
+def test_similarity_on_the_largest_grid(ctx, metric):
+    """The warp, the window statistics and their adjoint over the whole grid
+    (Sec. 2.6, Eq. LNCC): the moving image an affine function of the fixed
+    one, M = 2F + 1 with F = sin 0.7z + sin 0.9y + sin 1.1x and U = 0, so every
+    window's LNCC and SiLNCC residual is 0 up to rounding (each window's
+    variance is of order 1, far above the guards). A window whose statistics
+    mixed voxels of another place would not be."""
+    D, H, W = SHAPE
+    log(f"largest grid {SHAPE}: similarity {metric}, w 7")
+    F = torch.empty(SHAPE, device=DEV)
+    yy = torch.sin(0.9 * torch.arange(H, device=DEV, dtype=torch.float64)).view(1, -1, 1)
+    xx = torch.sin(1.1 * torch.arange(W, device=DEV, dtype=torch.float64)).view(1, 1, -1)
+    for z0 in range(0, D, SLAB):
+        z1 = min(D, z0 + SLAB)
+        zz = torch.sin(0.7 * torch.arange(z0, z1, device=DEV, dtype=torch.float64)).view(-1, 1, 1)
+        F[z0:z1] = (zz + yy + xx).to(torch.float32)
+    I = 2.0 * F + 1.0
+    U = torch.zeros((3,) + SHAPE, device=DEV)
+    val, g = ctx.sim(F, I, U, 7, metric, grad=True)
+    gmax = g.abs().max().item()
+    log(f"  loss {val:.3e}, largest gradient {gmax:.3e}")
+    # a plane of mismatched windows would add about 1e-3 to the mean loss, and
+    # a single mismatched window about 1 / (number of windows) = 1.4e-9 to
+    # the gradient; rounding leaves far less
+    assert abs(val) < 1e-4
+    assert math.isfinite(gmax) and gmax < 1e-10
+    del F, I, U, g
+    release(ctx)
