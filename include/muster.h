@@ -316,7 +316,7 @@ muster_status muster_exp(muster_ctx* ctx, void* stream, const int dims[3], int K
 /* grad_svf = d<G, Exp(sign*svf)>/dsvf for G = grad_disp (adjoint of
  * muster_exp), in MUSTER_EXP_STORE or _RECOMPUTE mode.  With K >= 2 the
  * squaring steps hand their scatter boxes to each other through staging
- * slots, as the registration's backward pass does (the kernels it times);
+ * slots, with the same kernels as the registration's backward pass;
  * mode | MUSTER_EXP_FLAT adds every step into a flat field instead. */
 #define MUSTER_EXP_FLAT 4
 muster_status muster_exp_bwd(muster_ctx* ctx, void* stream, const int dims[3], int K,
